@@ -1,0 +1,698 @@
+/*
+ * pcrt_oracle.c -- plain, slow, FP64 CPU oracle for point-cloud radio ray tracing.
+ *
+ * TEST INFRASTRUCTURE. This is the checker that the GPU library is compared
+ * against. Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may build, load or call it; the product path never does. It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * Method: Vaara et al., "Differentiable High-Performance Ray Tracing-Based
+ * Simulation of Radio Propagation with Point Clouds" (arXiv 2507.04021).
+ *   - Input: augmented point cloud (position, normal, surface label, material
+ *     label per point), TX and RX positions (Sec. II, opening paragraph).
+ *   - Each point is a planar disk of radius r_p (Sec. II-C).
+ *   - Rays keep a constant count; every interaction continues as a specular
+ *     reflection (Sec. II-B).
+ *   - Diffuse scattering is the last interaction, validated by a ray from the
+ *     scatter point to the RX (Sec. II-B.1).
+ *   - Specular paths minimise the path length of Eq. (1) on infinite planes,
+ *     then every interaction is validated with thresholds t_a, t_d and up to
+ *     kappa retries (Sec. II-B.2, Table I).
+ *   - Duplicates are removed with a key of surface labels (Sec. II-B.4).
+ *   - Field: Fresnel reflection from complex permittivity, scattering
+ *     coefficient, free-space spreading (the paper delegates this to its EM
+ *     back end; the readings used here are spelled out next to each function).
+ *
+ * Everything is brute force: every query tests every disk. All arithmetic is
+ * double precision; FP32 input arrays are promoted on entry. Parallelism is
+ * OpenMP over independent rays / (key, receiver) pairs only; every reduction
+ * is serial in a fixed order.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_C0 299792458.0
+#define ORC_EPS0 8.8541878128e-12
+#define ORC_PI 3.14159265358979323846
+#define ORC_KMAX 8
+
+enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4 };
+
+typedef struct {
+    int64_t n;
+    double *p;  /* [n][3] centres */
+    double *nr; /* [n][3] unit normals */
+    const uint16_t *mat;
+    const uint32_t *surf;
+    double r;
+} scene_t;
+
+typedef struct {
+    double eps_tie;  /* nearest-hit tie window (m) */
+    double eps_self; /* minimum hit distance from a ray origin (m) */
+    double cos_ta;   /* cos of the angle threshold t_a */
+    double t_d;      /* plane-distance threshold (m) */
+    int kappa;       /* refinement retries */
+} thr_t;
+
+typedef struct {
+    int n_labels;
+    const double *eps_r, *sigma, *scat;
+    double freq, omega, lambda, k0;
+} em_t;
+
+/* ------------------------------------------------------------------ vectors */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void sub3(double *r, const double *a, const double *b) { r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2]; }
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+static void scale3(double *a, double s) { a[0] *= s; a[1] *= s; a[2] *= s; }
+static void copy3(double *d, const double *s) { d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; }
+static void from_f32(double *d, const float *s) { d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; }
+
+static int scene_init(scene_t *s, int64_t n, const float *pos, const float *nrm, const uint16_t *mat,
+                      const uint32_t *surf, double r)
+{
+    s->n = n;
+    s->mat = mat;
+    s->surf = surf;
+    s->r = r;
+    s->p = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    s->nr = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!s->p || !s->nr) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        from_f32(s->p + 3 * i, pos + 3 * i);
+        from_f32(s->nr + 3 * i, nrm + 3 * i);
+        double l = norm3(s->nr + 3 * i);
+        if (!(l > 0.0) || !isfinite(l)) return -1;
+        scale3(s->nr + 3 * i, 1.0 / l);
+    }
+    return 0;
+}
+
+static void scene_free(scene_t *s)
+{
+    free(s->p);
+    free(s->nr);
+}
+
+/* ------------------------------------------------- launch directions (a3) */
+/* Fibonacci sphere: z = 1 - (2j+1)/N, phi = 2 pi frac(j g), g = (3 - sqrt 5)/2.
+ * Computed in FP64 and rounded to FP32; both implementations trace these FP32
+ * vectors. (The paper launches one ray per discretised point set; a uniform
+ * sphere is the launch used here.) */
+void orc_fib_dirs(int64_t n_budget, const int64_t *ids, int64_t n_ids, float *out)
+{
+    const double g = (3.0 - sqrt(5.0)) / 2.0;
+    for (int64_t q = 0; q < n_ids; ++q) {
+        int64_t j = ids[q];
+        double z = 1.0 - (2.0 * (double)j + 1.0) / (double)n_budget;
+        double rho = sqrt(fmax(0.0, 1.0 - z * z));
+        double f = (double)j * g;
+        f -= floor(f);
+        double phi = 2.0 * ORC_PI * f;
+        out[3 * q + 0] = (float)(rho * cos(phi));
+        out[3 * q + 1] = (float)(rho * sin(phi));
+        out[3 * q + 2] = (float)z;
+    }
+}
+
+/* ------------------------------------------------- ray-disk test (Sec. II-C) */
+/* Two-sided disk of centre p, unit normal n, radius r. Returns 1 on a hit with
+ * ray parameter t, hit point q and squared distance |q - p|^2. */
+static int ray_disk(const scene_t *s, int64_t i, const double *o, const double *d, double *t, double *q,
+                    double *d2)
+{
+    const double *p = s->p + 3 * i, *n = s->nr + 3 * i;
+    double a = dot3(d, n);
+    if (fabs(a) < 1e-6) return 0;
+    double w[3];
+    sub3(w, p, o);
+    double tt = dot3(w, n) / a;
+    double qq[3] = {o[0] + tt * d[0], o[1] + tt * d[1], o[2] + tt * d[2]};
+    double e[3];
+    sub3(e, qq, p);
+    double dd = dot3(e, e);
+    if (dd > s->r * s->r) return 0;
+    *t = tt;
+    copy3(q, qq);
+    *d2 = dd;
+    return 1;
+}
+
+/* Nearest hit with an order-independent two-pass rule:
+ *   t* = smallest t over hits in (t_lo, t_hi) not excluded;
+ *   candidates = hits with t <= t* + eps_tie;
+ *   winner = smallest (|q - p|^2, index), compared lexicographically.
+ * The paper picks the closest points at an intersection (Sec. II-B.4); the
+ * window makes coplanar overlapping disks resolve by disk centre distance. */
+static int64_t nearest(const scene_t *s, const double *o, const double *d, int64_t excl, double t_lo,
+                       double t_hi, double eps_tie, double *t_out, double *q_out)
+{
+    double tstar = INFINITY, t, q[3], d2;
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (i == excl) continue;
+        if (ray_disk(s, i, o, d, &t, q, &d2) && t > t_lo && t < t_hi && t < tstar) tstar = t;
+    }
+    if (!(tstar < INFINITY)) return -1;
+    int64_t best = -1;
+    double bd2 = INFINITY;
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (i == excl) continue;
+        if (ray_disk(s, i, o, d, &t, q, &d2) && t > t_lo && t < t_hi && t <= tstar + eps_tie) {
+            if (d2 < bd2) { /* ascending i: ties on d2 keep the smaller index */
+                bd2 = d2;
+                best = i;
+                *t_out = t;
+                copy3(q_out, q);
+            }
+        }
+    }
+    return best;
+}
+
+/* True iff some disk other than excl is hit strictly between a and b, more
+ * than eps_self away from both ends. */
+static int occluded(const scene_t *s, const double *a, const double *b, int64_t excl, double eps_self)
+{
+    double d[3];
+    sub3(d, b, a);
+    double len = norm3(d);
+    scale3(d, 1.0 / len);
+    double t, q[3], d2;
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (i == excl) continue;
+        if (ray_disk(s, i, a, d, &t, q, &d2) && t > eps_self && t < len - eps_self) return 1;
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------- Fresnel (field) */
+/* eta = eps_r - j sigma/(omega eps0) (time convention e^{+j omega t});
+ * w = sqrt(eta - sin^2) (principal branch);
+ * Gamma_TE = (c - w)/(c + w), Gamma_TM = (eta c - w)/(eta c + w), c = cos(theta_i).
+ * Derivatives with respect to eta are returned when requested. */
+static void fresnel(const em_t *em, int label, double c, double complex *gte, double complex *gtm,
+                    double complex *dte, double complex *dtm)
+{
+    double complex eta = em->eps_r[label] - I * (em->sigma[label] / (em->omega * ORC_EPS0));
+    double s2 = 1.0 - c * c;
+    double complex w = csqrt(eta - s2);
+    *gte = (c - w) / (c + w);
+    *gtm = (eta * c - w) / (eta * c + w);
+    if (dte) *dte = -c / (w * (c + w) * (c + w));
+    if (dtm) *dtm = c * (eta - 2.0 * s2) / (w * (eta * c + w) * (eta * c + w));
+}
+
+void orc_fresnel(double eps_r, double sigma, double freq, int64_t n, const double *cosv, double *out)
+{
+    em_t em = {1, &eps_r, &sigma, NULL, freq, 2.0 * ORC_PI * freq, ORC_C0 / freq, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double complex a, b, da, db;
+        fresnel(&em, 0, cosv[i], &a, &b, &da, &db);
+        out[8 * i + 0] = creal(a);
+        out[8 * i + 1] = cimag(a);
+        out[8 * i + 2] = creal(b);
+        out[8 * i + 3] = cimag(b);
+        out[8 * i + 4] = creal(da);
+        out[8 * i + 5] = cimag(da);
+        out[8 * i + 6] = creal(db);
+        out[8 * i + 7] = cimag(db);
+    }
+}
+
+/* A path as a chain of interactions: each has a material label, an incidence
+ * cosine and a factor kind (0: specular, amplitude R = sqrt(1 - S^2);
+ * 1: diffuse, amplitude S). amp0 is the geometric amplitude (lambda/4pi times
+ * spreading), len the phase length. Returns the two complex amplitudes and
+ * accumulates 1/2(|a_TE|^2 + |a_TM|^2) and its gradient with respect to
+ * (eps_r, sigma) of each label. */
+static void path_field(const em_t *em, int k, const int *label, const double *cosv, const int *kind,
+                       double amp0, double len, double complex *a_te, double complex *a_tm, double *g_acc,
+                       double *jac /* [n_labels][2] or NULL */)
+{
+    double complex gte[ORC_KMAX], gtm[ORC_KMAX], dte[ORC_KMAX], dtm[ORC_KMAX];
+    double fac[ORC_KMAX];
+    double complex pte = 1.0, ptm = 1.0;
+    for (int m = 0; m < k; ++m) {
+        fresnel(em, label[m], cosv[m], &gte[m], &gtm[m], &dte[m], &dtm[m]);
+        double S = em->scat[label[m]];
+        fac[m] = kind[m] ? S : sqrt(fmax(0.0, 1.0 - S * S));
+        pte *= fac[m] * gte[m];
+        ptm *= fac[m] * gtm[m];
+    }
+    double complex ph = cexp(-I * em->k0 * len);
+    *a_te = amp0 * pte * ph;
+    *a_tm = amp0 * ptm * ph;
+    *g_acc += 0.5 * (creal(*a_te * conj(*a_te)) + creal(*a_tm * conj(*a_tm)));
+    if (!jac) return;
+    const double complex deta[2] = {1.0, -I / (em->omega * ORC_EPS0)};
+    for (int m = 0; m < k; ++m) {
+        /* product of |f Gamma|^2 over every other interaction, per channel */
+        double rest_te = amp0 * amp0, rest_tm = amp0 * amp0;
+        for (int q = 0; q < k; ++q) {
+            if (q == m) continue;
+            rest_te *= fac[q] * fac[q] * creal(gte[q] * conj(gte[q]));
+            rest_tm *= fac[q] * fac[q] * creal(gtm[q] * conj(gtm[q]));
+        }
+        for (int p = 0; p < 2; ++p) {
+            double d_te = 2.0 * creal(conj(gte[m]) * dte[m] * deta[p]);
+            double d_tm = 2.0 * creal(conj(gtm[m]) * dtm[m] * deta[p]);
+            jac[2 * label[m] + p] += 0.5 * fac[m] * fac[m] * (rest_te * d_te + rest_tm * d_tm);
+        }
+    }
+}
+
+/* ------------------------------------------------------ bounce loop (a4-a5) */
+typedef struct {
+    int n;                 /* interactions recorded */
+    int64_t id[ORC_KMAX];  /* hit disk */
+    double x[ORC_KMAX][3]; /* hit point */
+    double nk[ORC_KMAX][3];/* hit normal flipped against the incoming ray */
+    double cs[ORC_KMAX];   /* incidence cosine */
+    double L[ORC_KMAX];    /* unfolded length from TX to the hit */
+} trace_t;
+
+/* Every interaction is treated as a specular reflection and the ray count stays
+ * constant (Sec. II-B). A miss ends the ray. */
+static void trace_ray(const scene_t *s, const double *tx, const float *dir32, int K, const thr_t *th,
+                      trace_t *tr)
+{
+    double o[3], d[3];
+    copy3(o, tx);
+    from_f32(d, dir32);
+    scale3(d, 1.0 / norm3(d));
+    double L = 0.0;
+    int64_t excl = -1;
+    tr->n = 0;
+    for (int k = 0; k < K; ++k) {
+        double t, q[3];
+        int64_t h = nearest(s, o, d, excl, th->eps_self, INFINITY, th->eps_tie, &t, q);
+        if (h < 0) break;
+        double n[3];
+        copy3(n, s->nr + 3 * h);
+        if (dot3(d, n) > 0.0) scale3(n, -1.0);
+        L += t;
+        tr->id[k] = h;
+        copy3(tr->x[k], q);
+        copy3(tr->nk[k], n);
+        tr->cs[k] = -dot3(d, n);
+        tr->L[k] = L;
+        tr->n = k + 1;
+        double dn = dot3(d, n);
+        for (int c = 0; c < 3; ++c) d[c] -= 2.0 * dn * n[c];
+        scale3(d, 1.0 / norm3(d));
+        copy3(o, q);
+        excl = h;
+    }
+}
+
+/* -------------------------------------------- specular refine + validate (a8) */
+/* Exact minimiser of Eq. (1) on infinite planes (image method), the convex
+ * limit of the paper's iterative phase 1; phase 2 validates every interaction
+ * with a ray from the previous point, thresholds t_a (angle) and t_d (plane
+ * distance), and up to kappa retries that replace the failing plane with the
+ * plane of the disk the validation ray hit. */
+typedef struct {
+    int valid, retries;
+    int64_t hid[ORC_KMAX];
+    double x[ORC_KMAX + 2][3];
+    double len;
+    double cs[ORC_KMAX];
+} spec_t;
+
+static int refine_on_planes(int k, const double *tx, const double *rx, double pp[][3], double pn[][3],
+                            double eps_self, double x[][3])
+{
+    double img[ORC_KMAX + 1][3];
+    copy3(img[0], tx);
+    for (int m = 1; m <= k; ++m) {
+        double w[3];
+        sub3(w, img[m - 1], pp[m - 1]);
+        double dd = dot3(w, pn[m - 1]);
+        for (int c = 0; c < 3; ++c) img[m][c] = img[m - 1][c] - 2.0 * dd * pn[m - 1][c];
+    }
+    copy3(x[0], tx);
+    copy3(x[k + 1], rx);
+    double cur[3];
+    copy3(cur, rx);
+    for (int m = k; m >= 1; --m) {
+        double seg[3], w[3];
+        sub3(seg, img[m], cur);
+        double den = dot3(seg, pn[m - 1]);
+        if (den == 0.0) return 0;
+        sub3(w, pp[m - 1], cur);
+        double sp = dot3(w, pn[m - 1]) / den;
+        if (!(sp > 0.0 && sp < 1.0)) return 0;
+        for (int c = 0; c < 3; ++c) x[m][c] = cur[c] + sp * seg[c];
+        copy3(cur, x[m]);
+    }
+    for (int m = 1; m <= k; ++m) {
+        double a[3], b[3];
+        sub3(a, x[m - 1], pp[m - 1]);
+        sub3(b, x[m + 1], pp[m - 1]);
+        double da = dot3(a, pn[m - 1]), db = dot3(b, pn[m - 1]);
+        if (!(da * db > 0.0 && fabs(da) > eps_self && fabs(db) > eps_self)) return 0;
+    }
+    return 1;
+}
+
+static void specular_one(const scene_t *s, const double *tx, const double *rx, int k, const uint32_t *key,
+                         const int64_t *rep_ids, const thr_t *th, spec_t *out)
+{
+    double pp[ORC_KMAX][3], pn[ORC_KMAX][3];
+    for (int m = 0; m < k; ++m) {
+        copy3(pp[m], s->p + 3 * rep_ids[m]);
+        copy3(pn[m], s->nr + 3 * rep_ids[m]);
+    }
+    out->valid = 0;
+    out->retries = 0;
+    for (;;) {
+        if (!refine_on_planes(k, tx, rx, pp, pn, th->eps_self, out->x)) return;
+        int64_t prev = -1;
+        int retry = 0;
+        for (int m = 1; m <= k; ++m) {
+            double u[3], t, q[3];
+            sub3(u, out->x[m], out->x[m - 1]);
+            scale3(u, 1.0 / norm3(u));
+            int64_t h = nearest(s, out->x[m - 1], u, prev, th->eps_self, INFINITY, th->eps_tie, &t, q);
+            if (h < 0 || s->surf[h] != key[m - 1]) return;
+            double w[3];
+            sub3(w, q, pp[m - 1]);
+            int ang_ok = fabs(dot3(s->nr + 3 * h, pn[m - 1])) >= th->cos_ta;
+            int dist_ok = fabs(dot3(w, pn[m - 1])) <= th->t_d;
+            if (!(ang_ok && dist_ok)) {
+                if (out->retries >= th->kappa) return;
+                out->retries++;
+                copy3(pp[m - 1], s->p + 3 * h);
+                copy3(pn[m - 1], s->nr + 3 * h);
+                retry = 1;
+                break;
+            }
+            out->hid[m - 1] = h;
+            prev = h;
+        }
+        if (retry) continue;
+        if (occluded(s, out->x[k], rx, out->hid[k - 1], th->eps_self)) return;
+        double len = 0.0;
+        for (int m = 0; m <= k; ++m) {
+            double w[3];
+            sub3(w, out->x[m + 1], out->x[m]);
+            len += norm3(w);
+        }
+        out->len = len;
+        for (int m = 1; m <= k; ++m) {
+            double u[3];
+            sub3(u, out->x[m], out->x[m - 1]);
+            scale3(u, 1.0 / norm3(u));
+            out->cs[m - 1] = fabs(dot3(u, pn[m - 1]));
+        }
+        out->valid = 1;
+        return;
+    }
+}
+
+/* ------------------------------------------------------- exported helpers */
+/* Nearest hit for a batch of queries (unit tests). excl < 0 means none. */
+int orc_nearest_batch(int64_t n_pts, const float *pos, const float *nrm, double r, int64_t n_q,
+                      const double *o, const double *d, const int64_t *excl, double t_lo, double t_hi,
+                      double eps_tie, int64_t *out_id, double *out_t, double *out_q)
+{
+    scene_t s;
+    int rc = scene_init(&s, n_pts, pos, nrm, NULL, NULL, r);
+    if (rc) { scene_free(&s); return rc; }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n_q; ++q) {
+        double dd[3];
+        copy3(dd, d + 3 * q);
+        scale3(dd, 1.0 / norm3(dd));
+        double t = NAN, qq[3] = {NAN, NAN, NAN};
+        out_id[q] = nearest(&s, o + 3 * q, dd, excl[q], t_lo, t_hi, eps_tie, &t, qq);
+        out_t[q] = t;
+        copy3(out_q + 3 * q, qq);
+    }
+    scene_free(&s);
+    return 0;
+}
+
+int orc_occluded_batch(int64_t n_pts, const float *pos, const float *nrm, double r, int64_t n_q,
+                       const double *a, const double *b, const int64_t *excl, double eps_self,
+                       uint8_t *out)
+{
+    scene_t s;
+    int rc = scene_init(&s, n_pts, pos, nrm, NULL, NULL, r);
+    if (rc) { scene_free(&s); return rc; }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n_q; ++q) out[q] = (uint8_t)occluded(&s, a + 3 * q, b + 3 * q, excl[q], eps_self);
+    scene_free(&s);
+    return 0;
+}
+
+/* ------------------------------------------------------------- full solve */
+typedef struct {
+    int len;
+    uint32_t s[ORC_KMAX];
+    int64_t ray_id;
+    int64_t slot; /* index into the traced list */
+} keyrec_t;
+
+static int key_cmp(const void *pa, const void *pb)
+{
+    const keyrec_t *a = (const keyrec_t *)pa, *b = (const keyrec_t *)pb;
+    if (a->len != b->len) return a->len < b->len ? -1 : 1;
+    for (int m = 0; m < a->len; ++m)
+        if (a->s[m] != b->s[m]) return a->s[m] < b->s[m] ? -1 : 1;
+    if (a->ray_id != b->ray_id) return a->ray_id < b->ray_id ? -1 : 1;
+    return 0;
+}
+
+/*
+ * One TX, all RX. Traces the rays with the given ids out of a budget of
+ * n_budget Fibonacci directions (the diffuse ray-tube weight always uses the
+ * full budget).
+ *
+ * thr[5] = {eps_tie, eps_self, t_a (degrees), t_d, kappa}.
+ *
+ * Outputs (NULL = not wanted):
+ *   seq      int64[n_trace*K]   hit disk per (ray, k), -1 after the ray ends
+ *   rec      double[n_trace*K*5] x, y, z, L, cos per (ray, k)
+ *   dvis     uint8[n_trace*K*n_rx] diffuse connection valid (lit side and unoccluded)
+ *   keys     uint32[key_cap*K], key_len int32[key_cap], key_rep int64[key_cap]
+ *   spec_valid uint8[key_cap*n_rx], spec_len double[key_cap*n_rx],
+ *   spec_amp double[key_cap*n_rx*4] (TE re, im, TM re, im), spec_hid int64[key_cap*n_rx*K]
+ *   out_rx   double[n_rx*8]: G_los, G_spec, G_diff, G, h_TE re, im, h_TM re, im
+ *   jac      double[n_rx*n_labels*2]: dG/d(eps_r, sigma) per label
+ * *n_keys receives the number of unique keys; returns -3 if key_cap is too small.
+ */
+int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf,
+              double r_p, int32_t n_labels, const double *eps_r, const double *sigma, const double *scat,
+              const float *tx32, int32_t n_rx, const float *rx32, double freq, int64_t n_budget,
+              int64_t n_trace, const int64_t *ray_ids, int32_t K, int32_t flags, const double *thr,
+              int64_t *seq, double *rec, uint8_t *dvis, int64_t key_cap, uint32_t *keys, int32_t *key_len,
+              int64_t *key_rep, int64_t *n_keys, uint8_t *spec_valid, double *spec_len, double *spec_amp,
+              int64_t *spec_hid, double *out_rx, double *jac)
+{
+    if (K < 1 || K > ORC_KMAX) return -1;
+    scene_t s;
+    int rc = scene_init(&s, n_pts, pos, nrm, mat, surf, r_p);
+    if (rc) { scene_free(&s); return rc; }
+    for (int64_t i = 0; i < n_pts; ++i)
+        if (mat[i] >= (uint32_t)n_labels) { scene_free(&s); return -1; }
+    thr_t th = {thr[0], thr[1], cos(thr[2] * ORC_PI / 180.0), thr[3], (int)thr[4]};
+    em_t em = {n_labels, eps_r, sigma, scat, freq, 2.0 * ORC_PI * freq, ORC_C0 / freq, 0.0};
+    em.k0 = 2.0 * ORC_PI / em.lambda;
+    const double a_iso = em.lambda / (4.0 * ORC_PI);
+    double tx[3];
+    from_f32(tx, tx32);
+    double *rx = (double *)malloc(sizeof(double) * 3 * (size_t)n_rx);
+    for (int r = 0; r < n_rx; ++r) from_f32(rx + 3 * r, rx32 + 3 * r);
+
+    double *G_los = calloc((size_t)n_rx, sizeof(double)), *G_spec = calloc((size_t)n_rx, sizeof(double));
+    double *G_diff = calloc((size_t)n_rx, sizeof(double));
+    double complex *h_te = calloc((size_t)n_rx, sizeof(double complex));
+    double complex *h_tm = calloc((size_t)n_rx, sizeof(double complex));
+    if (jac) memset(jac, 0, sizeof(double) * (size_t)n_rx * (size_t)n_labels * 2);
+
+    /* line of sight */
+    if (flags & ORC_LOS) {
+        for (int r = 0; r < n_rx; ++r) {
+            if (occluded(&s, tx, rx + 3 * r, -1, th.eps_self)) continue;
+            double w[3];
+            sub3(w, rx + 3 * r, tx);
+            double d = norm3(w);
+            double complex a = a_iso / d * cexp(-I * em.k0 * d);
+            G_los[r] += 0.5 * (creal(a * conj(a)) * 2.0);
+            h_te[r] += a;
+            h_tm[r] += a;
+        }
+    }
+
+    /* trace every requested ray */
+    trace_t *tr = (trace_t *)malloc(sizeof(trace_t) * (size_t)(n_trace > 0 ? n_trace : 1));
+    float *dirs = (float *)malloc(sizeof(float) * 3 * (size_t)(n_trace > 0 ? n_trace : 1));
+    orc_fib_dirs(n_budget, ray_ids, n_trace, dirs);
+    if (flags & (ORC_SPECULAR | ORC_DIFFUSE)) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t q = 0; q < n_trace; ++q) trace_ray(&s, tx, dirs + 3 * q, K, &th, &tr[q]);
+    } else {
+        for (int64_t q = 0; q < n_trace; ++q) tr[q].n = 0;
+    }
+    if (seq || rec) {
+        for (int64_t q = 0; q < n_trace; ++q)
+            for (int k = 0; k < K; ++k) {
+                int has = k < tr[q].n;
+                if (seq) seq[q * K + k] = has ? tr[q].id[k] : -1;
+                if (rec) {
+                    double *o = rec + (q * K + k) * 5;
+                    for (int c = 0; c < 3; ++c) o[c] = has ? tr[q].x[k][c] : NAN;
+                    o[3] = has ? tr[q].L[k] : NAN;
+                    o[4] = has ? tr[q].cs[k] : NAN;
+                }
+            }
+    }
+
+    /* diffuse connections from every interaction to every RX (Sec. II-B.1) */
+    if (flags & ORC_DIFFUSE) {
+        int64_t nslot = n_trace * K * (int64_t)n_rx;
+        double complex *ate = calloc((size_t)nslot, sizeof(double complex));
+        double complex *atm = calloc((size_t)nslot, sizeof(double complex));
+        double *pw = calloc((size_t)nslot, sizeof(double));
+        double *jl = jac ? calloc((size_t)nslot * (size_t)n_labels * 2, sizeof(double)) : NULL;
+        uint8_t *vis = calloc((size_t)nslot, 1);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t q = 0; q < n_trace; ++q) {
+            for (int k = 0; k < tr[q].n; ++k) {
+                int label[ORC_KMAX], kind[ORC_KMAX];
+                double cs[ORC_KMAX];
+                for (int m = 0; m <= k; ++m) {
+                    label[m] = s.mat[tr[q].id[m]];
+                    cs[m] = tr[q].cs[m];
+                    kind[m] = (m == k);
+                }
+                for (int r = 0; r < n_rx; ++r) {
+                    int64_t slot = (q * K + k) * n_rx + r;
+                    double v[3];
+                    sub3(v, rx + 3 * r, tr[q].x[k]);
+                    double vn = dot3(v, tr[q].nk[k]);
+                    if (!(vn > 0.0)) continue;
+                    if (occluded(&s, tr[q].x[k], rx + 3 * r, tr[q].id[k], th.eps_self)) continue;
+                    double rs = norm3(v);
+                    double cos_s = vn / rs;
+                    double amp0 = a_iso * sqrt(4.0 * cos_s / (double)n_budget) / rs;
+                    vis[slot] = 1;
+                    path_field(&em, k + 1, label, cs, kind, amp0, tr[q].L[k] + rs, &ate[slot], &atm[slot],
+                               &pw[slot], jl ? jl + slot * n_labels * 2 : NULL);
+                }
+            }
+        }
+        for (int64_t q = 0; q < n_trace; ++q)
+            for (int k = 0; k < K; ++k)
+                for (int r = 0; r < n_rx; ++r) {
+                    int64_t slot = (q * K + k) * n_rx + r;
+                    if (dvis) dvis[slot] = vis[slot];
+                    if (!vis[slot]) continue;
+                    G_diff[r] += pw[slot];
+                    h_te[r] += ate[slot];
+                    h_tm[r] += atm[slot];
+                    if (jac)
+                        for (int l = 0; l < 2 * n_labels; ++l) jac[r * n_labels * 2 + l] += jl[slot * n_labels * 2 + l];
+                }
+        free(ate); free(atm); free(pw); free(jl); free(vis);
+    } else if (dvis) {
+        memset(dvis, 0, (size_t)(n_trace * K * n_rx));
+    }
+
+    /* specular: keys of surface labels, representative = smallest ray id */
+    int64_t nk = 0;
+    int ret = 0;
+    if (flags & ORC_SPECULAR) {
+        int64_t total = 0;
+        for (int64_t q = 0; q < n_trace; ++q) total += tr[q].n;
+        keyrec_t *kr = (keyrec_t *)malloc(sizeof(keyrec_t) * (size_t)(total > 0 ? total : 1));
+        int64_t e = 0;
+        for (int64_t q = 0; q < n_trace; ++q)
+            for (int k = 1; k <= tr[q].n; ++k) {
+                memset(&kr[e], 0, sizeof(keyrec_t));
+                kr[e].len = k;
+                for (int m = 0; m < k; ++m) kr[e].s[m] = s.surf[tr[q].id[m]];
+                kr[e].ray_id = ray_ids[q];
+                kr[e].slot = q;
+                ++e;
+            }
+        qsort(kr, (size_t)total, sizeof(keyrec_t), key_cmp);
+        keyrec_t *uk = (keyrec_t *)malloc(sizeof(keyrec_t) * (size_t)(total > 0 ? total : 1));
+        for (int64_t i = 0; i < total; ++i) {
+            if (i > 0 && kr[i].len == kr[i - 1].len && !memcmp(kr[i].s, kr[i - 1].s, sizeof(uint32_t) * (size_t)kr[i].len))
+                continue;
+            uk[nk++] = kr[i];
+        }
+        free(kr);
+        if (nk > key_cap) {
+            ret = -3;
+        } else {
+            spec_t *sp = (spec_t *)malloc(sizeof(spec_t) * (size_t)(nk * n_rx > 0 ? nk * n_rx : 1));
+            int64_t npair = nk * n_rx;
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t pi = 0; pi < npair; ++pi) {
+                int64_t ki = pi / n_rx;
+                int r = (int)(pi % n_rx);
+                const keyrec_t *key = &uk[ki];
+                specular_one(&s, tx, rx + 3 * r, key->len, key->s, tr[key->slot].id, &th, &sp[pi]);
+            }
+            for (int64_t ki = 0; ki < nk; ++ki) {
+                if (keys)
+                    for (int m = 0; m < K; ++m) keys[ki * K + m] = m < uk[ki].len ? uk[ki].s[m] : 0xffffffffu;
+                if (key_len) key_len[ki] = uk[ki].len;
+                if (key_rep) key_rep[ki] = uk[ki].ray_id;
+                for (int r = 0; r < n_rx; ++r) {
+                    spec_t *p = &sp[ki * n_rx + r];
+                    int64_t o = ki * n_rx + r;
+                    if (spec_valid) spec_valid[o] = (uint8_t)p->valid;
+                    if (spec_hid)
+                        for (int m = 0; m < K; ++m) spec_hid[o * K + m] = (p->valid && m < uk[ki].len) ? p->hid[m] : -1;
+                    double complex ate = 0, atm = 0;
+                    if (p->valid) {
+                        int label[ORC_KMAX], kind[ORC_KMAX];
+                        for (int m = 0; m < uk[ki].len; ++m) {
+                            label[m] = s.mat[p->hid[m]];
+                            kind[m] = 0;
+                        }
+                        double g = 0.0;
+                        path_field(&em, uk[ki].len, label, p->cs, kind, a_iso / p->len, p->len, &ate, &atm, &g,
+                                   jac ? jac + (int64_t)r * n_labels * 2 : NULL);
+                        G_spec[r] += g;
+                        h_te[r] += ate;
+                        h_tm[r] += atm;
+                    }
+                    if (spec_len) spec_len[o] = p->valid ? p->len : NAN;
+                    if (spec_amp) {
+                        spec_amp[4 * o + 0] = creal(ate);
+                        spec_amp[4 * o + 1] = cimag(ate);
+                        spec_amp[4 * o + 2] = creal(atm);
+                        spec_amp[4 * o + 3] = cimag(atm);
+                    }
+                }
+            }
+            free(sp);
+        }
+        free(uk);
+    }
+    if (n_keys) *n_keys = nk;
+    if (out_rx)
+        for (int r = 0; r < n_rx; ++r) {
+            double *o = out_rx + 8 * r;
+            o[0] = G_los[r];
+            o[1] = G_spec[r];
+            o[2] = G_diff[r];
+            o[3] = G_los[r] + G_spec[r] + G_diff[r];
+            o[4] = creal(h_te[r]);
+            o[5] = cimag(h_te[r]);
+            o[6] = creal(h_tm[r]);
+            o[7] = cimag(h_tm[r]);
+        }
+    free(tr); free(dirs); free(rx); free(G_los); free(G_spec); free(G_diff); free(h_te); free(h_tm);
+    scene_free(&s);
+    return ret;
+}
