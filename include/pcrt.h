@@ -1,0 +1,217 @@
+/*
+ * pcrt.h -- C ABI of the MI355X (gfx950) point-cloud radio ray tracer.
+ *
+ * Method: Vaara et al., "Differentiable High-Performance Ray Tracing-Based
+ * Simulation of Radio Propagation with Point Clouds", arXiv 2507.04021.
+ *
+ * Problem statement (Sec. II, opening paragraph): the input is an augmented
+ * point cloud -- per point a position p_i, a surface normal n, a surface label
+ * l_s and a material label l_m -- together with TX and RX positions. The
+ * output here is, per receiver, the channel power gain and the coherent
+ * complex field of all paths found: line of sight, specular reflections
+ * (Sec. II-B.2) and diffuse scattering as the last interaction (Sec. II-B.1).
+ *
+ * Conventions
+ *   - Units: metres, hertz, siemens per metre. Gains are linear power.
+ *   - Time convention e^{+j omega t}: propagation over length L multiplies the
+ *     field by e^{-j k0 L}; eta = eps_r - j sigma / (omega eps0).
+ *   - Every device pointer is memory on the current HIP device, owned by the
+ *     caller. The library never frees caller memory.
+ *   - Every call returns a pcrt_status; none throws or aborts. On failure the
+ *     reason is available from pcrt_last_error() (thread-local).
+ *   - Calls that take a stream only enqueue work on that stream (no host
+ *     synchronisation) unless the comment says otherwise. The solve calls
+ *     allocate nothing; every scratch byte comes from the caller's workspace,
+ *     so they can be captured in a HIP graph.
+ */
+#ifndef PCRT_H
+#define PCRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCRT_OK = 0,
+    PCRT_EINVAL = -1,       /* invalid argument or input data */
+    PCRT_ENOMEM = -2,       /* workspace too small (required size in the error text) */
+    PCRT_EDEVICE = -3,      /* HIP runtime error */
+    PCRT_EUNSUPPORTED = -4, /* valid request outside the supported range */
+    PCRT_EOVERFLOW = -5     /* a device-side capacity was exceeded */
+} pcrt_status;
+
+/* Text of the last error on this thread; valid until the next call. */
+const char *pcrt_last_error(void);
+/* Library version string. */
+const char *pcrt_version(void);
+
+/* ------------------------------------------------------------------ scene */
+/* The point cloud as surface-aligned disks (Sec. II-C): disk i has centre
+ * pos[i], unit normal normal[i] (normalised by the library), radius
+ * disk_radius (one radius for all points). Disks are two-sided.
+ * pos, normal: device float[n_points][3]; material: device uint16[n_points]
+ * (material label, < n_labels of the solve); surface: device uint32[n_points]
+ * (surface label; keys of specular paths are sequences of these). */
+typedef struct {
+    const float *pos;
+    const float *normal;
+    const uint16_t *material;
+    const uint32_t *surface;
+    uint32_t n_points;
+    float disk_radius;
+} pcrt_points;
+
+/* Bounding-volume hierarchy options. leaf_size: disks per leaf, 1..8
+ * (0 = default 4). width: 2 (binary nodes; 0 = default). */
+typedef struct {
+    uint32_t leaf_size;
+    uint32_t width;
+} pcrt_bvh_opts;
+
+/* Scene statistics filled by pcrt_scene_create. */
+typedef struct {
+    uint32_t n_points;
+    uint32_t n_surfaces;   /* max surface label + 1 */
+    uint32_t n_materials;  /* max material label + 1 */
+    uint32_t depth;        /* deepest node of the hierarchy */
+    uint32_t n_nodes;
+    uint32_t leaf_size;
+    float bbox[6];         /* lo xyz, hi xyz of the disk bounds */
+    double build_ms;       /* device time of the build */
+} pcrt_scene_info;
+
+typedef struct pcrt_scene pcrt_scene; /* opaque host handle */
+
+/* Bytes of device workspace a scene of n_points needs (BVH + disk copies). */
+pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *opts, size_t *bytes);
+
+/* Validate the points, copy them, build the hierarchy (Morton codes, radix
+ * sort, linear BVH) in ws. The input arrays may be freed afterwards; ws must
+ * outlive the scene. This call synchronises the stream once at the end to
+ * read back validation results and statistics. Errors: EINVAL for NULL
+ * pointers, n_points == 0, disk_radius <= 0, non-finite positions or zero
+ * normals; ENOMEM for a small ws; EUNSUPPORTED if the hierarchy is deeper
+ * than the traversal stack (64). stream: hipStream_t or NULL. */
+pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts, void *ws, size_t ws_bytes,
+                              void *stream, pcrt_scene **out);
+pcrt_status pcrt_scene_get_info(const pcrt_scene *scene, pcrt_scene_info *info);
+pcrt_status pcrt_scene_destroy(pcrt_scene *scene);
+
+/* ------------------------------------------------------------------ solve */
+/* Material of one label: relative permittivity, conductivity (S/m) and
+ * scattering coefficient S in [0, 1]. Specular reflections carry
+ * sqrt(1 - S^2) times the Fresnel coefficient, diffuse ones S times it. */
+typedef struct {
+    float eps_r, sigma, scatter;
+} pcrt_material;
+
+/* Thresholds. eps_tie: nearest-hit tie window (m); eps_self: minimum distance
+ * from a ray origin to a hit (m); t_a_deg, t_d: validation thresholds of
+ * Table I (angle in degrees, plane distance in m); kappa: refinement retries.
+ * Zero fields take the defaults 1e-4, 1e-3, 1.0, 0.01, 10 (kappa = 0 is
+ * expressed as PCRT_KAPPA_NONE). */
+typedef struct {
+    float eps_tie, eps_self, t_a_deg, t_d;
+    uint32_t kappa;
+} pcrt_thresholds;
+#define PCRT_KAPPA_NONE 0xffffffffu
+
+enum {
+    PCRT_LOS = 1,      /* line of sight */
+    PCRT_SPECULAR = 2, /* specular paths (keys, refinement, validation) */
+    PCRT_DIFFUSE = 4,  /* diffuse scattering as the last interaction */
+    PCRT_RECORD = 8    /* keep the per-path tape in the workspace (for the gradient and path output) */
+};
+
+/* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
+ * sphere directions; the diffuse ray-tube weight uses N). ray_subset
+ * (optional device uint32[n_subset]): trace only these ray ids of the budget.
+ * max_interactions K: 1..8. */
+typedef struct {
+    float tx[3];
+    const float *rx;
+    uint32_t n_rx;
+    double freq_hz;
+    uint32_t n_rays;
+    uint32_t max_interactions;
+    uint32_t flags;
+    const uint32_t *ray_subset;
+    uint32_t n_subset;
+    pcrt_thresholds thr;
+} pcrt_solve_params;
+
+/* Outputs (device pointers; NULL = not wanted unless marked required).
+ *   gain       double[n_rx]         required: total power gain G_r
+ *   h_te, h_tm double[n_rx][2]      coherent complex field sums (re, im)
+ *   gain_parts double[n_rx][3]      G of LOS, specular, diffuse paths
+ *   ray_seq    int32[n_trace][K]    hit disk per interaction, -1 after the ray ends
+ *   counters   uint64[16]           see PCRT_CNT_* */
+typedef struct {
+    double *gain;
+    double *h_te;
+    double *h_tm;
+    double *gain_parts;
+    int32_t *ray_seq;
+    uint64_t *counters;
+} pcrt_outputs;
+
+enum {
+    PCRT_CNT_INTERACTIONS = 0, /* closest-hit interactions traced (sum of K_j) */
+    PCRT_CNT_RAYS = 1,         /* rays traced */
+    PCRT_CNT_SEGMENTS = 2,     /* diffuse connection segments tested for occlusion */
+    PCRT_CNT_KEYS = 3,         /* unique specular keys */
+    PCRT_CNT_SPECULAR = 4,     /* valid specular paths (over all receivers) */
+    PCRT_CNT_DIFFUSE = 5,      /* visible diffuse connections */
+    PCRT_CNT_STATUS = 6,       /* bit 0: key table overflow; bit 1: invalid material label */
+    PCRT_CNT_CANDIDATES = 7,   /* (key, RX) pairs that passed the geometric refinement */
+    PCRT_CNT_TIE_SPILL = 8,    /* nearest-hit queries that needed the exact second pass */
+    PCRT_CNT_COUNT = 16
+};
+
+/* Workspace bytes for one solve with these parameters (plus, with
+ * PCRT_RECORD, the tape). */
+pcrt_status pcrt_solve_workspace_size(const pcrt_scene *scene, const pcrt_solve_params *p, size_t *bytes);
+
+/* Trace and evaluate one transmitter against all receivers. mats: device
+ * pcrt_material[n_labels]. Asynchronous on stream; allocates nothing.
+ * Errors: EINVAL (bad sizes, NULL required pointers, freq <= 0, n_rays == 0
+ * with SPECULAR or DIFFUSE), EUNSUPPORTED (K > 8, or surface labels too many
+ * for exact keys: (n_surfaces + 1)^K must be < 2^64), ENOMEM (small ws).
+ * Device-side problems set bits in counters[PCRT_CNT_STATUS]. */
+pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                       const pcrt_solve_params *p, void *ws, size_t ws_bytes, const pcrt_outputs *out,
+                       void *stream);
+
+/* Specular path list of a PCRT_RECORD solve, copied out of its workspace.
+ * Keys are ordered by (representative ray id, length). For key q:
+ *   key_ray uint32[cap]   representative ray id (smallest ray id with this key)
+ *   key_len uint8[cap]    number of interactions k
+ *   key_seq int32[cap][K] disk ids of the representative ray's first k hits
+ * For (key q, receiver r), index q * n_rx + r:
+ *   valid uint8, length float (path length, m), amp float[4] (a_TE re, im,
+ *   a_TM re, im), hit int32[K] (validated disk per interaction).
+ * Any output pointer may be NULL. *n_keys receives the key count (host
+ * pointer; this call synchronises the stream). ws/params: those of the solve. */
+pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws,
+                            uint32_t cap, uint32_t *key_ray, uint8_t *key_len, int32_t *key_seq,
+                            uint8_t *valid, float *length, float *amp, int32_t *hit, uint32_t *n_keys,
+                            void *stream);
+
+/* Diffuse visibility of a PCRT_RECORD solve: uint8[n_trace][K][n_rx], 1 when
+ * the connection from interaction k of ray j to receiver r is lit and
+ * unoccluded (Sec. II-B.1). Device pointer; asynchronous. */
+pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws,
+                                  uint8_t *vis, void *stream);
+
+/* Launch directions on the Fibonacci sphere: z = 1 - (2j+1)/N, phi = 2 pi
+ * frac(j (3 - sqrt5)/2), evaluated in FP64 and rounded to FP32.
+ * ids: device uint32[n] (NULL = 0..n-1); out: device float[n][3]. */
+pcrt_status pcrt_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCRT_H */

@@ -1,0 +1,280 @@
+"""Python binding of libpcrt, the MI355X point-cloud radio ray tracer.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in include/pcrt.h. PyTorch supplies device memory
+and the stream. If the built library is missing, importing the binding
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcrt.so")
+
+LOS, SPECULAR, DIFFUSE, RECORD = 1, 2, 4, 8
+CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
+           tie_spill=8)
+KAPPA_NONE = 0xFFFFFFFF
+
+
+class PcrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pcrt error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("material", ctypes.c_void_p),
+                ("surface", ctypes.c_void_p), ("n_points", ctypes.c_uint32), ("disk_radius", ctypes.c_float)]
+
+
+class BvhOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32)]
+
+
+class SceneInfo(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_uint32), ("n_surfaces", ctypes.c_uint32), ("n_materials", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("leaf_size", ctypes.c_uint32),
+                ("bbox", ctypes.c_float * 6), ("build_ms", ctypes.c_double)]
+
+
+class Thresholds(ctypes.Structure):
+    _fields_ = [("eps_tie", ctypes.c_float), ("eps_self", ctypes.c_float), ("t_a_deg", ctypes.c_float),
+                ("t_d", ctypes.c_float), ("kappa", ctypes.c_uint32)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tx", ctypes.c_float * 3), ("rx", ctypes.c_void_p), ("n_rx", ctypes.c_uint32),
+                ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
+                ("thr", Thresholds)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("gain", ctypes.c_void_p), ("h_te", ctypes.c_void_p), ("h_tm", ctypes.c_void_p),
+                ("gain_parts", ctypes.c_void_p), ("ray_seq", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libpcrt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpcrt.so is not built (run paper_2507_04021_amd/build.py or "
+                              "__graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_size_t
+        L.pcrt_last_error.restype = ctypes.c_char_p
+        L.pcrt_version.restype = ctypes.c_char_p
+        L.pcrt_scene_workspace_size.argtypes = [u32, ctypes.POINTER(BvhOpts), ctypes.POINTER(sz)]
+        L.pcrt_scene_create.argtypes = [ctypes.POINTER(Points), ctypes.POINTER(BvhOpts), vp, sz, vp,
+                                        ctypes.POINTER(vp)]
+        L.pcrt_scene_get_info.argtypes = [vp, ctypes.POINTER(SceneInfo)]
+        L.pcrt_scene_destroy.argtypes = [vp]
+        L.pcrt_solve_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]
+        L.pcrt_solve.argtypes = [vp, vp, u32, ctypes.POINTER(SolveParams), vp, sz, ctypes.POINTER(Outputs), vp]
+        L.pcrt_paths_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, u32, vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(u32), vp]
+        L.pcrt_diffuse_vis_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
+        L.pcrt_raygen.argtypes = [u32, vp, u32, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise PcrtError(rc, lib().pcrt_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Scene:
+    """A point cloud of disks with its bounding-volume hierarchy on the GPU."""
+
+    def __init__(self, pos, normal, material, surface, radius, leaf_size=4, device="cuda", stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        pos = _dev(pos, torch.float32, self.device).reshape(-1, 3)
+        nrm = _dev(normal, torch.float32, self.device).reshape(-1, 3)
+        mat = _dev(np.asarray(material, np.int32) if not isinstance(material, torch.Tensor) else material,
+                   torch.int32, self.device).to(torch.int16)
+        surf = _dev(np.asarray(surface, np.int64) if not isinstance(surface, torch.Tensor) else surface,
+                    torch.int64, self.device).to(torch.int32)
+        n = pos.shape[0]
+        self.n = n
+        self.radius = float(radius)
+        opts = BvhOpts(leaf_size, 0)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().pcrt_scene_workspace_size(n, ctypes.byref(opts), ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
+        pts = Points(pos.data_ptr(), nrm.data_ptr(), mat.data_ptr(), surf.data_ptr(), n, radius)
+        h = ctypes.c_void_p()
+        _check(lib().pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), _ptr(self.ws), nbytes.value,
+                                       _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        info = SceneInfo()
+        _check(lib().pcrt_scene_get_info(self.handle, ctypes.byref(info)))
+        self.info = dict(n_points=info.n_points, n_surfaces=info.n_surfaces, n_materials=info.n_materials,
+                         depth=info.depth, n_nodes=info.n_nodes, leaf_size=info.leaf_size,
+                         bbox=list(info.bbox), build_ms=info.build_ms)
+
+    @classmethod
+    def from_scene(cls, sc, **kw):
+        """From a scenes.Scene (numpy arrays)."""
+        return cls(sc.pos, sc.normal, sc.material.astype(np.int32), sc.surface.astype(np.int64), sc.radius, **kw)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.pcrt_scene_destroy(h)
+            self.handle = None
+
+
+def materials_tensor(mats, device="cuda"):
+    """float32[n_labels, 3] (eps_r, sigma, S) on the device."""
+    torch = _torch()
+    return _dev(np.asarray(mats, np.float64).reshape(-1, 3), torch.float32, device)
+
+
+@dataclass
+class SolveResult:
+    gain: object           # float64[n_rx]
+    h_te: object           # complex as float64[n_rx, 2]
+    h_tm: object
+    parts: object          # float64[n_rx, 3] (los, specular, diffuse)
+    seq: object            # int32[n_trace, K] or None
+    counters: object       # uint64[16] as int64
+    ws: object             # the workspace (holds the tape of a RECORD solve)
+    params: SolveParams
+    scene: Scene
+    keep: tuple            # device tensors the params point to
+
+    def counter(self, name):
+        return int(self.counters[CNT[name]].item())
+
+
+def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None):
+    th = Thresholds(0.0, 0.0, 0.0, 0.0, 0)
+    if thr:
+        for k, v in thr.items():
+            setattr(th, k, v)
+    p = SolveParams()
+    p.tx = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(tx, np.float32).reshape(3)])
+    p.rx = rx_t.data_ptr()
+    p.n_rx = rx_t.shape[0]
+    p.freq_hz = float(freq)
+    p.n_rays = int(n_rays)
+    p.max_interactions = int(K)
+    p.flags = int(flags)
+    p.ray_subset = subset_t.data_ptr() if subset_t is not None else None
+    p.n_subset = subset_t.numel() if subset_t is not None else 0
+    p.thr = th
+    return p
+
+
+def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
+          want_seq=False, stream=None, ws=None, out=None) -> SolveResult:
+    """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor."""
+    torch = _torch()
+    dev = scene.device
+    mats_t = mats if isinstance(mats, torch.Tensor) and mats.device.type == "cuda" else materials_tensor(mats, dev)
+    rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
+                torch.float32, dev).reshape(-1, 3)
+    sub_t = None
+    if ray_subset is not None:
+        sub_t = _dev(np.asarray(ray_subset, np.int64).astype(np.int32) if not isinstance(ray_subset, torch.Tensor)
+                     else ray_subset, torch.int32, dev)
+    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)))
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    n_rx = rx_t.shape[0]
+    if out is None:
+        n_trace = 0 if not (flags & (SPECULAR | DIFFUSE)) else (sub_t.numel() if sub_t is not None else n_rays)
+        out = dict(gain=torch.empty(n_rx, dtype=torch.float64, device=dev),
+                   h_te=torch.empty(n_rx, 2, dtype=torch.float64, device=dev),
+                   h_tm=torch.empty(n_rx, 2, dtype=torch.float64, device=dev),
+                   parts=torch.empty(n_rx, 3, dtype=torch.float64, device=dev),
+                   seq=torch.empty(max(n_trace, 1), K, dtype=torch.int32, device=dev) if want_seq else None,
+                   counters=torch.empty(16, dtype=torch.int64, device=dev))
+    o = Outputs(out["gain"].data_ptr(), out["h_te"].data_ptr(), out["h_tm"].data_ptr(), out["parts"].data_ptr(),
+                out["seq"].data_ptr() if out.get("seq") is not None else None, out["counters"].data_ptr())
+    _check(lib().pcrt_solve(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), _ptr(ws), ws.numel(),
+                            ctypes.byref(o), _stream(stream)))
+    return SolveResult(out["gain"], out["h_te"], out["h_tm"], out["parts"], out.get("seq"), out["counters"], ws, p,
+                       scene, (mats_t, rx_t, sub_t))
+
+
+def paths(res: SolveResult, stream=None):
+    """Specular path list of a RECORD solve as numpy arrays."""
+    torch = _torch()
+    p = res.params
+    K, n_rx = p.max_interactions, p.n_rx
+    nk = ctypes.c_uint32(0)
+    _check(lib().pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), 0, None, None, None, None, None,
+                                 None, None, ctypes.byref(nk), _stream(stream)))
+    n = max(nk.value, 1)
+    dev = res.scene.device
+    key_ray = torch.empty(n, dtype=torch.int32, device=dev)
+    key_len = torch.empty(n, dtype=torch.uint8, device=dev)
+    key_seq = torch.empty(n, K, dtype=torch.int32, device=dev)
+    valid = torch.empty(n, n_rx, dtype=torch.uint8, device=dev)
+    length = torch.empty(n, n_rx, dtype=torch.float32, device=dev)
+    amp = torch.empty(n, n_rx, 4, dtype=torch.float32, device=dev)
+    hit = torch.empty(n, n_rx, K, dtype=torch.int32, device=dev)
+    _check(lib().pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), nk.value, _ptr(key_ray),
+                                 _ptr(key_len), _ptr(key_seq), _ptr(valid), _ptr(length), _ptr(amp), _ptr(hit),
+                                 ctypes.byref(nk), _stream(stream)))
+    m = nk.value
+    a = amp[:m].cpu().numpy()
+    return dict(n_keys=m, key_ray=key_ray[:m].cpu().numpy(), key_len=key_len[:m].cpu().numpy(),
+                key_seq=key_seq[:m].cpu().numpy(), valid=valid[:m].cpu().numpy().astype(bool),
+                length=length[:m].cpu().numpy(), amp_te=a[..., 0] + 1j * a[..., 1], amp_tm=a[..., 2] + 1j * a[..., 3],
+                hit=hit[:m].cpu().numpy())
+
+
+def diffuse_vis(res: SolveResult, stream=None):
+    torch = _torch()
+    p = res.params
+    n_trace = p.n_subset if p.ray_subset else p.n_rays
+    vis = torch.empty(n_trace, p.max_interactions, p.n_rx, dtype=torch.uint8, device=res.scene.device)
+    _check(lib().pcrt_diffuse_vis_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), _ptr(vis), _stream(stream)))
+    return vis
+
+
+def raygen(n_budget, ids=None, device="cuda", stream=None):
+    torch = _torch()
+    ids_t = None if ids is None else _dev(np.asarray(ids, np.int64).astype(np.int32), torch.int32, device)
+    n = n_budget if ids is None else ids_t.numel()
+    out = torch.empty(n, 3, dtype=torch.float32, device=device)
+    _check(lib().pcrt_raygen(n_budget, _ptr(ids_t), n, _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,453 @@
+// C ABI of libpcrt: argument checks, workspace planning, launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "pcrt.h"
+
+using namespace pcrt;
+
+struct pcrt_scene {
+    DevScene dev;
+    pcrt_scene_info info;
+    char *ws;
+    size_t ws_bytes;
+    SceneLayout L;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+pcrt_status fail(pcrt_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+pcrt_status ok() {
+    g_err.clear();
+    return PCRT_OK;
+}
+
+#define HIP_TRY(x)                                                                            \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) return fail(PCRT_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+uint32_t next_pow2(uint64_t v) {
+    uint64_t p = 64;
+    while (p < v && p < (1ull << 31)) p <<= 1;
+    return (uint32_t)p;
+}
+
+uint32_t round_up(uint32_t a, uint32_t b) { return (a + b - 1) / b * b; }
+
+struct Plan {
+    SolveDims D;
+    SolveLayout L;
+    uint32_t cap;
+    uint32_t n_trace;
+    Thr thr;
+    FieldConst fc;
+};
+
+Thr make_thr(const pcrt_thresholds &t) {
+    Thr r;
+    r.eps_tie = t.eps_tie > 0 ? t.eps_tie : 1e-4f;
+    r.eps_self = t.eps_self > 0 ? t.eps_self : 1e-3f;
+    float ta = t.t_a_deg > 0 ? t.t_a_deg : 1.0f;
+    r.cos_ta = (float)std::cos((double)ta * kPi / 180.0);
+    r.t_d = t.t_d > 0 ? t.t_d : 0.01f;
+    r.kappa = t.kappa == PCRT_KAPPA_NONE ? 0 : (t.kappa == 0 ? 10 : (int)t.kappa);
+    return r;
+}
+
+FieldConst make_fc(double f) {
+    FieldConst fc;
+    double lam = kC0 / f;
+    fc.amp_iso = (float)(lam / (4.0 * kPi));
+    double inv = 1.0 / lam;
+    fc.inv_lam_hi = (float)inv;
+    fc.inv_lam_lo = (float)(inv - (double)fc.inv_lam_hi);
+    fc.inv_we0 = (float)(1.0 / (2.0 * kPi * f * kEps0));
+    return fc;
+}
+
+// Per-item key-table capacity: twice the number of distinct keys possible.
+uint32_t key_capacity(uint64_t max_rays, uint32_t K, uint32_t n_surf) {
+    double combos = 0, p = 1;
+    for (uint32_t k = 1; k <= K; ++k) {
+        p *= (double)n_surf;
+        combos += p;
+    }
+    double lim = std::min<double>(combos, (double)max_rays * K);
+    return next_pow2((uint64_t)std::min<double>(2.0 * lim + 1, 2147483648.0));
+}
+
+pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
+    if (!sc || !p) return fail(PCRT_EINVAL, "scene and params are required");
+    if (p->max_interactions < 1 || p->max_interactions > (uint32_t)kMaxK)
+        return fail(PCRT_EUNSUPPORTED, "max_interactions must be in 1..%d (got %u)", kMaxK, p->max_interactions);
+    if (!(p->freq_hz > 0) || !std::isfinite(p->freq_hz)) return fail(PCRT_EINVAL, "freq_hz must be > 0");
+    if (p->n_rx == 0 || !p->rx) return fail(PCRT_EINVAL, "n_rx must be > 0 and rx non-NULL");
+    if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && p->n_rays == 0)
+        return fail(PCRT_EINVAL, "n_rays must be > 0 with SPECULAR or DIFFUSE");
+    if (p->ray_subset && p->n_subset == 0) return fail(PCRT_EINVAL, "n_subset must be > 0 with ray_subset");
+    if (!std::isfinite(p->tx[0]) || !std::isfinite(p->tx[1]) || !std::isfinite(p->tx[2]))
+        return fail(PCRT_EINVAL, "tx must be finite");
+    if (p->flags & PCRT_SPECULAR) {
+        double bits = p->max_interactions * std::log2((double)sc->info.n_surfaces + 1.0);
+        if (bits >= 63.9)
+            return fail(PCRT_EUNSUPPORTED, "(n_surfaces + 1)^K = 2^%.1f: keys do not fit 64 bits", bits);
+    }
+    uint64_t nt = p->ray_subset ? p->n_subset : p->n_rays;
+    if (nt * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
+    if ((uint64_t)p->n_rx > kSpillLanes) return fail(PCRT_EUNSUPPORTED, "too many receivers");
+    return PCRT_OK;
+}
+
+Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
+    Plan P;
+    const uint32_t K = p->max_interactions;
+    P.n_trace = (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) ? (p->ray_subset ? p->n_subset : p->n_rays) : 0;
+    SolveDims &D = P.D;
+    D.K = K;
+    D.n_rx = p->n_rx;
+    D.n_items = 1;
+    D.T = round_up(std::max<uint32_t>(P.n_trace, 1), kRayChunk);
+    P.cap = key_capacity(P.n_trace, K, sc->info.n_surfaces);
+    D.max_keys = (uint32_t)std::min<uint64_t>((uint64_t)D.T * K, (uint64_t)P.cap * D.n_items);
+    D.max_key_chunks = (D.max_keys + kKeyChunk - 1) / kKeyChunk + D.n_items;
+    D.n_ray_chunks = D.T / kRayChunk;
+    P.L = solve_layout(D, p->flags);
+    P.thr = make_thr(p->thr);
+    P.fc = make_fc(p->freq_hz);
+    return P;
+}
+
+struct ItemBatch {
+    Item it[96];
+    uint32_t n, base;
+};
+
+__global__ void k_put_items(ItemBatch b, Item *dst) {
+    uint32_t i = threadIdx.x;
+    if (i < b.n) dst[b.base + i] = b.it[i];
+}
+
+__global__ void k_copy_seq(const int *id, uint32_t n, int32_t *out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = id[i];
+}
+
+LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n_labels, const pcrt_solve_params *p,
+                     const Plan &P, char *ws, uint64_t *counters) {
+    LaunchArgs A;
+    memset(&A, 0, sizeof A);
+    const SolveLayout &L = P.L;
+    auto at = [&](size_t off) { return (void *)(ws + off); };
+    A.S = sc->dev;
+    A.S.spill = (int *)at(L.spill);
+    A.S.spill_lanes = kSpillLanes;
+    A.items = (const Item *)at(L.items);
+    A.subset = p->ray_subset;
+    A.rx = p->rx;
+    A.mats = (const float *)mats;
+    A.n_labels = n_labels;
+    A.n_surf1 = sc->info.n_surfaces + 1;
+    A.flags = p->flags;
+    A.thr = P.thr;
+    A.fc = P.fc;
+    A.D = P.D;
+    A.rb.id = (int *)at(L.rec_id);
+    A.rb.xl = (float4 *)at(L.rec_xl);
+    A.rb.cs = (float *)at(L.rec_cs);
+    A.rb.coef = (p->flags & PCRT_DIFFUSE) ? (float4 *)at(L.rec_coef) : nullptr;
+    A.rb.slot = (p->flags & PCRT_SPECULAR) ? (uint32_t *)at(L.rec_slot) : nullptr;
+    A.hb.key = (unsigned long long *)at(L.hkey);
+    A.hb.rep = (uint32_t *)at(L.hrep);
+    A.hb.cap = P.cap;
+    if ((p->flags & PCRT_RECORD) && (p->flags & PCRT_SPECULAR)) {
+        A.sb.valid = (uint8_t *)at(L.sp_valid);
+        A.sb.len = (float *)at(L.sp_len);
+        A.sb.amp = (float4 *)at(L.sp_amp);
+        A.sb.hit = (int *)at(L.sp_hit);
+        A.sb.cs = (float *)at(L.sp_cs);
+    }
+    A.work = (uint32_t *)at(L.work);
+    A.counters = counters ? counters : (uint64_t *)at(L.counters);
+    A.scan = (uint32_t *)at(L.scan);
+    A.scan_blk = (uint32_t *)at(L.scan_blk);
+    A.keylist = (uint32_t *)at(L.keylist);
+    A.key_off = (uint32_t *)at(L.key_off);
+    A.chunk_off = (uint32_t *)at(L.chunk_off);
+    A.spec_part = (double *)at(L.spec_part);
+    A.diff_part = (double *)at(L.diff_part);
+    A.los_part = (double *)at(L.los_part);
+    A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
+    return A;
+}
+
+}  // namespace
+
+namespace pcrt {
+SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
+    Bump b;
+    SolveLayout L;
+    memset(&L, 0, sizeof L);
+    const size_t nrec = (size_t)D.T * D.K;
+    const bool spec = flags & PCRT_SPECULAR, diff = flags & PCRT_DIFFUSE, rec = flags & PCRT_RECORD;
+    L.items = b.take(sizeof(Item) * D.n_items);
+    L.counters = b.take(sizeof(uint64_t) * PCRT_CNT_COUNT);
+    L.work = b.take(sizeof(uint32_t) * 8);
+    L.rec_id = b.take(sizeof(int) * nrec);
+    L.rec_xl = b.take(sizeof(float4) * nrec);
+    L.rec_cs = b.take(sizeof(float) * nrec);
+    L.key_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
+    L.chunk_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
+    L.los_part = b.take(sizeof(double) * 5 * (size_t)D.n_items * D.n_rx);
+    if (diff) {
+        L.rec_coef = b.take(sizeof(float4) * nrec);
+        L.diff_part = b.take(sizeof(double) * 5 * (size_t)D.n_ray_chunks * D.n_rx);
+        if (rec) L.dvis = b.take(nrec * D.n_rx);
+    }
+    if (spec) {
+        L.rec_slot = b.take(sizeof(uint32_t) * nrec);
+        L.scan = b.take(sizeof(uint32_t) * nrec);
+        L.scan_blk = b.take(sizeof(uint32_t) * ((nrec + 1023) / 1024 + 1));
+        L.keylist = b.take(sizeof(uint32_t) * D.max_keys);
+        L.spec_part = b.take(sizeof(double) * 5 * (size_t)D.max_key_chunks * D.n_rx);
+        if (rec) {
+            const size_t pairs = (size_t)D.max_keys * D.n_rx;
+            L.sp_valid = b.take(pairs);
+            L.sp_len = b.take(sizeof(float) * pairs);
+            L.sp_amp = b.take(sizeof(float4) * pairs);
+            L.sp_hit = b.take(sizeof(int) * pairs * D.K);
+            L.sp_cs = b.take(sizeof(float) * pairs * D.K);
+        }
+    }
+    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * kSpillLanes);
+    L.total = b.off;
+    return L;
+}
+}  // namespace pcrt
+
+// Hash-table sizes depend on the key capacity, which the layout does not
+// know; they are appended after the common layout.
+static size_t hash_bytes(const Plan &P, uint32_t flags) {
+    if (!(flags & PCRT_SPECULAR)) return 0;
+    size_t slots = (size_t)P.cap * P.D.n_items;
+    return ((sizeof(uint64_t) * slots + 255) & ~size_t(255)) + ((sizeof(uint32_t) * slots + 255) & ~size_t(255));
+}
+
+static void place_hash(Plan &P, uint32_t flags) {
+    if (!(flags & PCRT_SPECULAR)) {
+        P.L.hkey = P.L.hrep = 0;
+        return;
+    }
+    size_t slots = (size_t)P.cap * P.D.n_items;
+    P.L.hkey = P.L.total;
+    P.L.hrep = P.L.total + ((sizeof(uint64_t) * slots + 255) & ~size_t(255));
+    P.L.total += hash_bytes(P, flags);
+}
+
+extern "C" {
+
+const char *pcrt_last_error(void) { return g_err.c_str(); }
+const char *pcrt_version(void) { return "pcrt 0.1 (gfx950)"; }
+
+pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *opts, size_t *bytes) {
+    (void)opts;
+    if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
+    if (n_points == 0) return fail(PCRT_EINVAL, "n_points must be > 0");
+    if (n_points > (1u << 27)) return fail(PCRT_EUNSUPPORTED, "at most 2^27 points");
+    *bytes = scene_layout(n_points).total;
+    return ok();
+}
+
+pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts, void *ws, size_t ws_bytes,
+                              void *stream, pcrt_scene **out) {
+    if (!pts || !out || !ws) return fail(PCRT_EINVAL, "pts, ws and out are required");
+    if (!pts->pos || !pts->normal || !pts->material || !pts->surface)
+        return fail(PCRT_EINVAL, "point arrays must be non-NULL");
+    if (pts->n_points == 0) return fail(PCRT_EINVAL, "n_points must be > 0");
+    if (pts->n_points > (1u << 27)) return fail(PCRT_EUNSUPPORTED, "at most 2^27 points");
+    if (!(pts->disk_radius > 0.f) || !std::isfinite(pts->disk_radius))
+        return fail(PCRT_EINVAL, "disk_radius must be > 0");
+    uint32_t leaf = opts && opts->leaf_size ? opts->leaf_size : 4;
+    if (leaf < 1 || leaf > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
+    if (opts && opts->width && opts->width != 2) return fail(PCRT_EUNSUPPORTED, "only width 2 is implemented");
+    SceneLayout L = scene_layout(pts->n_points);
+    if (ws_bytes < L.total) return fail(PCRT_ENOMEM, "scene workspace too small: need %zu bytes", L.total);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(build_scene(pts->pos, pts->normal, pts->material, pts->surface, pts->n_points, pts->disk_radius, leaf,
+                        (char *)ws, L, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    uint32_t stat[8];
+    float bounds[6];
+    HIP_TRY(hipMemcpyAsync(stat, (char *)ws + L.stat, sizeof stat, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(bounds, (char *)ws + L.bounds, sizeof bounds, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (stat[0] & 1) return fail(PCRT_EINVAL, "non-finite point position");
+    if (stat[0] & 2) return fail(PCRT_EINVAL, "zero or non-finite normal");
+    if (stat[3] > (uint32_t)kStackMax)
+        return fail(PCRT_EUNSUPPORTED, "hierarchy depth %u exceeds the traversal stack (%d)", stat[3], kStackMax);
+    pcrt_scene *sc = new pcrt_scene;
+    memset(sc, 0, sizeof *sc);
+    sc->ws = (char *)ws;
+    sc->ws_bytes = ws_bytes;
+    sc->L = L;
+    const uint32_t n = pts->n_points;
+    sc->dev.node = (const float4 *)(sc->ws + L.node);
+    sc->dev.disk = (const float4 *)(sc->ws + L.disk);
+    sc->dev.pos = (const float4 *)(sc->ws + L.pos_id);
+    sc->dev.nrm = (const float4 *)(sc->ws + L.nrm_id);
+    sc->dev.r2 = pts->disk_radius * pts->disk_radius;
+    sc->dev.n = n;
+    sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : 0);
+    pcrt_scene_info &I = sc->info;
+    I.n_points = n;
+    I.n_surfaces = stat[1] + 1;
+    I.n_materials = stat[2] + 1;
+    I.depth = stat[3];
+    I.n_nodes = n > 1 ? n - 1 : 0;
+    I.leaf_size = leaf;
+    memcpy(I.bbox, bounds, sizeof bounds);
+    I.build_ms = ms;
+    *out = sc;
+    return ok();
+}
+
+pcrt_status pcrt_scene_get_info(const pcrt_scene *scene, pcrt_scene_info *info) {
+    if (!scene || !info) return fail(PCRT_EINVAL, "scene and info are required");
+    *info = scene->info;
+    return ok();
+}
+
+pcrt_status pcrt_scene_destroy(pcrt_scene *scene) {
+    delete scene;
+    return ok();
+}
+
+pcrt_status pcrt_solve_workspace_size(const pcrt_scene *scene, const pcrt_solve_params *p, size_t *bytes) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
+    Plan P = make_plan(scene, p);
+    place_hash(P, p->flags);
+    *bytes = P.L.total;
+    return ok();
+}
+
+pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                       const pcrt_solve_params *p, void *ws, size_t ws_bytes, const pcrt_outputs *out,
+                       void *stream) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    if (!out || !out->gain) return fail(PCRT_EINVAL, "out->gain is required");
+    if (!ws) return fail(PCRT_EINVAL, "ws is required");
+    if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && (!mats || n_labels == 0))
+        return fail(PCRT_EINVAL, "materials are required");
+    Plan P = make_plan(scene, p);
+    place_hash(P, p->flags);
+    if (ws_bytes < P.L.total) return fail(PCRT_ENOMEM, "solve workspace too small: need %zu bytes", P.L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    LaunchArgs A = make_args(scene, mats, n_labels, p, P, w, out->counters);
+    // graph-safe initialisation: fill kernels, items passed by value
+    fill_u32(A.work, 0, 8, s);
+    fill_u64(A.counters, 0, PCRT_CNT_COUNT, s);
+    fill_u32(A.key_off, 0, P.D.n_items + 1, s);
+    fill_u32(A.chunk_off, 0, P.D.n_items + 1, s);
+    ItemBatch ib;
+    memset(&ib, 0, sizeof ib);
+    ib.n = 1;
+    ib.base = 0;
+    Item &it = ib.it[0];
+    it.tx[0] = p->tx[0];
+    it.tx[1] = p->tx[1];
+    it.tx[2] = p->tx[2];
+    it.n_rays = P.n_trace;
+    it.ray_off = 0;
+    it.budget = p->n_rays ? p->n_rays : 1;
+    hipLaunchKernelGGL(k_put_items, dim3(1), dim3(96), 0, s, ib, (Item *)A.items);
+    if (p->flags & PCRT_SPECULAR) {
+        fill_u64((uint64_t *)A.hb.key, 0, (size_t)P.cap * P.D.n_items, s);
+        fill_u32(A.hb.rep, 0xffffffffu, (size_t)P.cap * P.D.n_items, s);
+    }
+    if (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) {
+        launch_trace(A, s);
+        if (out->ray_seq) {
+            uint32_t n = P.n_trace * P.D.K;
+            hipLaunchKernelGGL(k_copy_seq, dim3((n + 255) / 256), dim3(256), 0, s, A.rb.id, n, out->ray_seq);
+        }
+    }
+    if (p->flags & PCRT_SPECULAR) launch_specular(A, s);
+    if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
+    launch_los_and_combine(A, out->gain, out->h_te, out->h_tm, out->gain_parts, s);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws, uint32_t cap,
+                            uint32_t *key_ray, uint8_t *key_len, int32_t *key_seq, uint8_t *valid, float *length,
+                            float *amp, int32_t *hit, uint32_t *n_keys, void *stream) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    if (!(p->flags & PCRT_RECORD) || !(p->flags & PCRT_SPECULAR))
+        return fail(PCRT_EINVAL, "paths need a solve with RECORD and SPECULAR");
+    if (!ws) return fail(PCRT_EINVAL, "ws is required");
+    Plan P = make_plan(scene, p);
+    place_hash(P, p->flags);
+    hipStream_t s = (hipStream_t)stream;
+    LaunchArgs A = make_args(scene, nullptr, 0, p, P, (char *)ws, nullptr);
+    launch_paths_copy(A, cap, key_ray, key_len, key_seq, valid, length, amp, hit, s);
+    if (n_keys) {
+        HIP_TRY(hipMemcpyAsync(n_keys, A.key_off + P.D.n_items, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return ok();
+}
+
+pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws, uint8_t *vis,
+                                  void *stream) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    if (!(p->flags & PCRT_RECORD) || !(p->flags & PCRT_DIFFUSE))
+        return fail(PCRT_EINVAL, "visibility needs a solve with RECORD and DIFFUSE");
+    if (!ws || !vis) return fail(PCRT_EINVAL, "ws and vis are required");
+    Plan P = make_plan(scene, p);
+    place_hash(P, p->flags);
+    size_t bytes = (size_t)P.n_trace * P.D.K * P.D.n_rx;
+    HIP_TRY(hipMemcpyAsync(vis, (const char *)ws + P.L.dvis, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return ok();
+}
+
+pcrt_status pcrt_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, void *stream) {
+    if (n_budget == 0 || !out) return fail(PCRT_EINVAL, "n_budget > 0 and out are required");
+    if (n == 0) return ok();
+    launch_raygen(n_budget, ids, n, out, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+}  // extern "C"

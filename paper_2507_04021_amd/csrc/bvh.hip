@@ -1,0 +1,410 @@
+// Scene ingest and linear BVH build over disk bounding boxes.
+//
+// The paper hands point-set AABBs to a hardware ray-tracing API (Sec. II-A).
+// gfx950 has no ray-tracing units, so the hierarchy is built here: Morton
+// codes of disk centres, a hand-written LSD radix sort, the Karras (2012)
+// binary radix tree over the sorted codes, and a bottom-up refit that also
+// collapses small subtrees into leaves of up to `leaf_size` disks.
+#include "common.h"
+#include "internal.h"
+
+namespace pcrt {
+
+// --------------------------------------------------------------- ingest
+// Validates and normalises each point; writes the by-id tables and the
+// per-block bounds of disk centres. status bits: 1 non-finite position,
+// 2 zero or non-finite normal.
+__global__ void k_ingest(const float *__restrict__ pos, const float *__restrict__ nrm,
+                         const uint16_t *__restrict__ mat, const uint32_t *__restrict__ surf, uint32_t n,
+                         float4 *__restrict__ pos_id, float4 *__restrict__ nrm_id, float *__restrict__ blk_bounds,
+                         uint32_t *__restrict__ stat) {
+    __shared__ float red[6][256];
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t bad = 0, ms = 0, mm = 0;
+    if (i < n) {
+        float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2];
+        float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
+        if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1;
+        float l2 = nx * nx + ny * ny + nz * nz;
+        if (!(l2 > 0.f) || !isfinite(l2)) bad |= 2;
+        float il = bad & 2 ? 0.f : 1.0f / sqrtf(l2);
+        uint32_t s = surf[i], m = mat[i];
+        ms = s;
+        mm = m;
+        pos_id[i] = make_float4(px, py, pz, __uint_as_float(s));
+        nrm_id[i] = make_float4(nx * il, ny * il, nz * il, __uint_as_float(m));
+        if (!bad) {
+            lo[0] = hi[0] = px;
+            lo[1] = hi[1] = py;
+            lo[2] = hi[2] = pz;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = lo[a];
+        red[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+                red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) blk_bounds[6 * blockIdx.x + a] = red[a][0];
+    if (bad) atomicOr(&stat[0], bad);
+    if (i < n) {
+        atomicMax(&stat[1], ms);
+        atomicMax(&stat[2], mm);
+    }
+}
+
+// Final bounds over the per-block bounds (one block).
+__global__ void k_bounds(const float *__restrict__ blk, uint32_t nblk, float *__restrict__ out) {
+    __shared__ float red[6][256];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fminf(v[a], blk[6 * b + a]);
+            v[3 + a] = fmaxf(v[3 + a], blk[6 * b + 3 + a]);
+        }
+    for (int a = 0; a < 6; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+                red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) out[a] = red[a][0];
+}
+
+__device__ __forceinline__ uint64_t spread21(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+// 63-bit Morton code of each disk centre in the scene bounds.
+__global__ void k_morton(const float4 *__restrict__ pos_id, uint32_t n, const float *__restrict__ bounds,
+                         uint64_t *__restrict__ code, uint32_t *__restrict__ idx) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 p = pos_id[i];
+    float c[3] = {p.x, p.y, p.z};
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        float ext = bounds[3 + a] - bounds[a];
+        float u = ext > 0.f ? (c[a] - bounds[a]) / ext : 0.5f;
+        u = fminf(fmaxf(u, 0.f), 1.f);
+        q[a] = (uint64_t)(u * 2097151.0f);
+    }
+    code[i] = spread21(q[0]) << 2 | spread21(q[1]) << 1 | spread21(q[2]);
+    idx[i] = i;
+}
+
+// ----------------------------------------------------------- radix sort
+// LSD, 8-bit digits, 64-bit keys with 32-bit payload. Per pass: tile
+// histograms, one exclusive scan in digit-major order, stable scatter with a
+// wavefront multisplit (8 ballots per key) for the in-tile rank.
+constexpr int kRsBlock = 256;
+constexpr int kRsRounds = 8;
+constexpr int kRsTile = kRsBlock * kRsRounds;
+
+__global__ void k_rs_hist(const uint64_t *__restrict__ key, uint32_t n, int shift, uint32_t *__restrict__ hist,
+                          uint32_t tiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t base = blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        uint32_t i = base + r * kRsBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of a u32 array in one block of 1024 threads (build only).
+__global__ void k_scan_small(uint32_t *__restrict__ a, uint32_t n) {
+    __shared__ uint32_t part[1024];
+    uint32_t per = (n + 1023) / 1024;
+    uint32_t b = threadIdx.x * per, e = min(n, b + per);
+    uint32_t s = 0;
+    for (uint32_t i = b; i < e; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= (uint32_t)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (uint32_t i = b; i < e; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                             uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t n, int shift,
+                             const uint32_t *__restrict__ hist, uint32_t tiles) {
+    __shared__ uint32_t base[256], run[256];
+    __shared__ uint32_t wcnt[kRsBlock / kWave][256];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    base[threadIdx.x] = hist[threadIdx.x * tiles + blockIdx.x];
+    run[threadIdx.x] = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kRsRounds; ++r) {
+        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        uint32_t i = blockIdx.x * kRsTile + r * kRsBlock + threadIdx.x;
+        bool ok = i < n;
+        uint64_t k = ok ? kin[i] : 0;
+        uint32_t dg = (uint32_t)(k >> shift) & 255;
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        if (ok && rank == 0) wcnt[wave][dg] = __popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += wcnt[w][dg];
+            uint32_t dst = base[dg] + run[dg] + before + rank;
+            kout[dst] = k;
+            vout[dst] = vin[i];
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int w = 0; w < kRsBlock / kWave; ++w) tot += wcnt[w][threadIdx.x];
+        run[threadIdx.x] += tot;
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------- Karras radix tree
+__device__ __forceinline__ int delta(const uint64_t *k, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((uint32_t)i ^ (uint32_t)j);
+    return __clzll(a ^ b);
+}
+
+// Internal node i of n-1: children (int index or leaf encoded as ~pos) and
+// covered range [first, last] of sorted positions.
+__global__ void k_karras(const uint64_t *__restrict__ k, int n, int2 *__restrict__ child, int2 *__restrict__ range,
+                         int *__restrict__ parent_int, int *__restrict__ parent_leaf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(k, n, i, i - d);
+    int lmax = 2;
+    while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = delta(k, n, i, j);
+    int s = 0;
+    int div = 2;
+    for (;;) {
+        int t = (l + div - 1) / div;
+        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t == 1) break;
+        div <<= 1;
+    }
+    int gamma = i + s * d + min(d, 0);
+    int first = min(i, j), last = max(i, j);
+    int left = (first == gamma) ? ~gamma : gamma;
+    int right = (last == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+    child[i] = make_int2(left, right);
+    range[i] = make_int2(first, last);
+    if (left < 0) parent_leaf[~left] = i;
+    else parent_int[left] = i;
+    if (right < 0) parent_leaf[~right] = i;
+    else parent_int[right] = i;
+    if (i == 0) parent_int[0] = -1;
+}
+
+// Leaf-ordered disks and their padded bounding boxes.
+__global__ void k_gather(const float4 *__restrict__ pos_id, const float4 *__restrict__ nrm_id,
+                         const uint32_t *__restrict__ perm, uint32_t n, float r, float4 *__restrict__ disk,
+                         float *__restrict__ dbox) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t id = perm[i];
+    float4 p = pos_id[id], nn = nrm_id[id];
+    disk[2 * i] = make_float4(p.x, p.y, p.z, __int_as_float((int)id));
+    disk[2 * i + 1] = make_float4(nn.x, nn.y, nn.z, 0.f);
+    float c[3] = {p.x, p.y, p.z}, nv[3] = {nn.x, nn.y, nn.z};
+    for (int a = 0; a < 3; ++a) {
+        // tight half-extent of a disk along axis a, padded so that FP32
+        // slab tests stay conservative
+        float h = r * sqrtf(fmaxf(0.f, 1.f - nv[a] * nv[a]));
+        float pad = 1e-5f + 2e-6f * (fabsf(c[a]) + r);
+        dbox[6 * i + a] = c[a] - h - pad;
+        dbox[6 * i + 3 + a] = c[a] + h + pad;
+    }
+}
+
+// Bottom-up refit: the second thread to reach a node computes its box and
+// writes its traversal record; children covering <= L disks become leaves.
+__global__ void k_refit(int n, int L, const int2 *__restrict__ child, const int2 *__restrict__ range,
+                        const int *__restrict__ parent_int, const int *__restrict__ parent_leaf,
+                        const float *__restrict__ dbox, float *ibox, uint32_t *flags, float4 *__restrict__ node) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cur = parent_leaf[i];
+    while (cur >= 0) {
+        __threadfence();
+        if (atomicAdd(&flags[cur], 1u) == 0) return;
+        __threadfence();
+        int2 ch = child[cur];
+        float b[2][6];
+        int ref[2];
+        int cc[2] = {ch.x, ch.y};
+        for (int s = 0; s < 2; ++s) {
+            int c = cc[s];
+            if (c < 0) {
+                int p = ~c;
+                for (int a = 0; a < 6; ++a) b[s][a] = dbox[6 * p + a];
+                ref[s] = leaf_ref(p, 1);
+            } else {
+                const volatile float *vb = ibox + 6 * c;
+                for (int a = 0; a < 6; ++a) b[s][a] = vb[a];
+                int2 rg = range[c];
+                int cnt = rg.y - rg.x + 1;
+                ref[s] = cnt <= L ? leaf_ref(rg.x, cnt) : c;
+            }
+        }
+        volatile float *ob = ibox + 6 * cur;
+        for (int a = 0; a < 3; ++a) {
+            ob[a] = fminf(b[0][a], b[1][a]);
+            ob[3 + a] = fmaxf(b[0][3 + a], b[1][3 + a]);
+        }
+        float4 *nd = node + 4 * (size_t)cur;
+        nd[0] = make_float4(b[0][0], b[0][1], b[0][2], b[0][3]);
+        nd[1] = make_float4(b[0][4], b[0][5], b[1][0], b[1][1]);
+        nd[2] = make_float4(b[1][2], b[1][3], b[1][4], b[1][5]);
+        nd[3] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), 0.f, 0.f);
+        cur = parent_int[cur];
+    }
+}
+
+// Depth (number of internal ancestors) of each sorted leaf; max into *depth.
+__global__ void k_depth(int n, const int *__restrict__ parent_int, const int *__restrict__ parent_leaf,
+                        uint32_t *__restrict__ depth) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t dd = 0;
+    for (int cur = parent_leaf[i]; cur >= 0; cur = parent_int[cur]) ++dd;
+    atomicMax(depth, dd);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------ host side
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (!n) return;
+    uint32_t g = (uint32_t)std::min<size_t>(cdiv(n, 256), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, v, n);
+}
+void fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
+    if (!n) return;
+    uint32_t g = (uint32_t)std::min<size_t>(cdiv(n, 256), 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, s, p, v, n);
+}
+
+SceneLayout scene_layout(uint32_t n) {
+    Bump b;
+    SceneLayout L;
+    uint32_t ni = n > 1 ? n - 1 : 1;
+    uint32_t blk = cdiv(n, 256);
+    uint32_t tiles = cdiv(n, kRsTile);
+    L.pos_id = b.take(sizeof(float4) * n);
+    L.nrm_id = b.take(sizeof(float4) * n);
+    L.disk = b.take(sizeof(float4) * 2 * n);
+    L.node = b.take(sizeof(float4) * 4 * (size_t)ni);
+    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * kSpillLanes);
+    L.stat = b.take(sizeof(uint32_t) * 8);
+    L.bounds = b.take(sizeof(float) * 8);
+    L.blk_bounds = b.take(sizeof(float) * 6 * blk);
+    L.code0 = b.take(sizeof(uint64_t) * n);
+    L.code1 = b.take(sizeof(uint64_t) * n);
+    L.idx0 = b.take(sizeof(uint32_t) * n);
+    L.idx1 = b.take(sizeof(uint32_t) * n);
+    L.hist = b.take(sizeof(uint32_t) * 256 * (size_t)tiles);
+    L.child = b.take(sizeof(int2) * ni);
+    L.range = b.take(sizeof(int2) * ni);
+    L.parent_int = b.take(sizeof(int) * ni);
+    L.parent_leaf = b.take(sizeof(int) * n);
+    L.dbox = b.take(sizeof(float) * 6 * n);
+    L.ibox = b.take(sizeof(float) * 6 * ni);
+    L.flags = b.take(sizeof(uint32_t) * ni);
+    L.total = b.off;
+    return L;
+}
+
+hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
+                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s) {
+    auto P = [&](size_t off) { return ws + off; };
+    float4 *pos_id = (float4 *)P(L.pos_id), *nrm_id = (float4 *)P(L.nrm_id);
+    uint32_t *stat = (uint32_t *)P(L.stat);
+    float *bounds = (float *)P(L.bounds), *blkb = (float *)P(L.blk_bounds);
+    uint64_t *c0 = (uint64_t *)P(L.code0), *c1 = (uint64_t *)P(L.code1);
+    uint32_t *i0 = (uint32_t *)P(L.idx0), *i1 = (uint32_t *)P(L.idx1);
+    uint32_t *hist = (uint32_t *)P(L.hist);
+    uint32_t blk = cdiv(n, 256), tiles = cdiv(n, kRsTile);
+    fill_u32(stat, 0, 8, s);
+    hipLaunchKernelGGL(k_ingest, dim3(blk), dim3(256), 0, s, pos, nrm, mat, surf, n, pos_id, nrm_id, blkb, stat);
+    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, s, blkb, blk, bounds);
+    hipLaunchKernelGGL(k_morton, dim3(blk), dim3(256), 0, s, pos_id, n, bounds, c0, i0);
+    for (int shift = 0; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, s, c0, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, hist, 256 * tiles);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, s, c0, i0, c1, i1, n, shift, hist, tiles);
+        std::swap(c0, c1);
+        std::swap(i0, i1);
+    }
+    // after 8 passes the sorted data is back in code0/idx0
+    float *dbox = (float *)P(L.dbox);
+    hipLaunchKernelGGL(k_gather, dim3(blk), dim3(256), 0, s, pos_id, nrm_id, i0, n, r, (float4 *)P(L.disk), dbox);
+    if (n > 1) {
+        int2 *child = (int2 *)P(L.child), *range = (int2 *)P(L.range);
+        int *pint = (int *)P(L.parent_int), *pleaf = (int *)P(L.parent_leaf);
+        hipLaunchKernelGGL(k_karras, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, c0, (int)n, child, range, pint, pleaf);
+        fill_u32((uint32_t *)P(L.flags), 0, n - 1, s);
+        hipLaunchKernelGGL(k_refit, dim3(blk), dim3(256), 0, s, (int)n, (int)leaf, child, range, pint, pleaf, dbox,
+                           (float *)P(L.ibox), (uint32_t *)P(L.flags), (float4 *)P(L.node));
+        hipLaunchKernelGGL(k_depth, dim3(blk), dim3(256), 0, s, (int)n, pint, pleaf, stat + 3);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pcrt

@@ -1,0 +1,391 @@
+// Device-side types and routines shared by the HIP kernels of libpcrt.
+//
+// Geometry and field arithmetic are FP32; only per-receiver reductions are FP64.
+// Written for gfx950 (CDNA4): 64-lane wavefronts, LDS traversal stacks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcrt {
+
+constexpr int kMaxK = 8;          // max interactions per path
+constexpr int kWave = 64;         // wavefront width
+constexpr int kStackLds = 32;     // traversal stack entries kept in LDS per lane
+constexpr int kStackMax = 96;     // max stack entries (LDS + global spill)
+constexpr int kRayChunk = 128;    // rays per diffuse reduction chunk (item ray ranges are padded to this)
+constexpr int kKeyChunk = 64;     // specular keys per reduction chunk
+constexpr float kParallelEps = 1e-6f;  // |d.n| below this: ray parallel to a disk
+
+constexpr double kC0 = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- vectors
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float len(f3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / len(a)) * a; }
+__device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
+
+// ------------------------------------------------------------- scene
+// Child reference of a node: >= 0 internal node index; < 0 leaf,
+// v = -1 - ref, first disk = v >> 3, count = (v & 7) + 1.
+__host__ __device__ __forceinline__ int leaf_ref(int first, int count) { return -1 - ((first << 3) | (count - 1)); }
+
+struct DevScene {
+    const float4 *node;  // 4 float4 per binary node: child boxes + child refs
+    const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, 0)
+    const float4 *pos;   // by id: (p.xyz, surface bits)
+    const float4 *nrm;   // by id: (n.xyz, material bits)
+    int *spill;          // global spill of traversal stacks, [kStackMax - kStackLds][spill_lanes]
+    uint32_t spill_lanes;
+    int root;
+    float r2;
+    uint32_t n;
+};
+
+// Node layout (64 B): n0 = (lo0.x, lo0.y, lo0.z, hi0.x), n1 = (hi0.y, hi0.z, lo1.x, lo1.y),
+// n2 = (lo1.z, hi1.x, hi1.y, hi1.z), n3 = (ref0, ref1, -, -).
+
+struct Thr {
+    float eps_tie, eps_self, cos_ta, t_d;
+    int kappa;
+};
+
+struct Item {  // one transmitter of a (batched) solve, 32 B
+    float tx[3];
+    uint32_t n_rays;   // rays traced for this item
+    uint32_t ray_off;  // first flattened ray slot (multiple of kRayChunk)
+    uint32_t budget;   // ray budget N (Fibonacci directions, diffuse weight)
+    uint32_t pad[2];
+};
+
+// ---------------------------------------------------- traversal stack
+// Entries 0..kStackLds-1 live in LDS ([depth][lane] so lanes hit distinct
+// banks); deeper entries spill to a per-lane global region.
+struct Stack {
+    int *lds;        // this lane's column base: lds[s * kWave]
+    int *gl;         // this lane's spill column base: gl[(s - kStackLds) * lanes]
+    uint32_t lanes;
+    __device__ __forceinline__ void put(int s, int v) {
+        if (s < kStackLds) lds[s * kWave] = v;
+        else gl[(size_t)(s - kStackLds) * lanes] = v;
+    }
+    __device__ __forceinline__ int get(int s) const {
+        return s < kStackLds ? lds[s * kWave] : gl[(size_t)(s - kStackLds) * lanes];
+    }
+};
+
+__device__ __forceinline__ f3 safe_inv(f3 d) {
+    const float tiny = 1e-30f;
+    float x = fabsf(d.x) < tiny ? copysignf(tiny, d.x) : d.x;
+    float y = fabsf(d.y) < tiny ? copysignf(tiny, d.y) : d.y;
+    float z = fabsf(d.z) < tiny ? copysignf(tiny, d.z) : d.z;
+    return {1.0f / x, 1.0f / y, 1.0f / z};
+}
+
+// Slab test of one box against [t_lo, t_hi]; returns entry distance in tn.
+__device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 o, f3 inv,
+                                        float t_lo, float t_hi, float &tn) {
+    float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
+    float ay = (ly - o.y) * inv.y, by = (hy - o.y) * inv.y;
+    float az = (lz - o.z) * inv.z, bz = (hz - o.z) * inv.z;
+    float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t_lo));
+    float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t_hi));
+    tn = t0;
+    return t0 <= t1;
+}
+
+// Two-sided ray-disk test (Sec. II-C): plane hit t, squared distance of the
+// hit point from the centre.
+__device__ __forceinline__ bool disk_hit(f3 o, f3 d, f3 p, f3 n, float r2, float &t, float &d2) {
+    float a = dot(d, n);
+    if (fabsf(a) < kParallelEps) return false;
+    t = dot(p - o, n) / a;
+    f3 q = o + t * d;
+    f3 e = q - p;
+    d2 = dot(e, e);
+    return d2 <= r2;
+}
+
+// Nearest hit among disks != excl with t in (t_lo, inf), with the tie rule:
+// t* = min t; among hits with t <= t* + eps_tie the smallest (d2, id) wins.
+// Hits within the current window are kept in a 4-entry list that is pruned
+// whenever t* shrinks; if the list overflows, a second, exact pass over the
+// final window decides. Returns the disk id or -1; t of the winner.
+struct Cand {
+    float t, d2;
+    int id;
+};
+
+template <bool kSecond>
+__device__ __forceinline__ void visit_leaf(const DevScene &S, int ref, f3 o, f3 d, int excl, float t_lo, float eps_tie,
+                                           float &tmin, Cand *c, bool &spill, float t_win, float &best_d2,
+                                           int &best_id, float &best_t) {
+    int v = -1 - ref;
+    int first = v >> 3, cnt = (v & 7) + 1;
+    for (int i = 0; i < cnt; ++i) {
+        float4 dp = S.disk[2 * (first + i)];
+        float4 dn = S.disk[2 * (first + i) + 1];
+        int id = __float_as_int(dp.w);
+        if (id == excl) continue;
+        float t, d2;
+        if (!disk_hit(o, d, xyz(dp), xyz(dn), S.r2, t, d2)) continue;
+        if (!(t > t_lo)) continue;
+        if (kSecond) {
+            if (t <= t_win && (d2 < best_d2 || (d2 == best_d2 && id < best_id))) {
+                best_d2 = d2;
+                best_id = id;
+                best_t = t;
+            }
+            continue;
+        }
+        if (t > tmin + eps_tie) continue;
+        if (t < tmin) {
+            tmin = t;
+            float lim = tmin + eps_tie;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c[k].id >= 0 && c[k].t > lim) c[k].id = -1;
+        }
+        bool placed = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (!placed && c[k].id < 0) {
+                c[k].t = t;
+                c[k].d2 = d2;
+                c[k].id = id;
+                placed = true;
+            }
+        if (!placed) spill = true;
+    }
+}
+
+template <bool kSecond>
+__device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, f3 inv, int excl, float t_lo,
+                                                 float eps_tie, Stack &stk, float &tmin, Cand *c, bool &spill,
+                                                 float t_win, float &best_d2, int &best_id, float &best_t) {
+    int ref = S.root;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4 *nd = S.node + 4 * (size_t)ref;
+            float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
+            float tc = kSecond ? t_win : tmin + eps_tie;
+            float n0, n1;
+            bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, t_lo, tc, n0);
+            bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, o, inv, t_lo, tc, n1);
+            int r0 = __float_as_int(r.x), r1 = __float_as_int(r.y);
+            if (h0 && h1) {
+                bool f0 = n0 <= n1;
+                stk.put(sp++, f0 ? r1 : r0);
+                ref = f0 ? r0 : r1;
+                continue;
+            }
+            if (h0) { ref = r0; continue; }
+            if (h1) { ref = r1; continue; }
+        } else {
+            visit_leaf<kSecond>(S, ref, o, d, excl, t_lo, eps_tie, tmin, c, spill, t_win, best_d2, best_id, best_t);
+        }
+        if (sp == 0) break;
+        ref = stk.get(--sp);
+    }
+}
+
+__device__ __forceinline__ int closest_hit(const DevScene &S, f3 o, f3 d, int excl, float t_lo, float eps_tie,
+                                           Stack &stk, float &t_out, bool &spilled) {
+    f3 inv = safe_inv(d);
+    float tmin = INFINITY;
+    Cand c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = {INFINITY, INFINITY, -1};
+    bool spill = false;
+    float bd2 = INFINITY, bt = INFINITY;
+    int bid = 0x7fffffff;
+    traverse_closest<false>(S, o, d, inv, excl, t_lo, eps_tie, stk, tmin, c, spill, 0.f, bd2, bid, bt);
+    spilled = spill;
+    if (!(tmin < INFINITY)) return -1;
+    if (spill) {
+        float dummy = tmin;
+        traverse_closest<true>(S, o, d, inv, excl, t_lo, eps_tie, stk, dummy, c, spill, tmin + eps_tie, bd2, bid,
+                               bt);
+        t_out = bt;
+        return bid;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (c[k].id >= 0 && (c[k].d2 < bd2 || (c[k].d2 == bd2 && c[k].id < bid))) {
+            bd2 = c[k].d2;
+            bid = c[k].id;
+            bt = c[k].t;
+        }
+    t_out = bt;
+    return bid;
+}
+
+// True iff a disk != excl is hit with eps_self < t < |b - a| - eps_self on the
+// segment from a towards b.
+__device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl, float eps_self, Stack &stk) {
+    f3 dv = b - a;
+    float L = len(dv);
+    f3 d = (1.0f / L) * dv;
+    f3 inv = safe_inv(d);
+    float t_hi = L - eps_self;
+    if (!(t_hi > eps_self)) return false;
+    int ref = S.root;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4 *nd = S.node + 4 * (size_t)ref;
+            float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
+            float n0, n1;
+            bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, a, inv, eps_self, t_hi, n0);
+            bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, a, inv, eps_self, t_hi, n1);
+            int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
+            if (h0 && h1) {
+                bool f0 = n0 <= n1;
+                stk.put(sp++, f0 ? r1 : r0);
+                ref = f0 ? r0 : r1;
+                continue;
+            }
+            if (h0) { ref = r0; continue; }
+            if (h1) { ref = r1; continue; }
+        } else {
+            int v = -1 - ref;
+            int first = v >> 3, cnt = (v & 7) + 1;
+            for (int i = 0; i < cnt; ++i) {
+                float4 dp = S.disk[2 * (first + i)];
+                float4 dn = S.disk[2 * (first + i) + 1];
+                if (__float_as_int(dp.w) == excl) continue;
+                float t, d2;
+                if (disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2) && t > eps_self && t < t_hi) return true;
+            }
+        }
+        if (sp == 0) break;
+        ref = stk.get(--sp);
+    }
+    return false;
+}
+
+// ------------------------------------------------------------- field
+struct c32 {
+    float re, im;
+};
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ c32 cdiv(c32 a, c32 b) {
+    // scale by the larger component to keep |b|^2 in range (metals give |eta| ~ 1e8)
+    float s = fmaxf(fabsf(b.re), fabsf(b.im));
+    float inv_s = 1.0f / s;
+    c32 bs = {b.re * inv_s, b.im * inv_s};
+    c32 as = {a.re * inv_s, a.im * inv_s};
+    float den = bs.re * bs.re + bs.im * bs.im;
+    return {(as.re * bs.re + as.im * bs.im) / den, (as.im * bs.re - as.re * bs.im) / den};
+}
+__device__ __forceinline__ c32 csqrt_p(c32 z) {  // principal branch
+    float r = hypotf(z.re, z.im);
+    if (r == 0.f) return {0.f, 0.f};
+    if (z.re >= 0.f) {
+        float re = sqrtf(0.5f * (r + z.re));
+        return {re, z.im / (2.f * re)};
+    }
+    float im = copysignf(sqrtf(0.5f * (r - z.re)), z.im);
+    return {z.im / (2.f * im), im};
+}
+
+// Fresnel coefficients for eta = eps_r - j sigma/(omega eps0) at incidence
+// cosine c: w = sqrt(eta - (1 - c^2)), TE = (c - w)/(c + w),
+// TM = (eta c - w)/(eta c + w).
+__device__ __forceinline__ void fresnel(float eps_r, float sig_w /* sigma/(omega eps0) */, float c, c32 &te,
+                                        c32 &tm) {
+    c32 eta = {eps_r, -sig_w};
+    float s2 = 1.0f - c * c;
+    c32 w = csqrt_p({eta.re - s2, eta.im});
+    te = cdiv({c - w.re, -w.im}, {c + w.re, w.im});
+    c32 ec = {eta.re * c, eta.im * c};
+    tm = cdiv({ec.re - w.re, ec.im - w.im}, {ec.re + w.re, ec.im + w.im});
+}
+
+// Derivatives of the coefficients with respect to eta:
+// dTE/deta = -c / (w (c + w)^2), dTM/deta = c (eta - 2 s^2) / (w (eta c + w)^2).
+__device__ __forceinline__ void fresnel_deta(float eps_r, float sig_w, float c, c32 &dte, c32 &dtm) {
+    c32 eta = {eps_r, -sig_w};
+    float s2 = 1.0f - c * c;
+    c32 w = csqrt_p({eta.re - s2, eta.im});
+    c32 cw = {c + w.re, w.im};
+    c32 den = cmul(w, cmul(cw, cw));
+    dte = cdiv({-c, 0.f}, den);
+    c32 ecw = {eta.re * c + w.re, eta.im * c + w.im};
+    c32 den2 = cmul(w, cmul(ecw, ecw));
+    dtm = cdiv({c * (eta.re - 2.f * s2), c * eta.im}, den2);
+}
+
+// e^{-j 2 pi L / lambda} with the cycle count L/lambda reduced exactly:
+// (hi + lo) = 1/lambda split in two floats, Dekker product, then the
+// fractional part, so the phase error is that of L alone.
+__device__ __forceinline__ c32 propagate(float L, float inv_lam_hi, float inv_lam_lo) {
+    float p = L * inv_lam_hi;
+    float e = fmaf(L, inv_lam_hi, -p) + L * inv_lam_lo;
+    float f = (p - rintf(p)) + e;
+    float s, c;
+    sincospif(2.0f * f, &s, &c);
+    return {c, -s};
+}
+
+struct FieldConst {
+    float amp_iso;      // lambda / (4 pi)
+    float inv_lam_hi;   // 1/lambda, high part
+    float inv_lam_lo;   // 1/lambda, low part
+    float inv_we0;      // 1 / (omega eps0)
+};
+
+__device__ __forceinline__ float warp_sum_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ uint32_t warp_sum_u(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Item of a flattened ray slot (items sorted by ray_off).
+__device__ __forceinline__ int find_item(const Item *items, int n_items, uint32_t g) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].ray_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Fibonacci-sphere launch direction of ray j out of N, FP64 then rounded to FP32.
+__device__ __forceinline__ f3 fib_dir(uint32_t j, uint32_t N) {
+#pragma clang fp contract(off)
+    const double g = (3.0 - 2.2360679774997896964) * 0.5;  // (3 - sqrt 5)/2
+    double z = 1.0 - (2.0 * (double)j + 1.0) / (double)N;
+    double rho = sqrt(fmax(0.0, 1.0 - z * z));
+    double f = (double)j * g;
+    f -= floor(f);
+    double phi = 2.0 * kPi * f;
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    return {(float)(rho * cp), (float)(rho * sp), (float)z};
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {  // splitmix64 finaliser
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+}  // namespace pcrt

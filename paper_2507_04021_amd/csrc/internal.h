@@ -1,0 +1,118 @@
+// Host-side declarations shared by the translation units of libpcrt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstddef>
+
+#include "common.h"
+
+namespace pcrt {
+
+// Persistent launches: fixed grids whose waves pull work from an atomic counter.
+constexpr uint32_t kTraceBlocks = 4096;  // 64-lane blocks
+constexpr uint32_t kWideBlocks = 1024;   // 256-lane blocks
+constexpr uint32_t kSpillLanes = 262144; // >= lanes of any persistent launch
+
+struct Bump {  // 256-byte aligned offsets inside one workspace
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+struct SceneLayout {
+    size_t pos_id, nrm_id, disk, node, spill, stat, bounds, blk_bounds;
+    size_t code0, code1, idx0, idx1, hist, child, range, parent_int, parent_leaf, dbox, ibox, flags;
+    size_t total;
+};
+
+SceneLayout scene_layout(uint32_t n);
+hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
+                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+void fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+
+// Per-(ray, interaction) records, dense [T * K].
+struct RecBufs {
+    int *id;          // hit disk id, -1 = none
+    float4 *xl;       // hit point, unfolded length from TX
+    float *cs;        // incidence cosine, sign = orientation of the hit normal (n_k = sign * n)
+    float4 *coef;     // diffuse coefficient (TE re, im, TM re, im), incl. lambda/4pi and the chain before
+    uint32_t *slot;   // key-table slot of the prefix key
+};
+
+struct HashBufs {
+    unsigned long long *key;  // 0 = empty
+    uint32_t *rep;            // smallest ray id with this key
+    uint32_t cap;             // slots per item (power of two)
+};
+
+struct SpecBufs {  // specular results per (key, RX) pair, RECORD mode only
+    uint8_t *valid;
+    float *len;
+    float4 *amp;
+    int *hit;     // [pairs * K]
+    float *cs;    // [pairs * K]
+};
+
+struct SolveDims {
+    uint32_t T;        // flattened ray slots (items padded to kRayChunk)
+    uint32_t K;
+    uint32_t n_rx;
+    uint32_t n_items;
+    uint32_t max_keys;
+    uint32_t max_key_chunks;
+    uint32_t n_ray_chunks;
+};
+
+struct SolveLayout {
+    size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
+        key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill;
+    size_t total;
+};
+
+SolveLayout solve_layout(const SolveDims &D, uint32_t flags);
+
+struct LaunchArgs {
+    DevScene S;
+    const Item *items;
+    const uint32_t *subset;
+    const float *rx;
+    const float *mats;  // [n_labels][3]
+    uint32_t n_labels;
+    uint32_t n_surf1;   // surface labels + 1 (key radix)
+    uint32_t flags;
+    Thr thr;
+    FieldConst fc;
+    SolveDims D;
+    RecBufs rb;
+    HashBufs hb;
+    SpecBufs sb;
+    uint32_t *work;     // [8] atomic work counters
+    uint64_t *counters; // [16]
+    uint32_t *scan;
+    uint32_t *scan_blk;
+    uint32_t *keylist;
+    uint32_t *key_off;   // [n_items + 1]
+    uint32_t *chunk_off; // [n_items + 1]
+    double *spec_part;
+    double *diff_part;
+    double *los_part;
+    uint8_t *dvis;
+};
+
+void launch_trace(const LaunchArgs &A, hipStream_t s);
+void launch_specular(const LaunchArgs &A, hipStream_t s);
+void launch_diffuse(const LaunchArgs &A, hipStream_t s);
+void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
+                            hipStream_t s);
+void launch_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, hipStream_t s);
+void launch_paths_copy(const LaunchArgs &A, uint32_t cap, uint32_t *key_ray, uint8_t *key_len, int32_t *key_seq,
+                       uint8_t *valid, float *length, float *amp, int32_t *hit, hipStream_t s);
+
+}  // namespace pcrt

@@ -1,0 +1,139 @@
+// Ray launch and the constant-count bounce loop (Sec. II-B): every ray keeps
+// bouncing specularly for up to K interactions; each interaction is recorded,
+// its specular prefix key (surface-label sequence, Sec. II-B.4) is inserted
+// into a per-transmitter hash set, and -- for diffuse scattering -- the
+// Fresnel-weighted coefficient of the chain up to this point is stored.
+//
+// Persistent grid of one-wave blocks; each wave takes 64 consecutive ray
+// slots from an atomic counter until the rays run out.
+#include "common.h"
+#include "internal.h"
+
+namespace pcrt {
+
+__device__ __forceinline__ uint32_t key_insert(const HashBufs &hb, uint32_t base, uint64_t enc, uint32_t j,
+                                               uint64_t *status) {
+    const uint32_t mask = hb.cap - 1;
+    uint32_t slot = (uint32_t)mix64(enc) & mask;
+    for (uint32_t probe = 0; probe < hb.cap; ++probe) {
+        unsigned long long *kp = hb.key + base + slot;
+        unsigned long long cur = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0ull) cur = atomicCAS(kp, 0ull, (unsigned long long)enc);
+        if (cur == 0ull || cur == enc) {
+            uint32_t *rp = hb.rep + base + slot;
+            if (__hip_atomic_load(rp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > j) atomicMin(rp, j);
+            return slot;
+        }
+        slot = (slot + 1) & mask;
+    }
+    atomicOr((unsigned long long *)status, 1ull);
+    return 0xffffffffu;
+}
+
+__global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
+    __shared__ int lds_stack[kStackLds * kWave];
+    const int lane = threadIdx.x;
+    const uint32_t glane = blockIdx.x * kWave + lane;
+    Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
+    const uint32_t K = A.D.K, T = A.D.T;
+    const uint32_t n_units = (T + kWave - 1) / kWave;
+    const bool want_diff = A.flags & 4, want_spec = A.flags & 2;
+    uint32_t n_int = 0, n_ray = 0, n_spill = 0;
+    for (;;) {
+        uint32_t unit = 0;
+        if (lane == 0) unit = atomicAdd(&A.work[0], 1u);
+        unit = __shfl(unit, 0, kWave);
+        if (unit >= n_units) break;
+        const uint32_t g = unit * kWave + lane;
+        if (g >= T) continue;
+        const int it = find_item(A.items, A.D.n_items, g);
+        const Item I = A.items[it];
+        const uint32_t local = g - I.ray_off;
+        const size_t rb = (size_t)g * K;
+        if (local >= I.n_rays) {
+            for (uint32_t k = 0; k < K; ++k) A.rb.id[rb + k] = -1;
+            continue;
+        }
+        const uint32_t j = A.subset ? A.subset[local] : local;
+        f3 d = normalize(fib_dir(j, I.budget));
+        f3 o = mk(I.tx[0], I.tx[1], I.tx[2]);
+        float L = 0.f;
+        int excl = -1;
+        c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
+        uint64_t enc = 0;
+        uint32_t k = 0;
+        for (; k < K; ++k) {
+            float t;
+            bool sp;
+            int h = closest_hit(A.S, o, d, excl, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
+            n_spill += sp;
+            if (h < 0) break;
+            const float4 pn = A.S.nrm[h];
+            f3 n = xyz(pn);
+            float dn = dot(d, n);
+            float sgn = dn > 0.f ? -1.f : 1.f;
+            float cosi = fabsf(dn);
+            f3 q = o + t * d;
+            L += t;
+            A.rb.id[rb + k] = h;
+            A.rb.xl[rb + k] = make_float4(q.x, q.y, q.z, L);
+            A.rb.cs[rb + k] = sgn * cosi;
+            if (want_diff) {
+                uint32_t lab = __float_as_uint(pn.w);
+                if (lab >= A.n_labels) {
+                    atomicOr((unsigned long long *)&A.counters[6], 2ull);
+                    lab = 0;
+                }
+                float er = A.mats[3 * lab], sg = A.mats[3 * lab + 1], sc = A.mats[3 * lab + 2];
+                c32 te, tm;
+                fresnel(er, sg * A.fc.inv_we0, cosi, te, tm);
+                c32 cte = cmul(pte, te), ctm = cmul(ptm, tm);
+                float w = A.fc.amp_iso * sc;
+                A.rb.coef[rb + k] = make_float4(w * cte.re, w * cte.im, w * ctm.re, w * ctm.im);
+                float R = sqrtf(fmaxf(0.f, 1.f - sc * sc));
+                pte = {R * cte.re, R * cte.im};
+                ptm = {R * ctm.re, R * ctm.im};
+            }
+            if (want_spec) {
+                uint32_t su = __float_as_uint(A.S.pos[h].w);
+                enc = enc * (uint64_t)A.n_surf1 + (uint64_t)(su + 1);
+                A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
+            }
+            d = normalize(d - (2.f * dn) * n);
+            o = q;
+            excl = h;
+        }
+        for (uint32_t kk = k; kk < K; ++kk) A.rb.id[rb + kk] = -1;
+        n_int += k;
+        n_ray += 1;
+    }
+    n_int = warp_sum_u(n_int);
+    n_ray = warp_sum_u(n_ray);
+    n_spill = warp_sum_u(n_spill);
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&A.counters[0], (unsigned long long)n_int);
+        atomicAdd((unsigned long long *)&A.counters[1], (unsigned long long)n_ray);
+        atomicAdd((unsigned long long *)&A.counters[8], (unsigned long long)n_spill);
+    }
+}
+
+void launch_trace(const LaunchArgs &A, hipStream_t s) {
+    uint32_t units = (A.D.T + kWave - 1) / kWave;
+    uint32_t grid = std::min<uint32_t>(kTraceBlocks, std::max<uint32_t>(units, 1));
+    hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kWave), 0, s, A);
+}
+
+__global__ void k_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    f3 d = fib_dir(ids ? ids[i] : i, n_budget);
+    out[3 * i] = d.x;
+    out[3 * i + 1] = d.y;
+    out[3 * i + 2] = d.z;
+}
+
+void launch_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_raygen, dim3((n + 255) / 256), dim3(256), 0, s, n_budget, ids, n, out);
+}
+
+}  // namespace pcrt
