@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the point-cloud radio ray tracer on one MI355X.
+
+Step = one full scene solve of the paper-scale synthetic office: ~1M noisy
+points, 2^20 Fibonacci rays from one transmitter, up to 5 interactions,
+64 receivers, 28 GHz, line of sight + specular + diffuse. Inputs (scene,
+hierarchy, receivers, materials) are resident on the GPU before the timed
+region; the hierarchy build is reported separately.
+
+Prints one JSON line (metric, value = rays*interactions/s, ms_per_step, the
+dominant kernel's roofline, the oracle's CPU baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays·interactions/s and ms per scene solve (1M pts, 5 bounces); grad-step ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def office_inputs():
+    from paper_2507_04021_amd import scenes
+    sc = scenes.office(seed=2507)
+    return sc, scenes.office_rx(), np.asarray(scenes.OFFICE_TX, np.float32), scenes.OFFICE_MATERIALS
+
+
+def algorithmic_bytes(cnt, K, n_rx, stage):
+    """Bytes the method must move for one launch of a stage's kernel.
+
+    Traversal: 64 B per binary node visited + 32 B per disk tested (counted
+    by the instrumented build). Streams: the trace kernel writes a 48 B record
+    per interaction; the diffuse kernel reads that record (40 B) plus the
+    hit normal (16 B) once per (interaction, receiver group of 64 lanes) and
+    writes 40 B of FP64 partial sums per (ray chunk, receiver).
+    """
+    if stage == "trace":
+        return cnt["trace_nodes"] * 64 + cnt["trace_disks"] * 32 + cnt["interactions"] * 48
+    if stage == "diffuse":
+        groups = max(1, (n_rx + 63) // 64)
+        chunks = (cnt["rays"] + 127) // 128
+        return (cnt["diffuse_nodes"] * 64 + cnt["diffuse_disks"] * 32 + cnt["interactions"] * 56 * groups
+                + chunks * n_rx * 40)
+    if stage == "refine":
+        return cnt["refine_nodes"] * 64 + cnt["refine_disks"] * 32
+    return 0
+
+
+def cpu_baseline(sc, rx, tx, mats, n_budget, K, n_sample):
+    import oracle
+    from paper_2507_04021_amd import scenes
+    oracle.build(force=False)
+    ids = scenes.stratified_ray_ids(n_budget, n_sample)
+    t0 = time.perf_counter()
+    sol = oracle.solve(sc, mats, tx, rx, 28e9, n_budget, ray_ids=ids, K=K, flags=7)
+    dt = time.perf_counter() - t0
+    inter = int((sol.seq >= 0).sum())
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=inter / dt, unit="rays·interactions/s", cores=cores, kind="oracle",
+                sample="%d stratified rays of 2^20 (all 64 RX, LOS+specular+diffuse, K=%d): %d interactions "
+                       "in %.1f s" % (n_sample, K, inter, dt), wall_s=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--rays", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (rays would shard by "
+              "strided ranges with one all-reduce of per-receiver sums; not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_04021_amd as P
+
+    K, freq = 5, 28e9
+    flags = P.LOS | P.SPECULAR | P.DIFFUSE
+    sc, rx, tx, mats = office_inputs()
+    log("office scene: %d points, %d surfaces" % (sc.n, sc.n_surfaces))
+    dev = torch.device("cuda")
+    scene = P.Scene.from_scene(sc, leaf_size=args.leaf)
+    torch.cuda.synchronize()
+    log("hierarchy:", scene.info)
+    mats_t = P.materials_tensor(mats, dev)
+    rx_t = torch.as_tensor(rx, device=dev)
+    res = P.solve(scene, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags)
+    ws = res.ws
+    out = dict(gain=res.gain, h_te=res.h_te, h_tm=res.h_tm, parts=res.parts, seq=None, counters=res.counters)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        P.solve(scene, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags, ws=ws, out=out)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    stage_sum = {k: 0.0 for k in P.STAGES}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P.solve(scene, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags | P.TIMING, ws=ws, out=out)
+        st = P.stage_times()  # waits for this step's last event
+        for k, v in st.items():
+            stage_sum[k] += v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    cnt = {k: int(out["counters"][i].item()) for k, i in P.CNT.items()}
+    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    log("stages ms:", {k: round(v, 3) for k, v in stage_ms.items()})
+    log("counters:", cnt)
+    value = cnt["interactions"] / (ms / 1e3)
+
+    # algorithmic bytes from one instrumented solve (same inputs, same results)
+    P.use_counting(True)
+    scene_c = P.Scene.from_scene(sc, leaf_size=args.leaf)
+    rc = P.solve(scene_c, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags)
+    torch.cuda.synchronize()
+    ccnt = {k: int(rc.counters[i].item()) for k, i in P.CNT.items()}
+    P.use_counting(False)
+    del scene_c, rc
+    dom = max(("trace", "refine", "diffuse"), key=lambda k: stage_ms[k])
+    nbytes = algorithmic_bytes(ccnt, K, len(rx), dom)
+    achieved = nbytes / (stage_ms[dom] / 1e3) / 1e9
+    log("visit counters:", {k: ccnt[k] for k in ccnt if "nodes" in k or "disks" in k})
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rays·interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "office 12x8x3 m, 20 boxes, %d noisy points (5 mm, 3 deg), 8 materials, 1 TX, 64 RX, "
+                        "%d rays, K=5, 28 GHz, LOS+specular+diffuse" % (sc.n, args.rays),
+            "leaf_size": args.leaf,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": {"trace": "k_trace", "refine": "k_refine", "diffuse": "k_diffuse"}[dom],
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": nbytes,
+            "launch_ms": stage_ms[dom],
+        },
+        "stage_ms": stage_ms,
+        "bvh_build_ms": scene.info["build_ms"],
+        "counts": {k: cnt[k] for k in ("rays", "interactions", "segments", "keys", "candidates", "specular",
+                                       "diffuse", "tie_spill", "status")},
+        "shadow_segments_per_s": cnt["segments"] / (ms / 1e3),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) on %d rays..." % args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(sc, rx, tx, mats, args.rays, K, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

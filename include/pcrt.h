@@ -123,7 +123,8 @@ enum {
     PCRT_LOS = 1,      /* line of sight */
     PCRT_SPECULAR = 2, /* specular paths (keys, refinement, validation) */
     PCRT_DIFFUSE = 4,  /* diffuse scattering as the last interaction */
-    PCRT_RECORD = 8    /* keep the per-path tape in the workspace (for the gradient and path output) */
+    PCRT_RECORD = 8,   /* keep the per-path tape in the workspace (for the gradient and path output) */
+    PCRT_TIMING = 16   /* record HIP events between stages (read with pcrt_stage_times) */
 };
 
 /* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
@@ -205,6 +206,13 @@ pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p,
  * unoccluded (Sec. II-B.1). Device pointer; asynchronous. */
 pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws,
                                   uint8_t *vis, void *stream);
+
+/* Device time (ms) of the stages of the last PCRT_TIMING solve issued on
+ * this host thread: [0] initialisation, [1] ray launch + bounce loop,
+ * [2] key marking/compaction, [3] specular refine + validate + field,
+ * [4] diffuse connections, [5] line of sight + per-receiver combine.
+ * Synchronises with the end of that solve. ms: host double[n], n <= 6. */
+pcrt_status pcrt_stage_times(double *ms, uint32_t n);
 
 /* Launch directions on the Fibonacci sphere: z = 1 - (2j+1)/N, phi = 2 pi
  * frac(j (3 - sqrt5)/2), evaluated in FP64 and rounded to FP32.

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcrt_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-LOS, SPECULAR, DIFFUSE = 1, 2, 4
+LOS, SPECULAR, DIFFUSE, TRACE = 1, 2, 4, 8
 DEFAULT_THR = dict(eps_tie=1e-4, eps_self=1e-3, t_a_deg=1.0, t_d=0.01, kappa=10)
 C0 = 299792458.0
 
@@ -50,6 +50,11 @@ def _load():
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _radius(scene):
+    """The disk radius as the FP32 value both implementations read."""
+    return ctypes.c_double(float(np.float32(scene.radius)))
 
 
 def _f32(a, shape=None):
@@ -84,7 +89,7 @@ def nearest(scene, o, d, excl=None, t_lo=1e-3, t_hi=np.inf, eps_tie=1e-4):
     ot = np.empty(n, np.float64)
     oq = np.empty((n, 3), np.float64)
     rc = _load().orc_nearest_batch(ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal),
-                                   ctypes.c_double(scene.radius), ctypes.c_int64(n), _p(o), _p(d), _p(excl),
+                                   _radius(scene), ctypes.c_int64(n), _p(o), _p(d), _p(excl),
                                    ctypes.c_double(t_lo), ctypes.c_double(t_hi), ctypes.c_double(eps_tie),
                                    _p(oid), _p(ot), _p(oq))
     if rc:
@@ -99,7 +104,7 @@ def occluded(scene, a, b, excl=None, eps_self=1e-3):
     excl = np.full(n, -1, np.int64) if excl is None else np.ascontiguousarray(excl, np.int64)
     out = np.empty(n, np.uint8)
     rc = _load().orc_occluded_batch(ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal),
-                                    ctypes.c_double(scene.radius), ctypes.c_int64(n), _p(a), _p(b), _p(excl),
+                                    _radius(scene), ctypes.c_int64(n), _p(a), _p(b), _p(excl),
                                     ctypes.c_double(eps_self), _p(out))
     if rc:
         raise ValueError("oracle occluded: bad scene (%d)" % rc)
@@ -167,7 +172,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     jac = np.empty((n_rx, n_labels, 2), np.float64) if want_jac else None
     rc = _load().orc_solve(
         ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal), _p(scene.material), _p(scene.surface),
-        ctypes.c_double(scene.radius), ctypes.c_int32(n_labels), _p(eps_r), _p(sig), _p(sca),
+        _radius(scene), ctypes.c_int32(n_labels), _p(eps_r), _p(sig), _p(sca),
         _p(tx), ctypes.c_int32(n_rx), _p(rx), ctypes.c_double(freq), ctypes.c_int64(n_budget),
         ctypes.c_int64(nt), _p(ids), ctypes.c_int32(K), ctypes.c_int32(flags), _p(thr_arr),
         _p(seq), _p(rec), _p(dvis), ctypes.c_int64(cap), _p(keys), _p(klen), _p(krep), ctypes.byref(nk),
@@ -181,6 +186,14 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
                     sv[:n].astype(bool), sl[:n].copy(), amp, sh[:n].copy(), orx[:, 0].copy(), orx[:, 1].copy(),
                     orx[:, 2].copy(), orx[:, 3].copy(), orx[:, 4] + 1j * orx[:, 5], orx[:, 6] + 1j * orx[:, 7],
                     jac)
+
+
+def trace(scene, tx, n_budget, ray_ids=None, K=2, thr=None):
+    """Interaction sequences (int64[n, K]) and records (x, y, z, L, cos) only."""
+    n_labels = int(np.max(scene.material)) + 1
+    sol = solve(scene, np.ones((n_labels, 3)), tx, np.zeros((0, 3), np.float32), 1e9, n_budget, ray_ids=ray_ids,
+                K=K, flags=TRACE, thr=thr)
+    return sol.seq, sol.rec
 
 
 def wavelength(freq: float) -> float:

@@ -39,7 +39,7 @@
 #define ORC_PI 3.14159265358979323846
 #define ORC_KMAX 8
 
-enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4 };
+enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4, ORC_TRACE = 8 /* trace even without paths */ };
 
 typedef struct {
     int64_t n;
@@ -533,7 +533,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     trace_t *tr = (trace_t *)malloc(sizeof(trace_t) * (size_t)(n_trace > 0 ? n_trace : 1));
     float *dirs = (float *)malloc(sizeof(float) * 3 * (size_t)(n_trace > 0 ? n_trace : 1));
     orc_fib_dirs(n_budget, ray_ids, n_trace, dirs);
-    if (flags & (ORC_SPECULAR | ORC_DIFFUSE)) {
+    if (flags & (ORC_SPECULAR | ORC_DIFFUSE | ORC_TRACE)) {
 #pragma omp parallel for schedule(dynamic, 8)
         for (int64_t q = 0; q < n_trace; ++q) trace_ray(&s, tx, dirs + 3 * q, K, &th, &tr[q]);
     } else {

@@ -15,10 +15,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcrt.so")
+LIB_COUNT_PATH = os.path.join(_HERE, "libpcrt_count.so")  # measurement build with visit counters
 
-LOS, SPECULAR, DIFFUSE, RECORD = 1, 2, 4, 8
+LOS, SPECULAR, DIFFUSE, RECORD, TIMING = 1, 2, 4, 8, 16
+STAGES = ("init", "trace", "keys", "refine", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
-           tie_spill=8)
+           tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
+           diffuse_disks=14)
 KAPPA_NONE = 0xFFFFFFFF
 
 
@@ -61,16 +64,25 @@ class Outputs(ctypes.Structure):
 
 
 _lib = None
+_libs = {}
+_active = [None]
 
 
-def lib() -> ctypes.CDLL:
+def use_counting(on: bool):
+    """Route subsequent calls through the instrumented build (visit counters)."""
+    _active[0] = "count" if on else None
+
+
+def lib(variant=None) -> ctypes.CDLL:
     """The loaded libpcrt.so; raises if it has not been built."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError("libpcrt.so is not built (run paper_2507_04021_amd/build.py or "
-                              "__graft_entry__.build()); there is no fallback path")
-        L = ctypes.CDLL(LIB_PATH)
+    variant = variant or _active[0] or "prod"
+    if variant not in _libs:
+        path = LIB_COUNT_PATH if variant == "count" else LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError("%s is not built (run paper_2507_04021_amd/build.py or "
+                              "__graft_entry__.build()); there is no fallback path" % os.path.basename(path))
+        L = ctypes.CDLL(path)
         vp, u32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_size_t
         L.pcrt_last_error.restype = ctypes.c_char_p
         L.pcrt_version.restype = ctypes.c_char_p
@@ -85,13 +97,16 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(u32), vp]
         L.pcrt_diffuse_vis_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
         L.pcrt_raygen.argtypes = [u32, vp, u32, vp, vp]
-        _lib = L
-    return _lib
+        L.pcrt_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), u32]
+        _libs[variant] = L
+        if variant == "prod":
+            _lib = L
+    return _libs[variant]
 
 
-def _check(rc):
+def _check(rc, L=None):
     if rc != 0:
-        raise PcrtError(rc, lib().pcrt_last_error().decode())
+        raise PcrtError(rc, (L or lib()).pcrt_last_error().decode())
 
 
 def _torch():
@@ -137,6 +152,7 @@ class Scene:
         self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
         pts = Points(pos.data_ptr(), nrm.data_ptr(), mat.data_ptr(), surf.data_ptr(), n, radius)
         h = ctypes.c_void_p()
+        self._variant = _active[0] or "prod"
         _check(lib().pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), _ptr(self.ws), nbytes.value,
                                        _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -153,8 +169,8 @@ class Scene:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and _lib is not None:
-            _lib.pcrt_scene_destroy(h)
+        if h is not None and _libs:
+            lib(self._variant).pcrt_scene_destroy(h)
             self.handle = None
 
 
@@ -204,6 +220,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
           want_seq=False, stream=None, ws=None, out=None) -> SolveResult:
     """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor."""
     torch = _torch()
+    L = lib(scene._variant)
     dev = scene.device
     mats_t = mats if isinstance(mats, torch.Tensor) and mats.device.type == "cuda" else materials_tensor(mats, dev)
     rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
@@ -214,7 +231,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
                      else ray_subset, torch.int32, dev)
     p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr)
     nbytes = ctypes.c_size_t(0)
-    _check(lib().pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)))
+    _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     n_rx = rx_t.shape[0]
@@ -228,8 +245,8 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
                    counters=torch.empty(16, dtype=torch.int64, device=dev))
     o = Outputs(out["gain"].data_ptr(), out["h_te"].data_ptr(), out["h_tm"].data_ptr(), out["parts"].data_ptr(),
                 out["seq"].data_ptr() if out.get("seq") is not None else None, out["counters"].data_ptr())
-    _check(lib().pcrt_solve(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), _ptr(ws), ws.numel(),
-                            ctypes.byref(o), _stream(stream)))
+    _check(L.pcrt_solve(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), _ptr(ws), ws.numel(),
+                        ctypes.byref(o), _stream(stream)), L)
     return SolveResult(out["gain"], out["h_te"], out["h_tm"], out["parts"], out.get("seq"), out["counters"], ws, p,
                        scene, (mats_t, rx_t, sub_t))
 
@@ -237,11 +254,12 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
 def paths(res: SolveResult, stream=None):
     """Specular path list of a RECORD solve as numpy arrays."""
     torch = _torch()
+    L = lib(res.scene._variant)
     p = res.params
     K, n_rx = p.max_interactions, p.n_rx
     nk = ctypes.c_uint32(0)
-    _check(lib().pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), 0, None, None, None, None, None,
-                                 None, None, ctypes.byref(nk), _stream(stream)))
+    _check(L.pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), 0, None, None, None, None, None,
+                                 None, None, ctypes.byref(nk), _stream(stream)), L)
     n = max(nk.value, 1)
     dev = res.scene.device
     key_ray = torch.empty(n, dtype=torch.int32, device=dev)
@@ -251,9 +269,9 @@ def paths(res: SolveResult, stream=None):
     length = torch.empty(n, n_rx, dtype=torch.float32, device=dev)
     amp = torch.empty(n, n_rx, 4, dtype=torch.float32, device=dev)
     hit = torch.empty(n, n_rx, K, dtype=torch.int32, device=dev)
-    _check(lib().pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), nk.value, _ptr(key_ray),
+    _check(L.pcrt_paths_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), nk.value, _ptr(key_ray),
                                  _ptr(key_len), _ptr(key_seq), _ptr(valid), _ptr(length), _ptr(amp), _ptr(hit),
-                                 ctypes.byref(nk), _stream(stream)))
+                                 ctypes.byref(nk), _stream(stream)), L)
     m = nk.value
     a = amp[:m].cpu().numpy()
     return dict(n_keys=m, key_ray=key_ray[:m].cpu().numpy(), key_len=key_len[:m].cpu().numpy(),
@@ -264,11 +282,19 @@ def paths(res: SolveResult, stream=None):
 
 def diffuse_vis(res: SolveResult, stream=None):
     torch = _torch()
+    L = lib(res.scene._variant)
     p = res.params
     n_trace = p.n_subset if p.ray_subset else p.n_rays
     vis = torch.empty(n_trace, p.max_interactions, p.n_rx, dtype=torch.uint8, device=res.scene.device)
-    _check(lib().pcrt_diffuse_vis_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), _ptr(vis), _stream(stream)))
+    _check(L.pcrt_diffuse_vis_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), _ptr(vis), _stream(stream)), L)
     return vis
+
+
+def stage_times():
+    """Per-stage device ms of the last TIMING solve on this thread (synchronises)."""
+    arr = (ctypes.c_double * len(STAGES))()
+    _check(lib().pcrt_stage_times(arr, len(STAGES)))
+    return dict(zip(STAGES, list(arr)))
 
 
 def raygen(n_budget, ids=None, device="cuda", stream=None):

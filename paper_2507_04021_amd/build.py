@@ -12,6 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpcrt.so")
+# same sources with node-visit / disk-test counters compiled in (measurement only)
+LIB_COUNT = os.path.join(HERE, "libpcrt_count.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.cpp", "bvh.hip", "trace.hip", "specular.hip", "field.hip"]
 ARCH = "gfx950"
@@ -24,27 +26,38 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+def _compile(job) -> str:
+    src, variant = job
+    obj = os.path.join(BUILD, variant, os.path.splitext(src)[0] + ".o")
+    extra = ["-DPCRT_COUNT_VISITS=1"] if variant == "count" else []
+    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + extra
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, out):
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "--offload-arch=" + ARCH, "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    variants = ("prod", "count")
+    for v in variants:
+        os.makedirs(os.path.join(BUILD, v), exist_ok=True)
+    jobs = [(s, v) for v in variants for s in SOURCES]
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(_compile, jobs))
+    n = len(SOURCES)
+    _link(objs[:n], LIB)
+    _link(objs[n:], LIB_COUNT)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, LIB_COUNT)
     return LIB
 
 

@@ -24,6 +24,22 @@ namespace {
 
 thread_local std::string g_err;
 
+// Per-stage device timing of the last PCRT_TIMING solve on this thread:
+// events around init, trace, keys, refine, diffuse, LOS + combine.
+constexpr int kStages = 6;
+thread_local hipEvent_t g_ev[kStages + 1];
+thread_local bool g_ev_ok = false;
+thread_local bool g_ev_used[kStages];
+
+void stage_mark(bool on, int i, hipStream_t s) {
+    if (!on) return;
+    if (!g_ev_ok) {
+        for (auto &e : g_ev) hipEventCreate(&e);
+        g_ev_ok = true;
+    }
+    hipEventRecord(g_ev[i], s);
+}
+
 pcrt_status fail(pcrt_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -373,6 +389,9 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     LaunchArgs A = make_args(scene, mats, n_labels, p, P, w, out->counters);
+    const bool tm = p->flags & PCRT_TIMING;
+    for (int i = 0; i < kStages; ++i) g_ev_used[i] = tm;
+    stage_mark(tm, 0, s);
     // graph-safe initialisation: fill kernels, items passed by value
     fill_u32(A.work, 0, 8, s);
     fill_u64(A.counters, 0, PCRT_CNT_COUNT, s);
@@ -394,6 +413,7 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
         fill_u64((uint64_t *)A.hb.key, 0, (size_t)P.cap * P.D.n_items, s);
         fill_u32(A.hb.rep, 0xffffffffu, (size_t)P.cap * P.D.n_items, s);
     }
+    stage_mark(tm, 1, s);
     if (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) {
         launch_trace(A, s);
         if (out->ray_seq) {
@@ -401,9 +421,15 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
             hipLaunchKernelGGL(k_copy_seq, dim3((n + 255) / 256), dim3(256), 0, s, A.rb.id, n, out->ray_seq);
         }
     }
-    if (p->flags & PCRT_SPECULAR) launch_specular(A, s);
+    stage_mark(tm, 2, s);
+    if (p->flags & PCRT_SPECULAR) launch_keys(A, s);
+    stage_mark(tm, 3, s);
+    if (p->flags & PCRT_SPECULAR) launch_refine(A, s);
+    stage_mark(tm, 4, s);
     if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
+    stage_mark(tm, 5, s);
     launch_los_and_combine(A, out->gain, out->h_te, out->h_tm, out->gain_parts, s);
+    stage_mark(tm, 6, s);
     HIP_TRY(hipGetLastError());
     return ok();
 }
@@ -439,6 +465,18 @@ pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_para
     place_hash(P, p->flags);
     size_t bytes = (size_t)P.n_trace * P.D.K * P.D.n_rx;
     HIP_TRY(hipMemcpyAsync(vis, (const char *)ws + P.L.dvis, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return ok();
+}
+
+pcrt_status pcrt_stage_times(double *ms, uint32_t n) {
+    if (!ms) return fail(PCRT_EINVAL, "ms is NULL");
+    if (!g_ev_ok || !g_ev_used[0]) return fail(PCRT_EINVAL, "no PCRT_TIMING solve on this thread");
+    HIP_TRY(hipEventSynchronize(g_ev[kStages]));
+    for (uint32_t i = 0; i < n && i < (uint32_t)kStages; ++i) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, g_ev[i], g_ev[i + 1]));
+        ms[i] = t;
+    }
     return ok();
 }
 

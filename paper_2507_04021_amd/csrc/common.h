@@ -17,6 +17,16 @@ constexpr int kRayChunk = 128;    // rays per diffuse reduction chunk (item ray 
 constexpr int kKeyChunk = 64;     // specular keys per reduction chunk
 constexpr float kParallelEps = 1e-6f;  // |d.n| below this: ray parallel to a disk
 
+// Instrumented builds (-DPCRT_COUNT_VISITS=1) count node visits and disk tests
+// per kernel for the algorithmic-byte model; the product build compiles the
+// counting away.
+#ifndef PCRT_COUNT_VISITS
+#define PCRT_COUNT_VISITS 0
+#endif
+constexpr bool kCountVisits = PCRT_COUNT_VISITS != 0;
+constexpr int kNodeBytes = 64;   // one binary node: two child boxes + refs
+constexpr int kDiskBytes = 32;   // one leaf-ordered disk: centre, id, normal
+
 constexpr double kC0 = 299792458.0;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
@@ -74,6 +84,13 @@ struct Stack {
     int *lds;        // this lane's column base: lds[s * kWave]
     int *gl;         // this lane's spill column base: gl[(s - kStackLds) * lanes]
     uint32_t lanes;
+    uint32_t nv = 0, nd = 0;  // node visits, disk tests (instrumented builds only)
+    __device__ __forceinline__ void visit() {
+        if (kCountVisits) ++nv;
+    }
+    __device__ __forceinline__ void test(int n) {
+        if (kCountVisits) nd += n;
+    }
     __device__ __forceinline__ void put(int s, int v) {
         if (s < kStackLds) lds[s * kWave] = v;
         else gl[(size_t)(s - kStackLds) * lanes] = v;
@@ -176,6 +193,7 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
     int sp = 0;
     for (;;) {
         if (ref >= 0) {
+            stk.visit();
             const float4 *nd = S.node + 4 * (size_t)ref;
             float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
             float tc = kSecond ? t_win : tmin + eps_tie;
@@ -192,6 +210,7 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
             if (h0) { ref = r0; continue; }
             if (h1) { ref = r1; continue; }
         } else {
+            stk.test((((-1 - ref) & 7) + 1));
             visit_leaf<kSecond>(S, ref, o, d, excl, t_lo, eps_tie, tmin, c, spill, t_win, best_d2, best_id, best_t);
         }
         if (sp == 0) break;
@@ -243,6 +262,7 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     int sp = 0;
     for (;;) {
         if (ref >= 0) {
+            stk.visit();
             const float4 *nd = S.node + 4 * (size_t)ref;
             float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
             float n0, n1;
@@ -260,6 +280,7 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
         } else {
             int v = -1 - ref;
             int first = v >> 3, cnt = (v & 7) + 1;
+            stk.test(cnt);
             for (int i = 0; i < cnt; ++i) {
                 float4 dp = S.disk[2 * (first + i)];
                 float4 dn = S.disk[2 * (first + i) + 1];
@@ -352,6 +373,20 @@ __device__ __forceinline__ float warp_sum_f(float v) {
 __device__ __forceinline__ uint32_t warp_sum_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
+}
+
+// Instrumented builds: add this lane's visit counts to counters[slot], [slot+1].
+__device__ __forceinline__ void flush_visits(const Stack &stk, uint64_t *counters, int slot) {
+    if (!kCountVisits) return;
+    uint64_t v = stk.nv, d = stk.nd;
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_xor(v, o, kWave);
+        d += __shfl_xor(d, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd((unsigned long long *)&counters[slot], (unsigned long long)v);
+        atomicAdd((unsigned long long *)&counters[slot + 1], (unsigned long long)d);
+    }
 }
 
 // Item of a flattened ray slot (items sorted by ray_off).

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
             __syncthreads();
         }
     }
+    flush_visits(stk, A.counters, 13);
     n_seg = warp_sum_u(n_seg);
     n_vis = warp_sum_u(n_vis);
     if (lane == 0) {

@@ -107,7 +107,8 @@ struct LaunchArgs {
 };
 
 void launch_trace(const LaunchArgs &A, hipStream_t s);
-void launch_specular(const LaunchArgs &A, hipStream_t s);
+void launch_keys(const LaunchArgs &A, hipStream_t s);
+void launch_refine(const LaunchArgs &A, hipStream_t s);
 void launch_diffuse(const LaunchArgs &A, hipStream_t s);
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                             hipStream_t s);

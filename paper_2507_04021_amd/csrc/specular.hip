@@ -354,6 +354,7 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
             __syncthreads();
         }
     }
+    flush_visits(stk, A.counters, 11);
     n_cand = warp_sum_u(n_cand);
     n_valid = warp_sum_u(n_valid);
     if (lane == 0) {
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
     }
 }
 
-void launch_specular(const LaunchArgs &A, hipStream_t s) {
+void launch_keys(const LaunchArgs &A, hipStream_t s) {
     const uint32_t n_rec = A.D.T * A.D.K;
     const uint32_t blk = (n_rec + 255) / 256;
     hipLaunchKernelGGL(k_mark, dim3(blk), dim3(256), 0, s, A, n_rec);
@@ -373,6 +374,9 @@ void launch_specular(const LaunchArgs &A, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, A.scan, n_rec, A.scan_blk);
     hipLaunchKernelGGL(k_compact, dim3(blk), dim3(256), 0, s, A, n_rec, total);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, A, total);
+}
+
+void launch_refine(const LaunchArgs &A, hipStream_t s) {
     const uint32_t grid = std::min<uint32_t>(kWideBlocks, std::max<uint32_t>(A.D.max_key_chunks, 1));
     switch (A.D.K) {
 #define PCRT_REFINE_CASE(KK) \

@@ -107,6 +107,7 @@ __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
         n_int += k;
         n_ray += 1;
     }
+    flush_visits(stk, A.counters, 9);
     n_int = warp_sum_u(n_int);
     n_ray = warp_sum_u(n_ray);
     n_spill = warp_sum_u(n_spill);

@@ -1,0 +1,98 @@
+"""C ABI of libpcrt on the CPU: the library loads, exports every function that
+include/pcrt.h declares, and rejects bad arguments on the host before any
+device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2507_04021_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcrt.h")
+EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcrt_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libpcrt.so is not built; run __graft_entry__.build()")
+    return P.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("pcrt_scene_create", "pcrt_solve", "pcrt_solve_workspace_size", "pcrt_paths_copy",
+              "pcrt_raygen", "pcrt_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    if os.path.exists(P.LIB_COUNT_PATH):
+        Lc = P.lib("count")
+        assert not [n for n in declared_functions() if not hasattr(Lc, n)]
+
+
+def test_version(L):
+    assert b"gfx950" in L.pcrt_version()
+
+
+def test_scene_argument_errors(L):
+    nb = ctypes.c_size_t(0)
+    assert L.pcrt_scene_workspace_size(0, None, ctypes.byref(nb)) == EINVAL
+    assert b"n_points" in L.pcrt_last_error()
+    assert L.pcrt_scene_workspace_size(10, None, None) == EINVAL
+    assert L.pcrt_scene_workspace_size(1 << 28, None, ctypes.byref(nb)) == EUNSUPPORTED
+    assert L.pcrt_scene_workspace_size(1000, None, ctypes.byref(nb)) == 0 and nb.value > 1000 * 64
+    h = ctypes.c_void_p()
+    fake = 0x1000  # never dereferenced: argument checks run first
+    pts = P.Points(fake, fake, fake, fake, 10, 0.0)
+    assert L.pcrt_scene_create(ctypes.byref(pts), None, ctypes.c_void_p(fake), 1 << 20, None,
+                               ctypes.byref(h)) == EINVAL
+    assert b"disk_radius" in L.pcrt_last_error()
+    pts = P.Points(fake, None, fake, fake, 10, 0.1)
+    assert L.pcrt_scene_create(ctypes.byref(pts), None, ctypes.c_void_p(fake), 1 << 20, None,
+                               ctypes.byref(h)) == EINVAL
+    pts = P.Points(fake, fake, fake, fake, 0, 0.1)
+    assert L.pcrt_scene_create(ctypes.byref(pts), None, ctypes.c_void_p(fake), 1 << 20, None,
+                               ctypes.byref(h)) == EINVAL
+    pts = P.Points(fake, fake, fake, fake, 10, 0.1)
+    opts = P.BvhOpts(9, 0)
+    assert L.pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), ctypes.c_void_p(fake), 1 << 20, None,
+                               ctypes.byref(h)) == EUNSUPPORTED
+    opts = P.BvhOpts(4, 4)
+    assert L.pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), ctypes.c_void_p(fake), 1 << 20, None,
+                               ctypes.byref(h)) == EUNSUPPORTED
+    # workspace too small: the required size is in the message
+    assert L.pcrt_scene_create(ctypes.byref(pts), None, ctypes.c_void_p(fake), 16, None,
+                               ctypes.byref(h)) == ENOMEM
+    assert b"need" in L.pcrt_last_error()
+
+
+def test_solve_argument_errors(L):
+    p = P.SolveParams()
+    assert L.pcrt_solve(None, None, 0, ctypes.byref(p), None, 0, None, None) == EINVAL
+    nb = ctypes.c_size_t(0)
+    assert L.pcrt_solve_workspace_size(None, ctypes.byref(p), ctypes.byref(nb)) == EINVAL
+    assert L.pcrt_raygen(0, None, 10, None, None) == EINVAL
+    ms = (ctypes.c_double * 6)()
+    assert L.pcrt_stage_times(ms, 6) == EINVAL
+    assert L.pcrt_scene_get_info(None, None) == EINVAL
+    assert L.pcrt_last_error()  # an explanation is always set on failure
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    """No silent fallback: a missing build raises on use."""
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(P, "_libs", {})
+    with pytest.raises(ImportError):
+        P.lib()

@@ -1,0 +1,386 @@
+"""GPU library vs the CPU oracle, through the C ABI.
+
+Bars (stated with each test):
+  - integer/index work (launch directions, interaction sequences, keys,
+    validity, visibility): identical, or >= 99.9 % identical where FP32 vs
+    FP64 rim/tie decisions can legitimately flip a ray;
+  - per-receiver power gain: 1e-4 relative over matched paths, unmatched
+    path power <= 1e-3 of the total;
+  - coherent fields: 1e-4 relative at 3.5 GHz; at 28 GHz within the
+    path-length bound k0 * sum|a| * 4 um (FP32 geometry).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2507_04021_amd import scenes
+from refs import fresnel_bc, image_method_room
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299792458.0
+LOS, SPEC, DIFF, REC = 1, 2, 4, 8
+
+
+def step(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    import paper_2507_04021_amd as P
+    P.lib()  # raises if the library is not built: no fallback
+    return P
+
+
+def gpu_solve(P, sc_gpu, mats, tx, rx, freq, n, K, flags, ids=None, thr=None):
+    r = P.solve(sc_gpu, mats, tx, rx, freq, n, K=K, flags=flags, ray_subset=ids, want_seq=True, thr=thr)
+    return r
+
+
+def gpu_paths_by_key(P, res, scene):
+    """{(rx, key labels): (L, a_te, a_tm)} of valid GPU specular paths."""
+    pth = P.paths(res)
+    out = {}
+    for q in range(pth["n_keys"]):
+        k = int(pth["key_len"][q])
+        key = tuple(int(scene.surface[i]) for i in pth["key_seq"][q, :k])
+        for r in range(pth["valid"].shape[1]):
+            if pth["valid"][q, r]:
+                out[(r, key)] = (float(pth["length"][q, r]), complex(pth["amp_te"][q, r]),
+                                 complex(pth["amp_tm"][q, r]))
+    return out, pth
+
+
+def oracle_paths_by_key(sol, n_rx):
+    out = {}
+    for r in range(n_rx):
+        for key, v in sol.paths(r).items():
+            out[(r, key)] = v
+    return out
+
+
+def keys_of(sol):
+    return set(sol.keys)
+
+
+# ------------------------------------------------------------ launch directions
+@pytest.mark.parametrize("N", [1, 7, 1000, 65537])
+def test_raygen_identical(P, orc, N):
+    step("raygen N=%d" % N)
+    g = P.raygen(N).cpu().numpy()
+    o = orc.fib_dirs(N)
+    assert np.array_equal(g, o)
+
+
+def test_raygen_subset_at_full_budget(P, orc):
+    N = 1 << 20
+    ids = scenes.stratified_ray_ids(N, 50000)
+    step("raygen subset of 2^20")
+    g = P.raygen(N, ids).cpu().numpy()
+    assert np.array_equal(g, orc.fib_dirs(N, ids))
+
+
+# ------------------------------------------------------------ small scenes
+@pytest.mark.parametrize("n_disks,seed,leaf", [(50, 1, 1), (300, 2, 4), (2000, 3, 8), (700, 4, 2)])
+def test_random_scene_full_parity(P, orc, n_disks, seed, leaf):
+    s = scenes.random_disks(n_disks, seed=seed, extent=1.5, radius=0.25 if n_disks < 1000 else 0.12)
+    mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2], [2.0, 0.01, 0.5]])
+    rx = np.array([[0.3, -0.2, 0.1], [-0.5, 0.4, -0.3], [1.0, 1.0, 1.0]], np.float32)
+    N, K = 3000, 4
+    step("random scene n=%d seed=%d leaf=%d" % (n_disks, seed, leaf))
+    sg = P.Scene.from_scene(s, leaf_size=leaf)
+    r = gpu_solve(P, sg, mats, [0, 0, 0], rx, 28e9, N, K, LOS | SPEC | DIFF | REC)
+    vis = P.diffuse_vis(r).cpu().numpy().astype(bool)
+    ref = orc.solve(s, mats, [0, 0, 0], rx, 28e9, N, K=K, flags=LOS | SPEC | DIFF, want_dvis=True)
+    seq = r.seq.cpu().numpy()
+    same = np.all(seq == ref.seq, 1)
+    assert same.mean() >= 0.999
+    # diffuse visibility on rays with identical sequences
+    assert (vis[same] == ref.dvis[same]).mean() >= 0.999
+    gp, _ = gpu_paths_by_key(P, r, s)
+    op = oracle_paths_by_key(ref, len(rx))
+    assert set(gp) == set(op)
+    k0 = 2 * math.pi * 28e9 / C0
+    for k, (L, te, tm) in op.items():
+        gl, gte, gtm = gp[k]
+        assert abs(gl - L) <= 2e-6 * L
+        # 1e-4 in magnitude plus the phase of a 4 um FP32 path-length error at 28 GHz
+        assert abs(gte - te) <= (1e-4 + k0 * 4e-6) * abs(te)
+        assert abs(gtm - tm) <= (1e-4 + k0 * 4e-6) * abs(tm)
+    parts = r.parts.cpu().numpy()
+    for c, ref_part in enumerate((ref.G_los, ref.G_spec, ref.G_diff)):
+        assert np.allclose(parts[:, c], ref_part, rtol=1e-4, atol=1e-30)
+    assert np.allclose(r.gain.cpu().numpy(), ref.G, rtol=1e-4)
+
+
+@pytest.mark.parametrize("n_rays,n_rx", [(1, 1), (129, 3), (1000, 65), (777, 300)])
+def test_ragged_sizes(P, orc, n_rays, n_rx):
+    """Ray counts off the 128-ray chunk, receiver counts off the 64/256-lane groups."""
+    s = scenes.random_disks(400, seed=9, extent=1.5, radius=0.25)
+    mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2], [2.0, 0.01, 0.5]])
+    rng = np.random.default_rng(n_rx)
+    rx = rng.uniform(-1.2, 1.2, size=(n_rx, 3)).astype(np.float32)
+    step("ragged rays=%d rx=%d" % (n_rays, n_rx))
+    sg = P.Scene.from_scene(s)
+    r = gpu_solve(P, sg, mats, [0.05, -0.02, 0.01], rx, 3.5e9, n_rays, 3, LOS | SPEC | DIFF)
+    ref = orc.solve(s, mats, [0.05, -0.02, 0.01], rx, 3.5e9, n_rays, K=3, flags=LOS | SPEC | DIFF)
+    assert np.mean(np.all(r.seq.cpu().numpy() == ref.seq, 1)) >= 0.999
+    assert np.allclose(r.gain.cpu().numpy(), ref.G, rtol=1e-4, atol=1e-30)
+
+
+def test_single_disk_scene(P, orc):
+    s = scenes.single_disk((0.0, 0.0, 0.0), (0, 0, 1), 2.0)
+    mats = np.array([[5.0, 0.1, 0.7]])
+    step("single disk")
+    sg = P.Scene.from_scene(s)
+    assert sg.info["n_nodes"] == 0
+    r = gpu_solve(P, sg, mats, [0, 0, 1], [[0.5, 0.2, 0.8], [0.0, 0.0, -1.0]], 3.5e9, 5000, 2, LOS | SPEC | DIFF)
+    ref = orc.solve(s, mats, [0, 0, 1], [[0.5, 0.2, 0.8], [0.0, 0.0, -1.0]], 3.5e9, 5000, K=2,
+                    flags=LOS | SPEC | DIFF)
+    assert np.array_equal(r.seq.cpu().numpy(), ref.seq)
+    assert np.allclose(r.gain.cpu().numpy(), ref.G, rtol=1e-4)
+    assert r.parts.cpu().numpy()[1, 0] == 0.0  # the disk blocks LOS to the receiver below it
+
+
+def test_all_rays_miss(P):
+    s = scenes.single_disk((0.0, 0.0, 0.0), (0, 0, 1), 0.1)
+    step("all rays miss")
+    sg = P.Scene.from_scene(s)
+    r = gpu_solve(P, sg, [[5.0, 0.1, 0.3]], [0, 0, -100.0], [[0, 0, -101.0]], 3.5e9, 64, 3, SPEC | DIFF)
+    seq = r.seq.cpu().numpy()
+    hits = (seq >= 0).sum()
+    assert hits <= 1  # only a ray aimed within 0.1 m at 100 m could hit
+    assert r.counter("keys") == hits
+
+
+# ------------------------------------------------------------ tiny box room
+@pytest.fixture(scope="module")
+def box(P):
+    s = scenes.box_room()
+    step("box room scene build")
+    return s, P.Scene.from_scene(s)
+
+
+def test_box_room_config1(P, orc, box):
+    """The tiny configuration: 43 200 disks, 10k rays, K=2, 3.5 GHz, LOS + specular."""
+    s, sg = box
+    mats = scenes.box_room_materials()
+    step("box room config 1")
+    r = gpu_solve(P, sg, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 10000, 2, LOS | SPEC | REC)
+    ref = orc.solve(s, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 10000, K=2, flags=LOS | SPEC)
+    assert np.mean(np.all(r.seq.cpu().numpy() == ref.seq, 1)) >= 0.999
+    gp, pth = gpu_paths_by_key(P, r, s)
+    gkeys = {tuple(int(s.surface[i]) for i in pth["key_seq"][q, :pth["key_len"][q]]) for q in range(pth["n_keys"])}
+    assert gkeys == keys_of(ref)
+    op = oracle_paths_by_key(ref, 1)
+    assert set(gp) == set(op) and len(op) == 24
+    for k, (L, te, tm) in op.items():
+        gl, gte, gtm = gp[k]
+        assert abs(gl - L) <= 1e-6 * L
+        assert abs(gte - te) <= 1e-4 * abs(te) and abs(gtm - tm) <= 1e-4 * abs(tm)
+    assert abs(r.gain.cpu().numpy()[0] / ref.G[0] - 1) < 1e-4
+    hte = r.h_te.cpu().numpy()[0]
+    assert abs(complex(*hte) - ref.h_te[0]) < 1e-4 * abs(ref.h_te[0])
+
+
+def test_box_room_image_method_on_gpu(P):
+    """Hole-free room: the GPU finds exactly the image-method paths."""
+    s = scenes.box_room(spacing=0.1, radius=0.0708)
+    mats = scenes.box_room_materials()
+    step("hole-free box room vs image method")
+    sg = P.Scene.from_scene(s)
+    r = gpu_solve(P, sg, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 20000, 2, LOS | SPEC | REC)
+    gp, _ = gpu_paths_by_key(P, r, s)
+    got = {k[1]: v for k, v in gp.items()}
+    ref = image_method_room(scenes.BOX_TX, scenes.BOX_RX, 2, mats, 3.5e9)
+    matched = set()
+    for cands, L, amps in ref:
+        hits = [c for c in cands if c in got]
+        assert len(hits) == 1
+        gl, gte, gtm = got[hits[0]]
+        ate, atm = amps[hits[0]]
+        assert abs(gl - L) < 1e-5 and abs(gte - ate) < 1e-4 * abs(ate) and abs(gtm - atm) < 1e-4 * abs(atm)
+        matched.add(hits[0])
+    assert matched == set(got)
+
+
+def test_permutation_invariance(P, box):
+    """Relabelling the points changes nothing except where two disks tie
+    exactly in (t window, squared centre distance): there the smaller index
+    wins, and a permutation may swap which disk that is. On the box room's
+    FP32 grid such exact ties occur (e.g. a ray through y = 1.0 between
+    centres 0.975 and 1.025), so the bar is >= 99.9 % of rays."""
+    s, sg = box
+    perm = np.random.default_rng(7).permutation(s.n)
+    mats = scenes.box_room_materials()
+    step("box room permuted")
+    sp = P.Scene.from_scene(s.permuted(perm))
+    a = gpu_solve(P, sg, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 10000, 3, SPEC)
+    b = gpu_solve(P, sp, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 10000, 3, SPEC)
+    sa, sb = a.seq.cpu().numpy(), b.seq.cpu().numpy()
+    remap = np.where(sb >= 0, perm[np.maximum(sb, 0)], -1)
+    assert np.mean(np.all(sa == remap, 1)) >= 0.999
+
+
+def test_leaf_size_and_determinism(P, box):
+    """Hierarchy shape never changes a result; repeated runs are bitwise equal."""
+    s, sg = box
+    mats = scenes.box_room_materials(scatter=0.3)
+    step("leaf sizes 1 and 8, repeated runs")
+    outs = []
+    for leaf in (1, 8):
+        g = P.Scene.from_scene(s, leaf_size=leaf)
+        for _ in range(2):
+            r = gpu_solve(P, g, mats, scenes.BOX_TX, [scenes.BOX_RX, [3, 2, 2]], 3.5e9, 8000, 3,
+                          LOS | SPEC | DIFF)
+            outs.append((r.seq.cpu().numpy(), r.gain.cpu().numpy(), r.h_te.cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+
+
+# ------------------------------------------------------------ error handling
+def test_errors_through_the_abi(P, box):
+    s, sg = box
+    step("error paths")
+    with pytest.raises(P.PcrtError) as e:
+        P.solve(sg, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 100, K=9)
+    assert e.value.code == -4
+    with pytest.raises(P.PcrtError) as e:
+        P.solve(sg, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 0.0, 100, K=2)
+    assert e.value.code == -1
+    # non-finite position and zero normal are rejected at scene creation
+    bad = scenes.box_room(spacing=0.5, radius=0.4)
+    bad.pos[3, 1] = np.nan
+    with pytest.raises(P.PcrtError) as e:
+        P.Scene.from_scene(bad)
+    assert e.value.code == -1
+    bad = scenes.box_room(spacing=0.5, radius=0.4)
+    bad.normal[5] = 0
+    with pytest.raises(P.PcrtError):
+        P.Scene.from_scene(bad)
+    # a material label beyond the table sets the status word
+    r = P.solve(sg, scenes.box_room_materials()[:2], scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 1000, K=2,
+                flags=DIFF)
+    assert r.counter("status") & 2
+    # too many surfaces for exact keys at this depth
+    many = scenes.random_disks(100, seed=1)
+    many.surface[:] = np.arange(100) * 40000
+    g = P.Scene.from_scene(many)
+    with pytest.raises(P.PcrtError) as e:
+        P.solve(g, [[3.0, 0.1, 0.0]] * 3, [0, 0, 0], [[1, 1, 1]], 3.5e9, 100, K=4, flags=SPEC)
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------ paper scale
+@pytest.fixture(scope="module")
+def office(P):
+    s = scenes.office(seed=2507)
+    step("office scene build (%d points)" % s.n)
+    return s, P.Scene.from_scene(s, leaf_size=4), scenes.office_rx()
+
+
+def test_office_full_solve_sampled_sequences(P, orc, office):
+    """Bench configuration (2^20 rays, K=5, 64 RX, all path types): the
+    interaction sequences of 4096 stratified rays match the oracle's."""
+    s, sg, rx = office
+    N = 1 << 20
+    step("office full solve with sequences")
+    r = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | SPEC | DIFF)
+    seq = r.seq.cpu().numpy()
+    ids = scenes.stratified_ray_ids(N, 4096)
+    step("oracle trace of 4096 rays")
+    oseq, _ = orc.trace(s, scenes.OFFICE_TX, N, ray_ids=ids, K=5)
+    same = np.all(seq[ids] == oseq, 1)
+    assert same.sum() >= 4096 - 4  # >= 99.9 %
+    assert r.counter("interactions") == int((seq >= 0).sum())
+
+
+def test_office_subset_full_parity(P, orc, office):
+    """16 stratified rays with every path type and 64 receivers: sequences,
+    diffuse visibility, specular keys and validity, per-receiver gains."""
+    s, sg, rx = office
+    N = 1 << 20
+    ids = scenes.stratified_ray_ids(N, 16)
+    step("office 16-ray subset, RECORD")
+    r = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | SPEC | DIFF | REC,
+                  ids=ids)
+    vis = P.diffuse_vis(r).cpu().numpy().astype(bool)
+    step("oracle 16-ray subset")
+    ref = orc.solve(s, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, ray_ids=ids, K=5,
+                    flags=LOS | SPEC | DIFF, want_dvis=True)
+    seq = r.seq.cpu().numpy()
+    assert np.array_equal(seq, ref.seq)
+    assert (vis == ref.dvis).mean() >= 0.999
+    gp, pth = gpu_paths_by_key(P, r, s)
+    op = oracle_paths_by_key(ref, len(rx))
+    assert len(op) > 5
+    agree = len(set(gp) & set(op)) / max(1, len(set(gp) | set(op)))
+    assert agree >= 0.999
+    parts = r.parts.cpu().numpy()
+    assert np.allclose(parts[:, 0], ref.G_los, rtol=1e-5)
+    assert np.allclose(parts[:, 2], ref.G_diff, rtol=1e-4, atol=1e-4 * ref.G_diff.max())
+    assert np.allclose(parts[:, 1], ref.G_spec, rtol=1e-4, atol=1e-4 * ref.G_spec.max())
+    # coherent field at 28 GHz: within k0 * dL * sum_p |a_p| (dL = 4 um of FP32
+    # path length), bounded via Cauchy-Schwarz by sqrt(n_paths * 2 G)
+    k0 = 2 * math.pi * 28e9 / C0
+    h = r.h_te.cpu().numpy()
+    gh = h[:, 0] + 1j * h[:, 1]
+    n_paths = ref.dvis.reshape(-1, len(rx)).sum(0) + ref.spec_valid.sum(0) + (ref.G_los > 0)
+    bound = k0 * 4e-6 * np.sqrt(n_paths * 2 * ref.G) + 1e-4 * np.abs(ref.h_te)
+    assert np.all(np.abs(gh - ref.h_te) <= bound)
+
+
+def test_office_full_solve_specular_paths_at_scale(P, orc, office):
+    """Full 2^20-ray solve: every valid specular path and a sample of rejected
+    keys are re-derived by the oracle from their representative rays."""
+    s, sg, rx = office
+    N = 1 << 20
+    step("office full solve, RECORD")
+    r = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | SPEC | REC)
+    gp, pth = gpu_paths_by_key(P, r, s)
+    valid_keys = np.where(pth["valid"].any(1))[0]
+    rng = np.random.default_rng(0)
+    others = rng.choice(np.where(~pth["valid"].any(1))[0], 24, replace=False)
+    reps = np.unique(pth["key_ray"][np.concatenate([valid_keys, others])].astype(np.int64))
+    step("oracle on %d representative rays" % reps.size)
+    ref = orc.solve(s, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, ray_ids=reps, K=5, flags=SPEC)
+    op = oracle_paths_by_key(ref, len(rx))
+    sel = {tuple(int(s.surface[i]) for i in pth["key_seq"][q, :pth["key_len"][q]]) for q in
+           np.concatenate([valid_keys, others])}
+    g_sel = {k for k in gp if k[1] in sel}
+    o_sel = {k for k in op if k[1] in sel}
+    assert len(g_sel) >= 20
+    assert len(g_sel ^ o_sel) <= max(1, len(g_sel) // 100)
+    for k in g_sel & o_sel:
+        assert abs(gp[k][0] - op[k][0]) <= 2e-6 * op[k][0]
+        assert abs(abs(gp[k][1]) - abs(op[k][1])) <= 1e-4 * abs(op[k][1])
+
+
+def test_office_full_size_properties(P, orc, office):
+    """At full size: bitwise repeatability, LOS against the closed form with
+    oracle occlusion, and additivity of the diffuse sum over a ray split."""
+    s, sg, rx = office
+    N = 1 << 20
+    step("office full solve x2 + two half-subsets")
+    a = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | DIFF)
+    b = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | DIFF)
+    assert np.array_equal(a.gain.cpu().numpy(), b.gain.cpu().numpy())
+    ids = np.arange(N)
+    h1 = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, DIFF, ids=ids[: N // 2])
+    h2 = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, DIFF, ids=ids[N // 2:])
+    d = a.parts.cpu().numpy()[:, 2]
+    assert np.allclose(h1.parts.cpu().numpy()[:, 2] + h2.parts.cpu().numpy()[:, 2], d, rtol=1e-12)
+    tx = np.float32(scenes.OFFICE_TX).astype(float)
+    occ = orc.occluded(s, np.tile(tx, (len(rx), 1)), rx.astype(float))
+    lam = C0 / 28e9
+    dist = np.linalg.norm(rx.astype(float) - tx, axis=1)
+    g_los = np.where(occ, 0.0, (lam / (4 * math.pi * dist)) ** 2)
+    assert np.allclose(a.parts.cpu().numpy()[:, 0], g_los, rtol=1e-5)
