@@ -130,7 +130,9 @@ enum {
 /* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
  * sphere directions; the diffuse ray-tube weight uses N). ray_subset
  * (optional device uint32[n_subset]): trace only these ray ids of the budget.
- * max_interactions K: 1..8. */
+ * max_interactions K: 1..8. key_capacity: keys whose per-receiver results a
+ * PCRT_RECORD solve keeps on its tape (0 = min(rays * K, 262144)); more keys
+ * set bit 2 of the status word and are left off the tape (not off the gain). */
 typedef struct {
     float tx[3];
     const float *rx;
@@ -142,6 +144,7 @@ typedef struct {
     const uint32_t *ray_subset;
     uint32_t n_subset;
     pcrt_thresholds thr;
+    uint32_t key_capacity;
 } pcrt_solve_params;
 
 /* Outputs (device pointers; NULL = not wanted unless marked required).
@@ -166,7 +169,7 @@ enum {
     PCRT_CNT_KEYS = 3,         /* unique specular keys */
     PCRT_CNT_SPECULAR = 4,     /* valid specular paths (over all receivers) */
     PCRT_CNT_DIFFUSE = 5,      /* visible diffuse connections */
-    PCRT_CNT_STATUS = 6,       /* bit 0: key table overflow; bit 1: invalid material label */
+    PCRT_CNT_STATUS = 6,       /* bit 0: key table overflow; bit 1: invalid material label; bit 2: tape key capacity exceeded */
     PCRT_CNT_CANDIDATES = 7,   /* (key, RX) pairs that passed the geometric refinement */
     PCRT_CNT_TIE_SPILL = 8,    /* nearest-hit queries that needed the exact second pass */
     PCRT_CNT_COUNT = 16
@@ -206,6 +209,57 @@ pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p,
  * unoccluded (Sec. II-B.1). Device pointer; asynchronous. */
 pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws,
                                   uint8_t *vis, void *stream);
+
+/* ------------------------------------------------------ differentiation */
+/* The tape of a PCRT_RECORD solve lives in its workspace. It holds the path
+ * geometry, which does not depend on the materials, as interaction slots:
+ * slots [0, n_trace_slots) are the traced interactions (ray slot g, bounce m
+ * at g*K + m), the rest are the interactions of the specular paths
+ * ((key q * n_rx + receiver r) * K + m). Per slot the tape has the material
+ * label (0xffff for an empty slot) and the incidence cosine, a coefficient
+ * row coef[8] = (Gamma_TE re, im, Gamma_TM re, im, S, 0, 0, 0) and an
+ * adjoint row adj[8] = dL/d of those five values.
+ *
+ * The calls below use the workspace and parameters of that solve, run
+ * asynchronously on stream and allocate nothing. Materials enter only
+ * through the coefficient rows, so a learned coefficient model may write them
+ * instead of pcrt_tape_fresnel. */
+typedef struct {
+    uint32_t n_slots;
+    uint32_t n_trace_slots;
+    uint32_t key_capacity;
+    const uint16_t *label; /* device [n_slots] */
+    const float *cos;      /* device [n_slots] */
+    float *coef;           /* device [n_slots][8] */
+    float *adj;            /* device [n_slots][8] */
+} pcrt_tape;
+
+/* Pointers into the workspace (host call, no device work). */
+pcrt_status pcrt_tape_get(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, pcrt_tape *out);
+
+/* coef rows from per-label materials (the Fresnel model of the solve).
+ * mats: device pcrt_material[n_labels]. */
+pcrt_status pcrt_tape_fresnel(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                              const pcrt_material *mats, uint32_t n_labels, void *stream);
+
+/* Per-receiver gain and fields from the coef rows: the solve's reduction on
+ * the recorded geometry (line of sight is taken from the solve). out as for
+ * pcrt_solve (gain required). */
+pcrt_status pcrt_tape_forward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                              const pcrt_outputs *out, void *stream);
+
+/* Adjoint rows for a loss L(G): dL_dgain device double[n_rx] (dL/dG_r).
+ * Each path's power 1/2 (|a_TE|^2 + |a_TM|^2) is differentiated with
+ * respect to every coefficient of its chain. */
+pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                               const double *dL_dgain, void *stream);
+
+/* dL/d(eps_r, sigma, S) per label from the adjoint rows and the Fresnel
+ * derivatives dGamma/deta (deta/deps_r = 1, deta/dsigma = -j/(omega eps0)).
+ * Fixed-order FP64 reduction. mats: device pcrt_material[n_labels],
+ * n_labels <= 64; dL_dmat: device double[n_labels][3]. */
+pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                               const pcrt_material *mats, uint32_t n_labels, double *dL_dmat, void *stream);
 
 /* Device time (ms) of the stages of the last PCRT_TIMING solve issued on
  * this host thread: [0] initialisation, [1] ray launch + bounce loop,

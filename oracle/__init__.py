@@ -128,7 +128,7 @@ class Solution:
     G: np.ndarray
     h_te: np.ndarray
     h_tm: np.ndarray
-    jac: np.ndarray | None   # float64[n_rx, n_labels, 2]
+    jac: np.ndarray | None   # float64[n_rx, n_labels, 3]: dG/d(eps_r, sigma, S)
 
     def paths(self, r: int):
         """{key: (length, a_TE, a_TM)} of the valid specular paths at receiver r."""
@@ -169,7 +169,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     sa = np.empty((cap, n_rx, 4), np.float64)
     sh = np.empty((cap, n_rx, K), np.int64)
     orx = np.empty((n_rx, 8), np.float64)
-    jac = np.empty((n_rx, n_labels, 2), np.float64) if want_jac else None
+    jac = np.empty((n_rx, n_labels, 3), np.float64) if want_jac else None
     rc = _load().orc_solve(
         ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal), _p(scene.material), _p(scene.surface),
         _radius(scene), ctypes.c_int32(n_labels), _p(eps_r), _p(sig), _p(sca),

@@ -231,7 +231,7 @@ void orc_fresnel(double eps_r, double sigma, double freq, int64_t n, const doubl
  * (eps_r, sigma) of each label. */
 static void path_field(const em_t *em, int k, const int *label, const double *cosv, const int *kind,
                        double amp0, double len, double complex *a_te, double complex *a_tm, double *g_acc,
-                       double *jac /* [n_labels][2] or NULL */)
+                       double *jac /* [n_labels][3] or NULL */)
 {
     double complex gte[ORC_KMAX], gtm[ORC_KMAX], dte[ORC_KMAX], dtm[ORC_KMAX];
     double fac[ORC_KMAX];
@@ -248,6 +248,8 @@ static void path_field(const em_t *em, int k, const int *label, const double *co
     *a_tm = amp0 * ptm * ph;
     *g_acc += 0.5 * (creal(*a_te * conj(*a_te)) + creal(*a_tm * conj(*a_tm)));
     if (!jac) return;
+    /* d/d(eps_r, sigma) through Gamma, and d/dS through the factor:
+     * d(R^2)/dS = -2S for a specular interaction, d(S^2)/dS = 2S for a diffuse one */
     const double complex deta[2] = {1.0, -I / (em->omega * ORC_EPS0)};
     for (int m = 0; m < k; ++m) {
         /* product of |f Gamma|^2 over every other interaction, per channel */
@@ -260,8 +262,12 @@ static void path_field(const em_t *em, int k, const int *label, const double *co
         for (int p = 0; p < 2; ++p) {
             double d_te = 2.0 * creal(conj(gte[m]) * dte[m] * deta[p]);
             double d_tm = 2.0 * creal(conj(gtm[m]) * dtm[m] * deta[p]);
-            jac[2 * label[m] + p] += 0.5 * fac[m] * fac[m] * (rest_te * d_te + rest_tm * d_tm);
+            jac[3 * label[m] + p] += 0.5 * fac[m] * fac[m] * (rest_te * d_te + rest_tm * d_tm);
         }
+        double S = em->scat[label[m]];
+        double dfac2 = kind[m] ? 2.0 * S : -2.0 * S;
+        jac[3 * label[m] + 2] += 0.5 * dfac2 *
+                                 (rest_te * creal(gte[m] * conj(gte[m])) + rest_tm * creal(gtm[m] * conj(gtm[m])));
     }
 }
 
@@ -483,7 +489,7 @@ static int key_cmp(const void *pa, const void *pb)
  *   spec_valid uint8[key_cap*n_rx], spec_len double[key_cap*n_rx],
  *   spec_amp double[key_cap*n_rx*4] (TE re, im, TM re, im), spec_hid int64[key_cap*n_rx*K]
  *   out_rx   double[n_rx*8]: G_los, G_spec, G_diff, G, h_TE re, im, h_TM re, im
- *   jac      double[n_rx*n_labels*2]: dG/d(eps_r, sigma) per label
+ *   jac      double[n_rx*n_labels*3]: dG/d(eps_r, sigma, S) per label
  * *n_keys receives the number of unique keys; returns -3 if key_cap is too small.
  */
 int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf,
@@ -513,7 +519,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     double *G_diff = calloc((size_t)n_rx, sizeof(double));
     double complex *h_te = calloc((size_t)n_rx, sizeof(double complex));
     double complex *h_tm = calloc((size_t)n_rx, sizeof(double complex));
-    if (jac) memset(jac, 0, sizeof(double) * (size_t)n_rx * (size_t)n_labels * 2);
+    if (jac) memset(jac, 0, sizeof(double) * (size_t)n_rx * (size_t)n_labels * 3);
 
     /* line of sight */
     if (flags & ORC_LOS) {
@@ -559,7 +565,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
         double complex *ate = calloc((size_t)nslot, sizeof(double complex));
         double complex *atm = calloc((size_t)nslot, sizeof(double complex));
         double *pw = calloc((size_t)nslot, sizeof(double));
-        double *jl = jac ? calloc((size_t)nslot * (size_t)n_labels * 2, sizeof(double)) : NULL;
+        double *jl = jac ? calloc((size_t)nslot * (size_t)n_labels * 3, sizeof(double)) : NULL;
         uint8_t *vis = calloc((size_t)nslot, 1);
 #pragma omp parallel for schedule(dynamic, 4)
         for (int64_t q = 0; q < n_trace; ++q) {
@@ -583,7 +589,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                     double amp0 = a_iso * sqrt(4.0 * cos_s / (double)n_budget) / rs;
                     vis[slot] = 1;
                     path_field(&em, k + 1, label, cs, kind, amp0, tr[q].L[k] + rs, &ate[slot], &atm[slot],
-                               &pw[slot], jl ? jl + slot * n_labels * 2 : NULL);
+                               &pw[slot], jl ? jl + slot * n_labels * 3 : NULL);
                 }
             }
         }
@@ -597,7 +603,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                     h_te[r] += ate[slot];
                     h_tm[r] += atm[slot];
                     if (jac)
-                        for (int l = 0; l < 2 * n_labels; ++l) jac[r * n_labels * 2 + l] += jl[slot * n_labels * 2 + l];
+                        for (int l = 0; l < 3 * n_labels; ++l) jac[r * n_labels * 3 + l] += jl[slot * n_labels * 3 + l];
                 }
         free(ate); free(atm); free(pw); free(jl); free(vis);
     } else if (dvis) {
@@ -661,7 +667,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                         }
                         double g = 0.0;
                         path_field(&em, uk[ki].len, label, p->cs, kind, a_iso / p->len, p->len, &ate, &atm, &g,
-                                   jac ? jac + (int64_t)r * n_labels * 2 : NULL);
+                                   jac ? jac + (int64_t)r * n_labels * 3 : NULL);
                         G_spec[r] += g;
                         h_te[r] += ate;
                         h_tm[r] += atm;

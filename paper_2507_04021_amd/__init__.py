@@ -55,7 +55,13 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_float * 3), ("rx", ctypes.c_void_p), ("n_rx", ctypes.c_uint32),
                 ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
-                ("thr", Thresholds)]
+                ("thr", Thresholds), ("key_capacity", ctypes.c_uint32)]
+
+
+class Tape(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_uint32), ("n_trace_slots", ctypes.c_uint32), ("key_capacity", ctypes.c_uint32),
+                ("label", ctypes.c_void_p), ("cos", ctypes.c_void_p), ("coef", ctypes.c_void_p),
+                ("adj", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):
@@ -98,6 +104,11 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_diffuse_vis_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
         L.pcrt_raygen.argtypes = [u32, vp, u32, vp, vp]
         L.pcrt_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), u32]
+        L.pcrt_tape_get.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Tape)]
+        L.pcrt_tape_fresnel.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, u32, vp]
+        L.pcrt_tape_forward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Outputs), vp]
+        L.pcrt_tape_backward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
+        L.pcrt_material_grad.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, u32, vp, vp]
         _libs[variant] = L
         if variant == "prod":
             _lib = L
@@ -177,6 +188,8 @@ class Scene:
 def materials_tensor(mats, device="cuda"):
     """float32[n_labels, 3] (eps_r, sigma, S) on the device."""
     torch = _torch()
+    if isinstance(mats, torch.Tensor):
+        return mats.detach().to(device=device, dtype=torch.float32).reshape(-1, 3).contiguous()
     return _dev(np.asarray(mats, np.float64).reshape(-1, 3), torch.float32, device)
 
 
@@ -197,7 +210,7 @@ class SolveResult:
         return int(self.counters[CNT[name]].item())
 
 
-def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None):
+def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0):
     th = Thresholds(0.0, 0.0, 0.0, 0.0, 0)
     if thr:
         for k, v in thr.items():
@@ -213,11 +226,12 @@ def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None):
     p.ray_subset = subset_t.data_ptr() if subset_t is not None else None
     p.n_subset = subset_t.numel() if subset_t is not None else 0
     p.thr = th
+    p.key_capacity = int(key_capacity)
     return p
 
 
 def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
-          want_seq=False, stream=None, ws=None, out=None) -> SolveResult:
+          want_seq=False, stream=None, ws=None, out=None, key_capacity=0) -> SolveResult:
     """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor."""
     torch = _torch()
     L = lib(scene._variant)
@@ -229,7 +243,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
     if ray_subset is not None:
         sub_t = _dev(np.asarray(ray_subset, np.int64).astype(np.int32) if not isinstance(ray_subset, torch.Tensor)
                      else ray_subset, torch.int32, dev)
-    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr)
+    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity)
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:
@@ -288,6 +302,71 @@ def diffuse_vis(res: SolveResult, stream=None):
     vis = torch.empty(n_trace, p.max_interactions, p.n_rx, dtype=torch.uint8, device=res.scene.device)
     _check(L.pcrt_diffuse_vis_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), _ptr(vis), _stream(stream)), L)
     return vis
+
+
+# ------------------------------------------------------------------ tape
+def tape(res: SolveResult):
+    """Device views of a RECORD solve's tape: dict of torch tensors (label,
+    cos, coef [n_slots, 8], adj [n_slots, 8]) and sizes."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    t = Tape()
+    _check(L.pcrt_tape_get(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), ctypes.byref(t)), L)
+    base = res.ws.data_ptr()
+    n = t.n_slots
+
+    def view(ptr, nbytes, dtype, shape):
+        off = ptr - base
+        return res.ws[off:off + nbytes].view(dtype).reshape(shape)
+
+    return dict(n_slots=n, n_trace_slots=t.n_trace_slots, key_capacity=t.key_capacity,
+                label=view(t.label, 2 * n, torch.int16, (n,)), cos=view(t.cos, 4 * n, torch.float32, (n,)),
+                coef=view(t.coef, 32 * n, torch.float32, (n, 8)), adj=view(t.adj, 32 * n, torch.float32, (n, 8)))
+
+
+def tape_fresnel(res: SolveResult, mats, stream=None):
+    """Fill the tape's coefficient rows from per-label materials (n_labels, 3)."""
+    L = lib(res.scene._variant)
+    m = materials_tensor(mats, res.scene.device)
+    _check(L.pcrt_tape_fresnel(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), _ptr(m), m.shape[0],
+                               _stream(stream)), L)
+    return m
+
+
+def tape_forward(res: SolveResult, stream=None):
+    """Per-receiver gain (float64 tensor) from the tape's coefficient rows."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    n = res.params.n_rx
+    dev = res.scene.device
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    h_te = torch.empty(n, 2, dtype=torch.float64, device=dev)
+    h_tm = torch.empty(n, 2, dtype=torch.float64, device=dev)
+    parts = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    o = Outputs(g.data_ptr(), h_te.data_ptr(), h_tm.data_ptr(), parts.data_ptr(), None, None)
+    _check(L.pcrt_tape_forward(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), ctypes.byref(o),
+                               _stream(stream)), L)
+    return g, h_te, h_tm, parts
+
+
+def tape_backward(res: SolveResult, dl_dg, stream=None):
+    """Adjoint rows of the tape for dL/dG (float64 [n_rx])."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    d = dl_dg.to(device=res.scene.device, dtype=torch.float64).contiguous()
+    _check(L.pcrt_tape_backward(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), _ptr(d),
+                                _stream(stream)), L)
+    return d
+
+
+def material_grad(res: SolveResult, mats_dev, stream=None):
+    """dL/d(eps_r, sigma, S) per label (float64 [n_labels, 3]) from the adjoint rows."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    out = torch.empty(mats_dev.shape[0], 3, dtype=torch.float64, device=res.scene.device)
+    _check(L.pcrt_material_grad(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), _ptr(mats_dev),
+                                mats_dev.shape[0], _ptr(out), _stream(stream)), L)
+    return out
 
 
 def stage_times():

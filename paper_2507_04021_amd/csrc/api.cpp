@@ -146,6 +146,14 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
     D.max_keys = (uint32_t)std::min<uint64_t>((uint64_t)D.T * K, (uint64_t)P.cap * D.n_items);
     D.max_key_chunks = (D.max_keys + kKeyChunk - 1) / kKeyChunk + D.n_items;
     D.n_ray_chunks = D.T / kRayChunk;
+    if (p->flags & PCRT_RECORD) {
+        uint32_t want = p->key_capacity ? p->key_capacity : 262144u;
+        D.rec_keys = (p->flags & PCRT_SPECULAR) ? std::min(D.max_keys, want) : 0;
+        D.n_slots = D.T * K + D.rec_keys * D.n_rx * K;
+        D.n_slot_chunks = (D.n_slots + kSlotChunk - 1) / kSlotChunk;
+    } else {
+        D.rec_keys = D.n_slots = D.n_slot_chunks = 0;
+    }
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
@@ -212,6 +220,13 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.diff_part = (double *)at(L.diff_part);
     A.los_part = (double *)at(L.los_part);
     A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
+    if (p->flags & PCRT_RECORD) {
+        A.slot_label = (uint16_t *)at(L.slot_label);
+        A.slot_cos = (float *)at(L.slot_cos);
+        A.slot_coef = (float *)at(L.slot_coef);
+        A.slot_adj = (float *)at(L.slot_adj);
+        A.grad_part = (double *)at(L.grad_part);
+    }
     return A;
 }
 
@@ -245,13 +260,20 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.keylist = b.take(sizeof(uint32_t) * D.max_keys);
         L.spec_part = b.take(sizeof(double) * 5 * (size_t)D.max_key_chunks * D.n_rx);
         if (rec) {
-            const size_t pairs = (size_t)D.max_keys * D.n_rx;
+            const size_t pairs = (size_t)D.rec_keys * D.n_rx;
             L.sp_valid = b.take(pairs);
             L.sp_len = b.take(sizeof(float) * pairs);
             L.sp_amp = b.take(sizeof(float4) * pairs);
             L.sp_hit = b.take(sizeof(int) * pairs * D.K);
             L.sp_cs = b.take(sizeof(float) * pairs * D.K);
         }
+    }
+    if (rec) {
+        L.slot_label = b.take(sizeof(uint16_t) * (size_t)D.n_slots);
+        L.slot_cos = b.take(sizeof(float) * (size_t)D.n_slots);
+        L.slot_coef = b.take(sizeof(float) * 8 * (size_t)D.n_slots);
+        L.slot_adj = b.take(sizeof(float) * 8 * (size_t)D.n_slots);
+        L.grad_part = b.take(sizeof(double) * 3 * kMaxGradLabels * (size_t)std::max<uint32_t>(D.n_slot_chunks, 1));
     }
     L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * kSpillLanes);
     L.total = b.off;
@@ -429,6 +451,7 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
     if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
     stage_mark(tm, 5, s);
     launch_los_and_combine(A, out->gain, out->h_te, out->h_tm, out->gain_parts, s);
+    if (p->flags & PCRT_RECORD) launch_tape_slots(A, s);
     stage_mark(tm, 6, s);
     HIP_TRY(hipGetLastError());
     return ok();
@@ -465,6 +488,83 @@ pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_para
     place_hash(P, p->flags);
     size_t bytes = (size_t)P.n_trace * P.D.K * P.D.n_rx;
     HIP_TRY(hipMemcpyAsync(vis, (const char *)ws + P.L.dvis, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return ok();
+}
+
+static pcrt_status tape_args(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, LaunchArgs *A,
+                             Plan *P) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    if (!(p->flags & PCRT_RECORD)) return fail(PCRT_EINVAL, "the tape needs a solve with PCRT_RECORD");
+    if (!ws) return fail(PCRT_EINVAL, "ws is required");
+    *P = make_plan(scene, p);
+    place_hash(*P, p->flags);
+    *A = make_args(scene, nullptr, 0, p, *P, (char *)ws, nullptr);
+    return PCRT_OK;
+}
+
+pcrt_status pcrt_tape_get(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, pcrt_tape *out) {
+    LaunchArgs A;
+    Plan P;
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!out) return fail(PCRT_EINVAL, "out is NULL");
+    out->n_slots = P.D.n_slots;
+    out->n_trace_slots = P.D.T * P.D.K;
+    out->key_capacity = P.D.rec_keys;
+    out->label = A.slot_label;
+    out->cos = A.slot_cos;
+    out->coef = A.slot_coef;
+    out->adj = A.slot_adj;
+    return ok();
+}
+
+pcrt_status pcrt_tape_fresnel(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                              const pcrt_material *mats, uint32_t n_labels, void *stream) {
+    LaunchArgs A;
+    Plan P;
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!mats || n_labels == 0) return fail(PCRT_EINVAL, "materials are required");
+    launch_tape_fresnel(A, (const float *)mats, n_labels, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_tape_forward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                              const pcrt_outputs *out, void *stream) {
+    LaunchArgs A;
+    Plan P;
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!out || !out->gain) return fail(PCRT_EINVAL, "out->gain is required");
+    launch_tape_forward(A, out->gain, out->h_te, out->h_tm, out->gain_parts, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                               const double *dL_dgain, void *stream) {
+    LaunchArgs A;
+    Plan P;
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!dL_dgain) return fail(PCRT_EINVAL, "dL_dgain is required");
+    launch_tape_backward(A, dL_dgain, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                               const pcrt_material *mats, uint32_t n_labels, double *dL_dmat, void *stream) {
+    LaunchArgs A;
+    Plan P;
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!mats || !dL_dmat || n_labels == 0) return fail(PCRT_EINVAL, "mats and dL_dmat are required");
+    if (n_labels > kMaxGradLabels) return fail(PCRT_EUNSUPPORTED, "at most %u labels", kMaxGradLabels);
+    launch_material_grad(A, (const float *)mats, n_labels, dL_dmat, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
     return ok();
 }
 

@@ -17,8 +17,13 @@ namespace pcrt {
 // dealt to the groups round robin. For 64 receivers a wavefront handles one
 // interaction point against all receivers (one origin, coherent traversal).
 __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
-    __shared__ int lds_stack[4][kStackLds * kWave];
-    __shared__ double red[256][5];
+    // traversal stacks and the FP64 reduction buffer share LDS (never live together)
+    __shared__ union {
+        int stack[4][kStackLds * kWave];
+        double red[256][5];
+    } sm;
+    auto &lds_stack = sm.stack;
+    auto &red = sm.red;
     __shared__ uint32_t s_chunk;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t glane = blockIdx.x * 256 + tid;
@@ -80,6 +85,7 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
                     if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
                 }
             }
+            __syncthreads();  // every wave is done with its stack
             for (int a = 0; a < 5; ++a) red[tid][a] = acc[a];
             __syncthreads();
             if ((uint32_t)tid < nr) {
@@ -135,41 +141,56 @@ __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     o[4] = ai;
 }
 
-// Per (transmitter, receiver): LOS + specular chunks + diffuse chunks, in
-// chunk order.
-__global__ void k_combine(LaunchArgs A, double *gain, double *h_te, double *h_tm, double *parts) {
-    const uint32_t n = A.D.n_items * A.D.n_rx;
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+// Per (transmitter, receiver), one 256-lane block: LOS + specular chunks +
+// diffuse chunks. Lane t sums chunks t, t+256, ... in order; the lanes are
+// then combined by a fixed pairwise tree, so the result is bitwise repeatable.
+__global__ __launch_bounds__(256) void k_combine(LaunchArgs A, double *gain, double *h_te, double *h_tm,
+                                                 double *parts) {
+    __shared__ double red[256][10];
+    const uint32_t p = blockIdx.x;
     const uint32_t it = p / A.D.n_rx, r = p % A.D.n_rx;
     const uint32_t n_rx = A.D.n_rx;
-    double los[5] = {0, 0, 0, 0, 0}, sp[5] = {0, 0, 0, 0, 0}, df[5] = {0, 0, 0, 0, 0};
-    if (A.flags & 1)
-        for (int a = 0; a < 5; ++a) los[a] = A.los_part[(size_t)p * 5 + a];
+    const int t = threadIdx.x;
+    double sp[5] = {0, 0, 0, 0, 0}, df[5] = {0, 0, 0, 0, 0};
     if (A.flags & 2) {
-        for (uint32_t c = A.chunk_off[it]; c < A.chunk_off[it + 1]; ++c)
+        for (uint32_t c = A.chunk_off[it] + t; c < A.chunk_off[it + 1]; c += 256)
             for (int a = 0; a < 5; ++a) sp[a] += A.spec_part[((size_t)c * n_rx + r) * 5 + a];
     }
     if (A.flags & 4) {
         const Item I = A.items[it];
         const uint32_t c0 = I.ray_off / kRayChunk;
-        const uint32_t c1 = (I.ray_off + ((I.n_rays + kRayChunk - 1) / kRayChunk) * kRayChunk) / kRayChunk;
-        for (uint32_t c = c0; c < c1; ++c)
+        const uint32_t c1 = c0 + (I.n_rays + kRayChunk - 1) / kRayChunk;
+        for (uint32_t c = c0 + t; c < c1; c += 256)
             for (int a = 0; a < 5; ++a) df[a] += A.diff_part[((size_t)c * n_rx + r) * 5 + a];
     }
-    gain[p] = los[0] + sp[0] + df[0];
+    for (int a = 0; a < 5; ++a) {
+        red[t][a] = sp[a];
+        red[t][5 + a] = df[a];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int a = 0; a < 10; ++a) red[t][a] += red[t + s][a];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    double los[5] = {0, 0, 0, 0, 0};
+    if (A.flags & 1)
+        for (int a = 0; a < 5; ++a) los[a] = A.los_part[(size_t)p * 5 + a];
+    double *S = red[0];
+    gain[p] = los[0] + S[0] + S[5];
     if (h_te) {
-        h_te[2 * p] = los[1] + sp[1] + df[1];
-        h_te[2 * p + 1] = los[2] + sp[2] + df[2];
+        h_te[2 * p] = los[1] + S[1] + S[6];
+        h_te[2 * p + 1] = los[2] + S[2] + S[7];
     }
     if (h_tm) {
-        h_tm[2 * p] = los[3] + sp[3] + df[3];
-        h_tm[2 * p + 1] = los[4] + sp[4] + df[4];
+        h_tm[2 * p] = los[3] + S[3] + S[8];
+        h_tm[2 * p + 1] = los[4] + S[4] + S[9];
     }
     if (parts) {
         parts[3 * p] = los[0];
-        parts[3 * p + 1] = sp[0];
-        parts[3 * p + 2] = df[0];
+        parts[3 * p + 1] = S[0];
+        parts[3 * p + 2] = S[5];
     }
 }
 
@@ -177,7 +198,12 @@ void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, dou
                             hipStream_t s) {
     const uint32_t n = A.D.n_items * A.D.n_rx;
     if (A.flags & 1) hipLaunchKernelGGL(k_los, dim3((n + kWave - 1) / kWave), dim3(kWave), 0, s, A);
-    hipLaunchKernelGGL(k_combine, dim3((n + 127) / 128), dim3(128), 0, s, A, gain, h_te, h_tm, parts);
+    launch_combine(A, gain, h_te, h_tm, parts, s);
+}
+
+void launch_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts, hipStream_t s) {
+    const uint32_t n = A.D.n_items * A.D.n_rx;
+    hipLaunchKernelGGL(k_combine, dim3(n), dim3(256), 0, s, A, gain, h_te, h_tm, parts);
 }
 
 }  // namespace pcrt

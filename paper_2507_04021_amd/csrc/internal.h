@@ -68,11 +68,18 @@ struct SolveDims {
     uint32_t max_keys;
     uint32_t max_key_chunks;
     uint32_t n_ray_chunks;
+    uint32_t rec_keys;     // keys whose (key, RX) results are kept in RECORD mode
+    uint32_t n_slots;      // tape interaction slots: T*K traced + rec_keys*n_rx*K specular
+    uint32_t n_slot_chunks;
 };
+
+constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk
+constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 labels x 3 doubles
 
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
-        key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill;
+        key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part;
     size_t total;
 };
 
@@ -104,6 +111,11 @@ struct LaunchArgs {
     double *diff_part;
     double *los_part;
     uint8_t *dvis;
+    uint16_t *slot_label;  // RECORD tape: material label per interaction slot (0xffff: empty)
+    float *slot_cos;
+    float *slot_coef;      // [n_slots][8]: Gamma_TE re, im, Gamma_TM re, im, S
+    float *slot_adj;       // [n_slots][8]: dL/d of the same values
+    double *grad_part;     // [n_slot_chunks][kMaxGradLabels][3]
 };
 
 void launch_trace(const LaunchArgs &A, hipStream_t s);
@@ -112,6 +124,13 @@ void launch_refine(const LaunchArgs &A, hipStream_t s);
 void launch_diffuse(const LaunchArgs &A, hipStream_t s);
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                             hipStream_t s);
+void launch_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts, hipStream_t s);
+void launch_tape_slots(const LaunchArgs &A, hipStream_t s);
+void launch_tape_fresnel(const LaunchArgs &A, const float *mats, uint32_t n_labels, hipStream_t s);
+void launch_tape_forward(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
+                         hipStream_t s);
+void launch_tape_backward(const LaunchArgs &A, const double *dldg, hipStream_t s);
+void launch_material_grad(const LaunchArgs &A, const float *mats, uint32_t n_labels, double *out, hipStream_t s);
 void launch_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, hipStream_t s);
 void launch_paths_copy(const LaunchArgs &A, uint32_t cap, uint32_t *key_ray, uint8_t *key_len, int32_t *key_seq,
                        uint8_t *valid, float *length, float *amp, int32_t *hit, hipStream_t s);

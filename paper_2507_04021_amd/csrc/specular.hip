@@ -275,7 +275,7 @@ __device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const It
     po.tm = cmul({a0 * ptm.re, a0 * ptm.im}, ph);
     po.len = L;
     po.valid = true;
-    if (A.flags & 8) {
+    if ((A.flags & 8) && q < A.D.rec_keys) {
         size_t p = (size_t)q * A.D.n_rx + r;
 #pragma unroll
         for (int m = 0; m < KM; ++m)
@@ -290,8 +290,13 @@ __device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const It
 // (key, RX) pairs of it, accumulating FP64 sums per RX in a fixed order.
 template <int KM>
 __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
-    __shared__ int lds_stack[4][kStackLds * kWave];
-    __shared__ double red[256][5];
+    // traversal stacks and the FP64 reduction buffer share LDS (never live together)
+    __shared__ union {
+        int stack[4][kStackLds * kWave];
+        double red[256][5];
+    } sm;
+    auto &lds_stack = sm.stack;
+    auto &red = sm.red;
     __shared__ uint32_t s_chunk;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t glane = blockIdx.x * 256 + tid;
@@ -325,7 +330,9 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
                 for (uint32_t q = q0 + grp; q < q1; q += G) {
                     PairOut po;
                     solve_pair<KM>(A, q, r, I, stk, po, n_cand);
-                    if (A.flags & 8) {
+                    if ((A.flags & 8) && q >= A.D.rec_keys) {
+                        atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
+                    } else if (A.flags & 8) {
                         size_t p = (size_t)q * n_rx + r;
                         A.sb.valid[p] = po.valid;
                         A.sb.len[p] = po.valid ? po.len : 0.f;
@@ -342,6 +349,7 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
                     acc[4] += mi;
                 }
             }
+            __syncthreads();  // every wave is done with its stack
             for (int a = 0; a < 5; ++a) red[tid][a] = acc[a];
             __syncthreads();
             if ((uint32_t)tid < nr) {
@@ -399,7 +407,7 @@ __global__ void k_paths_copy(LaunchArgs A, uint32_t cap, uint32_t *key_ray, uint
                              uint8_t *valid, float *length, float *amp, int32_t *hit) {
     const uint32_t n_keys = A.key_off[A.D.n_items];
     const uint32_t K = A.D.K, n_rx = A.D.n_rx;
-    const uint32_t lim = min(n_keys, cap);
+    const uint32_t lim = min(min(n_keys, cap), A.D.rec_keys);
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < lim; q += gridDim.x * blockDim.x) {
         uint32_t rec = A.keylist[q];
         uint32_t g = rec / K;

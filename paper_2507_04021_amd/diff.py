@@ -1,0 +1,50 @@
+"""Differentiable gains for material learning (autograd around the HIP tape).
+
+The path geometry of a RECORD solve does not depend on the materials, so it
+is traced once and reused: each forward fills the tape's coefficient rows
+from per-label (eps_r, sigma, S) and reduces them to per-receiver gains; each
+backward runs the adjoint kernel and the per-label reduction. Both run in
+the library's kernels; this module only wires them into torch.autograd.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (DIFFUSE, LOS, RECORD, SPECULAR, SolveResult, material_grad, materials_tensor, solve,
+               tape_backward, tape_forward, tape_fresnel)
+
+
+def record(scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR | DIFFUSE, **kw) -> SolveResult:
+    """Trace once and keep the tape (a RECORD solve)."""
+    return solve(scene, mats, tx, rx, freq, n_rays, K=K, flags=flags | RECORD, **kw)
+
+
+class MaterialGain(torch.autograd.Function):
+    """G_r(materials) on a recorded tape. Input: (n_labels, 3) tensor of
+    (eps_r, sigma, S); output: float64 per-receiver gains."""
+
+    @staticmethod
+    def forward(ctx, mats, rec):
+        m = tape_fresnel(rec, mats.detach())
+        g, _, _, _ = tape_forward(rec)
+        ctx.rec = rec
+        ctx.mats_dev = m
+        ctx.shape = mats.shape
+        ctx.dtype = mats.dtype
+        ctx.device = mats.device
+        return g
+
+    @staticmethod
+    def backward(ctx, grad_g):
+        tape_backward(ctx.rec, grad_g.detach())
+        gm = material_grad(ctx.rec, ctx.mats_dev)
+        return gm.to(device=ctx.device, dtype=ctx.dtype).reshape(ctx.shape), None
+
+
+def gains(mats: torch.Tensor, rec: SolveResult) -> torch.Tensor:
+    return MaterialGain.apply(mats, rec)
+
+
+def db_mse_loss(g: torch.Tensor, target_db: torch.Tensor) -> torch.Tensor:
+    """Mean over receivers of (10 log10 G_r - T_r)^2."""
+    return torch.mean((10.0 * torch.log10(g) - target_db) ** 2)

@@ -386,7 +386,7 @@ def test_gradient_matches_finite_differences(orc, room_holefree):
     base = orc.solve(s, mats, scenes.BOX_TX, rx, 3.5e9, 1500, want_jac=True, **kw)
     assert base.G_diff.min() > 0 and base.G_spec.min() > 0
     for lab in range(8):
-        for p, rel in ((0, 1e-5), (1, 1e-4)):
+        for p, rel in ((0, 1e-5), (1, 1e-4), (2, 1e-4)):
             h = rel * mats[lab, p]
             mp, mn = mats.copy(), mats.copy()
             mp[lab, p] += h
