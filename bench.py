@@ -58,6 +58,73 @@ def algorithmic_bytes(cnt, K, n_rx, stage):
     return 0
 
 
+def timed(fn, reps, warm=1):
+    """Median device-synchronised wall ms of fn() over reps calls."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def batch_workload(reps):
+    """256 transmitter poses along a robot trajectory in the tiny box room,
+    ray counts uniform in [2^16, 2^20], K = 2, one graph launch per batch;
+    BVH leaf size and rays per wavefront fetch picked by the autotuner."""
+    import torch
+    import paper_2507_04021_amd as P
+    from paper_2507_04021_amd import scenes
+    s = scenes.box_room()
+    mats = scenes.box_room_materials()
+    tx, n = scenes.trajectory(seed=4021, n=256)
+    choice, rows = P.autotune(s, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 1 << 20, K=2, flags=P.LOS | P.SPECULAR,
+                              leaf_sizes=(1, 2, 4, 8), wave_rays=(64, 128, 256), reps=3,
+                              cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"))
+    sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"])
+    graph = P.BatchGraph(sg, mats, tx, n, [scenes.BOX_RX], 3.5e9, K=2, flags=P.LOS | P.SPECULAR,
+                         wave_rays=choice["wave_rays"])
+    ms = timed(lambda: graph.launch(), reps)
+    inter = int(graph.out["counters"][0].item())
+    return dict(workload="box room, 256 poses, %d rays total (2^16..2^20 each), K=2, 1 RX, 3.5 GHz, LOS+specular, "
+                         "one HIP graph launch" % int(n.sum()),
+                batch_ms=ms, ms_per_config=ms / 256, rays_interactions_per_s=inter / (ms / 1e3),
+                autotune=choice, autotune_table=rows)
+
+
+def grad_workload(reps):
+    """Material gradient on the box-room geometry with one label per surface
+    (8 labels x (eps_r, sigma, S)), 10^4 rays, K = 2, loss = MSE of per-RX
+    gain in dB against targets from hidden materials. grad-step = RECORD
+    solve + tape forward + loss + backward; train-iter = the same without the
+    solve (geometry reused)."""
+    import torch
+    import paper_2507_04021_amd as P
+    from paper_2507_04021_amd import diff, scenes
+    s = scenes.box_room(labels="surface")
+    sg = P.Scene.from_scene(s)
+    rx = np.array([scenes.BOX_RX, [2.0, 3.0, 2.0], [4.5, 0.7, 0.9], [1.5, 2.5, 1.0]], np.float32)
+    truth = scenes.hidden_materials(7, 8)
+    flags = P.LOS | P.SPECULAR
+    target = 10 * torch.log10(P.solve(sg, truth, scenes.BOX_TX, rx, 3.5e9, 10000, K=2, flags=flags).gain)
+    guess = torch.tensor(np.tile([5.0, 0.1, 0.0], (8, 1)), dtype=torch.float64, device="cuda", requires_grad=True)
+    state = {}
+
+    def step(with_solve):
+        if with_solve or "rec" not in state:
+            state["rec"] = diff.record(sg, guess.detach(), scenes.BOX_TX, rx, 3.5e9, 10000, K=2, flags=flags)
+        guess.grad = None
+        loss = diff.db_mse_loss(diff.gains(guess, state["rec"]), target)
+        loss.backward()
+    return dict(workload="box room, 8 surface labels x 3 parameters, 10^4 rays, K=2, 4 RX, 3.5 GHz, LOS+specular",
+                grad_step_ms=timed(lambda: step(True), reps), train_iter_ms=timed(lambda: step(False), reps))
+
+
 def cpu_baseline(sc, rx, tx, mats, n_budget, K, n_sample):
     import oracle
     from paper_2507_04021_amd import scenes
@@ -82,6 +149,7 @@ def main():
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch and gradient workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (rays would shard by "
@@ -174,6 +242,11 @@ def main():
                                        "diffuse", "tie_spill", "status")},
         "shadow_segments_per_s": cnt["segments"] / (ms / 1e3),
     }
+    if not args.no_extras:
+        log("batch workload...")
+        line["batch"] = batch_workload(max(3, args.steps // 2))
+        log("gradient workload...")
+        line["grad"] = grad_workload(max(5, args.steps))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on %d rays..." % args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(sc, rx, tx, mats, args.rays, K, args.cpu_sample)

@@ -145,6 +145,7 @@ typedef struct {
     uint32_t n_subset;
     pcrt_thresholds thr;
     uint32_t key_capacity;
+    uint32_t wave_rays; /* rays a wavefront takes per work fetch, multiple of 64 up to 1024 (0 = 64) */
 } pcrt_solve_params;
 
 /* Outputs (device pointers; NULL = not wanted unless marked required).
@@ -209,6 +210,55 @@ pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p,
  * unoccluded (Sec. II-B.1). Device pointer; asynchronous. */
 pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_params *p, const void *ws,
                                   uint8_t *vis, void *stream);
+
+/* ------------------------------------------------------------- batching */
+/* Many transmitter poses (e.g. a moving robot, Sec. I) against the same
+ * receivers, traced in one persistent launch: the rays of every item share
+ * one work queue; keys, refinement and reductions stay per item. */
+typedef struct {
+    float tx[3];
+    uint32_t n_rays; /* ray budget of this item (its Fibonacci directions) */
+} pcrt_batch_item;
+
+/* Workspace for a batch; p supplies everything but tx, n_rays and
+ * ray_subset (must be NULL). items: host array. */
+pcrt_status pcrt_batch_workspace_size(const pcrt_scene *scene, const pcrt_solve_params *p,
+                                      const pcrt_batch_item *items, uint32_t n_items, size_t *bytes);
+
+/* As pcrt_solve for every item; outputs are indexed [item][rx] (gain
+ * double[n_items][n_rx], h_te/h_tm double[n_items][n_rx][2], gain_parts
+ * double[n_items][n_rx][3]); ray_seq is ignored. Allocates nothing and never
+ * synchronises, so it can be captured. */
+pcrt_status pcrt_solve_batch(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                             const pcrt_solve_params *p, const pcrt_batch_item *items, uint32_t n_items, void *ws,
+                             size_t ws_bytes, const pcrt_outputs *out, void *stream);
+
+/* HIP graph of a batch solve: captured on stream (not the null stream) and
+ * instantiated. Every pointer and value is frozen at capture: a launch
+ * recomputes the batch from the current contents of the captured device
+ * buffers (e.g. new materials written in place). */
+typedef struct pcrt_graph pcrt_graph;
+pcrt_status pcrt_graph_capture_batch(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                                     const pcrt_solve_params *p, const pcrt_batch_item *items, uint32_t n_items,
+                                     void *ws, size_t ws_bytes, const pcrt_outputs *out, void *stream,
+                                     pcrt_graph **graph);
+pcrt_status pcrt_graph_launch(pcrt_graph *graph, void *stream);
+pcrt_status pcrt_graph_destroy(pcrt_graph *graph);
+
+/* Autotuner: builds the scene for every leaf size, times reps solves of p
+ * for every wave_rays value (HIP events on stream; synchronises), fills
+ * table[n_leaf * n_wave] (optional) and the fastest configuration. scene_ws
+ * must fit the scene at every leaf size, solve_ws the solve. */
+typedef struct {
+    uint32_t leaf_size;
+    uint32_t wave_rays;
+    double ms;
+} pcrt_tuning;
+pcrt_status pcrt_autotune(const pcrt_points *pts, const pcrt_solve_params *p, const pcrt_material *mats,
+                          uint32_t n_labels, const uint32_t *leaf_sizes, uint32_t n_leaf, const uint32_t *wave_rays,
+                          uint32_t n_wave, uint32_t reps, void *scene_ws, size_t scene_ws_bytes, void *solve_ws,
+                          size_t solve_ws_bytes, const pcrt_outputs *out, void *stream, pcrt_tuning *table,
+                          pcrt_tuning *best);
 
 /* ------------------------------------------------------ differentiation */
 /* The tape of a PCRT_RECORD solve lives in its workspace. It holds the path

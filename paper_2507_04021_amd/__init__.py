@@ -55,7 +55,15 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_float * 3), ("rx", ctypes.c_void_p), ("n_rx", ctypes.c_uint32),
                 ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
-                ("thr", Thresholds), ("key_capacity", ctypes.c_uint32)]
+                ("thr", Thresholds), ("key_capacity", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("tx", ctypes.c_float * 3), ("n_rays", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
 class Tape(ctypes.Structure):
@@ -104,6 +112,15 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_diffuse_vis_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
         L.pcrt_raygen.argtypes = [u32, vp, u32, vp, vp]
         L.pcrt_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), u32]
+        L.pcrt_batch_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), vp, u32, ctypes.POINTER(sz)]
+        L.pcrt_solve_batch.argtypes = [vp, vp, u32, ctypes.POINTER(SolveParams), vp, u32, vp, sz,
+                                       ctypes.POINTER(Outputs), vp]
+        L.pcrt_graph_capture_batch.argtypes = [vp, vp, u32, ctypes.POINTER(SolveParams), vp, u32, vp, sz,
+                                               ctypes.POINTER(Outputs), vp, ctypes.POINTER(vp)]
+        L.pcrt_graph_launch.argtypes = [vp, vp]
+        L.pcrt_graph_destroy.argtypes = [vp]
+        L.pcrt_autotune.argtypes = [ctypes.POINTER(Points), ctypes.POINTER(SolveParams), vp, u32, vp, u32, vp, u32,
+                                    u32, vp, sz, vp, sz, ctypes.POINTER(Outputs), vp, vp, ctypes.POINTER(Tuning)]
         L.pcrt_tape_get.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Tape)]
         L.pcrt_tape_fresnel.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, u32, vp]
         L.pcrt_tape_forward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Outputs), vp]
@@ -210,7 +227,7 @@ class SolveResult:
         return int(self.counters[CNT[name]].item())
 
 
-def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0):
+def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0, wave_rays=0):
     th = Thresholds(0.0, 0.0, 0.0, 0.0, 0)
     if thr:
         for k, v in thr.items():
@@ -227,11 +244,12 @@ def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_c
     p.n_subset = subset_t.numel() if subset_t is not None else 0
     p.thr = th
     p.key_capacity = int(key_capacity)
+    p.wave_rays = int(wave_rays)
     return p
 
 
 def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
-          want_seq=False, stream=None, ws=None, out=None, key_capacity=0) -> SolveResult:
+          want_seq=False, stream=None, ws=None, out=None, key_capacity=0, wave_rays=0) -> SolveResult:
     """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor."""
     torch = _torch()
     L = lib(scene._variant)
@@ -243,7 +261,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
     if ray_subset is not None:
         sub_t = _dev(np.asarray(ray_subset, np.int64).astype(np.int32) if not isinstance(ray_subset, torch.Tensor)
                      else ray_subset, torch.int32, dev)
-    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity)
+    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays)
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:
@@ -302,6 +320,148 @@ def diffuse_vis(res: SolveResult, stream=None):
     vis = torch.empty(n_trace, p.max_interactions, p.n_rx, dtype=torch.uint8, device=res.scene.device)
     _check(L.pcrt_diffuse_vis_copy(res.scene.handle, ctypes.byref(p), _ptr(res.ws), _ptr(vis), _stream(stream)), L)
     return vis
+
+
+# ------------------------------------------------------------------ batch
+@dataclass
+class BatchResult:
+    gain: object      # float64[n_items, n_rx]
+    h_te: object      # float64[n_items, n_rx, 2]
+    h_tm: object
+    parts: object     # float64[n_items, n_rx, 3]
+    counters: object
+    ws: object
+    params: SolveParams
+    items: object     # ctypes array of BatchItem
+    keep: tuple
+
+    def counter(self, name):
+        return int(self.counters[CNT[name]].item())
+
+
+def _items(tx, n_rays):
+    tx = np.asarray(tx, np.float32).reshape(-1, 3)
+    n_rays = np.broadcast_to(np.asarray(n_rays, np.int64), (tx.shape[0],))
+    arr = (BatchItem * tx.shape[0])()
+    for i in range(tx.shape[0]):
+        arr[i].tx = (ctypes.c_float * 3)(*[float(v) for v in tx[i]])
+        arr[i].n_rays = int(n_rays[i])
+    return arr
+
+
+def _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr, wave_rays):
+    torch = _torch()
+    dev = scene.device
+    mats_t = mats if isinstance(mats, torch.Tensor) and mats.device.type == "cuda" else materials_tensor(mats, dev)
+    rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
+                torch.float32, dev).reshape(-1, 3)
+    items = _items(tx, n_rays)
+    p = make_params([0, 0, 0], rx_t, freq, 1, K, flags, None, thr, 0, wave_rays)
+    L = lib(scene._variant)
+    nbytes = ctypes.c_size_t(0)
+    _check(L.pcrt_batch_workspace_size(scene.handle, ctypes.byref(p), items, len(items), ctypes.byref(nbytes)), L)
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    n, r = len(items), rx_t.shape[0]
+    out = dict(gain=torch.empty(n, r, dtype=torch.float64, device=dev),
+               h_te=torch.empty(n, r, 2, dtype=torch.float64, device=dev),
+               h_tm=torch.empty(n, r, 2, dtype=torch.float64, device=dev),
+               parts=torch.empty(n, r, 3, dtype=torch.float64, device=dev),
+               counters=torch.empty(16, dtype=torch.int64, device=dev))
+    o = Outputs(out["gain"].data_ptr(), out["h_te"].data_ptr(), out["h_tm"].data_ptr(), out["parts"].data_ptr(),
+                None, out["counters"].data_ptr())
+    return L, mats_t, rx_t, items, p, ws, out, o
+
+
+def solve_batch(scene: Scene, mats, tx, n_rays, rx, freq, K=2, flags=LOS | SPECULAR, thr=None, wave_rays=0,
+                stream=None) -> BatchResult:
+    """Many transmitters (tx[n, 3], n_rays[n]) against the same receivers in one launch sequence."""
+    L, mats_t, rx_t, items, p, ws, out, o = _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr,
+                                                         wave_rays)
+    _check(L.pcrt_solve_batch(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), items, len(items),
+                              _ptr(ws), ws.numel(), ctypes.byref(o), _stream(stream)), L)
+    return BatchResult(out["gain"], out["h_te"], out["h_tm"], out["parts"], out["counters"], ws, p, items,
+                       (mats_t, rx_t, o))
+
+
+class BatchGraph:
+    """A batch solve captured once as a HIP graph (by the library) and
+    replayed. Materials may be changed in place in `self.mats` between
+    launches; outputs land in the same tensors every launch."""
+
+    def __init__(self, scene: Scene, mats, tx, n_rays, rx, freq, K=2, flags=LOS | SPECULAR, thr=None, wave_rays=0,
+                 stream=None):
+        torch = _torch()
+        self.scene = scene
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        (self.L, self.mats, self.rx, self.items, self.params, self.ws, self.out,
+         self._o) = _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr, wave_rays)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(self.L.pcrt_graph_capture_batch(scene.handle, _ptr(self.mats), self.mats.shape[0],
+                                               ctypes.byref(self.params), self.items, len(self.items), _ptr(self.ws),
+                                               self.ws.numel(), ctypes.byref(self._o), _stream(self.stream),
+                                               ctypes.byref(h)), self.L)
+        self.handle = h
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else self.stream
+        _check(self.L.pcrt_graph_launch(self.handle, _stream(s)), self.L)
+        return self.out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None:
+            self.L.pcrt_graph_destroy(h)
+            self.handle = None
+
+
+def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_sizes=(1, 2, 4, 8),
+             wave_rays=(64, 128, 256), reps=3, cache_path=None, device="cuda"):
+    """Sweep BVH leaf size x rays per wavefront fetch with the library's tuner;
+    the winner is stored in a JSON cache keyed by the workload."""
+    import json
+    torch = _torch()
+    key = "n=%d rays=%d K=%d flags=%d rx=%d dev=%s" % (sc.n, n_rays, K, flags, np.asarray(rx).reshape(-1, 3).shape[0],
+                                                      torch.cuda.get_device_name(device))
+    cache_path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "pcrt_tuning.json")
+    try:
+        cache = json.load(open(cache_path))
+    except (OSError, ValueError):
+        cache = {}
+    if key in cache:
+        return cache[key], None
+    dev = torch.device(device)
+    pos = _dev(sc.pos, torch.float32, dev)
+    nrm = _dev(sc.normal, torch.float32, dev)
+    mat = _dev(sc.material.astype(np.int32), torch.int32, dev).to(torch.int16)
+    surf = _dev(sc.surface.astype(np.int64), torch.int64, dev).to(torch.int32)
+    pts = Points(pos.data_ptr(), nrm.data_ptr(), mat.data_ptr(), surf.data_ptr(), sc.n, sc.radius)
+    L = lib()
+    nb = ctypes.c_size_t(0)
+    _check(L.pcrt_scene_workspace_size(sc.n, None, ctypes.byref(nb)), L)
+    scene_ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    probe = Scene.from_scene(sc, device=device)
+    res = solve(probe, mats, tx, rx, freq, n_rays, K=K, flags=flags)
+    p = res.params
+    o = Outputs(res.gain.data_ptr(), res.h_te.data_ptr(), res.h_tm.data_ptr(), res.parts.data_ptr(), None,
+                res.counters.data_ptr())
+    leaf = (ctypes.c_uint32 * len(leaf_sizes))(*leaf_sizes)
+    wr = (ctypes.c_uint32 * len(wave_rays))(*wave_rays)
+    table = (Tuning * (len(leaf_sizes) * len(wave_rays)))()
+    best = Tuning()
+    mats_t = res.keep[0]
+    _check(L.pcrt_autotune(ctypes.byref(pts), ctypes.byref(p), _ptr(mats_t), mats_t.shape[0], leaf, len(leaf_sizes),
+                           wr, len(wave_rays), reps, _ptr(scene_ws), nb.value, _ptr(res.ws), res.ws.numel(),
+                           ctypes.byref(o), _stream(), table, ctypes.byref(best)), L)
+    choice = dict(leaf_size=best.leaf_size, wave_rays=best.wave_rays, ms=best.ms)
+    rows = [dict(leaf_size=t.leaf_size, wave_rays=t.wave_rays, ms=t.ms) for t in table]
+    cache[key] = choice
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        json.dump(cache, open(cache_path, "w"), indent=1)
+    except OSError:
+        pass
+    return choice, rows
 
 
 # ------------------------------------------------------------------ tape

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "pcrt.h"
@@ -133,16 +134,46 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     return PCRT_OK;
 }
 
-Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
+// Transmitters of a solve: one for pcrt_solve, many for pcrt_solve_batch.
+// Ray slots of item i start at ray_off (a multiple of kRayChunk) so that
+// reduction chunks never straddle two transmitters.
+std::vector<Item> single_items(const pcrt_solve_params *p) {
+    Item it;
+    memset(&it, 0, sizeof it);
+    for (int a = 0; a < 3; ++a) it.tx[a] = p->tx[a];
+    it.n_rays = (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) ? (p->ray_subset ? p->n_subset : p->n_rays) : 0;
+    it.budget = p->n_rays ? p->n_rays : 1;
+    return {it};
+}
+
+std::vector<Item> batch_items(const pcrt_solve_params *p, const pcrt_batch_item *b, uint32_t n) {
+    std::vector<Item> v(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        memset(&v[i], 0, sizeof(Item));
+        for (int a = 0; a < 3; ++a) v[i].tx[a] = b[i].tx[a];
+        v[i].n_rays = (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) ? b[i].n_rays : 0;
+        v[i].budget = b[i].n_rays ? b[i].n_rays : 1;
+    }
+    return v;
+}
+
+Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Item> &items) {
     Plan P;
     const uint32_t K = p->max_interactions;
-    P.n_trace = (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) ? (p->ray_subset ? p->n_subset : p->n_rays) : 0;
     SolveDims &D = P.D;
     D.K = K;
     D.n_rx = p->n_rx;
-    D.n_items = 1;
-    D.T = round_up(std::max<uint32_t>(P.n_trace, 1), kRayChunk);
-    P.cap = key_capacity(P.n_trace, K, sc->info.n_surfaces);
+    D.n_items = (uint32_t)items.size();
+    uint64_t off = 0, total = 0, max_rays = 0;
+    for (auto &it : items) {
+        it.ray_off = (uint32_t)off;
+        off += (uint64_t)round_up(it.n_rays, kRayChunk);
+        total += it.n_rays;
+        max_rays = std::max<uint64_t>(max_rays, it.n_rays);
+    }
+    P.n_trace = (uint32_t)total;
+    D.T = (uint32_t)std::max<uint64_t>(off, kRayChunk);
+    P.cap = key_capacity(max_rays, K, sc->info.n_surfaces);
     D.max_keys = (uint32_t)std::min<uint64_t>((uint64_t)D.T * K, (uint64_t)P.cap * D.n_items);
     D.max_key_chunks = (D.max_keys + kKeyChunk - 1) / kKeyChunk + D.n_items;
     D.n_ray_chunks = D.T / kRayChunk;
@@ -158,6 +189,11 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
     return P;
+}
+
+Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
+    std::vector<Item> items = single_items(p);
+    return make_plan(sc, p, items);
 }
 
 struct ItemBatch {
@@ -194,6 +230,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.thr = P.thr;
     A.fc = P.fc;
     A.D = P.D;
+    A.wave_rays = p->wave_rays ? p->wave_rays : kWave;
     A.rb.id = (int *)at(L.rec_id);
     A.rb.xl = (float4 *)at(L.rec_xl);
     A.rb.cs = (float *)at(L.rec_cs);
@@ -396,41 +433,47 @@ pcrt_status pcrt_solve_workspace_size(const pcrt_scene *scene, const pcrt_solve_
     return ok();
 }
 
-pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
-                       const pcrt_solve_params *p, void *ws, size_t ws_bytes, const pcrt_outputs *out,
-                       void *stream) {
+}  // extern "C"
+
+static pcrt_status check_common(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                                const pcrt_solve_params *p, void *ws, const pcrt_outputs *out) {
     pcrt_status st = check_params(scene, p);
     if (st) return st;
     if (!out || !out->gain) return fail(PCRT_EINVAL, "out->gain is required");
     if (!ws) return fail(PCRT_EINVAL, "ws is required");
     if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && (!mats || n_labels == 0))
         return fail(PCRT_EINVAL, "materials are required");
-    Plan P = make_plan(scene, p);
+    if (p->wave_rays && (p->wave_rays % kWave || p->wave_rays > 16 * kWave))
+        return fail(PCRT_EUNSUPPORTED, "wave_rays must be a multiple of 64 up to 1024");
+    return PCRT_OK;
+}
+
+// The whole launch sequence of a (batched) solve. Only kernels are enqueued:
+// no allocation, no memset node, no host synchronisation (except the event
+// records of PCRT_TIMING), so it can be captured in a HIP graph.
+static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                              const pcrt_solve_params *p, std::vector<Item> &items, void *ws, size_t ws_bytes,
+                              const pcrt_outputs *out, hipStream_t s) {
+    Plan P = make_plan(scene, p, items);
     place_hash(P, p->flags);
     if (ws_bytes < P.L.total) return fail(PCRT_ENOMEM, "solve workspace too small: need %zu bytes", P.L.total);
-    hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     LaunchArgs A = make_args(scene, mats, n_labels, p, P, w, out->counters);
     const bool tm = p->flags & PCRT_TIMING;
     for (int i = 0; i < kStages; ++i) g_ev_used[i] = tm;
     stage_mark(tm, 0, s);
-    // graph-safe initialisation: fill kernels, items passed by value
     fill_u32(A.work, 0, 8, s);
     fill_u64(A.counters, 0, PCRT_CNT_COUNT, s);
     fill_u32(A.key_off, 0, P.D.n_items + 1, s);
     fill_u32(A.chunk_off, 0, P.D.n_items + 1, s);
-    ItemBatch ib;
-    memset(&ib, 0, sizeof ib);
-    ib.n = 1;
-    ib.base = 0;
-    Item &it = ib.it[0];
-    it.tx[0] = p->tx[0];
-    it.tx[1] = p->tx[1];
-    it.tx[2] = p->tx[2];
-    it.n_rays = P.n_trace;
-    it.ray_off = 0;
-    it.budget = p->n_rays ? p->n_rays : 1;
-    hipLaunchKernelGGL(k_put_items, dim3(1), dim3(96), 0, s, ib, (Item *)A.items);
+    for (size_t b = 0; b < items.size(); b += 96) {
+        ItemBatch ib;
+        memset(&ib, 0, sizeof ib);
+        ib.n = (uint32_t)std::min<size_t>(96, items.size() - b);
+        ib.base = (uint32_t)b;
+        memcpy(ib.it, items.data() + b, sizeof(Item) * ib.n);
+        hipLaunchKernelGGL(k_put_items, dim3(1), dim3(96), 0, s, ib, (Item *)A.items);
+    }
     if (p->flags & PCRT_SPECULAR) {
         fill_u64((uint64_t *)A.hb.key, 0, (size_t)P.cap * P.D.n_items, s);
         fill_u32(A.hb.rep, 0xffffffffu, (size_t)P.cap * P.D.n_items, s);
@@ -438,7 +481,7 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
     stage_mark(tm, 1, s);
     if (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) {
         launch_trace(A, s);
-        if (out->ray_seq) {
+        if (out->ray_seq && P.D.n_items == 1) {
             uint32_t n = P.n_trace * P.D.K;
             hipLaunchKernelGGL(k_copy_seq, dim3((n + 255) / 256), dim3(256), 0, s, A.rb.id, n, out->ray_seq);
         }
@@ -454,6 +497,156 @@ pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint3
     if (p->flags & PCRT_RECORD) launch_tape_slots(A, s);
     stage_mark(tm, 6, s);
     HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+static pcrt_status check_batch(const pcrt_solve_params *p, const pcrt_batch_item *items, uint32_t n_items) {
+    if (!items || n_items == 0) return fail(PCRT_EINVAL, "items are required");
+    if (n_items > 65536) return fail(PCRT_EUNSUPPORTED, "at most 65536 items");
+    if (p->ray_subset) return fail(PCRT_EINVAL, "ray_subset is not supported in a batch");
+    if (p->flags & PCRT_RECORD) return fail(PCRT_EUNSUPPORTED, "tapes are kept for single-transmitter solves only");
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n_items; ++i) {
+        if (!std::isfinite(items[i].tx[0]) || !std::isfinite(items[i].tx[1]) || !std::isfinite(items[i].tx[2]))
+            return fail(PCRT_EINVAL, "item %u: tx must be finite", i);
+        if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && items[i].n_rays == 0)
+            return fail(PCRT_EINVAL, "item %u: n_rays must be > 0", i);
+        total += round_up(items[i].n_rays, kRayChunk);
+    }
+    if (total * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
+    if ((uint64_t)n_items * p->n_rx > kSpillLanes) return fail(PCRT_EUNSUPPORTED, "too many items x receivers");
+    return PCRT_OK;
+}
+
+struct pcrt_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+pcrt_status pcrt_solve(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                       const pcrt_solve_params *p, void *ws, size_t ws_bytes, const pcrt_outputs *out,
+                       void *stream) {
+    pcrt_status st = check_common(scene, mats, n_labels, p, ws, out);
+    if (st) return st;
+    std::vector<Item> items = single_items(p);
+    return solve_impl(scene, mats, n_labels, p, items, ws, ws_bytes, out, (hipStream_t)stream);
+}
+
+pcrt_status pcrt_batch_workspace_size(const pcrt_scene *scene, const pcrt_solve_params *p,
+                                      const pcrt_batch_item *items, uint32_t n_items, size_t *bytes) {
+    pcrt_status st = check_params(scene, p);
+    if (st) return st;
+    st = check_batch(p, items, n_items);
+    if (st) return st;
+    if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
+    std::vector<Item> v = batch_items(p, items, n_items);
+    Plan P = make_plan(scene, p, v);
+    place_hash(P, p->flags);
+    *bytes = P.L.total;
+    return ok();
+}
+
+pcrt_status pcrt_solve_batch(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                             const pcrt_solve_params *p, const pcrt_batch_item *items, uint32_t n_items, void *ws,
+                             size_t ws_bytes, const pcrt_outputs *out, void *stream) {
+    pcrt_status st = check_common(scene, mats, n_labels, p, ws, out);
+    if (st) return st;
+    st = check_batch(p, items, n_items);
+    if (st) return st;
+    std::vector<Item> v = batch_items(p, items, n_items);
+    return solve_impl(scene, mats, n_labels, p, v, ws, ws_bytes, out, (hipStream_t)stream);
+}
+
+pcrt_status pcrt_graph_capture_batch(const pcrt_scene *scene, const pcrt_material *mats, uint32_t n_labels,
+                                     const pcrt_solve_params *p, const pcrt_batch_item *items, uint32_t n_items,
+                                     void *ws, size_t ws_bytes, const pcrt_outputs *out, void *stream,
+                                     pcrt_graph **graph) {
+    if (!graph) return fail(PCRT_EINVAL, "graph is NULL");
+    if (!stream) return fail(PCRT_EINVAL, "capture needs a non-default stream");
+    if (p && (p->flags & PCRT_TIMING)) return fail(PCRT_EINVAL, "PCRT_TIMING cannot be captured");
+    pcrt_status st = check_common(scene, mats, n_labels, p, ws, out);
+    if (st) return st;
+    st = check_batch(p, items, n_items);
+    if (st) return st;
+    std::vector<Item> v = batch_items(p, items, n_items);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pcrt_status rs = solve_impl(scene, mats, n_labels, p, v, ws, ws_bytes, out, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rs != PCRT_OK) {
+        if (g) hipGraphDestroy(g);
+        return rs;
+    }
+    if (e != hipSuccess) return fail(PCRT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(PCRT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *graph = new pcrt_graph{g, x};
+    return ok();
+}
+
+pcrt_status pcrt_graph_launch(pcrt_graph *graph, void *stream) {
+    if (!graph) return fail(PCRT_EINVAL, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return ok();
+}
+
+pcrt_status pcrt_graph_destroy(pcrt_graph *graph) {
+    if (!graph) return ok();
+    hipGraphExecDestroy(graph->exec);
+    hipGraphDestroy(graph->graph);
+    delete graph;
+    return ok();
+}
+
+pcrt_status pcrt_autotune(const pcrt_points *pts, const pcrt_solve_params *p, const pcrt_material *mats,
+                          uint32_t n_labels, const uint32_t *leaf_sizes, uint32_t n_leaf, const uint32_t *wave_rays,
+                          uint32_t n_wave, uint32_t reps, void *scene_ws, size_t scene_ws_bytes, void *solve_ws,
+                          size_t solve_ws_bytes, const pcrt_outputs *out, void *stream, pcrt_tuning *table,
+                          pcrt_tuning *best) {
+    if (!pts || !p || !leaf_sizes || !wave_rays || !n_leaf || !n_wave || !best || !out)
+        return fail(PCRT_EINVAL, "pts, p, sweep lists, out and best are required");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    best->ms = INFINITY;
+    uint32_t idx = 0;
+    for (uint32_t a = 0; a < n_leaf; ++a) {
+        pcrt_bvh_opts o = {leaf_sizes[a], 2};
+        pcrt_scene *sc = nullptr;
+        pcrt_status st = pcrt_scene_create(pts, &o, scene_ws, scene_ws_bytes, stream, &sc);
+        if (st) return st;
+        for (uint32_t b = 0; b < n_wave; ++b, ++idx) {
+            pcrt_solve_params q = *p;
+            q.wave_rays = wave_rays[b];
+            q.flags &= ~(uint32_t)PCRT_TIMING;
+            st = pcrt_solve(sc, mats, n_labels, &q, solve_ws, solve_ws_bytes, out, stream);  // warm-up
+            if (st) {
+                pcrt_scene_destroy(sc);
+                return st;
+            }
+            HIP_TRY(hipEventRecord(e0, s));
+            for (uint32_t r = 0; r < std::max<uint32_t>(reps, 1); ++r)
+                pcrt_solve(sc, mats, n_labels, &q, solve_ws, solve_ws_bytes, out, stream);
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            pcrt_tuning t = {leaf_sizes[a], wave_rays[b], ms / std::max<uint32_t>(reps, 1)};
+            if (table) table[idx] = t;
+            if (t.ms < best->ms) *best = t;
+        }
+        pcrt_scene_destroy(sc);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
     return ok();
 }
 

@@ -100,6 +100,7 @@ struct LaunchArgs {
     RecBufs rb;
     HashBufs hb;
     SpecBufs sb;
+    uint32_t wave_rays; // rays a wavefront takes per work fetch (multiple of 64)
     uint32_t *work;     // [8] atomic work counters
     uint64_t *counters; // [16]
     uint32_t *scan;

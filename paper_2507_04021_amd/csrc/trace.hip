@@ -30,82 +30,96 @@ __device__ __forceinline__ uint32_t key_insert(const HashBufs &hb, uint32_t base
     return 0xffffffffu;
 }
 
+// One ray slot g: launch direction, up to K closest hits, records.
+__device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack &stk, uint32_t &n_int,
+                                          uint32_t &n_ray, uint32_t &n_spill) {
+    const uint32_t K = A.D.K;
+    const bool want_diff = A.flags & 4, want_spec = A.flags & 2;
+    const bool want_geom = A.flags & (4 | 8);  // points/lengths/cosines feed diffuse and the tape
+    const int it = find_item(A.items, A.D.n_items, g);
+    const Item I = A.items[it];
+    const uint32_t local = g - I.ray_off;
+    const size_t rb = (size_t)g * K;
+    if (local >= I.n_rays) {
+        for (uint32_t k = 0; k < K; ++k) A.rb.id[rb + k] = -1;
+        return;
+    }
+    const uint32_t j = A.subset ? A.subset[local] : local;
+    f3 d = normalize(fib_dir(j, I.budget));
+    f3 o = mk(I.tx[0], I.tx[1], I.tx[2]);
+    float L = 0.f;
+    int excl = -1;
+    c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
+    uint64_t enc = 0;
+    uint32_t k = 0;
+    for (; k < K; ++k) {
+        float t;
+        bool sp;
+        int h = closest_hit(A.S, o, d, excl, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
+        n_spill += sp;
+        if (h < 0) break;
+        const float4 pn = A.S.nrm[h];
+        f3 n = xyz(pn);
+        float dn = dot(d, n);
+        float sgn = dn > 0.f ? -1.f : 1.f;
+        float cosi = fabsf(dn);
+        f3 q = o + t * d;
+        L += t;
+        A.rb.id[rb + k] = h;
+        if (want_geom) {
+            A.rb.xl[rb + k] = make_float4(q.x, q.y, q.z, L);
+            A.rb.cs[rb + k] = sgn * cosi;
+        }
+        if (want_diff) {
+            uint32_t lab = __float_as_uint(pn.w);
+            if (lab >= A.n_labels) {
+                atomicOr((unsigned long long *)&A.counters[6], 2ull);
+                lab = 0;
+            }
+            float er = A.mats[3 * lab], sg = A.mats[3 * lab + 1], sc = A.mats[3 * lab + 2];
+            c32 te, tm;
+            fresnel(er, sg * A.fc.inv_we0, cosi, te, tm);
+            c32 cte = cmul(pte, te), ctm = cmul(ptm, tm);
+            float w = A.fc.amp_iso * sc;
+            A.rb.coef[rb + k] = make_float4(w * cte.re, w * cte.im, w * ctm.re, w * ctm.im);
+            float R = sqrtf(fmaxf(0.f, 1.f - sc * sc));
+            pte = {R * cte.re, R * cte.im};
+            ptm = {R * ctm.re, R * ctm.im};
+        }
+        if (want_spec) {
+            uint32_t su = __float_as_uint(A.S.pos[h].w);
+            enc = enc * (uint64_t)A.n_surf1 + (uint64_t)(su + 1);
+            A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
+        }
+        d = normalize(d - (2.f * dn) * n);
+        o = q;
+        excl = h;
+    }
+    for (uint32_t kk = k; kk < K; ++kk) A.rb.id[rb + kk] = -1;
+    n_int += k;
+    n_ray += 1;
+}
+
+// Persistent wavefronts take wave_rays consecutive ray slots per atomic
+// fetch; each lane traces wave_rays / 64 of them in turn.
 __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
     const int lane = threadIdx.x;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
-    const uint32_t K = A.D.K, T = A.D.T;
-    const uint32_t n_units = (T + kWave - 1) / kWave;
-    const bool want_diff = A.flags & 4, want_spec = A.flags & 2;
+    const uint32_t T = A.D.T;
+    const uint32_t U = A.wave_rays / kWave;
+    const uint32_t n_units = (T + A.wave_rays - 1) / A.wave_rays;
     uint32_t n_int = 0, n_ray = 0, n_spill = 0;
     for (;;) {
         uint32_t unit = 0;
         if (lane == 0) unit = atomicAdd(&A.work[0], 1u);
         unit = __shfl(unit, 0, kWave);
         if (unit >= n_units) break;
-        const uint32_t g = unit * kWave + lane;
-        if (g >= T) continue;
-        const int it = find_item(A.items, A.D.n_items, g);
-        const Item I = A.items[it];
-        const uint32_t local = g - I.ray_off;
-        const size_t rb = (size_t)g * K;
-        if (local >= I.n_rays) {
-            for (uint32_t k = 0; k < K; ++k) A.rb.id[rb + k] = -1;
-            continue;
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t g = unit * A.wave_rays + u * kWave + lane;
+            if (g < T) trace_one(A, g, stk, n_int, n_ray, n_spill);
         }
-        const uint32_t j = A.subset ? A.subset[local] : local;
-        f3 d = normalize(fib_dir(j, I.budget));
-        f3 o = mk(I.tx[0], I.tx[1], I.tx[2]);
-        float L = 0.f;
-        int excl = -1;
-        c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
-        uint64_t enc = 0;
-        uint32_t k = 0;
-        for (; k < K; ++k) {
-            float t;
-            bool sp;
-            int h = closest_hit(A.S, o, d, excl, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
-            n_spill += sp;
-            if (h < 0) break;
-            const float4 pn = A.S.nrm[h];
-            f3 n = xyz(pn);
-            float dn = dot(d, n);
-            float sgn = dn > 0.f ? -1.f : 1.f;
-            float cosi = fabsf(dn);
-            f3 q = o + t * d;
-            L += t;
-            A.rb.id[rb + k] = h;
-            A.rb.xl[rb + k] = make_float4(q.x, q.y, q.z, L);
-            A.rb.cs[rb + k] = sgn * cosi;
-            if (want_diff) {
-                uint32_t lab = __float_as_uint(pn.w);
-                if (lab >= A.n_labels) {
-                    atomicOr((unsigned long long *)&A.counters[6], 2ull);
-                    lab = 0;
-                }
-                float er = A.mats[3 * lab], sg = A.mats[3 * lab + 1], sc = A.mats[3 * lab + 2];
-                c32 te, tm;
-                fresnel(er, sg * A.fc.inv_we0, cosi, te, tm);
-                c32 cte = cmul(pte, te), ctm = cmul(ptm, tm);
-                float w = A.fc.amp_iso * sc;
-                A.rb.coef[rb + k] = make_float4(w * cte.re, w * cte.im, w * ctm.re, w * ctm.im);
-                float R = sqrtf(fmaxf(0.f, 1.f - sc * sc));
-                pte = {R * cte.re, R * cte.im};
-                ptm = {R * ctm.re, R * ctm.im};
-            }
-            if (want_spec) {
-                uint32_t su = __float_as_uint(A.S.pos[h].w);
-                enc = enc * (uint64_t)A.n_surf1 + (uint64_t)(su + 1);
-                A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
-            }
-            d = normalize(d - (2.f * dn) * n);
-            o = q;
-            excl = h;
-        }
-        for (uint32_t kk = k; kk < K; ++kk) A.rb.id[rb + kk] = -1;
-        n_int += k;
-        n_ray += 1;
     }
     flush_visits(stk, A.counters, 9);
     n_int = warp_sum_u(n_int);
@@ -119,7 +133,7 @@ __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
 }
 
 void launch_trace(const LaunchArgs &A, hipStream_t s) {
-    uint32_t units = (A.D.T + kWave - 1) / kWave;
+    uint32_t units = (A.D.T + A.wave_rays - 1) / A.wave_rays;
     uint32_t grid = std::min<uint32_t>(kTraceBlocks, std::max<uint32_t>(units, 1));
     hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kWave), 0, s, A);
 }
