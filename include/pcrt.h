@@ -311,6 +311,43 @@ pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params 
 pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                                const pcrt_material *mats, uint32_t n_labels, double *dL_dmat, void *stream);
 
+/* ------------------------------------------------ learned material model */
+/* A small network in place of the per-label Fresnel model: per interaction
+ * slot, x = [emb[label] (16), cos theta_i, log10(f / 1 GHz), 0 x 14] (32),
+ * h1..h3 = GELU(W h + b) (64 wide, exact erf GELU), z = W4 h3 + b4 (16, five
+ * used); Gamma_TE = (z0 + j z1) tanh|.|/|.|, Gamma_TM = (z2 + j z3) tanh|.|/|.|
+ * (|Gamma| < 1, a passive surface), S = sigmoid(z4). BF16 operands with FP32
+ * accumulation on the matrix cores; biases and the embedding table are FP32
+ * (the embedding is rounded to BF16 as an input).
+ * w: device bf16 bits, packed W1 [64][32], W2 [64][64], W3 [64][64], W4 [16][64]
+ * (row = output; W1 columns 18..31 and W4 rows 5..15 should be zero);
+ * b: device float b1 [64], b2 [64], b3 [64], b4 [16]; emb: device float
+ * [n_labels][16], n_labels <= 64. */
+typedef struct {
+    const uint16_t *w;
+    const float *b;
+    const float *emb;
+    uint32_t n_labels;
+} pcrt_mlp;
+
+/* Rows of 8 floats, in the tape's coefficient-row format: out[i] = (Gamma_TE
+ * re, im, Gamma_TM re, im, S, 0, 0, 0) for slot i; label 0xffff (an empty
+ * slot) gives zeros. label, cos: device [n]. Allocates nothing. */
+pcrt_status pcrt_mlp_forward(const pcrt_mlp *net, uint32_t n, const uint16_t *label, const float *cos, float log_f,
+                             float *out, void *stream);
+
+/* Workspace for pcrt_mlp_backward over n rows. */
+pcrt_status pcrt_mlp_workspace_size(uint32_t n, uint32_t n_labels, size_t *bytes);
+
+/* Gradients of sum_i g_out[i] . out[i] (g_out: device [n][8], e.g. the tape's
+ * adjoint rows) with respect to the parameters, written (not accumulated) to
+ * grad_w (float, packed like w), grad_b (float [208]) and grad_emb (float
+ * [n_labels][16]). The pass recomputes the forward; weight gradients are
+ * MFMA GEMMs over fixed row blocks summed in a fixed order. */
+pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *label, const float *cos, float log_f,
+                              const float *g_out, void *ws, size_t ws_bytes, float *grad_w, float *grad_b,
+                              float *grad_emb, void *stream);
+
 /* Device time (ms) of the stages of the last PCRT_TIMING solve issued on
  * this host thread: [0] initialisation, [1] ray launch + bounce loop,
  * [2] key marking/compaction, [3] specular refine + validate + field,

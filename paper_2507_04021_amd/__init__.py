@@ -66,6 +66,10 @@ class Tuning(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
+class Mlp(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("b", ctypes.c_void_p), ("emb", ctypes.c_void_p), ("n_labels", ctypes.c_uint32)]
+
+
 class Tape(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("n_trace_slots", ctypes.c_uint32), ("key_capacity", ctypes.c_uint32),
                 ("label", ctypes.c_void_p), ("cos", ctypes.c_void_p), ("coef", ctypes.c_void_p),
@@ -121,6 +125,9 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_graph_destroy.argtypes = [vp]
         L.pcrt_autotune.argtypes = [ctypes.POINTER(Points), ctypes.POINTER(SolveParams), vp, u32, vp, u32, vp, u32,
                                     u32, vp, sz, vp, sz, ctypes.POINTER(Outputs), vp, vp, ctypes.POINTER(Tuning)]
+        L.pcrt_mlp_forward.argtypes = [ctypes.POINTER(Mlp), u32, vp, vp, ctypes.c_float, vp, vp]
+        L.pcrt_mlp_workspace_size.argtypes = [u32, u32, ctypes.POINTER(sz)]
+        L.pcrt_mlp_backward.argtypes = [ctypes.POINTER(Mlp), u32, vp, vp, ctypes.c_float, vp, vp, sz, vp, vp, vp, vp]
         L.pcrt_tape_get.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Tape)]
         L.pcrt_tape_fresnel.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, u32, vp]
         L.pcrt_tape_forward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Outputs), vp]

@@ -185,6 +185,10 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     } else {
         D.rec_keys = D.n_slots = D.n_slot_chunks = 0;
     }
+    // every traversal launch indexes the stack spill by its global lane
+    const uint32_t wr = p->wave_rays ? p->wave_rays : kWave;
+    D.spill_lanes = std::max({trace_grid(D, wr) * kWave, wide_grid(D.n_ray_chunks) * 256u,
+                              wide_grid(D.max_key_chunks) * 256u, round_up(D.n_items * D.n_rx, kWave)});
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
@@ -219,7 +223,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     auto at = [&](size_t off) { return (void *)(ws + off); };
     A.S = sc->dev;
     A.S.spill = (int *)at(L.spill);
-    A.S.spill_lanes = kSpillLanes;
+    A.S.spill_lanes = P.D.spill_lanes;
     A.items = (const Item *)at(L.items);
     A.subset = p->ray_subset;
     A.rx = p->rx;
@@ -312,7 +316,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.slot_adj = b.take(sizeof(float) * 8 * (size_t)D.n_slots);
         L.grad_part = b.take(sizeof(double) * 3 * kMaxGradLabels * (size_t)std::max<uint32_t>(D.n_slot_chunks, 1));
     }
-    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * kSpillLanes);
+    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * D.spill_lanes);
     L.total = b.off;
     return L;
 }

@@ -351,7 +351,6 @@ SceneLayout scene_layout(uint32_t n) {
     L.nrm_id = b.take(sizeof(float4) * n);
     L.disk = b.take(sizeof(float4) * 2 * n);
     L.node = b.take(sizeof(float4) * 4 * (size_t)ni);
-    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * kSpillLanes);
     L.stat = b.take(sizeof(uint32_t) * 8);
     L.bounds = b.take(sizeof(float) * 8);
     L.blk_bounds = b.take(sizeof(float) * 6 * blk);

@@ -108,8 +108,7 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
 }
 
 void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
-    const uint32_t grid = std::min<uint32_t>(kWideBlocks, std::max<uint32_t>(A.D.n_ray_chunks, 1));
-    hipLaunchKernelGGL(k_diffuse, dim3(grid), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_diffuse, dim3(wide_grid(A.D.n_ray_chunks)), dim3(256), 0, s, A);
 }
 
 // Line of sight per (transmitter, receiver): a_TE = a_TM = lambda/(4 pi d) e^{-j k0 d}.

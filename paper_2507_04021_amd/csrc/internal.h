@@ -26,7 +26,7 @@ struct Bump {  // 256-byte aligned offsets inside one workspace
 };
 
 struct SceneLayout {
-    size_t pos_id, nrm_id, disk, node, spill, stat, bounds, blk_bounds;
+    size_t pos_id, nrm_id, disk, node, stat, bounds, blk_bounds;
     size_t code0, code1, idx0, idx1, hist, child, range, parent_int, parent_leaf, dbox, ibox, flags;
     size_t total;
 };
@@ -71,6 +71,7 @@ struct SolveDims {
     uint32_t rec_keys;     // keys whose (key, RX) results are kept in RECORD mode
     uint32_t n_slots;      // tape interaction slots: T*K traced + rec_keys*n_rx*K specular
     uint32_t n_slot_chunks;
+    uint32_t spill_lanes;  // lanes of the widest traversal launch of this solve
 };
 
 constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk
@@ -84,6 +85,8 @@ struct SolveLayout {
 };
 
 SolveLayout solve_layout(const SolveDims &D, uint32_t flags);
+uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays);
+uint32_t wide_grid(uint32_t work_units);
 
 struct LaunchArgs {
     DevScene S;

@@ -385,7 +385,7 @@ void launch_keys(const LaunchArgs &A, hipStream_t s) {
 }
 
 void launch_refine(const LaunchArgs &A, hipStream_t s) {
-    const uint32_t grid = std::min<uint32_t>(kWideBlocks, std::max<uint32_t>(A.D.max_key_chunks, 1));
+    const uint32_t grid = wide_grid(A.D.max_key_chunks);
     switch (A.D.K) {
 #define PCRT_REFINE_CASE(KK) \
     case KK: hipLaunchKernelGGL(k_refine<KK>, dim3(grid), dim3(256), 0, s, A); break;

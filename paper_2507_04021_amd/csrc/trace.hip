@@ -132,9 +132,15 @@ __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
     }
 }
 
+uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays) {
+    uint32_t units = (D.T + wave_rays - 1) / wave_rays;
+    return std::min<uint32_t>(kTraceBlocks, std::max<uint32_t>(units, 1));
+}
+
+uint32_t wide_grid(uint32_t work_units) { return std::min<uint32_t>(kWideBlocks, std::max<uint32_t>(work_units, 1)); }
+
 void launch_trace(const LaunchArgs &A, hipStream_t s) {
-    uint32_t units = (A.D.T + A.wave_rays - 1) / A.wave_rays;
-    uint32_t grid = std::min<uint32_t>(kTraceBlocks, std::max<uint32_t>(units, 1));
+    uint32_t grid = trace_grid(A.D, A.wave_rays);
     hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kWave), 0, s, A);
 }
 

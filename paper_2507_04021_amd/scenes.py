@@ -372,12 +372,13 @@ def trajectory(seed: int = 4021, n: int = 256, z: float = 0.5, step: float = 0.1
     return tx.astype(np.float32), rays.astype(np.int64)
 
 
-def hidden_materials(seed: int = 7, n_labels: int = 8) -> np.ndarray:
-    """float64[n_labels, 3]: eps_r ~ U[2,10], sigma ~ log-U[1e-3, 1], S = 0."""
+def hidden_materials(seed: int = 7, n_labels: int = 8, scatter=None) -> np.ndarray:
+    """float64[n_labels, 3]: eps_r ~ U[2,10], sigma ~ log-U[1e-3, 1], S = 0 or ~ U[scatter]."""
     rng = np.random.default_rng(seed)
     eps = rng.uniform(2.0, 10.0, n_labels)
     sig = np.exp(rng.uniform(math.log(1e-3), math.log(1.0), n_labels))
-    return np.stack([eps, sig, np.zeros(n_labels)], 1)
+    S = np.zeros(n_labels) if scatter is None else rng.uniform(scatter[0], scatter[1], n_labels)
+    return np.stack([eps, sig, S], 1)
 
 
 def random_links(seed: int, n_sets: int, n_rx: int, lo=(0.3, 0.3, 0.3), hi=(5.7, 3.7, 2.7)):
