@@ -351,8 +351,9 @@ pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *l
 /* Device time (ms) of the stages of the last PCRT_TIMING solve issued on
  * this host thread: [0] initialisation, [1] ray launch + bounce loop,
  * [2] key marking/compaction, [3] specular refine + validate + field,
- * [4] diffuse connections, [5] line of sight + per-receiver combine.
- * Synchronises with the end of that solve. ms: host double[n], n <= 6. */
+ * [4] Morton ordering of the interaction records, [5] diffuse connections,
+ * [6] line of sight + per-receiver combine.
+ * Synchronises with the end of that solve. ms: host double[n], n <= 7. */
 pcrt_status pcrt_stage_times(double *ms, uint32_t n);
 
 /* Launch directions on the Fibonacci sphere: z = 1 - (2j+1)/N, phi = 2 pi

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpcrt.so")
 LIB_COUNT_PATH = os.path.join(_HERE, "libpcrt_count.so")  # measurement build with visit counters
 
 LOS, SPECULAR, DIFFUSE, RECORD, TIMING = 1, 2, 4, 8, 16
-STAGES = ("init", "trace", "keys", "refine", "diffuse", "los_combine")
+STAGES = ("init", "trace", "keys", "refine", "diffuse_order", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
            tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
            diffuse_disks=14)

@@ -27,7 +27,7 @@ thread_local std::string g_err;
 
 // Per-stage device timing of the last PCRT_TIMING solve on this thread:
 // events around init, trace, keys, refine, diffuse, LOS + combine.
-constexpr int kStages = 6;
+constexpr int kStages = 7;
 thread_local hipEvent_t g_ev[kStages + 1];
 thread_local bool g_ev_ok = false;
 thread_local bool g_ev_used[kStages];
@@ -130,7 +130,7 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     }
     uint64_t nt = p->ray_subset ? p->n_subset : p->n_rays;
     if (nt * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
-    if ((uint64_t)p->n_rx > kSpillLanes) return fail(PCRT_EUNSUPPORTED, "too many receivers");
+    if ((uint64_t)p->n_rx > kMaxPairs) return fail(PCRT_EUNSUPPORTED, "too many receivers");
     return PCRT_OK;
 }
 
@@ -187,8 +187,10 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     }
     // every traversal launch indexes the stack spill by its global lane
     const uint32_t wr = p->wave_rays ? p->wave_rays : kWave;
-    D.spill_lanes = std::max({trace_grid(D, wr) * kWave, wide_grid(D.n_ray_chunks) * 256u,
-                              wide_grid(D.max_key_chunks) * 256u, round_up(D.n_items * D.n_rx, kWave)});
+    D.spill_lanes = std::max({trace_grid(D, wr) * kWave, diffuse_grid(D) * 256u, refine_grid(D) * 256u,
+                              round_up(D.n_items * D.n_rx, kWave)});
+    // a depth-first walk holds at most `depth` entries; the first kStackLds live in LDS
+    D.spill_depth = sc->info.depth > (uint32_t)kStackLds ? sc->info.depth - kStackLds : 0;
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
@@ -261,6 +263,14 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.diff_part = (double *)at(L.diff_part);
     A.los_part = (double *)at(L.los_part);
     A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
+    if (p->flags & PCRT_DIFFUSE) {
+        A.dsort.key0 = (uint64_t *)at(L.dkey0);
+        A.dsort.key1 = (uint64_t *)at(L.dkey1);
+        A.dsort.val0 = (uint32_t *)at(L.dval0);
+        A.dsort.val1 = (uint32_t *)at(L.dval1);
+        A.dsort.hist = (uint32_t *)at(L.dhist);
+        A.dsort.blk = (uint32_t *)at(L.dblk);
+    }
     if (p->flags & PCRT_RECORD) {
         A.slot_label = (uint16_t *)at(L.slot_label);
         A.slot_cos = (float *)at(L.slot_cos);
@@ -290,6 +300,12 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
     L.chunk_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
     L.los_part = b.take(sizeof(double) * 5 * (size_t)D.n_items * D.n_rx);
     if (diff) {
+        L.dkey0 = b.take(sizeof(uint64_t) * nrec);
+        L.dkey1 = b.take(sizeof(uint64_t) * nrec);
+        L.dval0 = b.take(sizeof(uint32_t) * nrec);
+        L.dval1 = b.take(sizeof(uint32_t) * nrec);
+        L.dhist = b.take(sizeof(uint32_t) * radix_hist_words((uint32_t)nrec));
+        L.dblk = b.take(sizeof(uint32_t) * scan_blk_words(radix_hist_words((uint32_t)nrec)));
         L.rec_coef = b.take(sizeof(float4) * nrec);
         L.diff_part = b.take(sizeof(double) * 5 * (size_t)D.n_ray_chunks * D.n_rx);
         if (rec) L.dvis = b.take(nrec * D.n_rx);
@@ -316,7 +332,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.slot_adj = b.take(sizeof(float) * 8 * (size_t)D.n_slots);
         L.grad_part = b.take(sizeof(double) * 3 * kMaxGradLabels * (size_t)std::max<uint32_t>(D.n_slot_chunks, 1));
     }
-    L.spill = b.take(sizeof(int) * (size_t)(kStackMax - kStackLds) * D.spill_lanes);
+    L.spill = b.take(sizeof(int) * (size_t)D.spill_depth * D.spill_lanes);
     L.total = b.off;
     return L;
 }
@@ -400,6 +416,7 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     sc->dev.disk = (const float4 *)(sc->ws + L.disk);
     sc->dev.pos = (const float4 *)(sc->ws + L.pos_id);
     sc->dev.nrm = (const float4 *)(sc->ws + L.nrm_id);
+    sc->dev.bounds = (const float *)(sc->ws + L.bounds);
     sc->dev.r2 = pts->disk_radius * pts->disk_radius;
     sc->dev.n = n;
     sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : 0);
@@ -495,11 +512,13 @@ static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats
     stage_mark(tm, 3, s);
     if (p->flags & PCRT_SPECULAR) launch_refine(A, s);
     stage_mark(tm, 4, s);
-    if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
+    if (p->flags & PCRT_DIFFUSE) A.dsort.order = launch_diffuse_order(A, s);
     stage_mark(tm, 5, s);
+    if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
+    stage_mark(tm, 6, s);
     launch_los_and_combine(A, out->gain, out->h_te, out->h_tm, out->gain_parts, s);
     if (p->flags & PCRT_RECORD) launch_tape_slots(A, s);
-    stage_mark(tm, 6, s);
+    stage_mark(tm, 7, s);
     HIP_TRY(hipGetLastError());
     return ok();
 }
@@ -518,7 +537,7 @@ static pcrt_status check_batch(const pcrt_solve_params *p, const pcrt_batch_item
         total += round_up(items[i].n_rays, kRayChunk);
     }
     if (total * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
-    if ((uint64_t)n_items * p->n_rx > kSpillLanes) return fail(PCRT_EUNSUPPORTED, "too many items x receivers");
+    if ((uint64_t)n_items * p->n_rx > kMaxPairs) return fail(PCRT_EUNSUPPORTED, "too many items x receivers");
     return PCRT_OK;
 }
 

@@ -113,91 +113,6 @@ __global__ void k_morton(const float4 *__restrict__ pos_id, uint32_t n, const fl
     idx[i] = i;
 }
 
-// ----------------------------------------------------------- radix sort
-// LSD, 8-bit digits, 64-bit keys with 32-bit payload. Per pass: tile
-// histograms, one exclusive scan in digit-major order, stable scatter with a
-// wavefront multisplit (8 ballots per key) for the in-tile rank.
-constexpr int kRsBlock = 256;
-constexpr int kRsRounds = 8;
-constexpr int kRsTile = kRsBlock * kRsRounds;
-
-__global__ void k_rs_hist(const uint64_t *__restrict__ key, uint32_t n, int shift, uint32_t *__restrict__ hist,
-                          uint32_t tiles) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t base = blockIdx.x * kRsTile;
-    for (int r = 0; r < kRsRounds; ++r) {
-        uint32_t i = base + r * kRsBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1u);
-    }
-    __syncthreads();
-    hist[threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan of a u32 array in one block of 1024 threads (build only).
-__global__ void k_scan_small(uint32_t *__restrict__ a, uint32_t n) {
-    __shared__ uint32_t part[1024];
-    uint32_t per = (n + 1023) / 1024;
-    uint32_t b = threadIdx.x * per, e = min(n, b + per);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += a[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (uint32_t)o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - s;
-    for (uint32_t i = b; i < e; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
-}
-
-__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                             uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t n, int shift,
-                             const uint32_t *__restrict__ hist, uint32_t tiles) {
-    __shared__ uint32_t base[256], run[256];
-    __shared__ uint32_t wcnt[kRsBlock / kWave][256];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    base[threadIdx.x] = hist[threadIdx.x * tiles + blockIdx.x];
-    run[threadIdx.x] = 0;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kRsRounds; ++r) {
-        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
-        __syncthreads();
-        uint32_t i = blockIdx.x * kRsTile + r * kRsBlock + threadIdx.x;
-        bool ok = i < n;
-        uint64_t k = ok ? kin[i] : 0;
-        uint32_t dg = (uint32_t)(k >> shift) & 255;
-        uint64_t peers = __ballot(ok);
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (dg >> b) & 1;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        uint32_t rank = __popcll(peers & lt);
-        if (ok && rank == 0) wcnt[wave][dg] = __popcll(peers);
-        __syncthreads();
-        if (ok) {
-            uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += wcnt[w][dg];
-            uint32_t dst = base[dg] + run[dg] + before + rank;
-            kout[dst] = k;
-            vout[dst] = vin[i];
-        }
-        __syncthreads();
-        uint32_t tot = 0;
-        for (int w = 0; w < kRsBlock / kWave; ++w) tot += wcnt[w][threadIdx.x];
-        run[threadIdx.x] += tot;
-        __syncthreads();
-    }
-}
-
 // -------------------------------------------------- Karras radix tree
 __device__ __forceinline__ int delta(const uint64_t *k, int n, int i, int j) {
     if (j < 0 || j >= n) return -1;
@@ -346,7 +261,6 @@ SceneLayout scene_layout(uint32_t n) {
     SceneLayout L;
     uint32_t ni = n > 1 ? n - 1 : 1;
     uint32_t blk = cdiv(n, 256);
-    uint32_t tiles = cdiv(n, kRsTile);
     L.pos_id = b.take(sizeof(float4) * n);
     L.nrm_id = b.take(sizeof(float4) * n);
     L.disk = b.take(sizeof(float4) * 2 * n);
@@ -358,7 +272,8 @@ SceneLayout scene_layout(uint32_t n) {
     L.code1 = b.take(sizeof(uint64_t) * n);
     L.idx0 = b.take(sizeof(uint32_t) * n);
     L.idx1 = b.take(sizeof(uint32_t) * n);
-    L.hist = b.take(sizeof(uint32_t) * 256 * (size_t)tiles);
+    L.hist = b.take(sizeof(uint32_t) * radix_hist_words(n));
+    L.scan_blk = b.take(sizeof(uint32_t) * scan_blk_words(radix_hist_words(n)));
     L.child = b.take(sizeof(int2) * ni);
     L.range = b.take(sizeof(int2) * ni);
     L.parent_int = b.take(sizeof(int) * ni);
@@ -379,19 +294,16 @@ hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, 
     uint64_t *c0 = (uint64_t *)P(L.code0), *c1 = (uint64_t *)P(L.code1);
     uint32_t *i0 = (uint32_t *)P(L.idx0), *i1 = (uint32_t *)P(L.idx1);
     uint32_t *hist = (uint32_t *)P(L.hist);
-    uint32_t blk = cdiv(n, 256), tiles = cdiv(n, kRsTile);
+    uint32_t blk = cdiv(n, 256);
     fill_u32(stat, 0, 8, s);
     hipLaunchKernelGGL(k_ingest, dim3(blk), dim3(256), 0, s, pos, nrm, mat, surf, n, pos_id, nrm_id, blkb, stat);
     hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, s, blkb, blk, bounds);
     hipLaunchKernelGGL(k_morton, dim3(blk), dim3(256), 0, s, pos_id, n, bounds, c0, i0);
-    for (int shift = 0; shift < 64; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(tiles), dim3(kRsBlock), 0, s, c0, n, shift, hist, tiles);
-        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, hist, 256 * tiles);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(tiles), dim3(kRsBlock), 0, s, c0, i0, c1, i1, n, shift, hist, tiles);
+    const bool in_tmp = radix_sort_u64(c0, i0, c1, i1, n, 0, 64, hist, (uint32_t *)P(L.scan_blk), s);
+    if (in_tmp) {
         std::swap(c0, c1);
         std::swap(i0, i1);
     }
-    // after 8 passes the sorted data is back in code0/idx0
     float *dbox = (float *)P(L.dbox);
     hipLaunchKernelGGL(k_gather, dim3(blk), dim3(256), 0, s, pos_id, nrm_id, i0, n, r, (float4 *)P(L.disk), dbox);
     if (n > 1) {

@@ -54,6 +54,7 @@ struct DevScene {
     const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, 0)
     const float4 *pos;   // by id: (p.xyz, surface bits)
     const float4 *nrm;   // by id: (n.xyz, material bits)
+    const float *bounds; // scene bounds of the disk centres: lo xyz, hi xyz
     int *spill;          // global spill of traversal stacks, [kStackMax - kStackLds][spill_lanes]
     uint32_t spill_lanes;
     int root;
@@ -109,16 +110,22 @@ __device__ __forceinline__ f3 safe_inv(f3 d) {
 }
 
 // Slab test of one box against [t_lo, t_hi]; returns entry distance in tn.
-__device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 o, f3 inv,
+// oi = o * inv (per ray), so each slab distance is one fused multiply-add
+// lo * inv - o * inv. Its extra rounding, at most |o * inv| * 2^-24, stays far
+// below the boxes' padding (>= 1e-5 * |inv| per axis), so no box that the
+// exact slab test would enter is skipped.
+__device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, float hy, float hz, f3 inv, f3 oi,
                                         float t_lo, float t_hi, float &tn) {
-    float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
-    float ay = (ly - o.y) * inv.y, by = (hy - o.y) * inv.y;
-    float az = (lz - o.z) * inv.z, bz = (hz - o.z) * inv.z;
-    float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t_lo));
-    float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t_hi));
+    const float ax = fmaf(lx, inv.x, -oi.x), bx = fmaf(hx, inv.x, -oi.x);
+    const float ay = fmaf(ly, inv.y, -oi.y), by = fmaf(hy, inv.y, -oi.y);
+    const float az = fmaf(lz, inv.z, -oi.z), bz = fmaf(hz, inv.z, -oi.z);
+    const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t_lo));
+    const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t_hi));
     tn = t0;
     return t0 <= t1;
 }
+
+__device__ __forceinline__ f3 times(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
 
 // Two-sided ray-disk test (Sec. II-C): plane hit t, squared distance of the
 // hit point from the centre.
@@ -143,52 +150,49 @@ struct Cand {
 };
 
 template <bool kSecond>
-__device__ __forceinline__ void visit_leaf(const DevScene &S, int ref, f3 o, f3 d, int excl, float t_lo, float eps_tie,
+__device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d, int excl, float t_lo, float eps_tie,
                                            float &tmin, Cand *c, bool &spill, float t_win, float &best_d2,
                                            int &best_id, float &best_t) {
-    int v = -1 - ref;
-    int first = v >> 3, cnt = (v & 7) + 1;
-    for (int i = 0; i < cnt; ++i) {
-        float4 dp = S.disk[2 * (first + i)];
-        float4 dn = S.disk[2 * (first + i) + 1];
-        int id = __float_as_int(dp.w);
-        if (id == excl) continue;
-        float t, d2;
-        if (!disk_hit(o, d, xyz(dp), xyz(dn), S.r2, t, d2)) continue;
-        if (!(t > t_lo)) continue;
-        if (kSecond) {
-            if (t <= t_win && (d2 < best_d2 || (d2 == best_d2 && id < best_id))) {
-                best_d2 = d2;
-                best_id = id;
-                best_t = t;
-            }
-            continue;
+    const float4 dp = S.disk[2 * i];
+    const float4 dn = S.disk[2 * i + 1];
+    const int id = __float_as_int(dp.w);
+    if (id == excl) return;
+    float t, d2;
+    if (!disk_hit(o, d, xyz(dp), xyz(dn), S.r2, t, d2)) return;
+    if (!(t > t_lo)) return;
+    if (kSecond) {
+        if (t <= t_win && (d2 < best_d2 || (d2 == best_d2 && id < best_id))) {
+            best_d2 = d2;
+            best_id = id;
+            best_t = t;
         }
-        if (t > tmin + eps_tie) continue;
-        if (t < tmin) {
-            tmin = t;
-            float lim = tmin + eps_tie;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (c[k].id >= 0 && c[k].t > lim) c[k].id = -1;
-        }
-        bool placed = false;
+        return;
+    }
+    if (t > tmin + eps_tie) return;
+    if (t < tmin) {
+        tmin = t;
+        const float lim = tmin + eps_tie;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (!placed && c[k].id < 0) {
-                c[k].t = t;
-                c[k].d2 = d2;
-                c[k].id = id;
-                placed = true;
-            }
-        if (!placed) spill = true;
+            if (c[k].id >= 0 && c[k].t > lim) c[k].id = -1;
     }
+    bool placed = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (!placed && c[k].id < 0) {
+            c[k].t = t;
+            c[k].d2 = d2;
+            c[k].id = id;
+            placed = true;
+        }
+    if (!placed) spill = true;
 }
 
 template <bool kSecond>
 __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, f3 inv, int excl, float t_lo,
                                                  float eps_tie, Stack &stk, float &tmin, Cand *c, bool &spill,
                                                  float t_win, float &best_d2, int &best_id, float &best_t) {
+    const f3 oi = times(o, inv);
     int ref = S.root;
     int sp = 0;
     for (;;) {
@@ -198,8 +202,8 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
             float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
             float tc = kSecond ? t_win : tmin + eps_tie;
             float n0, n1;
-            bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, t_lo, tc, n0);
-            bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, o, inv, t_lo, tc, n1);
+            bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, t_lo, tc, n0);
+            bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, inv, oi, t_lo, tc, n1);
             int r0 = __float_as_int(r.x), r1 = __float_as_int(r.y);
             if (h0 && h1) {
                 bool f0 = n0 <= n1;
@@ -210,8 +214,12 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
             if (h0) { ref = r0; continue; }
             if (h1) { ref = r1; continue; }
         } else {
-            stk.test((((-1 - ref) & 7) + 1));
-            visit_leaf<kSecond>(S, ref, o, d, excl, t_lo, eps_tie, tmin, c, spill, t_win, best_d2, best_id, best_t);
+            const int v = -1 - ref;
+            const int first = v >> 3, cnt = (v & 7) + 1;
+            stk.test(cnt);
+            for (int i = 0; i < cnt; ++i)
+                visit_disk<kSecond>(S, first + i, o, d, excl, t_lo, eps_tie, tmin, c, spill, t_win, best_d2, best_id,
+                                    best_t);
         }
         if (sp == 0) break;
         ref = stk.get(--sp);
@@ -258,6 +266,7 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     f3 inv = safe_inv(d);
     float t_hi = L - eps_self;
     if (!(t_hi > eps_self)) return false;
+    const f3 oi = times(a, inv);
     int ref = S.root;
     int sp = 0;
     for (;;) {
@@ -266,8 +275,8 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
             const float4 *nd = S.node + 4 * (size_t)ref;
             float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
             float n0, n1;
-            bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, a, inv, eps_self, t_hi, n0);
-            bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, a, inv, eps_self, t_hi, n1);
+            bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, eps_self, t_hi, n0);
+            bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, eps_self, t_hi, n1);
             int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
             if (h0 && h1) {
                 bool f0 = n0 <= n1;
@@ -278,12 +287,12 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
             if (h0) { ref = r0; continue; }
             if (h1) { ref = r1; continue; }
         } else {
-            int v = -1 - ref;
-            int first = v >> 3, cnt = (v & 7) + 1;
+            const int v = -1 - ref;
+            const int first = v >> 3, cnt = (v & 7) + 1;
             stk.test(cnt);
             for (int i = 0; i < cnt; ++i) {
-                float4 dp = S.disk[2 * (first + i)];
-                float4 dn = S.disk[2 * (first + i) + 1];
+                const float4 dp = S.disk[2 * (first + i)];
+                const float4 dn = S.disk[2 * (first + i) + 1];
                 if (__float_as_int(dp.w) == excl) continue;
                 float t, d2;
                 if (disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2) && t > eps_self && t < t_hi) return true;
@@ -365,6 +374,18 @@ struct FieldConst {
     float inv_lam_lo;   // 1/lambda, low part
     float inv_we0;      // 1 / (omega eps0)
 };
+
+// LDS written by some lanes of a wavefront is visible to the others after this.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {  // fixed xor-butterfly order
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
 
 __device__ __forceinline__ float warp_sum_f(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

@@ -12,88 +12,144 @@
 
 namespace pcrt {
 
-// Blocks of 256 lanes take one chunk of kRayChunk rays at a time. Lane t
-// serves receiver r0 + t % nr for group t / nr; the records of the chunk are
-// dealt to the groups round robin. For 64 receivers a wavefront handles one
-// interaction point against all receivers (one origin, coherent traversal).
+// Diffuse connections (Sec. II-B.1): each interaction point is joined to
+// every receiver on its lit side; a connection counts if nothing lies on the
+// open segment between them (any-hit, two-sided disks, the point's own disk
+// excluded, eps_self trimmed at both ends).
+//
+// Mapping. The records are first put in Morton order of their hit points,
+// with the transmitter index as the high key bits: a transmitter's records
+// keep their range of chunks and only their order inside it changes, so the
+// per-chunk partial sums still add up per transmitter. A wavefront takes 64
+// spatially adjacent interaction points and one receiver at a time, and each
+// lane walks its segment FROM THE RECEIVER towards its interaction point (the
+// test is symmetric in the two end points). All 64 walks then start at the
+// same point with nearly the same direction, make the same near-child
+// choices through the upper tree and only part near their own end points,
+// which keeps the lanes of a wavefront on the same nodes for most of the walk.
+//
+// Sums: per (wavefront, receiver) a fixed xor-butterfly over the lanes; lane
+// r of the wavefront keeps receiver r's running sum over its record groups in
+// order; the four wavefronts of a block are added in order into the chunk's
+// partial sum. The result does not depend on timing.
+__global__ void k_diffuse_keys(LaunchArgs A) {
+    const uint32_t n_rec = A.D.T * A.D.K;
+    const float *B = A.S.bounds;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rec; r += gridDim.x * blockDim.x) {
+        const uint32_t it = (uint32_t)find_item(A.items, A.D.n_items, r / A.D.K);
+        uint32_t code = 0xffffffffu;
+        if (A.rb.id[r] >= 0) {
+            const float4 x = A.rb.xl[r];
+            const float c[3] = {x.x, x.y, x.z};
+            uint32_t q[3];
+            for (int a = 0; a < 3; ++a) {
+                const float ext = B[3 + a] - B[a];
+                float u = ext > 0.f ? (c[a] - B[a]) / ext : 0.5f;
+                u = fminf(fmaxf(u, 0.f), 1.f);
+                uint32_t v = (uint32_t)(u * 1023.f);
+                v = (v | v << 16) & 0x030000ffu;
+                v = (v | v << 8) & 0x0300f00fu;
+                v = (v | v << 4) & 0x030c30c3u;
+                v = (v | v << 2) & 0x09249249u;
+                q[a] = v;
+            }
+            code = q[0] << 2 | q[1] << 1 | q[2];
+        }
+        A.dsort.key0[r] = (uint64_t)it << 32 | code;
+        A.dsort.val0[r] = r;
+    }
+}
+
+__device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t ri, f3 rx, float budget, double *v5) {
+    const float4 xl = A.rb.xl[ri];
+    f3 n = xyz(A.S.nrm[A.rb.id[ri]]);
+    if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+    const f3 v = rx - xyz(xl);
+    const float rs = len(v);
+    const float cos_s = dot(v, n) / rs;
+    const float a0 = sqrtf(4.f * cos_s / budget) / rs;
+    const c32 ph = propagate(xl.w + rs, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+    const float4 cf = A.rb.coef[ri];
+    const c32 te = cmul({a0 * cf.x, a0 * cf.y}, ph);
+    const c32 tm = cmul({a0 * cf.z, a0 * cf.w}, ph);
+    const double tr = te.re, ti = te.im, mr = tm.re, mi = tm.im;
+    v5[0] = 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+    v5[1] = tr;
+    v5[2] = ti;
+    v5[3] = mr;
+    v5[4] = mi;
+}
+
+constexpr int kDiffRxSlice = 64;
+
 __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
-    // traversal stacks and the FP64 reduction buffer share LDS (never live together)
+    // traversal stacks, per-wave receiver sums and the chunk index share LDS
+    // (never live together): 32 KiB per block
     __shared__ union {
         int stack[4][kStackLds * kWave];
-        double red[256][5];
+        double red[4][kDiffRxSlice][5];
+        uint32_t chunk;
     } sm;
-    auto &lds_stack = sm.stack;
-    auto &red = sm.red;
-    __shared__ uint32_t s_chunk;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t glane = blockIdx.x * 256 + tid;
-    Stack stk{lds_stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
+    Stack stk{sm.stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
     const uint32_t K = A.D.K, n_rx = A.D.n_rx;
     const uint32_t n_chunks = A.D.n_ray_chunks;
     const bool rec = A.flags & 8;
+    const float eps = A.thr.eps_self;
+    const uint32_t n_groups = kRayChunk * K / kWave;  // groups of 64 records per chunk
     uint32_t n_seg = 0, n_vis = 0;
     for (;;) {
-        if (tid == 0) s_chunk = atomicAdd(&A.work[2], 1u);
+        if (tid == 0) sm.chunk = atomicAdd(&A.work[2], 1u);
         __syncthreads();
-        const uint32_t c = s_chunk;
+        const uint32_t c = sm.chunk;
         __syncthreads();
         if (c >= n_chunks) break;
         const uint32_t g0 = c * kRayChunk;
         const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
         const float budget = (float)I.budget;
-        const uint32_t rec0 = g0 * K, nrec = kRayChunk * K;
-        for (uint32_t r0 = 0; r0 < n_rx; r0 += 256) {
-            const uint32_t nr = min(256u, n_rx - r0);
-            const uint32_t G = 256 / nr;
-            const uint32_t grp = tid / nr, r = r0 + tid % nr;
-            double acc[5] = {0, 0, 0, 0, 0};
-            if (grp < G) {
-                const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-                for (uint32_t e = grp; e < nrec; e += G) {
-                    const uint32_t ri = rec0 + e;
-                    const int id = A.rb.id[ri];
+        for (uint32_t r0 = 0; r0 < n_rx; r0 += kDiffRxSlice) {
+            const uint32_t nr = min((uint32_t)kDiffRxSlice, n_rx - r0);
+            double acc[5] = {0, 0, 0, 0, 0};  // lane l: receiver r0 + l
+            for (uint32_t q = wave; q < n_groups; q += 4) {
+                const uint32_t ri = A.dsort.order[g0 * K + q * kWave + lane];
+                const int id = A.rb.id[ri];
+                f3 x = mk(0.f, 0.f, 0.f), n = mk(0.f, 0.f, 1.f);
+                if (id >= 0) {
+                    x = xyz(A.rb.xl[ri]);
+                    n = xyz(A.S.nrm[id]);
+                    if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+                }
+                for (uint32_t rr = 0; rr < nr; ++rr) {
+                    const uint32_t r = r0 + rr;
+                    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
                     bool vis = false;
-                    if (id >= 0) {
-                        const float4 xl = A.rb.xl[ri];
-                        const float cs = A.rb.cs[ri];
-                        const f3 x = xyz(xl);
-                        f3 n = xyz(A.S.nrm[id]);
-                        if (cs < 0.f) n = (-1.f) * n;
-                        const f3 v = rx - x;
-                        const float vn = dot(v, n);
-                        if (vn > 0.f) {
-                            ++n_seg;
-                            if (!occluded(A.S, x, rx, id, A.thr.eps_self, stk)) {
-                                vis = true;
-                                ++n_vis;
-                                const float rs = len(v);
-                                const float cos_s = vn / rs;
-                                const float a0 = sqrtf(4.f * cos_s / budget) / rs;
-                                const c32 ph = propagate(xl.w + rs, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
-                                const float4 cf = A.rb.coef[ri];
-                                const c32 te = cmul({a0 * cf.x, a0 * cf.y}, ph);
-                                const c32 tm = cmul({a0 * cf.z, a0 * cf.w}, ph);
-                                const double tr = te.re, ti = te.im, mr = tm.re, mi = tm.im;
-                                acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
-                                acc[1] += tr;
-                                acc[2] += ti;
-                                acc[3] += mr;
-                                acc[4] += mi;
-                            }
-                        }
+                    if (id >= 0 && dot(rx - x, n) > 0.f) {
+                        ++n_seg;
+                        vis = !occluded(A.S, rx, x, id, eps, stk);
                     }
                     if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
+                    if (!__ballot(vis)) continue;
+                    double v5[5] = {0, 0, 0, 0, 0};
+                    if (vis) {
+                        ++n_vis;
+                        diffuse_amplitude(A, ri, rx, budget, v5);
+                    }
+                    for (int a = 0; a < 5; ++a) {
+                        const double sv = wave_sum_d(v5[a]);
+                        if ((uint32_t)lane == rr) acc[a] += sv;
+                    }
                 }
             }
             __syncthreads();  // every wave is done with its stack
-            for (int a = 0; a < 5; ++a) red[tid][a] = acc[a];
+            for (int a = 0; a < 5; ++a) sm.red[wave][lane][a] = acc[a];
             __syncthreads();
             if ((uint32_t)tid < nr) {
-                double s[5] = {0, 0, 0, 0, 0};
-                for (uint32_t gg = 0; gg < G; ++gg)
-                    for (int a = 0; a < 5; ++a) s[a] += red[gg * nr + tid][a];
+                double sum[5] = {0, 0, 0, 0, 0};
+                for (int w = 0; w < 4; ++w)
+                    for (int a = 0; a < 5; ++a) sum[a] += sm.red[w][tid][a];
                 double *o = A.diff_part + ((size_t)c * n_rx + r0 + tid) * 5;
-                for (int a = 0; a < 5; ++a) o[a] = s[a];
+                for (int a = 0; a < 5; ++a) o[a] = sum[a];
             }
             __syncthreads();
         }
@@ -107,11 +163,26 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
     }
 }
 
-void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
-    hipLaunchKernelGGL(k_diffuse, dim3(wide_grid(A.D.n_ray_chunks)), dim3(256), 0, s, A);
+uint32_t diffuse_grid(const SolveDims &D) {
+    static const uint32_t cap = resident_blocks((const void *)k_diffuse, 256);
+    return std::max<uint32_t>(1, std::min(cap, D.n_ray_chunks));
 }
 
-// Line of sight per (transmitter, receiver): a_TE = a_TM = lambda/(4 pi d) e^{-j k0 d}.
+const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s) {
+    const uint32_t n_rec = A.D.T * A.D.K;
+    hipLaunchKernelGGL(k_diffuse_keys, dim3(std::min<uint32_t>((n_rec + 255) / 256, 8192)), dim3(256), 0, s, A);
+    int item_bits = 0;
+    while ((1u << item_bits) < A.D.n_items) ++item_bits;
+    const int hi = 32 + 8 * ((item_bits + 7) / 8);  // 30 Morton bits, then the transmitter index
+    const bool in1 = radix_sort_u64(A.dsort.key0, A.dsort.val0, A.dsort.key1, A.dsort.val1, n_rec, 0, hi,
+                                    A.dsort.hist, A.dsort.blk, s);
+    return in1 ? A.dsort.val1 : A.dsort.val0;
+}
+
+void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
+    hipLaunchKernelGGL(k_diffuse, dim3(diffuse_grid(A.D)), dim3(256), 0, s, A);
+}
+
 __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
     const int lane = threadIdx.x;

@@ -11,10 +11,11 @@
 
 namespace pcrt {
 
-// Persistent launches: fixed grids whose waves pull work from an atomic counter.
-constexpr uint32_t kTraceBlocks = 4096;  // 64-lane blocks
-constexpr uint32_t kWideBlocks = 1024;   // 256-lane blocks
-constexpr uint32_t kSpillLanes = 262144; // >= lanes of any persistent launch
+// Persistent launches: grids of as many blocks as the device holds at once
+// (blocks per compute unit from the occupancy API x compute units); their
+// waves pull work from atomic counters until it runs out.
+uint32_t resident_blocks(const void *kernel, int block_threads);
+constexpr uint32_t kMaxPairs = 262144;  // (transmitter, receiver) pairs in one solve
 
 struct Bump {  // 256-byte aligned offsets inside one workspace
     size_t off = 0;
@@ -27,7 +28,7 @@ struct Bump {  // 256-byte aligned offsets inside one workspace
 
 struct SceneLayout {
     size_t pos_id, nrm_id, disk, node, stat, bounds, blk_bounds;
-    size_t code0, code1, idx0, idx1, hist, child, range, parent_int, parent_leaf, dbox, ibox, flags;
+    size_t code0, code1, idx0, idx1, hist, scan_blk, child, range, parent_int, parent_leaf, dbox, ibox, flags;
     size_t total;
 };
 
@@ -35,6 +36,11 @@ SceneLayout scene_layout(uint32_t n);
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
                        float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+uint32_t scan_blk_words(uint32_t n);
+uint32_t radix_hist_words(uint32_t n);
+void exclusive_scan(uint32_t *a, uint32_t n, uint32_t *blk, hipStream_t s);
+bool radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint32_t n, int bit_lo, int bit_hi,
+                    uint32_t *hist, uint32_t *blk, hipStream_t s);
 void fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 
 // Per-(ray, interaction) records, dense [T * K].
@@ -72,6 +78,7 @@ struct SolveDims {
     uint32_t n_slots;      // tape interaction slots: T*K traced + rec_keys*n_rx*K specular
     uint32_t n_slot_chunks;
     uint32_t spill_lanes;  // lanes of the widest traversal launch of this solve
+    uint32_t spill_depth;  // traversal stack entries beyond the LDS part (depth - kStackLds)
 };
 
 constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk
@@ -80,13 +87,20 @@ constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 l
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
         key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
-        slot_label, slot_cos, slot_coef, slot_adj, grad_part;
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk;
     size_t total;
 };
 
 SolveLayout solve_layout(const SolveDims &D, uint32_t flags);
 uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays);
-uint32_t wide_grid(uint32_t work_units);
+uint32_t refine_grid(const SolveDims &D);
+uint32_t diffuse_grid(const SolveDims &D);
+
+struct SortBufs {  // spatial ordering of the diffuse records
+    uint64_t *key0, *key1;
+    uint32_t *val0, *val1, *hist, *blk;
+    const uint32_t *order;  // sorted record indices (set by the launcher)
+};
 
 struct LaunchArgs {
     DevScene S;
@@ -120,12 +134,15 @@ struct LaunchArgs {
     float *slot_coef;      // [n_slots][8]: Gamma_TE re, im, Gamma_TM re, im, S
     float *slot_adj;       // [n_slots][8]: dL/d of the same values
     double *grad_part;     // [n_slot_chunks][kMaxGradLabels][3]
+    SortBufs dsort;
 };
 
 void launch_trace(const LaunchArgs &A, hipStream_t s);
 void launch_keys(const LaunchArgs &A, hipStream_t s);
 void launch_refine(const LaunchArgs &A, hipStream_t s);
-void launch_diffuse(const LaunchArgs &A, hipStream_t s);
+// Morton order of the interaction records (returns the sorted record indices)
+const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s);
+void launch_diffuse(const LaunchArgs &A, hipStream_t s);  // needs A.dsort.order
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                             hipStream_t s);
 void launch_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts, hipStream_t s);

@@ -41,52 +41,6 @@ __global__ void k_mark(LaunchArgs A, uint32_t n_rec) {
     A.scan[r] = f;
 }
 
-// Device-wide exclusive scan: per-1024-element block scan, scan of the block
-// sums, add-back.
-__global__ __launch_bounds__(1024) void k_scan_block(uint32_t *a, uint32_t n, uint32_t *blk) {
-    __shared__ uint32_t s[1024];
-    uint32_t i = blockIdx.x * 1024 + threadIdx.x;
-    uint32_t v = i < n ? a[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (i < n) a[i] = s[threadIdx.x] - v;
-    if (threadIdx.x == 1023) blk[blockIdx.x] = s[1023];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t *a, uint32_t n, uint32_t *total) {
-    __shared__ uint32_t part[1024];
-    uint32_t per = (n + 1023) / 1024;
-    uint32_t b = threadIdx.x * per, e = min(n, b + per);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += a[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = threadIdx.x >= (uint32_t)o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - s;
-    for (uint32_t i = b; i < e; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    if (threadIdx.x == 1023) *total = part[1023];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_add(uint32_t *a, uint32_t n, const uint32_t *blk) {
-    uint32_t i = blockIdx.x * 1024 + threadIdx.x;
-    if (i < n) a[i] += blk[blockIdx.x];
-}
-
 // keylist[scan[r]] = r for every marked record (mark = scan[r+1] - scan[r]).
 __global__ void k_compact(LaunchArgs A, uint32_t n_rec, const uint32_t *total) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,37 +131,53 @@ struct PairOut {
     c32 te, tm;
 };
 
+// The representative's interaction planes of key q (its first k hit disks).
 template <int KM>
-__device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, Stack &stk, PairOut &po,
-                           uint32_t &n_cand) {
-    po.valid = false;
+struct KeyPlanes {
+    f3 pp[KM], pn[KM];
+    uint32_t ks[KM];  // surface labels
+    int k;
+};
+
+template <int KM>
+__device__ __forceinline__ void load_planes(const LaunchArgs &A, uint32_t q, KeyPlanes<KM> &kp) {
     const uint32_t K = A.D.K;
     const uint32_t rec = A.keylist[q];
     const uint32_t g = rec / K;
-    const int k = (int)(rec % K) + 1;
-    f3 pp[KM], pn[KM];
-    uint32_t ks[KM];
+    kp.k = (int)(rec % K) + 1;
 #pragma unroll
     for (int m = 0; m < KM; ++m)
-        if (m < k) {
-            int id = A.rb.id[(size_t)g * K + m];
-            float4 p4 = A.S.pos[id];
-            pp[m] = xyz(p4);
-            ks[m] = __float_as_uint(p4.w);
-            pn[m] = xyz(A.S.nrm[id]);
+        if (m < kp.k) {
+            const int id = A.rb.id[(size_t)g * K + m];
+            const float4 p4 = A.S.pos[id];
+            kp.pp[m] = xyz(p4);
+            kp.ks[m] = __float_as_uint(p4.w);
+            kp.pn[m] = xyz(A.S.nrm[id]);
         }
+}
+
+__device__ __forceinline__ f3 rx_point(const LaunchArgs &A, uint32_t r) {
+    return mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+}
+
+// Validation and field of one (key, receiver) candidate whose first image
+// solution exists: a ray from each point to the next must hit a disk of the
+// expected surface, close in angle (t_a) and plane distance (t_d); otherwise
+// the plane is replaced by the hit disk's and the image solution recomputed,
+// at most kappa times. The last point must see the receiver.
+template <int KM>
+__device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, KeyPlanes<KM> kp,
+                              Stack &stk, PairOut &po) {
+    po.valid = false;
+    const uint32_t K = A.D.K;
+    const int k = kp.k;
     const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
-    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+    const f3 rx = rx_point(A, r);
     f3 x[KM + 1];
     int hid[KM];
     int retries = 0;
-    bool counted = false;
     for (;;) {
-        if (!refine_planes<KM>(k, tx, rx, pp, pn, A.thr.eps_self, x)) return;
-        if (!counted) {
-            ++n_cand;
-            counted = true;
-        }
+        if (!refine_planes<KM>(k, tx, rx, kp.pp, kp.pn, A.thr.eps_self, x)) return;
         int prev = -1;
         bool retry = false, fail = false;
 #pragma unroll
@@ -219,16 +189,16 @@ __device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const It
             int h = closest_hit(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
             if (h < 0) { fail = true; continue; }
             float4 hp = A.S.pos[h];
-            if (__float_as_uint(hp.w) != ks[m - 1]) { fail = true; continue; }
+            if (__float_as_uint(hp.w) != kp.ks[m - 1]) { fail = true; continue; }
             f3 hn = xyz(A.S.nrm[h]);
             f3 qh = x[m - 1] + t * u;
-            bool ang_ok = fabsf(dot(hn, pn[m - 1])) >= A.thr.cos_ta;
-            bool dist_ok = fabsf(dot(qh - pp[m - 1], pn[m - 1])) <= A.thr.t_d;
+            bool ang_ok = fabsf(dot(hn, kp.pn[m - 1])) >= A.thr.cos_ta;
+            bool dist_ok = fabsf(dot(qh - kp.pp[m - 1], kp.pn[m - 1])) <= A.thr.t_d;
             if (!(ang_ok && dist_ok)) {
                 if (retries >= A.thr.kappa) { fail = true; continue; }
                 ++retries;
-                pp[m - 1] = xyz(hp);
-                pn[m - 1] = hn;
+                kp.pp[m - 1] = xyz(hp);
+                kp.pn[m - 1] = hn;
                 retry = true;
                 continue;
             }
@@ -257,7 +227,7 @@ __device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const It
         f3 seg = x[m] - x[m - 1];
         float sl = len(seg);
         L += sl;
-        float c = fabsf(dot((1.0f / sl) * seg, pn[m - 1]));
+        float c = fabsf(dot((1.0f / sl) * seg, kp.pn[m - 1]));
         csv[m - 1] = c;
         uint32_t lab = __float_as_uint(A.S.nrm[hid[m - 1]].w);
         if (lab >= A.n_labels) lab = 0;
@@ -286,28 +256,42 @@ __device__ void solve_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const It
     }
 }
 
-// Persistent blocks of 256 lanes; each takes a key chunk and evaluates all
-// (key, RX) pairs of it, accumulating FP64 sums per RX in a fixed order.
+// Persistent blocks of 256 lanes take one key chunk at a time. For each
+// slice of up to 64 receivers, the chunk's (key, receiver) pairs are dealt to
+// the four wavefronts in tiles of 64. A wavefront first solves the image
+// method for its tile (cheap, no traversal) and appends the pairs that have a
+// solution to a queue in LDS, in pair order; whenever 64 are queued, all 64
+// lanes validate one each. Most pairs fail the image test, so this keeps the
+// traversals -- the expensive part -- on full wavefronts.
+//
+// Sums: every batch's results go to LDS, and lane r adds those of receiver
+// r in queue order, i.e. in increasing key order; the four wavefronts'
+// sums are added in order into the chunk's partial sum. The result does not
+// depend on timing.
+constexpr int kRefineRxSlice = 64;
+
 template <int KM>
 __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
-    // traversal stacks and the FP64 reduction buffer share LDS (never live together)
+    // traversal stacks, per-wave receiver sums and the chunk index share LDS
     __shared__ union {
         int stack[4][kStackLds * kWave];
-        double red[256][5];
+        double red[4][kRefineRxSlice][5];
+        uint32_t chunk;
     } sm;
-    auto &lds_stack = sm.stack;
-    auto &red = sm.red;
-    __shared__ uint32_t s_chunk;
+    __shared__ uint32_t queue[4][2 * kWave];  // pair indices within the slice
+    __shared__ float4 res[4][kWave];          // a batch's TE and TM amplitudes
+    __shared__ int res_rx[4][kWave];          // its receiver in the slice, -1 if not a path
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t glane = blockIdx.x * 256 + tid;
-    Stack stk{lds_stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
+    Stack stk{sm.stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
     const uint32_t n_rx = A.D.n_rx, n_items = A.D.n_items;
     const uint32_t n_chunks = A.chunk_off[n_items];
+    const bool rec = A.flags & 8;
     uint32_t n_cand = 0, n_valid = 0;
     for (;;) {
-        if (tid == 0) s_chunk = atomicAdd(&A.work[1], 1u);
+        if (tid == 0) sm.chunk = atomicAdd(&A.work[1], 1u);
         __syncthreads();
-        const uint32_t c = s_chunk;
+        const uint32_t c = sm.chunk;
         __syncthreads();
         if (c >= n_chunks) break;
         // item of this chunk
@@ -319,45 +303,102 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
         }
         const int it = lo;
         const Item I = A.items[it];
+        const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
         const uint32_t q0 = A.key_off[it] + (c - A.chunk_off[it]) * kKeyChunk;
         const uint32_t q1 = min(q0 + kKeyChunk, A.key_off[it + 1]);
-        for (uint32_t r0 = 0; r0 < n_rx; r0 += 256) {
-            const uint32_t nr = min(256u, n_rx - r0);
-            const uint32_t G = 256 / nr;
-            const uint32_t grp = tid / nr, r = r0 + tid % nr;
-            double acc[5] = {0, 0, 0, 0, 0};
-            if (grp < G) {
-                for (uint32_t q = q0 + grp; q < q1; q += G) {
-                    PairOut po;
-                    solve_pair<KM>(A, q, r, I, stk, po, n_cand);
-                    if ((A.flags & 8) && q >= A.D.rec_keys) {
-                        atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
-                    } else if (A.flags & 8) {
-                        size_t p = (size_t)q * n_rx + r;
+        for (uint32_t r0 = 0; r0 < n_rx; r0 += kRefineRxSlice) {
+            const uint32_t nr = min((uint32_t)kRefineRxSlice, n_rx - r0);
+            const uint32_t ne = (q1 - q0) * nr;  // pairs of this slice, e = key * nr + receiver
+            double acc[5] = {0, 0, 0, 0, 0};     // lane l: receiver r0 + l
+            uint32_t qn = 0;                     // queued candidates (wave-uniform)
+            auto run_batch = [&](uint32_t nb) {
+                PairOut po;
+                po.valid = false;
+                int rr = -1;
+                if ((uint32_t)lane < nb) {
+                    const uint32_t e = queue[wave][lane];
+                    const uint32_t q = q0 + e / nr;
+                    rr = (int)(e % nr);
+                    KeyPlanes<KM> kp;
+                    load_planes<KM>(A, q, kp);
+                    validate_pair<KM>(A, q, r0 + rr, I, kp, stk, po);
+                    if (rec && q < A.D.rec_keys) {
+                        const size_t p = (size_t)q * n_rx + r0 + rr;
                         A.sb.valid[p] = po.valid;
                         A.sb.len[p] = po.valid ? po.len : 0.f;
                         A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
                                                : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
-                    if (!po.valid) continue;
-                    ++n_valid;
-                    double tr = po.te.re, ti = po.te.im, mr = po.tm.re, mi = po.tm.im;
-                    acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
-                    acc[1] += tr;
-                    acc[2] += ti;
-                    acc[3] += mr;
-                    acc[4] += mi;
+                    n_valid += po.valid;
                 }
+                res[wave][lane] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
+                res_rx[wave][lane] = po.valid ? rr : -1;
+                wave_sync();
+                for (uint32_t j = 0; j < nb; ++j)
+                    if (res_rx[wave][j] == lane) {
+                        const float4 v = res[wave][j];
+                        const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
+                        acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+                        acc[1] += tr;
+                        acc[2] += ti;
+                        acc[3] += mr;
+                        acc[4] += mi;
+                    }
+                wave_sync();
+            };
+            // one code path for the image test of a tile and for a batch, so
+            // that the validation is inlined once
+            for (uint32_t t = wave;;) {
+                const bool more = t * kWave < ne;
+                if (more) {
+                    const uint32_t e = t * kWave + lane;
+                    bool cand = false;
+                    if (e < ne) {
+                        const uint32_t q = q0 + e / nr, r = r0 + e % nr;
+                        KeyPlanes<KM> kp;
+                        load_planes<KM>(A, q, kp);
+                        f3 x[KM + 1];
+                        cand = refine_planes<KM>(kp.k, tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
+                        if (rec) {
+                            if (q >= A.D.rec_keys) {
+                                atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
+                            } else if (!cand) {
+                                const size_t p = (size_t)q * n_rx + r;
+                                A.sb.valid[p] = 0;
+                                A.sb.len[p] = 0.f;
+                                A.sb.amp[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                            }
+                        }
+                    }
+                    n_cand += cand;
+                    const uint64_t m = __ballot(cand);
+                    const uint32_t pos = qn + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+                    if (cand) queue[wave][pos] = e;
+                    qn += (uint32_t)__popcll(m);
+                    wave_sync();
+                    t += 4;
+                }
+                if (qn >= (uint32_t)kWave || (!more && qn > 0)) {
+                    const uint32_t nb = min(qn, (uint32_t)kWave);
+                    run_batch(nb);
+                    const uint32_t left = qn - nb;
+                    const uint32_t v = (uint32_t)lane < left ? queue[wave][nb + lane] : 0u;
+                    wave_sync();
+                    if ((uint32_t)lane < left) queue[wave][lane] = v;
+                    wave_sync();
+                    qn = left;
+                }
+                if (!more && qn == 0) break;
             }
             __syncthreads();  // every wave is done with its stack
-            for (int a = 0; a < 5; ++a) red[tid][a] = acc[a];
+            for (int a = 0; a < 5; ++a) sm.red[wave][lane][a] = acc[a];
             __syncthreads();
             if ((uint32_t)tid < nr) {
-                double s[5] = {0, 0, 0, 0, 0};
-                for (uint32_t gg = 0; gg < G; ++gg)
-                    for (int a = 0; a < 5; ++a) s[a] += red[gg * nr + tid][a];
+                double sum[5] = {0, 0, 0, 0, 0};
+                for (int w = 0; w < 4; ++w)
+                    for (int a = 0; a < 5; ++a) sum[a] += sm.red[w][tid][a];
                 double *o = A.spec_part + ((size_t)c * n_rx + r0 + tid) * 5;
-                for (int a = 0; a < 5; ++a) o[a] = s[a];
+                for (int a = 0; a < 5; ++a) o[a] = sum[a];
             }
             __syncthreads();
         }
@@ -377,15 +418,34 @@ void launch_keys(const LaunchArgs &A, hipStream_t s) {
     hipLaunchKernelGGL(k_mark, dim3(blk), dim3(256), 0, s, A, n_rec);
     const uint32_t nb = (n_rec + 1023) / 1024;
     uint32_t *total = A.scan_blk + nb;
-    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(1024), 0, s, A.scan, n_rec, A.scan_blk);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, A.scan_blk, nb, total);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, A.scan, n_rec, A.scan_blk);
+    exclusive_scan(A.scan, n_rec, A.scan_blk, s);
     hipLaunchKernelGGL(k_compact, dim3(blk), dim3(256), 0, s, A, n_rec, total);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, A, total);
 }
 
+template <int KM>
+uint32_t refine_cap() {
+    static const uint32_t cap = resident_blocks((const void *)k_refine<KM>, 256);
+    return cap;
+}
+
+uint32_t refine_grid(const SolveDims &D) {
+    uint32_t cap = 0;
+    switch (D.K) {
+        case 1: cap = refine_cap<1>(); break;
+        case 2: cap = refine_cap<2>(); break;
+        case 3: cap = refine_cap<3>(); break;
+        case 4: cap = refine_cap<4>(); break;
+        case 5: cap = refine_cap<5>(); break;
+        case 6: cap = refine_cap<6>(); break;
+        case 7: cap = refine_cap<7>(); break;
+        default: cap = refine_cap<8>(); break;
+    }
+    return std::max<uint32_t>(1, std::min(cap, D.max_key_chunks));
+}
+
 void launch_refine(const LaunchArgs &A, hipStream_t s) {
-    const uint32_t grid = wide_grid(A.D.max_key_chunks);
+    const uint32_t grid = refine_grid(A.D);
     switch (A.D.K) {
 #define PCRT_REFINE_CASE(KK) \
     case KK: hipLaunchKernelGGL(k_refine<KK>, dim3(grid), dim3(256), 0, s, A); break;

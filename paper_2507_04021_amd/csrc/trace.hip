@@ -132,12 +132,22 @@ __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
     }
 }
 
-uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays) {
-    uint32_t units = (D.T + wave_rays - 1) / wave_rays;
-    return std::min<uint32_t>(kTraceBlocks, std::max<uint32_t>(units, 1));
+uint32_t resident_blocks(const void *kernel, int block_threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 2048;  // no device to ask: an upper bound for 256 compute units
+    }
+    return (uint32_t)std::max(per_cu, 1) * (uint32_t)std::max(cus, 1);
 }
 
-uint32_t wide_grid(uint32_t work_units) { return std::min<uint32_t>(kWideBlocks, std::max<uint32_t>(work_units, 1)); }
+uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays) {
+    static const uint32_t cap = resident_blocks((const void *)k_trace, kWave);
+    const uint32_t units = (D.T + wave_rays - 1) / wave_rays;
+    return std::max<uint32_t>(1, std::min(cap, units));
+}
 
 void launch_trace(const LaunchArgs &A, hipStream_t s) {
     uint32_t grid = trace_grid(A.D, A.wave_rays);
