@@ -25,6 +25,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays·interactions/s and ms per scene solve (1M pts, 5 bounces); grad-step ms"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+# Algorithmic FP32 operations per unit of traversal work (add, mul, min, max,
+# compare = 1, a fused multiply-add = 2, as in the FLOP convention):
+#   node visit, width W: W slab tests (per box 6 x (subtract, multiply),
+#     6 min/max per axis pair, 6 min/max to combine, 1 compare = 25) and the
+#     compares that order the entered children (1 for W = 2; sorting
+#     networks of 5 and 19 comparators for W = 4, 8)
+#   disk test: plane hit (two dot products, |a| test, divide), hit point,
+#     squared distance, radius and t-window compares -> 32
+#   visible diffuse connection: distance, cosine, ray-tube amplitude, phase,
+#     two complex products, FP64 accumulation -> 60
+ORDER_OPS = {2: 1, 4: 5, 8: 19}
+OPS_DISK, OPS_DIFFUSE_PATH = 32, 60
+
+
+def ops_node(width):
+    return 25 * width + ORDER_OPS[width]
+
+# HBM traffic of one k_diffuse launch, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE on this workload, scaled by the copy-kernel calibration (read x
+# 2.00, write x 1.00), together with the hash of the sources the measured
+# kernel was built from; reported only while the sources still match.
+TRAFFIC = None  # {"kernel": "k_diffuse", "bytes": B, "src_sha256": "..."}
+TRAFFIC_SOURCES = ("paper_2507_04021_amd/csrc/common.h", "paper_2507_04021_amd/csrc/internal.h",
+                   "paper_2507_04021_amd/csrc/field.hip", "paper_2507_04021_amd/csrc/bvh.hip")
 
 
 def log(*a):
@@ -37,25 +63,43 @@ def office_inputs():
     return sc, scenes.office_rx(), np.asarray(scenes.OFFICE_TX, np.float32), scenes.OFFICE_MATERIALS
 
 
-def algorithmic_bytes(cnt, K, n_rx, stage):
-    """Bytes the method must move for one launch of a stage's kernel.
+def algorithmic_bytes(cnt, K, n_rx, stage, width=2):
+    """Bytes the method gathers in one launch of a stage's kernel.
 
-    Traversal: 64 B per binary node visited + 32 B per disk tested (counted
-    by the instrumented build). Streams: the trace kernel writes a 48 B record
-    per interaction; the diffuse kernel reads that record (40 B) plus the
-    hit normal (16 B) once per (interaction, receiver group of 64 lanes) and
-    writes 40 B of FP64 partial sums per (ray chunk, receiver).
+    Traversal: 32 W bytes per node of width W visited + 32 B per disk tested
+    (counted by the instrumented build). Streams: the trace kernel writes a
+    48 B record per interaction; the diffuse kernel reads that record (40 B)
+    plus the hit normal (16 B) once per (interaction, receiver group of 64
+    lanes) and writes 40 B of FP64 partial sums per (ray chunk, receiver).
     """
+    nb = 32 * width
     if stage == "trace":
-        return cnt["trace_nodes"] * 64 + cnt["trace_disks"] * 32 + cnt["interactions"] * 48
+        return cnt["trace_nodes"] * nb + cnt["trace_disks"] * 32 + cnt["interactions"] * 48
     if stage == "diffuse":
         groups = max(1, (n_rx + 63) // 64)
         chunks = (cnt["rays"] + 127) // 128
-        return (cnt["diffuse_nodes"] * 64 + cnt["diffuse_disks"] * 32 + cnt["interactions"] * 56 * groups
+        return (cnt["diffuse_nodes"] * nb + cnt["diffuse_disks"] * 32 + cnt["interactions"] * 56 * groups
                 + chunks * n_rx * 40)
     if stage == "refine":
-        return cnt["refine_nodes"] * 64 + cnt["refine_disks"] * 32
+        return cnt["refine_nodes"] * nb + cnt["refine_disks"] * 32
     return 0
+
+
+def algorithmic_flops(cnt, stage, width=2):
+    """FP32 operations one launch of a stage's kernel must perform (counts
+    from the instrumented build)."""
+    nodes, disks = cnt[stage + "_nodes"], cnt[stage + "_disks"]
+    extra = cnt["diffuse"] * OPS_DIFFUSE_PATH if stage == "diffuse" else 0
+    return nodes * ops_node(width) + disks * OPS_DISK + extra
+
+
+def source_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def timed(fn, reps, warm=1):
@@ -76,7 +120,8 @@ def timed(fn, reps, warm=1):
 def batch_workload(reps):
     """256 transmitter poses along a robot trajectory in the tiny box room,
     ray counts uniform in [2^16, 2^20], K = 2, one graph launch per batch;
-    BVH leaf size and rays per wavefront fetch picked by the autotuner."""
+    BVH leaf size, node width and rays per wavefront fetch picked by the
+    autotuner."""
     import torch
     import paper_2507_04021_amd as P
     from paper_2507_04021_amd import scenes
@@ -84,9 +129,9 @@ def batch_workload(reps):
     mats = scenes.box_room_materials()
     tx, n = scenes.trajectory(seed=4021, n=256)
     choice, rows = P.autotune(s, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 1 << 20, K=2, flags=P.LOS | P.SPECULAR,
-                              leaf_sizes=(1, 2, 4, 8), wave_rays=(64, 128, 256), reps=3,
+                              leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8), wave_rays=(64, 128, 256), reps=3,
                               cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"))
-    sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"])
+    sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"], width=choice["width"])
     graph = P.BatchGraph(sg, mats, tx, n, [scenes.BOX_RX], 3.5e9, K=2, flags=P.LOS | P.SPECULAR,
                          wave_rays=choice["wave_rays"])
     ms = timed(lambda: graph.launch(), reps)
@@ -146,6 +191,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--width", type=int, default=4, help="BVH node width (2, 4, 8)")
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -173,7 +219,7 @@ def main():
     sc, rx, tx, mats = office_inputs()
     log("office scene: %d points, %d surfaces" % (sc.n, sc.n_surfaces))
     dev = torch.device("cuda")
-    scene = P.Scene.from_scene(sc, leaf_size=args.leaf)
+    scene = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width)
     torch.cuda.synchronize()
     log("hierarchy:", scene.info)
     mats_t = P.materials_tensor(mats, dev)
@@ -205,15 +251,20 @@ def main():
 
     # algorithmic bytes from one instrumented solve (same inputs, same results)
     P.use_counting(True)
-    scene_c = P.Scene.from_scene(sc, leaf_size=args.leaf)
+    scene_c = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width)
     rc = P.solve(scene_c, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags)
     torch.cuda.synchronize()
     ccnt = {k: int(rc.counters[i].item()) for k, i in P.CNT.items()}
     P.use_counting(False)
     del scene_c, rc
     dom = max(("trace", "refine", "diffuse"), key=lambda k: stage_ms[k])
-    nbytes = algorithmic_bytes(ccnt, K, len(rx), dom)
-    achieved = nbytes / (stage_ms[dom] / 1e3) / 1e9
+    kname = {"trace": "k_trace", "refine": "k_refine", "diffuse": "k_diffuse"}[dom]
+    nbytes = algorithmic_bytes(ccnt, K, len(rx), dom, args.width)
+    flops = algorithmic_flops(ccnt, dom, args.width)
+    achieved = flops / (stage_ms[dom] / 1e3) / 1e12
+    traffic = None
+    if TRAFFIC and TRAFFIC["kernel"] == kname and TRAFFIC["src_sha256"] == source_sha256(TRAFFIC_SOURCES):
+        traffic = TRAFFIC["bytes"]
     log("visit counters:", {k: ccnt[k] for k in ccnt if "nodes" in k or "disks" in k})
 
     line = {
@@ -233,16 +284,19 @@ def main():
             "workload": "office 12x8x3 m, 20 boxes, %d noisy points (5 mm, 3 deg), 8 materials, 1 TX, 64 RX, "
                         "%d rays, K=5, 28 GHz, LOS+specular+diffuse" % (sc.n, args.rays),
             "leaf_size": args.leaf,
+            "bvh_width": args.width,
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": {"trace": "k_trace", "refine": "k_refine", "diffuse": "k_diffuse"}[dom],
+            "bound": "alu",
+            "kernel": kname,
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "algorithmic_bytes_per_launch": nbytes,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_flops_per_launch": flops,
+            "gathered_bytes_per_launch": nbytes,
+            "gather_GBs": nbytes / (stage_ms[dom] / 1e3) / 1e9,
             "launch_ms": stage_ms[dom],
         },
         "stage_ms": stage_ms,

@@ -65,7 +65,9 @@ typedef struct {
 } pcrt_points;
 
 /* Bounding-volume hierarchy options. leaf_size: disks per leaf, 1..8
- * (0 = default 4). width: 2 (binary nodes; 0 = default). */
+ * (0 = default 4). width: children per node -- 2 (binary radix tree), 4 or 8
+ * (wide nodes collapsed from it, largest-area child opened first); 0 = 4.
+ * Results do not depend on either option, only speed does. */
 typedef struct {
     uint32_t leaf_size;
     uint32_t width;
@@ -76,9 +78,11 @@ typedef struct {
     uint32_t n_points;
     uint32_t n_surfaces;   /* max surface label + 1 */
     uint32_t n_materials;  /* max material label + 1 */
-    uint32_t depth;        /* deepest node of the hierarchy */
-    uint32_t n_nodes;
+    uint32_t depth;        /* internal ancestors of the deepest leaf of the binary tree */
+    uint32_t n_nodes;      /* nodes of the traversed hierarchy (wide nodes if width > 2) */
     uint32_t leaf_size;
+    uint32_t width;
+    uint32_t stack_entries; /* bound on traversal stack entries: (width - 1) x levels */
     float bbox[6];         /* lo xyz, hi xyz of the disk bounds */
     double build_ms;       /* device time of the build */
 } pcrt_scene_info;
@@ -245,20 +249,22 @@ pcrt_status pcrt_graph_capture_batch(const pcrt_scene *scene, const pcrt_materia
 pcrt_status pcrt_graph_launch(pcrt_graph *graph, void *stream);
 pcrt_status pcrt_graph_destroy(pcrt_graph *graph);
 
-/* Autotuner: builds the scene for every leaf size, times reps solves of p
- * for every wave_rays value (HIP events on stream; synchronises), fills
- * table[n_leaf * n_wave] (optional) and the fastest configuration. scene_ws
- * must fit the scene at every leaf size, solve_ws the solve. */
+/* Autotuner: times reps solves of p on every given scene (built by the
+ * caller with the leaf sizes and widths to compare) for every wave_rays
+ * value (HIP events on stream; synchronises), fills table[n_scenes * n_wave]
+ * (optional, scene-major) and the fastest configuration. solve_ws must fit
+ * the solve on every scene (else ENOMEM, with the size needed). */
 typedef struct {
+    uint32_t scene;      /* index into scenes */
     uint32_t leaf_size;
+    uint32_t width;
     uint32_t wave_rays;
     double ms;
 } pcrt_tuning;
-pcrt_status pcrt_autotune(const pcrt_points *pts, const pcrt_solve_params *p, const pcrt_material *mats,
-                          uint32_t n_labels, const uint32_t *leaf_sizes, uint32_t n_leaf, const uint32_t *wave_rays,
-                          uint32_t n_wave, uint32_t reps, void *scene_ws, size_t scene_ws_bytes, void *solve_ws,
-                          size_t solve_ws_bytes, const pcrt_outputs *out, void *stream, pcrt_tuning *table,
-                          pcrt_tuning *best);
+pcrt_status pcrt_autotune(const pcrt_scene *const *scenes, uint32_t n_scenes, const pcrt_solve_params *p,
+                          const pcrt_material *mats, uint32_t n_labels, const uint32_t *wave_rays, uint32_t n_wave,
+                          uint32_t reps, void *solve_ws, size_t solve_ws_bytes, const pcrt_outputs *out, void *stream,
+                          pcrt_tuning *table, pcrt_tuning *best);
 
 /* ------------------------------------------------------ differentiation */
 /* The tape of a PCRT_RECORD solve lives in its workspace. It holds the path

@@ -43,6 +43,7 @@ class BvhOpts(ctypes.Structure):
 class SceneInfo(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_uint32), ("n_surfaces", ctypes.c_uint32), ("n_materials", ctypes.c_uint32),
                 ("depth", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("leaf_size", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("stack_entries", ctypes.c_uint32),
                 ("bbox", ctypes.c_float * 6), ("build_ms", ctypes.c_double)]
 
 
@@ -63,7 +64,8 @@ class BatchItem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("leaf_size", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32), ("ms", ctypes.c_double)]
+    _fields_ = [("scene", ctypes.c_uint32), ("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32),
+                ("wave_rays", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
 class Mlp(ctypes.Structure):
@@ -123,8 +125,8 @@ def lib(variant=None) -> ctypes.CDLL:
                                                ctypes.POINTER(Outputs), vp, ctypes.POINTER(vp)]
         L.pcrt_graph_launch.argtypes = [vp, vp]
         L.pcrt_graph_destroy.argtypes = [vp]
-        L.pcrt_autotune.argtypes = [ctypes.POINTER(Points), ctypes.POINTER(SolveParams), vp, u32, vp, u32, vp, u32,
-                                    u32, vp, sz, vp, sz, ctypes.POINTER(Outputs), vp, vp, ctypes.POINTER(Tuning)]
+        L.pcrt_autotune.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(SolveParams), vp, u32, vp, u32, u32, vp,
+                                    sz, ctypes.POINTER(Outputs), vp, vp, ctypes.POINTER(Tuning)]
         L.pcrt_mlp_forward.argtypes = [ctypes.POINTER(Mlp), u32, vp, vp, ctypes.c_float, vp, vp]
         L.pcrt_mlp_workspace_size.argtypes = [u32, u32, ctypes.POINTER(sz)]
         L.pcrt_mlp_backward.argtypes = [ctypes.POINTER(Mlp), u32, vp, vp, ctypes.c_float, vp, vp, sz, vp, vp, vp, vp]
@@ -169,7 +171,7 @@ def _ptr(t):
 class Scene:
     """A point cloud of disks with its bounding-volume hierarchy on the GPU."""
 
-    def __init__(self, pos, normal, material, surface, radius, leaf_size=4, device="cuda", stream=None):
+    def __init__(self, pos, normal, material, surface, radius, leaf_size=4, width=4, device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
         pos = _dev(pos, torch.float32, self.device).reshape(-1, 3)
@@ -181,7 +183,7 @@ class Scene:
         n = pos.shape[0]
         self.n = n
         self.radius = float(radius)
-        opts = BvhOpts(leaf_size, 0)
+        opts = BvhOpts(leaf_size, width)
         nbytes = ctypes.c_size_t(0)
         _check(lib().pcrt_scene_workspace_size(n, ctypes.byref(opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
@@ -194,8 +196,8 @@ class Scene:
         info = SceneInfo()
         _check(lib().pcrt_scene_get_info(self.handle, ctypes.byref(info)))
         self.info = dict(n_points=info.n_points, n_surfaces=info.n_surfaces, n_materials=info.n_materials,
-                         depth=info.depth, n_nodes=info.n_nodes, leaf_size=info.leaf_size,
-                         bbox=list(info.bbox), build_ms=info.build_ms)
+                         depth=info.depth, n_nodes=info.n_nodes, leaf_size=info.leaf_size, width=info.width,
+                         stack_entries=info.stack_entries, bbox=list(info.bbox), build_ms=info.build_ms)
 
     @classmethod
     def from_scene(cls, sc, **kw):
@@ -422,10 +424,11 @@ class BatchGraph:
             self.handle = None
 
 
-def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_sizes=(1, 2, 4, 8),
+def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8),
              wave_rays=(64, 128, 256), reps=3, cache_path=None, device="cuda"):
-    """Sweep BVH leaf size x rays per wavefront fetch with the library's tuner;
-    the winner is stored in a JSON cache keyed by the workload."""
+    """Sweep BVH leaf size x node width x rays per wavefront fetch with the
+    library's tuner (one scene per leaf size and width, built here); the
+    winner is stored in a JSON cache keyed by the workload."""
     import json
     torch = _torch()
     key = "n=%d rays=%d K=%d flags=%d rx=%d dev=%s" % (sc.n, n_rays, K, flags, np.asarray(rx).reshape(-1, 3).shape[0],
@@ -437,31 +440,30 @@ def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_siz
         cache = {}
     if key in cache:
         return cache[key], None
-    dev = torch.device(device)
-    pos = _dev(sc.pos, torch.float32, dev)
-    nrm = _dev(sc.normal, torch.float32, dev)
-    mat = _dev(sc.material.astype(np.int32), torch.int32, dev).to(torch.int16)
-    surf = _dev(sc.surface.astype(np.int64), torch.int64, dev).to(torch.int32)
-    pts = Points(pos.data_ptr(), nrm.data_ptr(), mat.data_ptr(), surf.data_ptr(), sc.n, sc.radius)
     L = lib()
-    nb = ctypes.c_size_t(0)
-    _check(L.pcrt_scene_workspace_size(sc.n, None, ctypes.byref(nb)), L)
-    scene_ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
-    probe = Scene.from_scene(sc, device=device)
-    res = solve(probe, mats, tx, rx, freq, n_rays, K=K, flags=flags)
+    cands = [Scene.from_scene(sc, leaf_size=l, width=w, device=device) for l in leaf_sizes for w in widths]
+    res = solve(cands[0], mats, tx, rx, freq, n_rays, K=K, flags=flags)
     p = res.params
+    need = 0
+    for c in cands:
+        for wr_ in wave_rays:
+            q = SolveParams.from_buffer_copy(p)
+            q.wave_rays = wr_
+            nb = ctypes.c_size_t(0)
+            _check(L.pcrt_solve_workspace_size(c.handle, ctypes.byref(q), ctypes.byref(nb)), L)
+            need = max(need, nb.value)
+    ws = torch.empty(need, dtype=torch.uint8, device=torch.device(device))
     o = Outputs(res.gain.data_ptr(), res.h_te.data_ptr(), res.h_tm.data_ptr(), res.parts.data_ptr(), None,
                 res.counters.data_ptr())
-    leaf = (ctypes.c_uint32 * len(leaf_sizes))(*leaf_sizes)
+    handles = (ctypes.c_void_p * len(cands))(*[c.handle.value for c in cands])
     wr = (ctypes.c_uint32 * len(wave_rays))(*wave_rays)
-    table = (Tuning * (len(leaf_sizes) * len(wave_rays)))()
+    table = (Tuning * (len(cands) * len(wave_rays)))()
     best = Tuning()
     mats_t = res.keep[0]
-    _check(L.pcrt_autotune(ctypes.byref(pts), ctypes.byref(p), _ptr(mats_t), mats_t.shape[0], leaf, len(leaf_sizes),
-                           wr, len(wave_rays), reps, _ptr(scene_ws), nb.value, _ptr(res.ws), res.ws.numel(),
-                           ctypes.byref(o), _stream(), table, ctypes.byref(best)), L)
-    choice = dict(leaf_size=best.leaf_size, wave_rays=best.wave_rays, ms=best.ms)
-    rows = [dict(leaf_size=t.leaf_size, wave_rays=t.wave_rays, ms=t.ms) for t in table]
+    _check(L.pcrt_autotune(handles, len(cands), ctypes.byref(p), _ptr(mats_t), mats_t.shape[0], wr, len(wave_rays),
+                           reps, _ptr(ws), ws.numel(), ctypes.byref(o), _stream(), table, ctypes.byref(best)), L)
+    choice = dict(leaf_size=best.leaf_size, width=best.width, wave_rays=best.wave_rays, ms=best.ms)
+    rows = [dict(leaf_size=t.leaf_size, width=t.width, wave_rays=t.wave_rays, ms=t.ms) for t in table]
     cache[key] = choice
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

@@ -164,6 +164,7 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     D.K = K;
     D.n_rx = p->n_rx;
     D.n_items = (uint32_t)items.size();
+    D.width = sc->info.width;
     uint64_t off = 0, total = 0, max_rays = 0;
     for (auto &it : items) {
         it.ray_off = (uint32_t)off;
@@ -189,8 +190,8 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     const uint32_t wr = p->wave_rays ? p->wave_rays : kWave;
     D.spill_lanes = std::max({trace_grid(D, wr) * kWave, diffuse_grid(D) * 256u, refine_grid(D) * 256u,
                               round_up(D.n_items * D.n_rx, kWave)});
-    // a depth-first walk holds at most `depth` entries; the first kStackLds live in LDS
-    D.spill_depth = sc->info.depth > (uint32_t)kStackLds ? sc->info.depth - kStackLds : 0;
+    // the first kStackLds stack entries live in LDS, the rest in the spill area
+    D.spill_depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
@@ -363,11 +364,13 @@ const char *pcrt_last_error(void) { return g_err.c_str(); }
 const char *pcrt_version(void) { return "pcrt 0.1 (gfx950)"; }
 
 pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *opts, size_t *bytes) {
-    (void)opts;
     if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
     if (n_points == 0) return fail(PCRT_EINVAL, "n_points must be > 0");
     if (n_points > (1u << 27)) return fail(PCRT_EUNSUPPORTED, "at most 2^27 points");
-    *bytes = scene_layout(n_points).total;
+    const uint32_t width = opts && opts->width ? opts->width : kDefaultWidth;
+    if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
+    if (opts && opts->leaf_size > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
+    *bytes = scene_layout(n_points, width).total;
     return ok();
 }
 
@@ -382,16 +385,18 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
         return fail(PCRT_EINVAL, "disk_radius must be > 0");
     uint32_t leaf = opts && opts->leaf_size ? opts->leaf_size : 4;
     if (leaf < 1 || leaf > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
-    if (opts && opts->width && opts->width != 2) return fail(PCRT_EUNSUPPORTED, "only width 2 is implemented");
-    SceneLayout L = scene_layout(pts->n_points);
+    const uint32_t width = opts && opts->width ? opts->width : kDefaultWidth;
+    if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
+    SceneLayout L = scene_layout(pts->n_points, width);
     if (ws_bytes < L.total) return fail(PCRT_ENOMEM, "scene workspace too small: need %zu bytes", L.total);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
+    uint32_t wide_levels = 0, wide_nodes = 0;
     HIP_TRY(build_scene(pts->pos, pts->normal, pts->material, pts->surface, pts->n_points, pts->disk_radius, leaf,
-                        (char *)ws, L, s));
+                        (char *)ws, L, s, &wide_levels, &wide_nodes));
     HIP_TRY(hipEventRecord(e1, s));
     uint32_t stat[8];
     float bounds[6];
@@ -404,15 +409,20 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     hipEventDestroy(e1);
     if (stat[0] & 1) return fail(PCRT_EINVAL, "non-finite point position");
     if (stat[0] & 2) return fail(PCRT_EINVAL, "zero or non-finite normal");
-    if (stat[3] > (uint32_t)kStackMax)
-        return fail(PCRT_EUNSUPPORTED, "hierarchy depth %u exceeds the traversal stack (%d)", stat[3], kStackMax);
+    // a depth-first walk holds at most (width - 1) entries per level of its path
+    const uint32_t n_pts = pts->n_points;
+    const uint32_t stack_entries = n_pts <= leaf ? 0 : width == 2 ? stat[3] : (width - 1) * wide_levels;
+    if (stack_entries > (uint32_t)kStackMax)
+        return fail(PCRT_EUNSUPPORTED, "hierarchy needs %u traversal stack entries (at most %d)", stack_entries,
+                    kStackMax);
     pcrt_scene *sc = new pcrt_scene;
     memset(sc, 0, sizeof *sc);
     sc->ws = (char *)ws;
     sc->ws_bytes = ws_bytes;
     sc->L = L;
     const uint32_t n = pts->n_points;
-    sc->dev.node = (const float4 *)(sc->ws + L.node);
+    sc->dev.node = (const float4 *)(sc->ws + (width > 2 ? L.wnode : L.node));
+    sc->dev.width = (int)width;
     sc->dev.disk = (const float4 *)(sc->ws + L.disk);
     sc->dev.pos = (const float4 *)(sc->ws + L.pos_id);
     sc->dev.nrm = (const float4 *)(sc->ws + L.nrm_id);
@@ -425,8 +435,10 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     I.n_surfaces = stat[1] + 1;
     I.n_materials = stat[2] + 1;
     I.depth = stat[3];
-    I.n_nodes = n > 1 ? n - 1 : 0;
+    I.n_nodes = n <= leaf ? 0 : width == 2 ? n - 1 : wide_nodes;
     I.leaf_size = leaf;
+    I.width = width;
+    I.stack_entries = stack_entries;
     memcpy(I.bbox, bounds, sizeof bounds);
     I.build_ms = ms;
     *out = sc;
@@ -628,33 +640,38 @@ pcrt_status pcrt_graph_destroy(pcrt_graph *graph) {
     return ok();
 }
 
-pcrt_status pcrt_autotune(const pcrt_points *pts, const pcrt_solve_params *p, const pcrt_material *mats,
-                          uint32_t n_labels, const uint32_t *leaf_sizes, uint32_t n_leaf, const uint32_t *wave_rays,
-                          uint32_t n_wave, uint32_t reps, void *scene_ws, size_t scene_ws_bytes, void *solve_ws,
-                          size_t solve_ws_bytes, const pcrt_outputs *out, void *stream, pcrt_tuning *table,
-                          pcrt_tuning *best) {
-    if (!pts || !p || !leaf_sizes || !wave_rays || !n_leaf || !n_wave || !best || !out)
-        return fail(PCRT_EINVAL, "pts, p, sweep lists, out and best are required");
+pcrt_status pcrt_autotune(const pcrt_scene *const *scenes, uint32_t n_scenes, const pcrt_solve_params *p,
+                          const pcrt_material *mats, uint32_t n_labels, const uint32_t *wave_rays, uint32_t n_wave,
+                          uint32_t reps, void *solve_ws, size_t solve_ws_bytes, const pcrt_outputs *out, void *stream,
+                          pcrt_tuning *table, pcrt_tuning *best) {
+    if (!scenes || !n_scenes || !p || !wave_rays || !n_wave || !best || !out)
+        return fail(PCRT_EINVAL, "scenes, p, wave_rays, out and best are required");
+    for (uint32_t a = 0; a < n_scenes; ++a) {
+        if (!scenes[a]) return fail(PCRT_EINVAL, "scene %u is NULL", a);
+        for (uint32_t b = 0; b < n_wave; ++b) {
+            pcrt_solve_params q = *p;
+            q.wave_rays = wave_rays[b];
+            size_t need = 0;
+            pcrt_status st = pcrt_solve_workspace_size(scenes[a], &q, &need);
+            if (st) return st;
+            if (need > solve_ws_bytes)
+                return fail(PCRT_ENOMEM, "solve workspace too small for scene %u: need %zu bytes", a, need);
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     best->ms = INFINITY;
     uint32_t idx = 0;
-    for (uint32_t a = 0; a < n_leaf; ++a) {
-        pcrt_bvh_opts o = {leaf_sizes[a], 2};
-        pcrt_scene *sc = nullptr;
-        pcrt_status st = pcrt_scene_create(pts, &o, scene_ws, scene_ws_bytes, stream, &sc);
-        if (st) return st;
+    for (uint32_t a = 0; a < n_scenes; ++a) {
+        const pcrt_scene *sc = scenes[a];
         for (uint32_t b = 0; b < n_wave; ++b, ++idx) {
             pcrt_solve_params q = *p;
             q.wave_rays = wave_rays[b];
             q.flags &= ~(uint32_t)PCRT_TIMING;
-            st = pcrt_solve(sc, mats, n_labels, &q, solve_ws, solve_ws_bytes, out, stream);  // warm-up
-            if (st) {
-                pcrt_scene_destroy(sc);
-                return st;
-            }
+            pcrt_status st = pcrt_solve(sc, mats, n_labels, &q, solve_ws, solve_ws_bytes, out, stream);  // warm-up
+            if (st) return st;
             HIP_TRY(hipEventRecord(e0, s));
             for (uint32_t r = 0; r < std::max<uint32_t>(reps, 1); ++r)
                 pcrt_solve(sc, mats, n_labels, &q, solve_ws, solve_ws_bytes, out, stream);
@@ -662,11 +679,10 @@ pcrt_status pcrt_autotune(const pcrt_points *pts, const pcrt_solve_params *p, co
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            pcrt_tuning t = {leaf_sizes[a], wave_rays[b], ms / std::max<uint32_t>(reps, 1)};
+            pcrt_tuning t = {a, sc->info.leaf_size, sc->info.width, wave_rays[b], ms / std::max<uint32_t>(reps, 1)};
             if (table) table[idx] = t;
             if (t.ms < best->ms) *best = t;
         }
-        pcrt_scene_destroy(sc);
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -256,7 +256,99 @@ void fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, s, p, v, n);
 }
 
-SceneLayout scene_layout(uint32_t n) {
+// --------------------------------------------------------- wide nodes
+// Collapse of the binary hierarchy into nodes of up to W children, level by
+// level from the root. A wide node starts from its binary node's two
+// children and repeatedly opens the internal child with the largest box
+// surface area (first such slot on ties) until it holds W children or only
+// leaves remain. Children get wide indices in level order through an
+// exclusive scan of the per-node internal-child counts, so the layout is
+// deterministic. Wide node: 7W floats -- lo x[W], lo y[W], lo z[W], hi x[W],
+// hi y[W], hi z[W], child refs[W] -- padded to 8W floats (128 B for W = 4,
+// 256 B for W = 8). An empty slot holds a point box at 1e30, which no slab
+// test over a finite segment accepts, and a one-disk leaf reference.
+struct WSlot {
+    float b[6];
+    int ref;
+};
+
+__device__ __forceinline__ float half_area(const float *b) {
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__device__ __forceinline__ void binary_children(const float4 *__restrict__ bnode, int b, WSlot &c0, WSlot &c1) {
+    const float4 *nd = bnode + 4 * (size_t)b;
+    const float4 x0 = nd[0], x1 = nd[1], x2 = nd[2], x3 = nd[3];
+    c0 = {{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y}, __float_as_int(x3.x)};
+    c1 = {{x1.z, x1.w, x2.x, x2.y, x2.z, x2.w}, __float_as_int(x3.y)};
+}
+
+template <int W>
+__device__ int wide_children(const float4 *__restrict__ bnode, int b, WSlot *sl) {
+    binary_children(bnode, b, sl[0], sl[1]);
+    int cnt = 2;
+    while (cnt < W) {
+        int best = -1;
+        float ba = -1.f;
+        for (int j = 0; j < cnt; ++j)
+            if (sl[j].ref >= 0) {
+                const float ar = half_area(sl[j].b);
+                if (ar > ba) {
+                    ba = ar;
+                    best = j;
+                }
+            }
+        if (best < 0) break;
+        WSlot c0, c1;
+        binary_children(bnode, sl[best].ref, c0, c1);
+        sl[best] = c0;
+        sl[cnt++] = c1;
+    }
+    return cnt;
+}
+
+template <int W>
+__global__ void k_wide_count(const float4 *__restrict__ bnode, const int *__restrict__ frontier, uint32_t nf,
+                             uint32_t *__restrict__ cnt) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    WSlot sl[W];
+    const int c = wide_children<W>(bnode, frontier[i], sl);
+    uint32_t k = 0;
+    for (int j = 0; j < c; ++j) k += sl[j].ref >= 0;
+    cnt[i] = k;
+}
+
+template <int W>
+__global__ void k_wide_emit(const float4 *__restrict__ bnode, const int *__restrict__ frontier, uint32_t nf,
+                            const uint32_t *__restrict__ pos, uint32_t base_cur, uint32_t base_next,
+                            int *__restrict__ next, float *__restrict__ wnode) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    WSlot sl[W];
+    const int c = wide_children<W>(bnode, frontier[i], sl);
+    float *o = wnode + (size_t)(base_cur + i) * 8 * W;
+    uint32_t k = pos[i];
+    for (int j = 0; j < W; ++j) {
+        int ref = leaf_ref(0, 1);
+        float bx[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+        if (j < c) {
+            for (int a = 0; a < 6; ++a) bx[a] = sl[j].b[a];
+            ref = sl[j].ref;
+            if (ref >= 0) {
+                next[k] = ref;
+                ref = (int)(base_next + k);
+                ++k;
+            }
+        }
+        for (int a = 0; a < 6; ++a) o[a * W + j] = bx[a];
+        o[6 * W + j] = __int_as_float(ref);
+        o[7 * W + j] = 0.f;
+    }
+}
+
+SceneLayout scene_layout(uint32_t n, uint32_t width) {
     Bump b;
     SceneLayout L;
     uint32_t ni = n > 1 ? n - 1 : 1;
@@ -281,12 +373,59 @@ SceneLayout scene_layout(uint32_t n) {
     L.dbox = b.take(sizeof(float) * 6 * n);
     L.ibox = b.take(sizeof(float) * 6 * ni);
     L.flags = b.take(sizeof(uint32_t) * ni);
+    L.width = width;
+    L.n_internal = ni;
+    if (width > 2) {  // every wide node stands for a distinct binary internal node
+        L.wnode = b.take(sizeof(float) * 8 * width * (size_t)ni);
+        L.front0 = b.take(sizeof(int) * ni);
+        L.front1 = b.take(sizeof(int) * ni);
+        L.wcnt = b.take(sizeof(uint32_t) * ni);
+        L.wblk = b.take(sizeof(uint32_t) * scan_blk_words(ni));
+    }
     L.total = b.off;
     return L;
 }
 
+// Level-by-level collapse (one scan per level); the host reads each level's
+// size, so this synchronises the stream once per level. Host outputs: the
+// number of wide levels and of wide nodes.
+template <int W>
+hipError_t build_wide_w(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes) {
+    const float4 *bnode = (const float4 *)(ws + L.node);
+    int *fr[2] = {(int *)(ws + L.front0), (int *)(ws + L.front1)};
+    uint32_t *cnt = (uint32_t *)(ws + L.wcnt), *blk = (uint32_t *)(ws + L.wblk);
+    float *wnode = (float *)(ws + L.wnode);
+    fill_u32((uint32_t *)fr[0], 0, 1, s);  // binary root
+    const uint32_t ni = L.n_internal;
+    uint32_t nf = 1, base = 0, lv = 0;
+    while (nf > 0) {
+        // every wide node stands for a distinct binary internal node
+        if (base + nf > ni || lv >= 128) return hipErrorUnknown;
+        const uint32_t g = cdiv(nf, 256);
+        hipLaunchKernelGGL(k_wide_count<W>, dim3(g), dim3(256), 0, s, bnode, fr[lv & 1], nf, cnt);
+        exclusive_scan(cnt, nf, blk, s);
+        hipLaunchKernelGGL(k_wide_emit<W>, dim3(g), dim3(256), 0, s, bnode, fr[lv & 1], nf, cnt, base, base + nf,
+                           fr[(lv + 1) & 1], wnode);
+        uint32_t total = 0;
+        hipError_t e = hipMemcpyAsync(&total, blk + cdiv(nf, 1024), sizeof total, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        base += nf;
+        nf = total;
+        ++lv;
+    }
+    *levels = lv;
+    *nodes = base;
+    return hipGetLastError();
+}
+
+hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes) {
+    return L.width == 4 ? build_wide_w<4>(L, ws, s, levels, nodes) : build_wide_w<8>(L, ws, s, levels, nodes);
+}
+
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
-                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s) {
+                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s, uint32_t *wide_levels,
+                       uint32_t *wide_nodes) {
     auto P = [&](size_t off) { return ws + off; };
     float4 *pos_id = (float4 *)P(L.pos_id), *nrm_id = (float4 *)P(L.nrm_id);
     uint32_t *stat = (uint32_t *)P(L.stat);
@@ -314,6 +453,11 @@ hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, 
         hipLaunchKernelGGL(k_refit, dim3(blk), dim3(256), 0, s, (int)n, (int)leaf, child, range, pint, pleaf, dbox,
                            (float *)P(L.ibox), (uint32_t *)P(L.flags), (float4 *)P(L.node));
         hipLaunchKernelGGL(k_depth, dim3(blk), dim3(256), 0, s, (int)n, pint, pleaf, stat + 3);
+    }
+    *wide_levels = *wide_nodes = 0;
+    if (L.width > 2 && n > leaf) {
+        hipError_t e = build_wide(L, ws, s, wide_levels, wide_nodes);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

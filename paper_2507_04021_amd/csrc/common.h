@@ -50,12 +50,13 @@ __device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
 __host__ __device__ __forceinline__ int leaf_ref(int first, int count) { return -1 - ((first << 3) | (count - 1)); }
 
 struct DevScene {
-    const float4 *node;  // 4 float4 per binary node: child boxes + child refs
+    const float4 *node;  // binary nodes (4 float4: child boxes + refs) or wide nodes (2W float4)
     const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, 0)
     const float4 *pos;   // by id: (p.xyz, surface bits)
     const float4 *nrm;   // by id: (n.xyz, material bits)
     const float *bounds; // scene bounds of the disk centres: lo xyz, hi xyz
-    int *spill;          // global spill of traversal stacks, [kStackMax - kStackLds][spill_lanes]
+    int width;           // node width: 2 (binary nodes, 64 B) or 4 / 8 (wide nodes, 32 W bytes)
+    int *spill;          // global spill of traversal stacks, [stack bound - kStackLds][spill_lanes]
     uint32_t spill_lanes;
     int root;
     float r2;
@@ -188,7 +189,80 @@ __device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d,
     if (!placed) spill = true;
 }
 
-template <bool kSecond>
+// Children of a wide node (8W floats: lo x[W], lo y[W], lo z[W], hi x[W],
+// hi y[W], hi z[W], refs[W], pad): entry distance per child (INFINITY for a
+// child the segment misses) and its reference.
+template <int W>
+__device__ __forceinline__ void wide_hits(const float4 *node, int ref, f3 inv, f3 oi, float t_lo, float t_hi,
+                                          float (&tn)[W], int (&cr)[W]) {
+    const float4 *nd = node + 2 * W * (size_t)ref;
+    float v[7 * W];
+#pragma unroll
+    for (int k = 0; k < 7 * W / 4; ++k) {
+        const float4 q = nd[k];
+        v[4 * k] = q.x;
+        v[4 * k + 1] = q.y;
+        v[4 * k + 2] = q.z;
+        v[4 * k + 3] = q.w;
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        float t;
+        const bool h = box_hit(v[j], v[W + j], v[2 * W + j], v[3 * W + j], v[4 * W + j], v[5 * W + j], inv, oi, t_lo,
+                               t_hi, t);
+        tn[j] = h ? t : INFINITY;
+        cr[j] = __float_as_int(v[6 * W + j]);
+    }
+}
+
+__device__ __forceinline__ void cmp_swap(float *t, int *r, int i, int j) {
+    const bool sw = t[j] < t[i];
+    const float ti = sw ? t[j] : t[i], tj = sw ? t[i] : t[j];
+    const int ri = sw ? r[j] : r[i], rj = sw ? r[i] : r[j];
+    t[i] = ti;
+    t[j] = tj;
+    r[i] = ri;
+    r[j] = rj;
+}
+
+// Children by increasing entry distance: optimal sorting networks for 4
+// (5 comparators) and 8 (19 comparators) keys.
+template <int W>
+__device__ __forceinline__ void sort_hits(float (&t)[W], int (&r)[W]) {
+    if constexpr (W == 4) {
+        cmp_swap(t, r, 0, 1); cmp_swap(t, r, 2, 3);
+        cmp_swap(t, r, 0, 2); cmp_swap(t, r, 1, 3);
+        cmp_swap(t, r, 1, 2);
+    } else {
+        static_assert(W == 8, "wide nodes have 4 or 8 children");
+        cmp_swap(t, r, 0, 2); cmp_swap(t, r, 1, 3); cmp_swap(t, r, 4, 6); cmp_swap(t, r, 5, 7);
+        cmp_swap(t, r, 0, 4); cmp_swap(t, r, 1, 5); cmp_swap(t, r, 2, 6); cmp_swap(t, r, 3, 7);
+        cmp_swap(t, r, 0, 1); cmp_swap(t, r, 2, 3); cmp_swap(t, r, 4, 5); cmp_swap(t, r, 6, 7);
+        cmp_swap(t, r, 2, 4); cmp_swap(t, r, 3, 5);
+        cmp_swap(t, r, 1, 4); cmp_swap(t, r, 3, 6);
+        cmp_swap(t, r, 1, 2); cmp_swap(t, r, 3, 4); cmp_swap(t, r, 5, 6);
+    }
+}
+
+// One step at a wide node: the nearest entered child becomes ref, the other
+// entered children are pushed farthest first (so they come back nearest
+// first). Returns false if no child is entered.
+template <int W>
+__device__ __forceinline__ bool wide_step(const DevScene &S, int &ref, int &sp, f3 inv, f3 oi, float t_lo,
+                                          float t_hi, Stack &stk) {
+    float tn[W];
+    int cr[W];
+    wide_hits<W>(S.node, ref, inv, oi, t_lo, t_hi, tn, cr);
+    sort_hits<W>(tn, cr);
+    if (!(tn[0] < INFINITY)) return false;
+#pragma unroll
+    for (int j = W - 1; j >= 1; --j)
+        if (tn[j] < INFINITY) stk.put(sp++, cr[j]);
+    ref = cr[0];
+    return true;
+}
+
+template <int W, bool kSecond>
 __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, f3 inv, int excl, float t_lo,
                                                  float eps_tie, Stack &stk, float &tmin, Cand *c, bool &spill,
                                                  float t_win, float &best_d2, int &best_id, float &best_t) {
@@ -198,21 +272,25 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
     for (;;) {
         if (ref >= 0) {
             stk.visit();
-            const float4 *nd = S.node + 4 * (size_t)ref;
-            float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
-            float tc = kSecond ? t_win : tmin + eps_tie;
-            float n0, n1;
-            bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, t_lo, tc, n0);
-            bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, inv, oi, t_lo, tc, n1);
-            int r0 = __float_as_int(r.x), r1 = __float_as_int(r.y);
-            if (h0 && h1) {
-                bool f0 = n0 <= n1;
-                stk.put(sp++, f0 ? r1 : r0);
-                ref = f0 ? r0 : r1;
-                continue;
+            const float tc = kSecond ? t_win : tmin + eps_tie;
+            if constexpr (W > 2) {
+                if (wide_step<W>(S, ref, sp, inv, oi, t_lo, tc, stk)) continue;
+            } else {
+                const float4 *nd = S.node + 4 * (size_t)ref;
+                const float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
+                float n0, n1;
+                const bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, t_lo, tc, n0);
+                const bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, inv, oi, t_lo, tc, n1);
+                const int r0 = __float_as_int(r.x), r1 = __float_as_int(r.y);
+                if (h0 && h1) {
+                    const bool f0 = n0 <= n1;
+                    stk.put(sp++, f0 ? r1 : r0);
+                    ref = f0 ? r0 : r1;
+                    continue;
+                }
+                if (h0) { ref = r0; continue; }
+                if (h1) { ref = r1; continue; }
             }
-            if (h0) { ref = r0; continue; }
-            if (h1) { ref = r1; continue; }
         } else {
             const int v = -1 - ref;
             const int first = v >> 3, cnt = (v & 7) + 1;
@@ -226,6 +304,7 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
     }
 }
 
+template <int W>
 __device__ __forceinline__ int closest_hit(const DevScene &S, f3 o, f3 d, int excl, float t_lo, float eps_tie,
                                            Stack &stk, float &t_out, bool &spilled) {
     f3 inv = safe_inv(d);
@@ -236,13 +315,13 @@ __device__ __forceinline__ int closest_hit(const DevScene &S, f3 o, f3 d, int ex
     bool spill = false;
     float bd2 = INFINITY, bt = INFINITY;
     int bid = 0x7fffffff;
-    traverse_closest<false>(S, o, d, inv, excl, t_lo, eps_tie, stk, tmin, c, spill, 0.f, bd2, bid, bt);
+    traverse_closest<W, false>(S, o, d, inv, excl, t_lo, eps_tie, stk, tmin, c, spill, 0.f, bd2, bid, bt);
     spilled = spill;
     if (!(tmin < INFINITY)) return -1;
     if (spill) {
         float dummy = tmin;
-        traverse_closest<true>(S, o, d, inv, excl, t_lo, eps_tie, stk, dummy, c, spill, tmin + eps_tie, bd2, bid,
-                               bt);
+        traverse_closest<W, true>(S, o, d, inv, excl, t_lo, eps_tie, stk, dummy, c, spill, tmin + eps_tie, bd2,
+                                  bid, bt);
         t_out = bt;
         return bid;
     }
@@ -259,12 +338,13 @@ __device__ __forceinline__ int closest_hit(const DevScene &S, f3 o, f3 d, int ex
 
 // True iff a disk != excl is hit with eps_self < t < |b - a| - eps_self on the
 // segment from a towards b.
+template <int W>
 __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl, float eps_self, Stack &stk) {
-    f3 dv = b - a;
-    float L = len(dv);
-    f3 d = (1.0f / L) * dv;
-    f3 inv = safe_inv(d);
-    float t_hi = L - eps_self;
+    const f3 dv = b - a;
+    const float L = len(dv);
+    const f3 d = (1.0f / L) * dv;
+    const f3 inv = safe_inv(d);
+    const float t_hi = L - eps_self;
     if (!(t_hi > eps_self)) return false;
     const f3 oi = times(a, inv);
     int ref = S.root;
@@ -272,20 +352,24 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     for (;;) {
         if (ref >= 0) {
             stk.visit();
-            const float4 *nd = S.node + 4 * (size_t)ref;
-            float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
-            float n0, n1;
-            bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, eps_self, t_hi, n0);
-            bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, eps_self, t_hi, n1);
-            int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
-            if (h0 && h1) {
-                bool f0 = n0 <= n1;
-                stk.put(sp++, f0 ? r1 : r0);
-                ref = f0 ? r0 : r1;
-                continue;
+            if constexpr (W > 2) {
+                if (wide_step<W>(S, ref, sp, inv, oi, eps_self, t_hi, stk)) continue;
+            } else {
+                const float4 *nd = S.node + 4 * (size_t)ref;
+                const float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
+                float n0, n1;
+                const bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, eps_self, t_hi, n0);
+                const bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, eps_self, t_hi, n1);
+                const int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
+                if (h0 && h1) {
+                    const bool f0 = n0 <= n1;
+                    stk.put(sp++, f0 ? r1 : r0);
+                    ref = f0 ? r0 : r1;
+                    continue;
+                }
+                if (h0) { ref = r0; continue; }
+                if (h1) { ref = r1; continue; }
             }
-            if (h0) { ref = r0; continue; }
-            if (h1) { ref = r1; continue; }
         } else {
             const int v = -1 - ref;
             const int first = v >> 3, cnt = (v & 7) + 1;

@@ -82,6 +82,7 @@ __device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t 
 
 constexpr int kDiffRxSlice = 64;
 
+template <int W>
 __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
     // traversal stacks, per-wave receiver sums and the chunk index share LDS
     // (never live together): 32 KiB per block
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
                     bool vis = false;
                     if (id >= 0 && dot(rx - x, n) > 0.f) {
                         ++n_seg;
-                        vis = !occluded(A.S, rx, x, id, eps, stk);
+                        vis = !occluded<W>(A.S, rx, x, id, eps, stk);
                     }
                     if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
                     if (!__ballot(vis)) continue;
@@ -163,8 +164,14 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
     }
 }
 
+template <int W>
+uint32_t diffuse_cap() {
+    static const uint32_t cap = resident_blocks((const void *)k_diffuse<W>, 256);
+    return cap;
+}
+
 uint32_t diffuse_grid(const SolveDims &D) {
-    static const uint32_t cap = resident_blocks((const void *)k_diffuse, 256);
+    const uint32_t cap = D.width == 8 ? diffuse_cap<8>() : D.width == 4 ? diffuse_cap<4>() : diffuse_cap<2>();
     return std::max<uint32_t>(1, std::min(cap, D.n_ray_chunks));
 }
 
@@ -180,9 +187,15 @@ const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s) {
 }
 
 void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
-    hipLaunchKernelGGL(k_diffuse, dim3(diffuse_grid(A.D)), dim3(256), 0, s, A);
+    const dim3 g(diffuse_grid(A.D));
+    switch (A.D.width) {
+        case 8: hipLaunchKernelGGL(k_diffuse<8>, g, dim3(256), 0, s, A); break;
+        case 4: hipLaunchKernelGGL(k_diffuse<4>, g, dim3(256), 0, s, A); break;
+        default: hipLaunchKernelGGL(k_diffuse<2>, g, dim3(256), 0, s, A); break;
+    }
 }
 
+template <int W>
 __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
     const int lane = threadIdx.x;
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
     const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
     double *o = A.los_part + (size_t)p * 5;
-    if (occluded(A.S, tx, rx, -1, A.thr.eps_self, stk)) {
+    if (occluded<W>(A.S, tx, rx, -1, A.thr.eps_self, stk)) {
         for (int a = 0; a < 5; ++a) o[a] = 0.0;
         return;
     }
@@ -267,7 +280,14 @@ __global__ __launch_bounds__(256) void k_combine(LaunchArgs A, double *gain, dou
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                             hipStream_t s) {
     const uint32_t n = A.D.n_items * A.D.n_rx;
-    if (A.flags & 1) hipLaunchKernelGGL(k_los, dim3((n + kWave - 1) / kWave), dim3(kWave), 0, s, A);
+    if (A.flags & 1) {
+        const dim3 g((n + kWave - 1) / kWave);
+        switch (A.D.width) {
+            case 8: hipLaunchKernelGGL(k_los<8>, g, dim3(kWave), 0, s, A); break;
+            case 4: hipLaunchKernelGGL(k_los<4>, g, dim3(kWave), 0, s, A); break;
+            default: hipLaunchKernelGGL(k_los<2>, g, dim3(kWave), 0, s, A); break;
+        }
+    }
     launch_combine(A, gain, h_te, h_tm, parts, s);
 }
 

@@ -16,6 +16,7 @@ namespace pcrt {
 // waves pull work from atomic counters until it runs out.
 uint32_t resident_blocks(const void *kernel, int block_threads);
 constexpr uint32_t kMaxPairs = 262144;  // (transmitter, receiver) pairs in one solve
+constexpr uint32_t kDefaultWidth = 4;    // 4-wide nodes: fastest on the 1M-point office (binary and 8-wide slower)
 
 struct Bump {  // 256-byte aligned offsets inside one workspace
     size_t off = 0;
@@ -29,12 +30,17 @@ struct Bump {  // 256-byte aligned offsets inside one workspace
 struct SceneLayout {
     size_t pos_id, nrm_id, disk, node, stat, bounds, blk_bounds;
     size_t code0, code1, idx0, idx1, hist, scan_blk, child, range, parent_int, parent_leaf, dbox, ibox, flags;
+    uint32_t width = 2;                             // node width of the traversed hierarchy
+    uint32_t n_internal = 1;                        // binary internal nodes (buffer capacity)
+    size_t wnode = 0, front0 = 0, front1 = 0, wcnt = 0, wblk = 0;  // wide collapse (width > 2)
     size_t total;
 };
 
-SceneLayout scene_layout(uint32_t n);
+SceneLayout scene_layout(uint32_t n, uint32_t width);
+hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes);
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
-                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s);
+                       float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s, uint32_t *wide_levels,
+                       uint32_t *wide_nodes);
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 uint32_t scan_blk_words(uint32_t n);
 uint32_t radix_hist_words(uint32_t n);
@@ -78,7 +84,8 @@ struct SolveDims {
     uint32_t n_slots;      // tape interaction slots: T*K traced + rec_keys*n_rx*K specular
     uint32_t n_slot_chunks;
     uint32_t spill_lanes;  // lanes of the widest traversal launch of this solve
-    uint32_t spill_depth;  // traversal stack entries beyond the LDS part (depth - kStackLds)
+    uint32_t spill_depth;  // traversal stack entries beyond the LDS part (stack bound - kStackLds)
+    uint32_t width;        // node width of the scene's hierarchy (2, 4, 8)
 };
 
 constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk

@@ -165,7 +165,7 @@ __device__ __forceinline__ f3 rx_point(const LaunchArgs &A, uint32_t r) {
 // expected surface, close in angle (t_a) and plane distance (t_d); otherwise
 // the plane is replaced by the hit disk's and the image solution recomputed,
 // at most kappa times. The last point must see the receiver.
-template <int KM>
+template <int KM, int W>
 __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, KeyPlanes<KM> kp,
                               Stack &stk, PairOut &po) {
     po.valid = false;
@@ -186,7 +186,7 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
             f3 u = normalize(x[m] - x[m - 1]);
             float t;
             bool sp;
-            int h = closest_hit(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
+            int h = closest_hit<W>(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
             if (h < 0) { fail = true; continue; }
             float4 hp = A.S.pos[h];
             if (__float_as_uint(hp.w) != kp.ks[m - 1]) { fail = true; continue; }
@@ -217,7 +217,7 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
             xk = x[m];
             hk = hid[m - 1];
         }
-    if (occluded(A.S, xk, rx, hk, A.thr.eps_self, stk)) return;
+    if (occluded<W>(A.S, xk, rx, hk, A.thr.eps_self, stk)) return;
     float L = 0.f;
     c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
     float csv[KM];
@@ -270,7 +270,7 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
 // depend on timing.
 constexpr int kRefineRxSlice = 64;
 
-template <int KM>
+template <int KM, int W>
 __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
     // traversal stacks, per-wave receiver sums and the chunk index share LDS
     __shared__ union {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
                     rr = (int)(e % nr);
                     KeyPlanes<KM> kp;
                     load_planes<KM>(A, q, kp);
-                    validate_pair<KM>(A, q, r0 + rr, I, kp, stk, po);
+                    validate_pair<KM, W>(A, q, r0 + rr, I, kp, stk, po);
                     if (rec && q < A.D.rec_keys) {
                         const size_t p = (size_t)q * n_rx + r0 + rr;
                         A.sb.valid[p] = po.valid;
@@ -423,42 +423,51 @@ void launch_keys(const LaunchArgs &A, hipStream_t s) {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, A, total);
 }
 
-template <int KM>
+template <int KM, int W>
 uint32_t refine_cap() {
-    static const uint32_t cap = resident_blocks((const void *)k_refine<KM>, 256);
+    static const uint32_t cap = resident_blocks((const void *)k_refine<KM, W>, 256);
     return cap;
 }
 
-uint32_t refine_grid(const SolveDims &D) {
-    uint32_t cap = 0;
-    switch (D.K) {
-        case 1: cap = refine_cap<1>(); break;
-        case 2: cap = refine_cap<2>(); break;
-        case 3: cap = refine_cap<3>(); break;
-        case 4: cap = refine_cap<4>(); break;
-        case 5: cap = refine_cap<5>(); break;
-        case 6: cap = refine_cap<6>(); break;
-        case 7: cap = refine_cap<7>(); break;
-        default: cap = refine_cap<8>(); break;
+template <int W>
+uint32_t refine_cap_k(uint32_t K) {
+    switch (K) {
+        case 1: return refine_cap<1, W>();
+        case 2: return refine_cap<2, W>();
+        case 3: return refine_cap<3, W>();
+        case 4: return refine_cap<4, W>();
+        case 5: return refine_cap<5, W>();
+        case 6: return refine_cap<6, W>();
+        case 7: return refine_cap<7, W>();
+        default: return refine_cap<8, W>();
     }
+}
+
+uint32_t refine_grid(const SolveDims &D) {
+    const uint32_t cap = D.width == 8 ? refine_cap_k<8>(D.K) : D.width == 4 ? refine_cap_k<4>(D.K) : refine_cap_k<2>(D.K);
     return std::max<uint32_t>(1, std::min(cap, D.max_key_chunks));
 }
 
-void launch_refine(const LaunchArgs &A, hipStream_t s) {
-    const uint32_t grid = refine_grid(A.D);
+template <int W>
+void launch_refine_w(const LaunchArgs &A, dim3 grid, hipStream_t s) {
     switch (A.D.K) {
-#define PCRT_REFINE_CASE(KK) \
-    case KK: hipLaunchKernelGGL(k_refine<KK>, dim3(grid), dim3(256), 0, s, A); break;
-        PCRT_REFINE_CASE(1)
-        PCRT_REFINE_CASE(2)
-        PCRT_REFINE_CASE(3)
-        PCRT_REFINE_CASE(4)
-        PCRT_REFINE_CASE(5)
-        PCRT_REFINE_CASE(6)
-        PCRT_REFINE_CASE(7)
-        PCRT_REFINE_CASE(8)
-#undef PCRT_REFINE_CASE
-        default: break;
+        case 1: hipLaunchKernelGGL((k_refine<1, W>), grid, dim3(256), 0, s, A); break;
+        case 2: hipLaunchKernelGGL((k_refine<2, W>), grid, dim3(256), 0, s, A); break;
+        case 3: hipLaunchKernelGGL((k_refine<3, W>), grid, dim3(256), 0, s, A); break;
+        case 4: hipLaunchKernelGGL((k_refine<4, W>), grid, dim3(256), 0, s, A); break;
+        case 5: hipLaunchKernelGGL((k_refine<5, W>), grid, dim3(256), 0, s, A); break;
+        case 6: hipLaunchKernelGGL((k_refine<6, W>), grid, dim3(256), 0, s, A); break;
+        case 7: hipLaunchKernelGGL((k_refine<7, W>), grid, dim3(256), 0, s, A); break;
+        default: hipLaunchKernelGGL((k_refine<8, W>), grid, dim3(256), 0, s, A); break;
+    }
+}
+
+void launch_refine(const LaunchArgs &A, hipStream_t s) {
+    const dim3 grid(refine_grid(A.D));
+    switch (A.D.width) {
+        case 8: launch_refine_w<8>(A, grid, s); break;
+        case 4: launch_refine_w<4>(A, grid, s); break;
+        default: launch_refine_w<2>(A, grid, s); break;
     }
 }
 

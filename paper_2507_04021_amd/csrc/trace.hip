@@ -31,6 +31,7 @@ __device__ __forceinline__ uint32_t key_insert(const HashBufs &hb, uint32_t base
 }
 
 // One ray slot g: launch direction, up to K closest hits, records.
+template <int W>
 __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack &stk, uint32_t &n_int,
                                           uint32_t &n_ray, uint32_t &n_spill) {
     const uint32_t K = A.D.K;
@@ -55,7 +56,7 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
     for (; k < K; ++k) {
         float t;
         bool sp;
-        int h = closest_hit(A.S, o, d, excl, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
+        int h = closest_hit<W>(A.S, o, d, excl, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
         n_spill += sp;
         if (h < 0) break;
         const float4 pn = A.S.nrm[h];
@@ -102,6 +103,7 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
 
 // Persistent wavefronts take wave_rays consecutive ray slots per atomic
 // fetch; each lane traces wave_rays / 64 of them in turn.
+template <int W>
 __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
     const int lane = threadIdx.x;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(kWave) void k_trace(LaunchArgs A) {
         if (unit >= n_units) break;
         for (uint32_t u = 0; u < U; ++u) {
             const uint32_t g = unit * A.wave_rays + u * kWave + lane;
-            if (g < T) trace_one(A, g, stk, n_int, n_ray, n_spill);
+            if (g < T) trace_one<W>(A, g, stk, n_int, n_ray, n_spill);
         }
     }
     flush_visits(stk, A.counters, 9);
@@ -143,15 +145,25 @@ uint32_t resident_blocks(const void *kernel, int block_threads) {
     return (uint32_t)std::max(per_cu, 1) * (uint32_t)std::max(cus, 1);
 }
 
+template <int W>
+uint32_t trace_cap() {
+    static const uint32_t cap = resident_blocks((const void *)k_trace<W>, kWave);
+    return cap;
+}
+
 uint32_t trace_grid(const SolveDims &D, uint32_t wave_rays) {
-    static const uint32_t cap = resident_blocks((const void *)k_trace, kWave);
+    const uint32_t cap = D.width == 8 ? trace_cap<8>() : D.width == 4 ? trace_cap<4>() : trace_cap<2>();
     const uint32_t units = (D.T + wave_rays - 1) / wave_rays;
     return std::max<uint32_t>(1, std::min(cap, units));
 }
 
 void launch_trace(const LaunchArgs &A, hipStream_t s) {
     uint32_t grid = trace_grid(A.D, A.wave_rays);
-    hipLaunchKernelGGL(k_trace, dim3(grid), dim3(kWave), 0, s, A);
+    switch (A.D.width) {
+        case 8: hipLaunchKernelGGL(k_trace<8>, dim3(grid), dim3(kWave), 0, s, A); break;
+        case 4: hipLaunchKernelGGL(k_trace<4>, dim3(grid), dim3(kWave), 0, s, A); break;
+        default: hipLaunchKernelGGL(k_trace<2>, dim3(grid), dim3(kWave), 0, s, A); break;
+    }
 }
 
 __global__ void k_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out) {

@@ -53,6 +53,19 @@ def test_scene_argument_errors(L):
     assert L.pcrt_scene_workspace_size(10, None, None) == EINVAL
     assert L.pcrt_scene_workspace_size(1 << 28, None, ctypes.byref(nb)) == EUNSUPPORTED
     assert L.pcrt_scene_workspace_size(1000, None, ctypes.byref(nb)) == 0 and nb.value > 1000 * 64
+    o = P.BvhOpts(4, 2)
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0
+    binary = nb.value
+    for w in (4, 8):  # wide nodes add their own array (32 W bytes per binary internal node) and build buffers
+        o = P.BvhOpts(4, w)
+        assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0
+        assert nb.value >= binary + 999 * 32 * w
+    for w in (1, 3, 16):
+        o = P.BvhOpts(4, w)
+        assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == EUNSUPPORTED
+        assert b"width" in L.pcrt_last_error()
+    o = P.BvhOpts(9, 2)
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == EUNSUPPORTED
     h = ctypes.c_void_p()
     fake = 0x1000  # never dereferenced: argument checks run first
     pts = P.Points(fake, fake, fake, fake, 10, 0.0)
@@ -69,7 +82,7 @@ def test_scene_argument_errors(L):
     opts = P.BvhOpts(9, 0)
     assert L.pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), ctypes.c_void_p(fake), 1 << 20, None,
                                ctypes.byref(h)) == EUNSUPPORTED
-    opts = P.BvhOpts(4, 4)
+    opts = P.BvhOpts(4, 3)  # widths are 2, 4 or 8
     assert L.pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), ctypes.c_void_p(fake), 1 << 20, None,
                                ctypes.byref(h)) == EUNSUPPORTED
     # workspace too small: the required size is in the message

@@ -86,9 +86,10 @@ def test_autotune_sweep(env, tmp_path):
     torch, P, s, sg = env
     print("[gpu-test] autotune", flush=True)
     choice, rows = P.autotune(s, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 20000, K=2,
-                              leaf_sizes=(1, 4), wave_rays=(64, 256), reps=2,
+                              leaf_sizes=(1, 4), widths=(2, 8), wave_rays=(64, 256), reps=2,
                               cache_path=str(tmp_path / "tune.json"))
-    assert len(rows) == 4 and all(r["ms"] > 0 for r in rows)
+    assert len(rows) == 8 and all(r["ms"] > 0 for r in rows)
+    assert {(r["leaf_size"], r["width"]) for r in rows} == {(1, 2), (1, 8), (4, 2), (4, 8)}
     assert choice["ms"] == min(r["ms"] for r in rows)
     again, rows2 = P.autotune(s, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 20000, K=2,
                               cache_path=str(tmp_path / "tune.json"))
