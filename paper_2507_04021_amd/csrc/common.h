@@ -262,6 +262,34 @@ __device__ __forceinline__ bool wide_step(const DevScene &S, int &ref, int &sp, 
     return true;
 }
 
+// Any-hit step at a wide node: only the nearest entered child is singled out
+// (walked next); the other entered children are pushed in slot order. The
+// order cannot change an any-hit answer, only how soon it is found.
+template <int W>
+__device__ __forceinline__ bool wide_step_any(const DevScene &S, int &ref, int &sp, f3 inv, f3 oi, float t_lo,
+                                              float t_hi, Stack &stk) {
+    float tn[W];
+    int cr[W];
+    wide_hits<W>(S.node, ref, inv, oi, t_lo, t_hi, tn, cr);
+    float tb = tn[0];
+    int jb = 0;
+#pragma unroll
+    for (int j = 1; j < W; ++j) {
+        const bool lt = tn[j] < tb;
+        tb = lt ? tn[j] : tb;
+        jb = lt ? j : jb;
+    }
+    if (!(tb < INFINITY)) return false;
+    int nref = cr[0];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j > 0) nref = jb == j ? cr[j] : nref;
+        if (tn[j] < INFINITY && j != jb) stk.put(sp++, cr[j]);
+    }
+    ref = nref;
+    return true;
+}
+
 template <int W, bool kSecond>
 __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, f3 inv, int excl, float t_lo,
                                                  float eps_tie, Stack &stk, float &tmin, Cand *c, bool &spill,
@@ -353,7 +381,7 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
         if (ref >= 0) {
             stk.visit();
             if constexpr (W > 2) {
-                if (wide_step<W>(S, ref, sp, inv, oi, eps_self, t_hi, stk)) continue;
+                if (wide_step_any<W>(S, ref, sp, inv, oi, eps_self, t_hi, stk)) continue;
             } else {
                 const float4 *nd = S.node + 4 * (size_t)ref;
                 const float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
