@@ -192,9 +192,33 @@ __device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d,
 // Children of a wide node (8W floats: lo x[W], lo y[W], lo z[W], hi x[W],
 // hi y[W], hi z[W], refs[W], pad): entry distance per child (INFINITY for a
 // child the segment misses) and its reference.
+//
+// Octant form of the slab test: the sign of each inverse direction
+// component fixes which of lo / hi is the near plane on that axis for every
+// box, so a lane loads its near and far coordinate rows directly (per-lane
+// float4 offsets into the same node) and needs no per-box min/max. The
+// slab values are the same FMAs as in box_hit, and rounding is monotonic,
+// so each near / far value is exactly the one min / max would pick.
+struct Octant {
+    int nx, ny, nz, fx, fy, fz;  // float4 row offsets (in units of W floats / 4) of near and far planes
+};
+
+__device__ __forceinline__ Octant octant(f3 inv) {
+    Octant q;
+    q.nx = inv.x >= 0.f ? 0 : 3;
+    q.ny = inv.y >= 0.f ? 1 : 4;
+    q.nz = inv.z >= 0.f ? 2 : 5;
+    q.fx = 3 - q.nx;
+    q.fy = 5 - q.ny;
+    q.fz = 7 - q.nz;
+    return q;
+}
+
+// Same children test without the octant registers (the closest-hit walks are
+// register-bound: per-box min / max instead of per-lane row offsets).
 template <int W>
-__device__ __forceinline__ void wide_hits(const float4 *node, int ref, f3 inv, f3 oi, float t_lo, float t_hi,
-                                          float (&tn)[W], int (&cr)[W]) {
+__device__ __forceinline__ void wide_hits_minmax(const float4 *node, int ref, f3 inv, f3 oi, float t_lo, float t_hi,
+                                                 float (&tn)[W], int (&cr)[W]) {
     const float4 *nd = node + 2 * W * (size_t)ref;
     float v[7 * W];
 #pragma unroll
@@ -212,6 +236,46 @@ __device__ __forceinline__ void wide_hits(const float4 *node, int ref, f3 inv, f
                                t_hi, t);
         tn[j] = h ? t : INFINITY;
         cr[j] = __float_as_int(v[6 * W + j]);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void wide_hits(const float4 *node, int ref, const Octant &q, f3 inv, f3 oi, float t_lo,
+                                          float t_hi, float (&tn)[W], int (&cr)[W]) {
+    constexpr int R = W / 4;  // float4 per row of W floats
+    const float4 *nd = node + 2 * W * (size_t)ref;
+    float nx[W], ny[W], nz[W], fx[W], fy[W], fz[W];
+    auto row = [&](int r, float (&out)[W]) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float4 v = nd[r * R + k];
+            out[4 * k] = v.x;
+            out[4 * k + 1] = v.y;
+            out[4 * k + 2] = v.z;
+            out[4 * k + 3] = v.w;
+        }
+    };
+    row(q.nx, nx);
+    row(q.ny, ny);
+    row(q.nz, nz);
+    row(q.fx, fx);
+    row(q.fy, fy);
+    row(q.fz, fz);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const float4 v = nd[6 * R + k];
+        cr[4 * k] = __float_as_int(v.x);
+        cr[4 * k + 1] = __float_as_int(v.y);
+        cr[4 * k + 2] = __float_as_int(v.z);
+        cr[4 * k + 3] = __float_as_int(v.w);
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const float t0 = fmaxf(fmaxf(fmaf(nx[j], inv.x, -oi.x), fmaf(ny[j], inv.y, -oi.y)),
+                               fmaxf(fmaf(nz[j], inv.z, -oi.z), t_lo));
+        const float t1 = fminf(fminf(fmaf(fx[j], inv.x, -oi.x), fmaf(fy[j], inv.y, -oi.y)),
+                               fminf(fmaf(fz[j], inv.z, -oi.z), t_hi));
+        tn[j] = t0 <= t1 ? t0 : INFINITY;
     }
 }
 
@@ -252,7 +316,7 @@ __device__ __forceinline__ bool wide_step(const DevScene &S, int &ref, int &sp, 
                                           float t_hi, Stack &stk) {
     float tn[W];
     int cr[W];
-    wide_hits<W>(S.node, ref, inv, oi, t_lo, t_hi, tn, cr);
+    wide_hits_minmax<W>(S.node, ref, inv, oi, t_lo, t_hi, tn, cr);
     sort_hits<W>(tn, cr);
     if (!(tn[0] < INFINITY)) return false;
 #pragma unroll
@@ -266,11 +330,11 @@ __device__ __forceinline__ bool wide_step(const DevScene &S, int &ref, int &sp, 
 // (walked next); the other entered children are pushed in slot order. The
 // order cannot change an any-hit answer, only how soon it is found.
 template <int W>
-__device__ __forceinline__ bool wide_step_any(const DevScene &S, int &ref, int &sp, f3 inv, f3 oi, float t_lo,
-                                              float t_hi, Stack &stk) {
+__device__ __forceinline__ bool wide_step_any(const DevScene &S, int &ref, int &sp, const Octant &q, f3 inv, f3 oi,
+                                              float t_lo, float t_hi, Stack &stk) {
     float tn[W];
     int cr[W];
-    wide_hits<W>(S.node, ref, inv, oi, t_lo, t_hi, tn, cr);
+    wide_hits<W>(S.node, ref, q, inv, oi, t_lo, t_hi, tn, cr);
     float tb = tn[0];
     int jb = 0;
 #pragma unroll
@@ -375,13 +439,14 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     const float t_hi = L - eps_self;
     if (!(t_hi > eps_self)) return false;
     const f3 oi = times(a, inv);
+    const Octant oq = octant(inv);
     int ref = S.root;
     int sp = 0;
     for (;;) {
         if (ref >= 0) {
             stk.visit();
             if constexpr (W > 2) {
-                if (wide_step_any<W>(S, ref, sp, inv, oi, eps_self, t_hi, stk)) continue;
+                if (wide_step_any<W>(S, ref, sp, oq, inv, oi, eps_self, t_hi, stk)) continue;
             } else {
                 const float4 *nd = S.node + 4 * (size_t)ref;
                 const float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
