@@ -48,7 +48,8 @@ def ops_node(width):
 # WRITE_SIZE on this workload, scaled by the copy-kernel calibration (read x
 # 2.00, write x 1.00), together with the hash of the sources the measured
 # kernel was built from; reported only while the sources still match.
-TRAFFIC = None  # {"kernel": "k_diffuse", "bytes": B, "src_sha256": "..."}
+TRAFFIC = {"kernel": "k_diffuse", "bytes": 72301578752,
+           "src_sha256": "383fbf8a38f3aeac29a06d360170435eebe1efe1484197acb3b8542450f52829"}
 TRAFFIC_SOURCES = ("paper_2507_04021_amd/csrc/common.h", "paper_2507_04021_amd/csrc/internal.h",
                    "paper_2507_04021_amd/csrc/field.hip", "paper_2507_04021_amd/csrc/bvh.hip")
 
@@ -170,6 +171,68 @@ def grad_workload(reps):
                 grad_step_ms=timed(lambda: step(True), reps), train_iter_ms=timed(lambda: step(False), reps))
 
 
+def mlp_workload(iters):
+    """Learned materials: box room with one label per surface (8 labels);
+    512 channel sets, 256 at 3.5 GHz and 256 at 28 GHz, each 1 TX + 8 RX at
+    seeded random positions (seed 11); targets from hidden per-label
+    materials (seed 7). 448 sets train the network through their recorded
+    tapes (Adam, 8 sets per iteration), 64 are held out. Reports the held-out
+    mean |dG| in dB for the nominal per-label Fresnel model (the method
+    without the learned part) and for the trained network, the training
+    iteration time, and the BF16 MFMA forward / backward kernels' throughput
+    on 2^20 interaction rows."""
+    import torch
+    import paper_2507_04021_amd as P
+    from paper_2507_04021_amd import diff, mlp as M, scenes
+    s = scenes.box_room(labels="surface")
+    sg = P.Scene.from_scene(s)
+    truth = scenes.hidden_materials(7, 8, scatter=(0.1, 0.5))
+    nominal = scenes.box_room_materials("surface", scatter=0.2)
+    n_sets, rays, flags = 512, 3000, P.LOS | P.SPECULAR | P.DIFFUSE
+    tx, rx = scenes.random_links(11, n_sets, 8)
+    sets = []
+    t0 = time.perf_counter()
+    for i in range(n_sets):
+        f = 3.5e9 if i < n_sets // 2 else 28e9
+        tgt = 10 * torch.log10(P.solve(sg, truth, tx[i], rx[i], f, rays, K=2, flags=flags).gain)
+        sets.append((diff.record(sg, nominal, tx[i], rx[i], f, rays, K=2, flags=flags), f, tgt))
+    torch.cuda.synchronize()
+    rec_s = time.perf_counter() - t0
+    order = np.random.default_rng(11).permutation(n_sets)
+    train_sets, held = [sets[i] for i in order[:448]], [sets[i] for i in order[448:]]
+    net = M.MaterialMLP(M.init_params(8, seed=0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = M.train(net, train_sets, iters=iters, batch=8, lr=5e-3)
+    torch.cuda.synchronize()
+    iter_ms = (time.perf_counter() - t0) * 1e3 / iters
+    e_mlp = float(torch.cat([M.db_error(net.gains(r, f), t) for r, f, t in held]).mean())
+    e_nom = []
+    for r, f, t in held:
+        P.tape_fresnel(r, nominal)
+        e_nom.append(M.db_error(P.tape_forward(r)[0], t))
+    e_nom = float(torch.cat(e_nom).mean())
+    # kernel throughput on 2^20 rows (forward and backward MFMA GEMM chains)
+    n = 1 << 20
+    g = torch.Generator(device="cuda").manual_seed(3)
+    lab = torch.randint(0, 8, (n,), device="cuda", generator=g).to(torch.int16)
+    cs = torch.rand(n, device="cuda", generator=g)
+    out = torch.empty(n, 8, device="cuda")
+    g_out = torch.randn(n, 8, device="cuda", generator=g)
+    f_ms = timed(lambda: net.forward_rows(lab, cs, 28e9, out), 5)
+    b_ms = timed(lambda: net.backward_rows(lab, cs, 28e9, g_out), 5)
+    # per row: forward 2 x (32x64 + 64x64 + 64x64 + 64x16) flops; backward =
+    # forward recompute + input-gradient chain + weight gradients (3 x forward)
+    fw = 2 * (32 * 64 + 64 * 64 + 64 * 64 + 64 * 16)
+    return dict(workload="box room, 8 surface labels, 512 channel sets (256 at 3.5 GHz, 256 at 28 GHz), 1 TX + 8 RX "
+                         "each, %d rays, K=2, LOS+specular+diffuse; 448 train / 64 held out" % rays,
+                record_s=rec_s, train_iters=iters, train_iter_ms=iter_ms, loss_first=hist[0], loss_last=hist[-1],
+                heldout_db_error_nominal=e_nom, heldout_db_error_mlp=e_mlp,
+                mlp_forward_ms_1M_rows=f_ms, mlp_backward_ms_1M_rows=b_ms,
+                mlp_forward_tflops=fw * n / (f_ms / 1e3) / 1e12, mlp_backward_tflops=3 * fw * n / (b_ms / 1e3) / 1e12,
+                mfma_bf16_peak_tflops=2500.0)
+
+
 def cpu_baseline(sc, rx, tx, mats, n_budget, K, n_sample):
     import oracle
     from paper_2507_04021_amd import scenes
@@ -194,6 +257,7 @@ def main():
     ap.add_argument("--width", type=int, default=4, help="BVH node width (2, 4, 8)")
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--mlp-iters", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and gradient workloads")
     ap.add_argument("--copy-calib", action="store_true",
@@ -310,6 +374,8 @@ def main():
         line["batch"] = batch_workload(max(3, args.steps // 2))
         log("gradient workload...")
         line["grad"] = grad_workload(max(5, args.steps))
+        log("learned-material workload...")
+        line["mlp"] = mlp_workload(args.mlp_iters)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on %d rays..." % args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(sc, rx, tx, mats, args.rays, K, args.cpu_sample)
