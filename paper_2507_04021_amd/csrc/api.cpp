@@ -293,7 +293,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
     const bool spec = flags & PCRT_SPECULAR, diff = flags & PCRT_DIFFUSE, rec = flags & PCRT_RECORD;
     L.items = b.take(sizeof(Item) * D.n_items);
     L.counters = b.take(sizeof(uint64_t) * PCRT_CNT_COUNT);
-    L.work = b.take(sizeof(uint32_t) * 8);
+    L.work = b.take(sizeof(uint32_t) * kWorkWords);
     L.rec_id = b.take(sizeof(int) * nrec);
     L.rec_xl = b.take(sizeof(float4) * nrec);
     L.rec_cs = b.take(sizeof(float) * nrec);
@@ -495,7 +495,7 @@ static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats
     const bool tm = p->flags & PCRT_TIMING;
     for (int i = 0; i < kStages; ++i) g_ev_used[i] = tm;
     stage_mark(tm, 0, s);
-    fill_u32(A.work, 0, 8, s);
+    fill_u32(A.work, 0, kWorkWords, s);
     fill_u64(A.counters, 0, PCRT_CNT_COUNT, s);
     fill_u32(A.key_off, 0, P.D.n_items + 1, s);
     fill_u32(A.chunk_off, 0, P.D.n_items + 1, s);

@@ -100,8 +100,25 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
     const float eps = A.thr.eps_self;
     const uint32_t n_groups = kRayChunk * K / kWave;  // groups of 64 records per chunk
     uint32_t n_seg = 0, n_vis = 0;
+    // Workgroups are dealt to the XCDs round robin, and each XCD has its own
+    // L2: the blocks of XCD x take chunks from the x-th eighth of the
+    // (Morton-ordered) chunk range first, so one XCD's L2 serves one region
+    // of the scene, then help the other ranges in turn.
+    const uint32_t xcd = blockIdx.x % kXcds;
     for (;;) {
-        if (tid == 0) sm.chunk = atomicAdd(&A.work[2], 1u);
+        if (tid == 0) {
+            uint32_t c = n_chunks;
+            for (uint32_t k = 0; k < kXcds; ++k) {
+                const uint32_t x = (xcd + k) % kXcds;
+                const uint32_t hi = (uint32_t)((uint64_t)(x + 1) * n_chunks / kXcds);
+                const uint32_t cc = (uint32_t)((uint64_t)x * n_chunks / kXcds) + atomicAdd(&A.work[8 + x], 1u);
+                if (cc < hi) {
+                    c = cc;
+                    break;
+                }
+            }
+            sm.chunk = c;
+        }
         __syncthreads();
         const uint32_t c = sm.chunk;
         __syncthreads();

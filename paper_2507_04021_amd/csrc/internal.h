@@ -16,6 +16,10 @@ namespace pcrt {
 // waves pull work from atomic counters until it runs out.
 uint32_t resident_blocks(const void *kernel, int block_threads);
 constexpr uint32_t kMaxPairs = 262144;  // (transmitter, receiver) pairs in one solve
+// Work counters of the persistent launches: [0] trace units, [1] refine chunks,
+// [8, 16) diffuse chunks, one counter per XCD range.
+constexpr uint32_t kWorkWords = 32;
+constexpr uint32_t kXcds = 8;  // MI355X: 8 accelerator complex dies, workgroups dealt round robin
 constexpr uint32_t kDefaultWidth = 4;    // 4-wide nodes: fastest on the 1M-point office (binary and 8-wide slower)
 
 struct Bump {  // 256-byte aligned offsets inside one workspace
