@@ -121,8 +121,8 @@ def timed(fn, reps, warm=1):
 def batch_workload(reps):
     """256 transmitter poses along a robot trajectory in the tiny box room,
     ray counts uniform in [2^16, 2^20], K = 2, one graph launch per batch;
-    BVH leaf size, node width and rays per wavefront fetch picked by the
-    autotuner."""
+    BVH builder, leaf size, node width and rays per wavefront fetch picked by
+    the autotuner."""
     import torch
     import paper_2507_04021_amd as P
     from paper_2507_04021_amd import scenes
@@ -130,9 +130,9 @@ def batch_workload(reps):
     mats = scenes.box_room_materials()
     tx, n = scenes.trajectory(seed=4021, n=256)
     choice, rows = P.autotune(s, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 1 << 20, K=2, flags=P.LOS | P.SPECULAR,
-                              leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8), wave_rays=(64, 128, 256), reps=3,
-                              cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"))
-    sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"], width=choice["width"])
+                              leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8), wave_rays=(64, 128, 256), builders=(1, 2),
+                              reps=3, cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"))
+    sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"], width=choice["width"], builder=choice["builder"])
     graph = P.BatchGraph(sg, mats, tx, n, [scenes.BOX_RX], 3.5e9, K=2, flags=P.LOS | P.SPECULAR,
                          wave_rays=choice["wave_rays"])
     ms = timed(lambda: graph.launch(), reps)
@@ -253,8 +253,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=2)
     ap.add_argument("--width", type=int, default=4, help="BVH node width (2, 4, 8)")
+    ap.add_argument("--builder", type=int, default=0, help="BVH builder: 0 default, 1 radix tree, 2 clustering")
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--mlp-iters", type=int, default=300)
@@ -283,7 +284,7 @@ def main():
     sc, rx, tx, mats = office_inputs()
     log("office scene: %d points, %d surfaces" % (sc.n, sc.n_surfaces))
     dev = torch.device("cuda")
-    scene = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width)
+    scene = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width, builder=args.builder)
     torch.cuda.synchronize()
     log("hierarchy:", scene.info)
     mats_t = P.materials_tensor(mats, dev)
@@ -315,7 +316,7 @@ def main():
 
     # algorithmic bytes from one instrumented solve (same inputs, same results)
     P.use_counting(True)
-    scene_c = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width)
+    scene_c = P.Scene.from_scene(sc, leaf_size=args.leaf, width=args.width, builder=args.builder)
     rc = P.solve(scene_c, mats_t, tx, rx_t, freq, args.rays, K=K, flags=flags)
     torch.cuda.synchronize()
     ccnt = {k: int(rc.counters[i].item()) for k, i in P.CNT.items()}
@@ -349,6 +350,7 @@ def main():
                         "%d rays, K=5, 28 GHz, LOS+specular+diffuse" % (sc.n, args.rays),
             "leaf_size": args.leaf,
             "bvh_width": args.width,
+            "bvh_builder": scene.info["builder"],
         },
         "roofline": {
             "bound": "alu",

@@ -71,7 +71,14 @@ typedef struct {
 typedef struct {
     uint32_t leaf_size;
     uint32_t width;
+    uint32_t builder; /* PCRT_BUILD_*; 0 = default (PCRT_BUILD_PLOC) */
 } pcrt_bvh_opts;
+
+enum {
+    PCRT_BUILD_LBVH = 1, /* Karras radix tree over Morton codes of the disk centres */
+    PCRT_BUILD_PLOC = 2  /* locally-ordered clustering: mutual nearest neighbours by merged surface area within
+                            +-16 positions of the Morton order, disks renumbered depth-first */
+};
 
 /* Scene statistics filled by pcrt_scene_create. */
 typedef struct {
@@ -83,6 +90,7 @@ typedef struct {
     uint32_t leaf_size;
     uint32_t width;
     uint32_t stack_entries; /* bound on traversal stack entries: (width - 1) x levels */
+    uint32_t builder;
     float bbox[6];         /* lo xyz, hi xyz of the disk bounds */
     double build_ms;       /* device time of the build */
 } pcrt_scene_info;

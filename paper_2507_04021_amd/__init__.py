@@ -37,13 +37,16 @@ class Points(ctypes.Structure):
 
 
 class BvhOpts(ctypes.Structure):
-    _fields_ = [("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32)]
+    _fields_ = [("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32), ("builder", ctypes.c_uint32)]
+
+
+BUILD_LBVH, BUILD_PLOC = 1, 2
 
 
 class SceneInfo(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_uint32), ("n_surfaces", ctypes.c_uint32), ("n_materials", ctypes.c_uint32),
                 ("depth", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("leaf_size", ctypes.c_uint32),
-                ("width", ctypes.c_uint32), ("stack_entries", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("stack_entries", ctypes.c_uint32), ("builder", ctypes.c_uint32),
                 ("bbox", ctypes.c_float * 6), ("build_ms", ctypes.c_double)]
 
 
@@ -171,7 +174,8 @@ def _ptr(t):
 class Scene:
     """A point cloud of disks with its bounding-volume hierarchy on the GPU."""
 
-    def __init__(self, pos, normal, material, surface, radius, leaf_size=4, width=4, device="cuda", stream=None):
+    def __init__(self, pos, normal, material, surface, radius, leaf_size=4, width=4, builder=0, device="cuda",
+                 stream=None):
         torch = _torch()
         self.device = torch.device(device)
         pos = _dev(pos, torch.float32, self.device).reshape(-1, 3)
@@ -183,7 +187,7 @@ class Scene:
         n = pos.shape[0]
         self.n = n
         self.radius = float(radius)
-        opts = BvhOpts(leaf_size, width)
+        opts = BvhOpts(leaf_size, width, builder)
         nbytes = ctypes.c_size_t(0)
         _check(lib().pcrt_scene_workspace_size(n, ctypes.byref(opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
@@ -197,7 +201,8 @@ class Scene:
         _check(lib().pcrt_scene_get_info(self.handle, ctypes.byref(info)))
         self.info = dict(n_points=info.n_points, n_surfaces=info.n_surfaces, n_materials=info.n_materials,
                          depth=info.depth, n_nodes=info.n_nodes, leaf_size=info.leaf_size, width=info.width,
-                         stack_entries=info.stack_entries, bbox=list(info.bbox), build_ms=info.build_ms)
+                         stack_entries=info.stack_entries, builder=info.builder, bbox=list(info.bbox),
+                         build_ms=info.build_ms)
 
     @classmethod
     def from_scene(cls, sc, **kw):
@@ -425,10 +430,10 @@ class BatchGraph:
 
 
 def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8),
-             wave_rays=(64, 128, 256), reps=3, cache_path=None, device="cuda"):
-    """Sweep BVH leaf size x node width x rays per wavefront fetch with the
-    library's tuner (one scene per leaf size and width, built here); the
-    winner is stored in a JSON cache keyed by the workload."""
+             wave_rays=(64, 128, 256), builders=(0,), reps=3, cache_path=None, device="cuda"):
+    """Sweep BVH builder x leaf size x node width x rays per wavefront fetch
+    with the library's tuner (one scene per builder, leaf size and width,
+    built here); the winner is stored in a JSON cache keyed by the workload."""
     import json
     torch = _torch()
     key = "n=%d rays=%d K=%d flags=%d rx=%d dev=%s" % (sc.n, n_rays, K, flags, np.asarray(rx).reshape(-1, 3).shape[0],
@@ -441,7 +446,8 @@ def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_siz
     if key in cache:
         return cache[key], None
     L = lib()
-    cands = [Scene.from_scene(sc, leaf_size=l, width=w, device=device) for l in leaf_sizes for w in widths]
+    cands = [Scene.from_scene(sc, leaf_size=l, width=w, builder=b, device=device)
+             for b in builders for l in leaf_sizes for w in widths]
     res = solve(cands[0], mats, tx, rx, freq, n_rays, K=K, flags=flags)
     p = res.params
     need = 0
@@ -462,8 +468,10 @@ def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_siz
     mats_t = res.keep[0]
     _check(L.pcrt_autotune(handles, len(cands), ctypes.byref(p), _ptr(mats_t), mats_t.shape[0], wr, len(wave_rays),
                            reps, _ptr(ws), ws.numel(), ctypes.byref(o), _stream(), table, ctypes.byref(best)), L)
-    choice = dict(leaf_size=best.leaf_size, width=best.width, wave_rays=best.wave_rays, ms=best.ms)
-    rows = [dict(leaf_size=t.leaf_size, width=t.width, wave_rays=t.wave_rays, ms=t.ms) for t in table]
+    choice = dict(builder=cands[best.scene].info["builder"], leaf_size=best.leaf_size, width=best.width,
+                  wave_rays=best.wave_rays, ms=best.ms)
+    rows = [dict(builder=cands[t.scene].info["builder"], leaf_size=t.leaf_size, width=t.width, wave_rays=t.wave_rays,
+                 ms=t.ms) for t in table]
     cache[key] = choice
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

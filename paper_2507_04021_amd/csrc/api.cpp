@@ -370,7 +370,9 @@ pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *op
     const uint32_t width = opts && opts->width ? opts->width : kDefaultWidth;
     if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
     if (opts && opts->leaf_size > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
-    *bytes = scene_layout(n_points, width).total;
+    const uint32_t builder = opts && opts->builder ? opts->builder : kDefaultBuilder;
+    if (builder != kBuildLbvh && builder != kBuildPloc) return fail(PCRT_EUNSUPPORTED, "builder must be 1 or 2");
+    *bytes = scene_layout(n_points, width, builder).total;
     return ok();
 }
 
@@ -387,7 +389,9 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     if (leaf < 1 || leaf > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
     const uint32_t width = opts && opts->width ? opts->width : kDefaultWidth;
     if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
-    SceneLayout L = scene_layout(pts->n_points, width);
+    const uint32_t builder = opts && opts->builder ? opts->builder : kDefaultBuilder;
+    if (builder != kBuildLbvh && builder != kBuildPloc) return fail(PCRT_EUNSUPPORTED, "builder must be 1 or 2");
+    SceneLayout L = scene_layout(pts->n_points, width, builder);
     if (ws_bytes < L.total) return fail(PCRT_ENOMEM, "scene workspace too small: need %zu bytes", L.total);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -395,8 +399,9 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
     uint32_t wide_levels = 0, wide_nodes = 0;
+    int broot = 0;
     HIP_TRY(build_scene(pts->pos, pts->normal, pts->material, pts->surface, pts->n_points, pts->disk_radius, leaf,
-                        (char *)ws, L, s, &wide_levels, &wide_nodes));
+                        (char *)ws, L, s, &wide_levels, &wide_nodes, &broot));
     HIP_TRY(hipEventRecord(e1, s));
     uint32_t stat[8];
     float bounds[6];
@@ -429,7 +434,8 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     sc->dev.bounds = (const float *)(sc->ws + L.bounds);
     sc->dev.r2 = pts->disk_radius * pts->disk_radius;
     sc->dev.n = n;
-    sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : 0);
+    // the wide hierarchy's root is node 0; the binary root is the builder's
+    sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : (width > 2 ? 0 : broot));
     pcrt_scene_info &I = sc->info;
     I.n_points = n;
     I.n_surfaces = stat[1] + 1;
@@ -439,6 +445,7 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     I.leaf_size = leaf;
     I.width = width;
     I.stack_entries = stack_entries;
+    I.builder = builder;
     memcpy(I.bbox, bounds, sizeof bounds);
     I.build_ms = ms;
     *out = sc;

@@ -8,6 +8,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <vector>
+
 namespace pcrt {
 
 // --------------------------------------------------------------- ingest
@@ -256,6 +258,138 @@ void fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, s, p, v, n);
 }
 
+// --------------------------------------------------- clustering builder
+// Parallel locally-ordered clustering (Meister & Bittner, 2018) over the
+// Morton-ordered disks. Each pass: every cluster finds, within +-kPlocRadius
+// positions, the cluster whose merged box has the smallest surface area
+// (ties: smaller index); mutual nearest pairs merge into a new internal node
+// (lower index keeps the slot) and the list is compacted by an exclusive
+// scan. The order on pairs (area, lower index, higher index) is total, so
+// the globally cheapest pair is always mutual and every pass merges at least
+// one pair. Internal nodes are numbered in creation order; the root is the
+// last. The disks are then renumbered in depth-first order so that every
+// subtree owns a contiguous disk range, which is what the refit and the leaf
+// references expect.
+constexpr int kPlocRadius = 16;
+
+__device__ __forceinline__ float merged_half_area(const float *a, const float *b) {
+    const float dx = fmaxf(a[3], b[3]) - fminf(a[0], b[0]);
+    const float dy = fmaxf(a[4], b[4]) - fminf(a[1], b[1]);
+    const float dz = fmaxf(a[5], b[5]) - fminf(a[2], b[2]);
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_nn(const float *__restrict__ cbox, uint32_t n, int *__restrict__ nn) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float bi[6];
+    for (int a = 0; a < 6; ++a) bi[a] = cbox[6 * (size_t)i + a];
+    const uint32_t lo = i > (uint32_t)kPlocRadius ? i - kPlocRadius : 0u;
+    const uint32_t hi = min(n - 1, i + kPlocRadius);
+    float best = INFINITY;
+    int bj = -1;
+    for (uint32_t j = lo; j <= hi; ++j) {  // increasing j: a strict < keeps the smaller index on ties
+        if (j == i) continue;
+        const float c = merged_half_area(bi, cbox + 6 * (size_t)j);
+        if (c < best) {
+            best = c;
+            bj = (int)j;
+        }
+    }
+    nn[i] = bj;
+}
+
+__global__ void k_ploc_flags(const int *__restrict__ nn, uint32_t n, uint32_t *__restrict__ merge,
+                             uint32_t *__restrict__ keep) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = nn[i];
+    const bool mutual = nn[j] == (int)i;
+    merge[i] = mutual && (int)i < j;
+    keep[i] = !(mutual && (int)i > j);
+}
+
+__global__ void k_ploc_apply(const float *__restrict__ cbox, const int *__restrict__ cid,
+                             const uint32_t *__restrict__ csize, const int *__restrict__ nn, uint32_t n,
+                             const uint32_t *__restrict__ mpos, const uint32_t *__restrict__ kpos, uint32_t node_base,
+                             float *__restrict__ obox, int *__restrict__ oid, uint32_t *__restrict__ osize,
+                             int2 *__restrict__ child, uint32_t *__restrict__ nsize, int *__restrict__ parent_int,
+                             int *__restrict__ parent_leaf) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = nn[i];
+    const bool mutual = nn[j] == (int)i;
+    if (mutual && (int)i > j) return;  // merged into the lower slot
+    const uint32_t p = kpos[i];
+    if (!mutual) {
+        for (int a = 0; a < 6; ++a) obox[6 * (size_t)p + a] = cbox[6 * (size_t)i + a];
+        oid[p] = cid[i];
+        osize[p] = csize[i];
+        return;
+    }
+    const int node = (int)(node_base + mpos[i]);
+    const int a = cid[i], b = cid[j];
+    child[node] = make_int2(a, b);
+    const uint32_t sz = csize[i] + csize[j];
+    nsize[node] = sz;
+    if (a < 0) parent_leaf[~a] = node;
+    else parent_int[a] = node;
+    if (b < 0) parent_leaf[~b] = node;
+    else parent_int[b] = node;
+    const float *x = cbox + 6 * (size_t)i, *y = cbox + 6 * (size_t)j;
+    for (int k = 0; k < 3; ++k) {
+        obox[6 * (size_t)p + k] = fminf(x[k], y[k]);
+        obox[6 * (size_t)p + 3 + k] = fmaxf(x[3 + k], y[3 + k]);
+    }
+    oid[p] = node;
+    osize[p] = sz;
+}
+
+// Depth-first offsets, one creation pass at a time from the root's down
+// (a node's parent is always created in a later pass).
+__global__ void k_dfs_pass(const int2 *__restrict__ child, const uint32_t *__restrict__ nsize, uint32_t lo,
+                           uint32_t hi, uint32_t *__restrict__ noff, uint32_t *__restrict__ leaf_pos) {
+    const uint32_t node = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= hi) return;
+    const uint32_t o = noff[node];
+    const int2 c = child[node];
+    const uint32_t sa = c.x < 0 ? 1u : nsize[c.x];
+    if (c.x < 0) leaf_pos[~c.x] = o;
+    else noff[c.x] = o;
+    if (c.y < 0) leaf_pos[~c.y] = o + sa;
+    else noff[c.y] = o + sa;
+}
+
+__global__ void k_dfs_leaves(uint32_t n, const uint32_t *__restrict__ leaf_pos, const uint32_t *__restrict__ sorted_id,
+                             const int *__restrict__ parent_leaf_old, uint32_t *__restrict__ perm,
+                             int *__restrict__ parent_leaf) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = leaf_pos[i];
+    perm[p] = sorted_id[i];
+    parent_leaf[p] = parent_leaf_old[i];
+}
+
+__global__ void k_dfs_nodes(uint32_t n_int, const uint32_t *__restrict__ leaf_pos, const uint32_t *__restrict__ noff,
+                            const uint32_t *__restrict__ nsize, int2 *__restrict__ child, int2 *__restrict__ range) {
+    const uint32_t node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= n_int) return;
+    int2 c = child[node];
+    if (c.x < 0) c.x = ~(int)leaf_pos[~c.x];
+    if (c.y < 0) c.y = ~(int)leaf_pos[~c.y];
+    child[node] = c;
+    range[node] = make_int2((int)noff[node], (int)(noff[node] + nsize[node] - 1));
+}
+
+__global__ void k_ploc_init(const float *__restrict__ dbox, uint32_t n, float *__restrict__ cbox, int *__restrict__ cid,
+                            uint32_t *__restrict__ csize) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int a = 0; a < 6; ++a) cbox[6 * (size_t)i + a] = dbox[6 * (size_t)i + a];
+    cid[i] = ~(int)i;
+    csize[i] = 1;
+}
+
 // --------------------------------------------------------- wide nodes
 // Collapse of the binary hierarchy into nodes of up to W children, level by
 // level from the root. A wide node starts from its binary node's two
@@ -348,7 +482,7 @@ __global__ void k_wide_emit(const float4 *__restrict__ bnode, const int *__restr
     }
 }
 
-SceneLayout scene_layout(uint32_t n, uint32_t width) {
+SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder) {
     Bump b;
     SceneLayout L;
     uint32_t ni = n > 1 ? n - 1 : 1;
@@ -375,6 +509,23 @@ SceneLayout scene_layout(uint32_t n, uint32_t width) {
     L.flags = b.take(sizeof(uint32_t) * ni);
     L.width = width;
     L.n_internal = ni;
+    L.builder = builder;
+    if (builder == kBuildPloc) {
+        for (int k = 0; k < 2; ++k) {
+            L.cbox[k] = b.take(sizeof(float) * 6 * (size_t)n);
+            L.cid[k] = b.take(sizeof(int) * n);
+            L.csz[k] = b.take(sizeof(uint32_t) * n);
+        }
+        L.nn = b.take(sizeof(int) * n);
+        L.mflag = b.take(sizeof(uint32_t) * n);
+        L.kflag = b.take(sizeof(uint32_t) * n);
+        L.pblk = b.take(sizeof(uint32_t) * scan_blk_words(n));
+        L.nsize = b.take(sizeof(uint32_t) * ni);
+        L.noff = b.take(sizeof(uint32_t) * ni);
+        L.leaf_pos = b.take(sizeof(uint32_t) * n);
+        L.perm2 = b.take(sizeof(uint32_t) * n);
+        L.pleaf2 = b.take(sizeof(int) * n);
+    }
     if (width > 2) {  // every wide node stands for a distinct binary internal node
         L.wnode = b.take(sizeof(float) * 8 * width * (size_t)ni);
         L.front0 = b.take(sizeof(int) * ni);
@@ -386,16 +537,70 @@ SceneLayout scene_layout(uint32_t n, uint32_t width) {
     return L;
 }
 
+// Clustering build over the Morton-ordered disk boxes in dbox (n >= 2):
+// fills child / parent arrays, renumbers the disks depth-first (perm2,
+// pleaf2, range) and returns the root.
+hipError_t build_ploc(const SceneLayout &L, char *ws, uint32_t n, const uint32_t *sorted_id, hipStream_t s,
+                      int *root) {
+    auto P = [&](size_t off) { return ws + off; };
+    float *cbox[2] = {(float *)P(L.cbox[0]), (float *)P(L.cbox[1])};
+    int *cid[2] = {(int *)P(L.cid[0]), (int *)P(L.cid[1])};
+    uint32_t *csz[2] = {(uint32_t *)P(L.csz[0]), (uint32_t *)P(L.csz[1])};
+    int *nn = (int *)P(L.nn);
+    uint32_t *mflag = (uint32_t *)P(L.mflag), *kflag = (uint32_t *)P(L.kflag), *pblk = (uint32_t *)P(L.pblk);
+    uint32_t *nsize = (uint32_t *)P(L.nsize), *noff = (uint32_t *)P(L.noff), *leaf_pos = (uint32_t *)P(L.leaf_pos);
+    int2 *child = (int2 *)P(L.child), *range = (int2 *)P(L.range);
+    int *pint = (int *)P(L.parent_int), *pleaf = (int *)P(L.parent_leaf);
+    hipLaunchKernelGGL(k_ploc_init, dim3(cdiv(n, 256)), dim3(256), 0, s, (const float *)P(L.dbox), n, cbox[0], cid[0],
+                       csz[0]);
+    std::vector<uint32_t> bases;
+    uint32_t m = n, node_base = 0;
+    int cur = 0;
+    while (m > 1) {
+        if (bases.size() >= n) return hipErrorUnknown;  // every pass merges at least one pair
+        const uint32_t g = cdiv(m, 256);
+        hipLaunchKernelGGL(k_ploc_nn, dim3(g), dim3(256), 0, s, cbox[cur], m, nn);
+        hipLaunchKernelGGL(k_ploc_flags, dim3(g), dim3(256), 0, s, nn, m, mflag, kflag);
+        exclusive_scan(kflag, m, pblk, s);
+        exclusive_scan(mflag, m, pblk, s);  // merge count lands in pblk[cdiv(m, 1024)]
+        hipLaunchKernelGGL(k_ploc_apply, dim3(g), dim3(256), 0, s, cbox[cur], cid[cur], csz[cur], nn, m, mflag, kflag,
+                           node_base, cbox[cur ^ 1], cid[cur ^ 1], csz[cur ^ 1], child, nsize, pint, pleaf);
+        uint32_t merges = 0;
+        hipError_t e = hipMemcpyAsync(&merges, pblk + cdiv(m, 1024), sizeof merges, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (merges == 0 || merges > m / 2) return hipErrorUnknown;
+        bases.push_back(node_base);
+        node_base += merges;
+        m -= merges;
+        cur ^= 1;
+    }
+    if (node_base != n - 1) return hipErrorUnknown;
+    const int r = (int)(n - 2);
+    fill_u32((uint32_t *)pint + r, 0xffffffffu, 1, s);
+    fill_u32(noff + r, 0, 1, s);
+    for (size_t t = bases.size(); t-- > 0;) {
+        const uint32_t lo = bases[t], hi = t + 1 < bases.size() ? bases[t + 1] : node_base;
+        hipLaunchKernelGGL(k_dfs_pass, dim3(cdiv(hi - lo, 256)), dim3(256), 0, s, child, nsize, lo, hi, noff, leaf_pos);
+    }
+    hipLaunchKernelGGL(k_dfs_leaves, dim3(cdiv(n, 256)), dim3(256), 0, s, n, leaf_pos, sorted_id, pleaf,
+                       (uint32_t *)P(L.perm2), (int *)P(L.pleaf2));
+    hipLaunchKernelGGL(k_dfs_nodes, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, n - 1, leaf_pos, noff, nsize, child,
+                       range);
+    *root = r;
+    return hipGetLastError();
+}
+
 // Level-by-level collapse (one scan per level); the host reads each level's
 // size, so this synchronises the stream once per level. Host outputs: the
 // number of wide levels and of wide nodes.
 template <int W>
-hipError_t build_wide_w(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes) {
+hipError_t build_wide_w(const SceneLayout &L, char *ws, hipStream_t s, int broot, uint32_t *levels, uint32_t *nodes) {
     const float4 *bnode = (const float4 *)(ws + L.node);
     int *fr[2] = {(int *)(ws + L.front0), (int *)(ws + L.front1)};
     uint32_t *cnt = (uint32_t *)(ws + L.wcnt), *blk = (uint32_t *)(ws + L.wblk);
     float *wnode = (float *)(ws + L.wnode);
-    fill_u32((uint32_t *)fr[0], 0, 1, s);  // binary root
+    fill_u32((uint32_t *)fr[0], (uint32_t)broot, 1, s);  // binary root
     const uint32_t ni = L.n_internal;
     uint32_t nf = 1, base = 0, lv = 0;
     while (nf > 0) {
@@ -419,13 +624,14 @@ hipError_t build_wide_w(const SceneLayout &L, char *ws, hipStream_t s, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes) {
-    return L.width == 4 ? build_wide_w<4>(L, ws, s, levels, nodes) : build_wide_w<8>(L, ws, s, levels, nodes);
+hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, int broot, uint32_t *levels, uint32_t *nodes) {
+    return L.width == 4 ? build_wide_w<4>(L, ws, s, broot, levels, nodes)
+                        : build_wide_w<8>(L, ws, s, broot, levels, nodes);
 }
 
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
                        float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s, uint32_t *wide_levels,
-                       uint32_t *wide_nodes) {
+                       uint32_t *wide_nodes, int *root) {
     auto P = [&](size_t off) { return ws + off; };
     float4 *pos_id = (float4 *)P(L.pos_id), *nrm_id = (float4 *)P(L.nrm_id);
     uint32_t *stat = (uint32_t *)P(L.stat);
@@ -445,18 +651,30 @@ hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, 
     }
     float *dbox = (float *)P(L.dbox);
     hipLaunchKernelGGL(k_gather, dim3(blk), dim3(256), 0, s, pos_id, nrm_id, i0, n, r, (float4 *)P(L.disk), dbox);
+    int broot = 0;
     if (n > 1) {
         int2 *child = (int2 *)P(L.child), *range = (int2 *)P(L.range);
         int *pint = (int *)P(L.parent_int), *pleaf = (int *)P(L.parent_leaf);
-        hipLaunchKernelGGL(k_karras, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, c0, (int)n, child, range, pint, pleaf);
+        if (L.builder == kBuildPloc) {
+            hipError_t e = build_ploc(L, ws, n, i0, s, &broot);
+            if (e != hipSuccess) return e;
+            // disks and their boxes again, now in depth-first order
+            hipLaunchKernelGGL(k_gather, dim3(blk), dim3(256), 0, s, pos_id, nrm_id, (const uint32_t *)P(L.perm2), n, r,
+                               (float4 *)P(L.disk), dbox);
+            pleaf = (int *)P(L.pleaf2);
+        } else {
+            hipLaunchKernelGGL(k_karras, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, c0, (int)n, child, range, pint,
+                               pleaf);
+        }
         fill_u32((uint32_t *)P(L.flags), 0, n - 1, s);
         hipLaunchKernelGGL(k_refit, dim3(blk), dim3(256), 0, s, (int)n, (int)leaf, child, range, pint, pleaf, dbox,
                            (float *)P(L.ibox), (uint32_t *)P(L.flags), (float4 *)P(L.node));
         hipLaunchKernelGGL(k_depth, dim3(blk), dim3(256), 0, s, (int)n, pint, pleaf, stat + 3);
     }
+    *root = broot;
     *wide_levels = *wide_nodes = 0;
     if (L.width > 2 && n > leaf) {
-        hipError_t e = build_wide(L, ws, s, wide_levels, wide_nodes);
+        hipError_t e = build_wide(L, ws, s, broot, wide_levels, wide_nodes);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();

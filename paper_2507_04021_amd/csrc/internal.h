@@ -21,6 +21,7 @@ constexpr uint32_t kMaxPairs = 262144;  // (transmitter, receiver) pairs in one 
 constexpr uint32_t kWorkWords = 32;
 constexpr uint32_t kXcds = 8;  // MI355X: 8 accelerator complex dies, workgroups dealt round robin
 constexpr uint32_t kDefaultWidth = 4;    // 4-wide nodes: fastest on the 1M-point office (binary and 8-wide slower)
+constexpr uint32_t kDefaultBuilder = 2;  // clustering: 6 % fewer node visits than the radix tree on the office
 
 struct Bump {  // 256-byte aligned offsets inside one workspace
     size_t off = 0;
@@ -31,20 +32,26 @@ struct Bump {  // 256-byte aligned offsets inside one workspace
     }
 };
 
+constexpr uint32_t kBuildLbvh = 1;  // Karras radix tree over Morton codes
+constexpr uint32_t kBuildPloc = 2;  // locally-ordered clustering (surface-area merges)
+
 struct SceneLayout {
     size_t pos_id, nrm_id, disk, node, stat, bounds, blk_bounds;
     size_t code0, code1, idx0, idx1, hist, scan_blk, child, range, parent_int, parent_leaf, dbox, ibox, flags;
     uint32_t width = 2;                             // node width of the traversed hierarchy
     uint32_t n_internal = 1;                        // binary internal nodes (buffer capacity)
+    uint32_t builder = kBuildLbvh;
+    size_t cbox[2] = {0, 0}, cid[2] = {0, 0}, csz[2] = {0, 0};  // clustering build (builder == kBuildPloc)
+    size_t nn = 0, mflag = 0, kflag = 0, pblk = 0, nsize = 0, noff = 0, leaf_pos = 0, perm2 = 0, pleaf2 = 0;
     size_t wnode = 0, front0 = 0, front1 = 0, wcnt = 0, wblk = 0;  // wide collapse (width > 2)
     size_t total;
 };
 
-SceneLayout scene_layout(uint32_t n, uint32_t width);
-hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, uint32_t *levels, uint32_t *nodes);
+SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder);
+hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, int broot, uint32_t *levels, uint32_t *nodes);
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
                        float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s, uint32_t *wide_levels,
-                       uint32_t *wide_nodes);
+                       uint32_t *wide_nodes, int *root);
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 uint32_t scan_blk_words(uint32_t n);
 uint32_t radix_hist_words(uint32_t n);

@@ -53,11 +53,11 @@ def test_scene_argument_errors(L):
     assert L.pcrt_scene_workspace_size(10, None, None) == EINVAL
     assert L.pcrt_scene_workspace_size(1 << 28, None, ctypes.byref(nb)) == EUNSUPPORTED
     assert L.pcrt_scene_workspace_size(1000, None, ctypes.byref(nb)) == 0 and nb.value > 1000 * 64
-    o = P.BvhOpts(4, 2)
+    o = P.BvhOpts(4, 2, 1)
     assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0
     binary = nb.value
     for w in (4, 8):  # wide nodes add their own array (32 W bytes per binary internal node) and build buffers
-        o = P.BvhOpts(4, w)
+        o = P.BvhOpts(4, w, 1)
         assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0
         assert nb.value >= binary + 999 * 32 * w
     for w in (1, 3, 16):
@@ -66,6 +66,10 @@ def test_scene_argument_errors(L):
         assert b"width" in L.pcrt_last_error()
     o = P.BvhOpts(9, 2)
     assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == EUNSUPPORTED
+    o = P.BvhOpts(4, 2, 3)  # builders are 1 (radix tree) and 2 (clustering)
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == EUNSUPPORTED
+    o = P.BvhOpts(4, 2, 2)  # the clustering build needs its own buffers
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0 and nb.value > binary
     h = ctypes.c_void_p()
     fake = 0x1000  # never dereferenced: argument checks run first
     pts = P.Points(fake, fake, fake, fake, 10, 0.0)

@@ -88,16 +88,17 @@ def test_raygen_subset_at_full_budget(P, orc):
 
 
 # ------------------------------------------------------------ small scenes
-@pytest.mark.parametrize("n_disks,seed,leaf,width", [(50, 1, 1, 2), (300, 2, 4, 2), (2000, 3, 8, 2), (700, 4, 2, 2),
-                                                     (300, 2, 4, 4), (2000, 3, 1, 4), (700, 4, 2, 8),
-                                                     (2000, 3, 8, 8)])
-def test_random_scene_full_parity(P, orc, n_disks, seed, leaf, width):
+@pytest.mark.parametrize("n_disks,seed,leaf,width,builder", [(50, 1, 1, 2, 1), (300, 2, 4, 2, 1), (2000, 3, 8, 2, 1),
+                                                             (700, 4, 2, 2, 1), (300, 2, 4, 4, 1), (2000, 3, 1, 4, 1),
+                                                             (700, 4, 2, 8, 1), (2000, 3, 8, 8, 1), (50, 1, 1, 2, 2),
+                                                             (2000, 3, 4, 4, 2), (700, 4, 8, 8, 2)])
+def test_random_scene_full_parity(P, orc, n_disks, seed, leaf, width, builder):
     s = scenes.random_disks(n_disks, seed=seed, extent=1.5, radius=0.25 if n_disks < 1000 else 0.12)
     mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2], [2.0, 0.01, 0.5]])
     rx = np.array([[0.3, -0.2, 0.1], [-0.5, 0.4, -0.3], [1.0, 1.0, 1.0]], np.float32)
     N, K = 3000, 4
-    step("random scene n=%d seed=%d leaf=%d width=%d" % (n_disks, seed, leaf, width))
-    sg = P.Scene.from_scene(s, leaf_size=leaf, width=width)
+    step("random scene n=%d seed=%d leaf=%d width=%d builder=%d" % (n_disks, seed, leaf, width, builder))
+    sg = P.Scene.from_scene(s, leaf_size=leaf, width=width, builder=builder)
     r = gpu_solve(P, sg, mats, [0, 0, 0], rx, 28e9, N, K, LOS | SPEC | DIFF | REC)
     vis = P.diffuse_vis(r).cpu().numpy().astype(bool)
     ref = orc.solve(s, mats, [0, 0, 0], rx, 28e9, N, K=K, flags=LOS | SPEC | DIFF, want_dvis=True)
@@ -248,20 +249,20 @@ def test_leaf_size_and_determinism(P, box):
         assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
 
 
-@pytest.mark.parametrize("leaf", [1, 4, 8])
-def test_node_width_never_changes_a_result(P, box, leaf):
-    """Binary, 4-wide and 8-wide hierarchies give bitwise equal sequences,
-    path records and per-receiver sums (order-free tie rule; any-hit is a
-    predicate), and the wide trees obey their stack bound."""
+@pytest.mark.parametrize("leaf,builder", [(1, 1), (4, 1), (8, 1), (1, 2), (4, 2)])
+def test_node_width_never_changes_a_result(P, box, leaf, builder):
+    """Binary, 4-wide and 8-wide hierarchies from either builder give bitwise
+    equal sequences, path records and per-receiver sums (order-free tie rule;
+    any-hit is a predicate), and the wide trees obey their stack bound."""
     s, _ = box
     mats = scenes.box_room_materials(scatter=0.3)
     rx = [scenes.BOX_RX, [3, 2, 2], [0.5, 3.5, 2.8]]
     outs = []
     for w in (2, 4, 8):
-        step("box room leaf=%d width=%d" % (leaf, w))
-        g = P.Scene.from_scene(s, leaf_size=leaf, width=w)
+        step("box room leaf=%d width=%d builder=%d" % (leaf, w, builder))
+        g = P.Scene.from_scene(s, leaf_size=leaf, width=w, builder=builder)
         info = g.info
-        assert info["width"] == w
+        assert info["width"] == w and info["builder"] == builder
         if w == 2:
             assert info["stack_entries"] == info["depth"] and info["n_nodes"] == s.n - 1
         else:
@@ -417,18 +418,18 @@ def test_office_full_size_properties(P, orc, office):
 
 
 def test_office_node_width_bitwise(P, office):
-    """Bench configuration (2^20 rays, K=5, 64 RX, all path types): binary
-    and 8-wide hierarchies give every output of the default 4-wide one bit
-    for bit."""
+    """Bench configuration (2^20 rays, K=5, 64 RX, all path types): radix
+    trees of width 2, 4, 8 and a binary clustering tree give every output of
+    the default (4-wide clustering) tree bit for bit."""
     s, sg, rx = office
     assert sg.info["width"] == 4
     N = 1 << 20
     step("office full solve, 4-wide tree")
     ref = gpu_solve(P, sg, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | SPEC | DIFF)
     want = [x.cpu().numpy() for x in (ref.seq, ref.gain, ref.h_te, ref.h_tm, ref.parts)]
-    for w in (2, 8):
-        step("office full solve, width %d" % w)
-        g = P.Scene.from_scene(s, leaf_size=4, width=w)
+    for w, b in ((2, 1), (4, 1), (8, 1), (2, 2)):
+        step("office full solve, width %d, builder %d" % (w, b))
+        g = P.Scene.from_scene(s, leaf_size=4, width=w, builder=b)
         r = gpu_solve(P, g, scenes.OFFICE_MATERIALS, scenes.OFFICE_TX, rx, 28e9, N, 5, LOS | SPEC | DIFF)
         for a, b in zip((r.seq, r.gain, r.h_te, r.h_tm, r.parts), want):
             assert np.array_equal(a.cpu().numpy(), b)
