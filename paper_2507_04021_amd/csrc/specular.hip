@@ -256,44 +256,46 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
     }
 }
 
-// Persistent blocks of 256 lanes take one key chunk at a time. For each
-// slice of up to 64 receivers, the chunk's (key, receiver) pairs are dealt to
-// the four wavefronts in tiles of 64. A wavefront first solves the image
-// method for its tile (cheap, no traversal) and appends the pairs that have a
-// solution to a queue in LDS, in pair order; whenever 64 are queued, all 64
-// lanes validate one each. Most pairs fail the image test, so this keeps the
-// traversals -- the expensive part -- on full wavefronts.
+// Persistent single-wavefront blocks. A work unit is (key chunk, slice of up
+// to kRefineRxSlice receivers); units are handed out by an atomic counter,
+// slice-minor so that consecutive units reuse a chunk's key planes. The
+// wavefront deals the unit's (key, receiver) pairs to its lanes in tiles of
+// 64, solves the image method for each pair (cheap, no traversal) and
+// appends the pairs that have a solution to a queue in LDS, in pair order;
+// whenever 64 are queued, all 64 lanes validate one each. Most pairs fail
+// the image test, so this keeps the traversals -- the expensive part -- on
+// full wavefronts, and the small units balance the uneven candidate counts
+// of the chunks.
 //
 // Sums: every batch's results go to LDS, and lane r adds those of receiver
-// r in queue order, i.e. in increasing key order; the four wavefronts'
-// sums are added in order into the chunk's partial sum. The result does not
+// r in queue order, i.e. in increasing key order; lane r then writes the
+// unit's partial sum of receiver r0 + r for chunk c. The result does not
 // depend on timing.
-constexpr int kRefineRxSlice = 64;
+constexpr int kRefineRxSlice = 16;
 
 template <int KM, int W>
-__global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
-    // traversal stacks, per-wave receiver sums and the chunk index share LDS
-    __shared__ union {
-        int stack[4][kStackLds * kWave];
-        double red[4][kRefineRxSlice][5];
-        uint32_t chunk;
-    } sm;
-    __shared__ uint32_t queue[4][2 * kWave];  // pair indices within the slice
-    __shared__ float4 res[4][kWave];          // a batch's TE and TM amplitudes
-    __shared__ int res_rx[4][kWave];          // its receiver in the slice, -1 if not a path
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t glane = blockIdx.x * 256 + tid;
-    Stack stk{sm.stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
+__global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
+    __shared__ int lds_stack[kStackLds * kWave];
+    __shared__ uint32_t queue[2 * kWave];  // pair indices within the unit
+    __shared__ float4 res[kWave];          // a batch's TE and TM amplitudes
+    __shared__ int res_rx[kWave];          // its receiver in the slice, -1 if not a path
+    const int lane = threadIdx.x;
+    const uint32_t glane = blockIdx.x * kWave + lane;
+    Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
     const uint32_t n_rx = A.D.n_rx, n_items = A.D.n_items;
     const uint32_t n_chunks = A.chunk_off[n_items];
+    const uint32_t n_slices = (n_rx + kRefineRxSlice - 1) / kRefineRxSlice;
+    const uint32_t n_units = n_chunks * n_slices;
     const bool rec = A.flags & 8;
     uint32_t n_cand = 0, n_valid = 0;
     for (;;) {
-        if (tid == 0) sm.chunk = atomicAdd(&A.work[1], 1u);
-        __syncthreads();
-        const uint32_t c = sm.chunk;
-        __syncthreads();
-        if (c >= n_chunks) break;
+        uint32_t u = 0;
+        if (lane == 0) u = atomicAdd(&A.work[1], 1u);
+        u = __builtin_amdgcn_readfirstlane(u);
+        if (u >= n_units) break;
+        const uint32_t c = u / n_slices;
+        const uint32_t r0 = (u % n_slices) * kRefineRxSlice;
+        const uint32_t nr = min((uint32_t)kRefineRxSlice, n_rx - r0);
         // item of this chunk
         int lo = 0, hi = (int)n_items - 1;
         while (lo < hi) {
@@ -306,101 +308,91 @@ __global__ __launch_bounds__(256) void k_refine(LaunchArgs A) {
         const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
         const uint32_t q0 = A.key_off[it] + (c - A.chunk_off[it]) * kKeyChunk;
         const uint32_t q1 = min(q0 + kKeyChunk, A.key_off[it + 1]);
-        for (uint32_t r0 = 0; r0 < n_rx; r0 += kRefineRxSlice) {
-            const uint32_t nr = min((uint32_t)kRefineRxSlice, n_rx - r0);
-            const uint32_t ne = (q1 - q0) * nr;  // pairs of this slice, e = key * nr + receiver
-            double acc[5] = {0, 0, 0, 0, 0};     // lane l: receiver r0 + l
-            uint32_t qn = 0;                     // queued candidates (wave-uniform)
-            auto run_batch = [&](uint32_t nb) {
-                PairOut po;
-                po.valid = false;
-                int rr = -1;
-                if ((uint32_t)lane < nb) {
-                    const uint32_t e = queue[wave][lane];
-                    const uint32_t q = q0 + e / nr;
-                    rr = (int)(e % nr);
+        const uint32_t ne = (q1 - q0) * nr;  // pairs of this unit, e = key * nr + receiver
+        double acc[5] = {0, 0, 0, 0, 0};     // lane l < nr: receiver r0 + l
+        uint32_t qn = 0;                     // queued candidates (wave-uniform)
+        auto run_batch = [&](uint32_t nb) {
+            PairOut po;
+            po.valid = false;
+            int rr = -1;
+            if ((uint32_t)lane < nb) {
+                const uint32_t e = queue[lane];
+                const uint32_t q = q0 + e / nr;
+                rr = (int)(e % nr);
+                KeyPlanes<KM> kp;
+                load_planes<KM>(A, q, kp);
+                validate_pair<KM, W>(A, q, r0 + rr, I, kp, stk, po);
+                if (rec && q < A.D.rec_keys) {
+                    const size_t p = (size_t)q * n_rx + r0 + rr;
+                    A.sb.valid[p] = po.valid;
+                    A.sb.len[p] = po.valid ? po.len : 0.f;
+                    A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                n_valid += po.valid;
+            }
+            res[lane] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
+            res_rx[lane] = po.valid ? rr : -1;
+            wave_sync();
+            for (uint32_t j = 0; j < nb; ++j)
+                if (res_rx[j] == lane) {
+                    const float4 v = res[j];
+                    const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
+                    acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+                    acc[1] += tr;
+                    acc[2] += ti;
+                    acc[3] += mr;
+                    acc[4] += mi;
+                }
+            wave_sync();
+        };
+        // one code path for the image test of a tile and for a batch, so
+        // that the validation is inlined once
+        for (uint32_t t = 0;;) {
+            const bool more = t * kWave < ne;
+            if (more) {
+                const uint32_t e = t * kWave + lane;
+                bool cand = false;
+                if (e < ne) {
+                    const uint32_t q = q0 + e / nr, r = r0 + e % nr;
                     KeyPlanes<KM> kp;
                     load_planes<KM>(A, q, kp);
-                    validate_pair<KM, W>(A, q, r0 + rr, I, kp, stk, po);
-                    if (rec && q < A.D.rec_keys) {
-                        const size_t p = (size_t)q * n_rx + r0 + rr;
-                        A.sb.valid[p] = po.valid;
-                        A.sb.len[p] = po.valid ? po.len : 0.f;
-                        A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                    n_valid += po.valid;
-                }
-                res[wave][lane] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
-                res_rx[wave][lane] = po.valid ? rr : -1;
-                wave_sync();
-                for (uint32_t j = 0; j < nb; ++j)
-                    if (res_rx[wave][j] == lane) {
-                        const float4 v = res[wave][j];
-                        const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
-                        acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
-                        acc[1] += tr;
-                        acc[2] += ti;
-                        acc[3] += mr;
-                        acc[4] += mi;
-                    }
-                wave_sync();
-            };
-            // one code path for the image test of a tile and for a batch, so
-            // that the validation is inlined once
-            for (uint32_t t = wave;;) {
-                const bool more = t * kWave < ne;
-                if (more) {
-                    const uint32_t e = t * kWave + lane;
-                    bool cand = false;
-                    if (e < ne) {
-                        const uint32_t q = q0 + e / nr, r = r0 + e % nr;
-                        KeyPlanes<KM> kp;
-                        load_planes<KM>(A, q, kp);
-                        f3 x[KM + 1];
-                        cand = refine_planes<KM>(kp.k, tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
-                        if (rec) {
-                            if (q >= A.D.rec_keys) {
-                                atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
-                            } else if (!cand) {
-                                const size_t p = (size_t)q * n_rx + r;
-                                A.sb.valid[p] = 0;
-                                A.sb.len[p] = 0.f;
-                                A.sb.amp[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-                            }
+                    f3 x[KM + 1];
+                    cand = refine_planes<KM>(kp.k, tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
+                    if (rec) {
+                        if (q >= A.D.rec_keys) {
+                            atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
+                        } else if (!cand) {
+                            const size_t p = (size_t)q * n_rx + r;
+                            A.sb.valid[p] = 0;
+                            A.sb.len[p] = 0.f;
+                            A.sb.amp[p] = make_float4(0.f, 0.f, 0.f, 0.f);
                         }
                     }
-                    n_cand += cand;
-                    const uint64_t m = __ballot(cand);
-                    const uint32_t pos = qn + (uint32_t)__popcll(m & ((1ull << lane) - 1));
-                    if (cand) queue[wave][pos] = e;
-                    qn += (uint32_t)__popcll(m);
-                    wave_sync();
-                    t += 4;
                 }
-                if (qn >= (uint32_t)kWave || (!more && qn > 0)) {
-                    const uint32_t nb = min(qn, (uint32_t)kWave);
-                    run_batch(nb);
-                    const uint32_t left = qn - nb;
-                    const uint32_t v = (uint32_t)lane < left ? queue[wave][nb + lane] : 0u;
-                    wave_sync();
-                    if ((uint32_t)lane < left) queue[wave][lane] = v;
-                    wave_sync();
-                    qn = left;
-                }
-                if (!more && qn == 0) break;
+                n_cand += cand;
+                const uint64_t m = __ballot(cand);
+                const uint32_t pos = qn + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+                if (cand) queue[pos] = e;
+                qn += (uint32_t)__popcll(m);
+                wave_sync();
+                ++t;
             }
-            __syncthreads();  // every wave is done with its stack
-            for (int a = 0; a < 5; ++a) sm.red[wave][lane][a] = acc[a];
-            __syncthreads();
-            if ((uint32_t)tid < nr) {
-                double sum[5] = {0, 0, 0, 0, 0};
-                for (int w = 0; w < 4; ++w)
-                    for (int a = 0; a < 5; ++a) sum[a] += sm.red[w][tid][a];
-                double *o = A.spec_part + ((size_t)c * n_rx + r0 + tid) * 5;
-                for (int a = 0; a < 5; ++a) o[a] = sum[a];
+            if (qn >= (uint32_t)kWave || (!more && qn > 0)) {
+                const uint32_t nb = min(qn, (uint32_t)kWave);
+                run_batch(nb);
+                const uint32_t left = qn - nb;
+                const uint32_t v = (uint32_t)lane < left ? queue[nb + lane] : 0u;
+                wave_sync();
+                if ((uint32_t)lane < left) queue[lane] = v;
+                wave_sync();
+                qn = left;
             }
-            __syncthreads();
+            if (!more && qn == 0) break;
+        }
+        if ((uint32_t)lane < nr) {
+            double *o = A.spec_part + ((size_t)c * n_rx + r0 + lane) * 5;
+            for (int a = 0; a < 5; ++a) o[a] = acc[a];
         }
     }
     flush_visits(stk, A.counters, 11);
@@ -425,7 +417,7 @@ void launch_keys(const LaunchArgs &A, hipStream_t s) {
 
 template <int KM, int W>
 uint32_t refine_cap() {
-    static const uint32_t cap = resident_blocks((const void *)k_refine<KM, W>, 256);
+    static const uint32_t cap = resident_blocks((const void *)k_refine<KM, W>, kWave);
     return cap;
 }
 
@@ -445,20 +437,21 @@ uint32_t refine_cap_k(uint32_t K) {
 
 uint32_t refine_grid(const SolveDims &D) {
     const uint32_t cap = D.width == 8 ? refine_cap_k<8>(D.K) : D.width == 4 ? refine_cap_k<4>(D.K) : refine_cap_k<2>(D.K);
-    return std::max<uint32_t>(1, std::min(cap, D.max_key_chunks));
+    const uint32_t units = D.max_key_chunks * ((D.n_rx + kRefineRxSlice - 1) / kRefineRxSlice);
+    return std::max<uint32_t>(1, std::min(cap, units));
 }
 
 template <int W>
 void launch_refine_w(const LaunchArgs &A, dim3 grid, hipStream_t s) {
     switch (A.D.K) {
-        case 1: hipLaunchKernelGGL((k_refine<1, W>), grid, dim3(256), 0, s, A); break;
-        case 2: hipLaunchKernelGGL((k_refine<2, W>), grid, dim3(256), 0, s, A); break;
-        case 3: hipLaunchKernelGGL((k_refine<3, W>), grid, dim3(256), 0, s, A); break;
-        case 4: hipLaunchKernelGGL((k_refine<4, W>), grid, dim3(256), 0, s, A); break;
-        case 5: hipLaunchKernelGGL((k_refine<5, W>), grid, dim3(256), 0, s, A); break;
-        case 6: hipLaunchKernelGGL((k_refine<6, W>), grid, dim3(256), 0, s, A); break;
-        case 7: hipLaunchKernelGGL((k_refine<7, W>), grid, dim3(256), 0, s, A); break;
-        default: hipLaunchKernelGGL((k_refine<8, W>), grid, dim3(256), 0, s, A); break;
+        case 1: hipLaunchKernelGGL((k_refine<1, W>), grid, dim3(kWave), 0, s, A); break;
+        case 2: hipLaunchKernelGGL((k_refine<2, W>), grid, dim3(kWave), 0, s, A); break;
+        case 3: hipLaunchKernelGGL((k_refine<3, W>), grid, dim3(kWave), 0, s, A); break;
+        case 4: hipLaunchKernelGGL((k_refine<4, W>), grid, dim3(kWave), 0, s, A); break;
+        case 5: hipLaunchKernelGGL((k_refine<5, W>), grid, dim3(kWave), 0, s, A); break;
+        case 6: hipLaunchKernelGGL((k_refine<6, W>), grid, dim3(kWave), 0, s, A); break;
+        case 7: hipLaunchKernelGGL((k_refine<7, W>), grid, dim3(kWave), 0, s, A); break;
+        default: hipLaunchKernelGGL((k_refine<8, W>), grid, dim3(kWave), 0, s, A); break;
     }
 }
 
