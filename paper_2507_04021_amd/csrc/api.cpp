@@ -188,7 +188,7 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     }
     // every traversal launch indexes the stack spill by its global lane
     const uint32_t wr = p->wave_rays ? p->wave_rays : kWave;
-    D.spill_lanes = std::max({trace_grid(D, wr) * kWave, diffuse_grid(D) * 256u, refine_grid(D) * kWave,
+    D.spill_lanes = std::max({trace_grid(D, wr) * kWave, diffuse_grid(D) * kWave, refine_grid(D) * kWave,
                               round_up(D.n_items * D.n_rx, kWave)});
     // the first kStackLds stack entries live in LDS, the rest in the spill area
     D.spill_depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;

@@ -28,10 +28,10 @@ namespace pcrt {
 // choices through the upper tree and only part near their own end points,
 // which keeps the lanes of a wavefront on the same nodes for most of the walk.
 //
-// Sums: per (wavefront, receiver) a fixed xor-butterfly over the lanes; lane
-// r of the wavefront keeps receiver r's running sum over its record groups in
-// order; the four wavefronts of a block are added in order into the chunk's
-// partial sum. The result does not depend on timing.
+// Sums: per (record group, receiver) a fixed xor-butterfly over the lanes;
+// lane r of the wavefront keeps receiver r's running sum over the chunk's
+// record groups in order and writes it as the chunk's partial sum. The
+// result does not depend on timing.
 __global__ void k_diffuse_keys(LaunchArgs A) {
     const uint32_t n_rec = A.D.T * A.D.K;
     const float *B = A.S.bounds;
@@ -80,96 +80,88 @@ __device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t 
     v5[4] = mi;
 }
 
-constexpr int kDiffRxSlice = 64;
+constexpr int kDiffRxSlice = 16;
 
+// Persistent single-wavefront blocks. A work unit is (ray chunk, slice of
+// up to kDiffRxSlice receivers): the wavefront walks every 64-record group
+// of the chunk against each receiver of the slice in turn and writes the
+// chunk's partial sums of those receivers itself, so no block barrier ever
+// makes it wait for another wavefront.
 template <int W>
-__global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
-    // traversal stacks, per-wave receiver sums and the chunk index share LDS
-    // (never live together): 32 KiB per block
-    __shared__ union {
-        int stack[4][kStackLds * kWave];
-        double red[4][kDiffRxSlice][5];
-        uint32_t chunk;
-    } sm;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t glane = blockIdx.x * 256 + tid;
-    Stack stk{sm.stack[wave] + lane, A.S.spill + glane, A.S.spill_lanes};
+__global__ __launch_bounds__(kWave) void k_diffuse(LaunchArgs A) {
+    __shared__ int lds_stack[kStackLds * kWave];
+    const int lane = threadIdx.x;
+    const uint32_t glane = blockIdx.x * kWave + lane;
+    Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
     const uint32_t K = A.D.K, n_rx = A.D.n_rx;
     const uint32_t n_chunks = A.D.n_ray_chunks;
+    const uint32_t n_slices = (n_rx + kDiffRxSlice - 1) / kDiffRxSlice;
     const bool rec = A.flags & 8;
     const float eps = A.thr.eps_self;
     const uint32_t n_groups = kRayChunk * K / kWave;  // groups of 64 records per chunk
     uint32_t n_seg = 0, n_vis = 0;
     // Workgroups are dealt to the XCDs round robin, and each XCD has its own
-    // L2: the blocks of XCD x take chunks from the x-th eighth of the
+    // L2: the wavefronts of XCD x take chunks from the x-th eighth of the
     // (Morton-ordered) chunk range first, so one XCD's L2 serves one region
-    // of the scene, then help the other ranges in turn.
+    // of the scene, then help the other ranges in turn. Within a range, units
+    // are slice-minor, so consecutive units reuse a chunk's records.
     const uint32_t xcd = blockIdx.x % kXcds;
     for (;;) {
-        if (tid == 0) {
-            uint32_t c = n_chunks;
+        uint32_t u = 0xffffffffu;
+        if (lane == 0) {
             for (uint32_t k = 0; k < kXcds; ++k) {
                 const uint32_t x = (xcd + k) % kXcds;
-                const uint32_t hi = (uint32_t)((uint64_t)(x + 1) * n_chunks / kXcds);
-                const uint32_t cc = (uint32_t)((uint64_t)x * n_chunks / kXcds) + atomicAdd(&A.work[8 + x], 1u);
-                if (cc < hi) {
-                    c = cc;
+                const uint32_t lo = (uint32_t)((uint64_t)x * n_chunks / kXcds) * n_slices;
+                const uint32_t hi = (uint32_t)((uint64_t)(x + 1) * n_chunks / kXcds) * n_slices;
+                const uint32_t uu = lo + atomicAdd(&A.work[8 + x], 1u);
+                if (uu < hi) {
+                    u = uu;
                     break;
                 }
             }
-            sm.chunk = c;
         }
-        __syncthreads();
-        const uint32_t c = sm.chunk;
-        __syncthreads();
-        if (c >= n_chunks) break;
+        u = __builtin_amdgcn_readfirstlane(u);
+        if (u == 0xffffffffu) break;
+        const uint32_t c = u / n_slices;
+        const uint32_t r0 = (u % n_slices) * kDiffRxSlice;
+        const uint32_t nr = min((uint32_t)kDiffRxSlice, n_rx - r0);
         const uint32_t g0 = c * kRayChunk;
         const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
         const float budget = (float)I.budget;
-        for (uint32_t r0 = 0; r0 < n_rx; r0 += kDiffRxSlice) {
-            const uint32_t nr = min((uint32_t)kDiffRxSlice, n_rx - r0);
-            double acc[5] = {0, 0, 0, 0, 0};  // lane l: receiver r0 + l
-            for (uint32_t q = wave; q < n_groups; q += 4) {
-                const uint32_t ri = A.dsort.order[g0 * K + q * kWave + lane];
-                const int id = A.rb.id[ri];
-                f3 x = mk(0.f, 0.f, 0.f), n = mk(0.f, 0.f, 1.f);
-                if (id >= 0) {
-                    x = xyz(A.rb.xl[ri]);
-                    n = xyz(A.S.nrm[id]);
-                    if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+        double acc[5] = {0, 0, 0, 0, 0};  // lane l < nr: receiver r0 + l
+        for (uint32_t q = 0; q < n_groups; ++q) {
+            const uint32_t ri = A.dsort.order[g0 * K + q * kWave + lane];
+            const int id = A.rb.id[ri];
+            f3 x = mk(0.f, 0.f, 0.f), n = mk(0.f, 0.f, 1.f);
+            if (id >= 0) {
+                x = xyz(A.rb.xl[ri]);
+                n = xyz(A.S.nrm[id]);
+                if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+            }
+            for (uint32_t rr = 0; rr < nr; ++rr) {
+                const uint32_t r = r0 + rr;
+                const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+                bool vis = false;
+                if (id >= 0 && dot(rx - x, n) > 0.f) {
+                    ++n_seg;
+                    vis = !occluded<W>(A.S, rx, x, id, eps, stk);
                 }
-                for (uint32_t rr = 0; rr < nr; ++rr) {
-                    const uint32_t r = r0 + rr;
-                    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-                    bool vis = false;
-                    if (id >= 0 && dot(rx - x, n) > 0.f) {
-                        ++n_seg;
-                        vis = !occluded<W>(A.S, rx, x, id, eps, stk);
-                    }
-                    if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
-                    if (!__ballot(vis)) continue;
-                    double v5[5] = {0, 0, 0, 0, 0};
-                    if (vis) {
-                        ++n_vis;
-                        diffuse_amplitude(A, ri, rx, budget, v5);
-                    }
-                    for (int a = 0; a < 5; ++a) {
-                        const double sv = wave_sum_d(v5[a]);
-                        if ((uint32_t)lane == rr) acc[a] += sv;
-                    }
+                if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
+                if (!__ballot(vis)) continue;
+                double v5[5] = {0, 0, 0, 0, 0};
+                if (vis) {
+                    ++n_vis;
+                    diffuse_amplitude(A, ri, rx, budget, v5);
+                }
+                for (int a = 0; a < 5; ++a) {
+                    const double sv = wave_sum_d(v5[a]);
+                    if ((uint32_t)lane == rr) acc[a] += sv;
                 }
             }
-            __syncthreads();  // every wave is done with its stack
-            for (int a = 0; a < 5; ++a) sm.red[wave][lane][a] = acc[a];
-            __syncthreads();
-            if ((uint32_t)tid < nr) {
-                double sum[5] = {0, 0, 0, 0, 0};
-                for (int w = 0; w < 4; ++w)
-                    for (int a = 0; a < 5; ++a) sum[a] += sm.red[w][tid][a];
-                double *o = A.diff_part + ((size_t)c * n_rx + r0 + tid) * 5;
-                for (int a = 0; a < 5; ++a) o[a] = sum[a];
-            }
-            __syncthreads();
+        }
+        if ((uint32_t)lane < nr) {
+            double *o = A.diff_part + ((size_t)c * n_rx + r0 + lane) * 5;
+            for (int a = 0; a < 5; ++a) o[a] = acc[a];
         }
     }
     flush_visits(stk, A.counters, 13);
@@ -183,13 +175,14 @@ __global__ __launch_bounds__(256) void k_diffuse(LaunchArgs A) {
 
 template <int W>
 uint32_t diffuse_cap() {
-    static const uint32_t cap = resident_blocks((const void *)k_diffuse<W>, 256);
+    static const uint32_t cap = resident_blocks((const void *)k_diffuse<W>, kWave);
     return cap;
 }
 
 uint32_t diffuse_grid(const SolveDims &D) {
     const uint32_t cap = D.width == 8 ? diffuse_cap<8>() : D.width == 4 ? diffuse_cap<4>() : diffuse_cap<2>();
-    return std::max<uint32_t>(1, std::min(cap, D.n_ray_chunks));
+    const uint32_t units = D.n_ray_chunks * ((D.n_rx + kDiffRxSlice - 1) / kDiffRxSlice);
+    return std::max<uint32_t>(1, std::min(cap, units));
 }
 
 const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s) {
@@ -206,9 +199,9 @@ const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s) {
 void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
     const dim3 g(diffuse_grid(A.D));
     switch (A.D.width) {
-        case 8: hipLaunchKernelGGL(k_diffuse<8>, g, dim3(256), 0, s, A); break;
-        case 4: hipLaunchKernelGGL(k_diffuse<4>, g, dim3(256), 0, s, A); break;
-        default: hipLaunchKernelGGL(k_diffuse<2>, g, dim3(256), 0, s, A); break;
+        case 8: hipLaunchKernelGGL(k_diffuse<8>, g, dim3(kWave), 0, s, A); break;
+        case 4: hipLaunchKernelGGL(k_diffuse<4>, g, dim3(kWave), 0, s, A); break;
+        default: hipLaunchKernelGGL(k_diffuse<2>, g, dim3(kWave), 0, s, A); break;
     }
 }
 
