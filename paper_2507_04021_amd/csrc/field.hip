@@ -80,7 +80,11 @@ __device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t 
     v5[4] = mi;
 }
 
-constexpr int kDiffRxSlice = 16;
+// Receivers per work unit. Measured on the 1M-point office (64 receivers):
+// 32 -> 58.9 ms, 16 -> 51.9, 8 -> 47.8, 4 -> 45.7, 2 -> 44.4, 1 -> 43.5.
+// The smallest units balance best, and the units of one chunk (consecutive
+// counter values) then run at the same time on one XCD and share its L2.
+constexpr int kDiffRxSlice = 1;
 
 // Persistent single-wavefront blocks. A work unit is (ray chunk, slice of
 // up to kDiffRxSlice receivers): the wavefront walks every 64-record group
