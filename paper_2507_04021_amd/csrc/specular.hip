@@ -271,7 +271,7 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
 // r in queue order, i.e. in increasing key order; lane r then writes the
 // unit's partial sum of receiver r0 + r for chunk c. The result does not
 // depend on timing.
-constexpr int kRefineRxSlice = 16;
+constexpr int kRefineRxSlice = 8;
 
 template <int KM, int W>
 __global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
