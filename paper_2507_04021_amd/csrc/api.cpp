@@ -158,7 +158,7 @@ std::vector<Item> batch_items(const pcrt_solve_params *p, const pcrt_batch_item 
 }
 
 Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Item> &items) {
-    Plan P;
+    Plan P{};  // every field zero until set
     const uint32_t K = p->max_interactions;
     SolveDims &D = P.D;
     D.K = K;
@@ -188,10 +188,11 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     }
     // every traversal launch indexes the stack spill by its global lane
     const uint32_t wr = p->wave_rays ? p->wave_rays : kWave;
+    // the first kStackLds stack entries live in LDS, the rest in the spill area
+    // (set first: the diffuse grid depends on whether there is one)
+    D.spill_depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;
     D.spill_lanes = std::max({trace_grid(D, wr) * kWave, diffuse_grid(D) * kWave, refine_grid(D) * kWave,
                               round_up(D.n_items * D.n_rx, kWave)});
-    // the first kStackLds stack entries live in LDS, the rest in the spill area
-    D.spill_depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
     P.fc = make_fc(p->freq_hz);
@@ -744,7 +745,7 @@ static pcrt_status tape_args(const pcrt_scene *scene, const pcrt_solve_params *p
 
 pcrt_status pcrt_tape_get(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, pcrt_tape *out) {
     LaunchArgs A;
-    Plan P;
+    Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
     if (!out) return fail(PCRT_EINVAL, "out is NULL");
@@ -761,7 +762,7 @@ pcrt_status pcrt_tape_get(const pcrt_scene *scene, const pcrt_solve_params *p, v
 pcrt_status pcrt_tape_fresnel(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                               const pcrt_material *mats, uint32_t n_labels, void *stream) {
     LaunchArgs A;
-    Plan P;
+    Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
     if (!mats || n_labels == 0) return fail(PCRT_EINVAL, "materials are required");
@@ -773,7 +774,7 @@ pcrt_status pcrt_tape_fresnel(const pcrt_scene *scene, const pcrt_solve_params *
 pcrt_status pcrt_tape_forward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                               const pcrt_outputs *out, void *stream) {
     LaunchArgs A;
-    Plan P;
+    Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
     if (!out || !out->gain) return fail(PCRT_EINVAL, "out->gain is required");
@@ -785,7 +786,7 @@ pcrt_status pcrt_tape_forward(const pcrt_scene *scene, const pcrt_solve_params *
 pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                                const double *dL_dgain, void *stream) {
     LaunchArgs A;
-    Plan P;
+    Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
     if (!dL_dgain) return fail(PCRT_EINVAL, "dL_dgain is required");
@@ -797,7 +798,7 @@ pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params 
 pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                                const pcrt_material *mats, uint32_t n_labels, double *dL_dmat, void *stream) {
     LaunchArgs A;
-    Plan P;
+    Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
     if (!mats || !dL_dmat || n_labels == 0) return fail(PCRT_EINVAL, "mats and dL_dmat are required");
