@@ -105,8 +105,11 @@ pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *op
  * outlive the scene. This call synchronises the stream once at the end to
  * read back validation results and statistics. Errors: EINVAL for NULL
  * pointers, n_points == 0, disk_radius <= 0, non-finite positions or zero
- * normals; ENOMEM for a small ws; EUNSUPPORTED if the hierarchy is deeper
- * than the traversal stack (64). stream: hipStream_t or NULL. */
+ * normals; ENOMEM for a small ws; EUNSUPPORTED for more than 2^26 points
+ * (the traversal kernels address the node and disk arrays with 32-bit byte
+ * offsets), an unsupported leaf size, width or builder, or a hierarchy whose
+ * traversal stack bound exceeds the supported maximum. stream: hipStream_t
+ * or NULL. */
 pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts, void *ws, size_t ws_bytes,
                               void *stream, pcrt_scene **out);
 pcrt_status pcrt_scene_get_info(const pcrt_scene *scene, pcrt_scene_info *info);

@@ -367,7 +367,7 @@ const char *pcrt_version(void) { return "pcrt 0.1 (gfx950)"; }
 pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *opts, size_t *bytes) {
     if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
     if (n_points == 0) return fail(PCRT_EINVAL, "n_points must be > 0");
-    if (n_points > (1u << 27)) return fail(PCRT_EUNSUPPORTED, "at most 2^27 points");
+    if (n_points > (1u << 26)) return fail(PCRT_EUNSUPPORTED, "at most 2^26 points");
     const uint32_t width = opts && opts->width ? opts->width : kDefaultWidth;
     if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
     if (opts && opts->leaf_size > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
@@ -383,7 +383,7 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     if (!pts->pos || !pts->normal || !pts->material || !pts->surface)
         return fail(PCRT_EINVAL, "point arrays must be non-NULL");
     if (pts->n_points == 0) return fail(PCRT_EINVAL, "n_points must be > 0");
-    if (pts->n_points > (1u << 27)) return fail(PCRT_EUNSUPPORTED, "at most 2^27 points");
+    if (pts->n_points > (1u << 26)) return fail(PCRT_EUNSUPPORTED, "at most 2^26 points");
     if (!(pts->disk_radius > 0.f) || !std::isfinite(pts->disk_radius))
         return fail(PCRT_EINVAL, "disk_radius must be > 0");
     uint32_t leaf = opts && opts->leaf_size ? opts->leaf_size : 4;

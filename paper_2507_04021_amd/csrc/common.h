@@ -49,6 +49,14 @@ __device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
 // v = -1 - ref, first disk = v >> 3, count = (v & 7) + 1.
 __host__ __device__ __forceinline__ int leaf_ref(int first, int count) { return -1 - ((first << 3) | (count - 1)); }
 
+// float4 at a 32-bit byte offset from a wavefront-uniform array base. The
+// address is then one scalar base plus one per-lane 32-bit offset, instead of
+// a 64-bit add per lane; scenes are capped (2^26 points) so that the node and
+// disk arrays stay below 4 GiB.
+__device__ __forceinline__ float4 ld4(const float4 *base, uint32_t off) {
+    return *(const float4 *)((const char *)base + off);
+}
+
 struct DevScene {
     const float4 *node;  // binary nodes (4 float4: child boxes + refs) or wide nodes (2W float4)
     const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, 0)
@@ -98,7 +106,12 @@ struct Stack {
         else gl[(size_t)(s - kStackLds) * lanes] = v;
     }
     __device__ __forceinline__ int get(int s) const {
-        return s < kStackLds ? lds[s * kWave] : gl[(size_t)(s - kStackLds) * lanes];
+        // The LDS read is always in bounds; the global read only for spilled
+        // entries (keeps the common pop an LDS access, not a generic one).
+        int v = lds[min(s, kStackLds - 1) * kWave];
+        __asm__ volatile("" : "+v"(v));  // opaque use: the LDS read stays a read of its own
+        if (s >= kStackLds) v = gl[(size_t)(s - kStackLds) * lanes];
+        return v;
     }
 };
 
@@ -129,15 +142,16 @@ __device__ __forceinline__ bool box_hit(float lx, float ly, float lz, float hx, 
 __device__ __forceinline__ f3 times(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
 
 // Two-sided ray-disk test (Sec. II-C): plane hit t, squared distance of the
-// hit point from the centre.
+// hit point from the centre. Evaluated without early exits (a ray parallel
+// to the plane gives a non-finite t and d2 and fails on |d.n|), so the loads
+// of a disk are issued together and every caller rounds identically.
 __device__ __forceinline__ bool disk_hit(f3 o, f3 d, f3 p, f3 n, float r2, float &t, float &d2) {
-    float a = dot(d, n);
-    if (fabsf(a) < kParallelEps) return false;
+    const float a = dot(d, n);
     t = dot(p - o, n) / a;
-    f3 q = o + t * d;
-    f3 e = q - p;
+    const f3 q = o + t * d;
+    const f3 e = q - p;
     d2 = dot(e, e);
-    return d2 <= r2;
+    return (fabsf(a) >= kParallelEps) & (d2 <= r2);
 }
 
 // Nearest hit among disks != excl with t in (t_lo, inf), with the tie rule:
@@ -154,8 +168,8 @@ template <bool kSecond>
 __device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d, int excl, float t_lo, float eps_tie,
                                            float &tmin, Cand *c, bool &spill, float t_win, float &best_d2,
                                            int &best_id, float &best_t) {
-    const float4 dp = S.disk[2 * i];
-    const float4 dn = S.disk[2 * i + 1];
+    const float4 dp = ld4(S.disk, (uint32_t)i * 32u);
+    const float4 dn = ld4(S.disk, (uint32_t)i * 32u + 16u);
     const int id = __float_as_int(dp.w);
     if (id == excl) return;
     float t, d2;
@@ -200,17 +214,19 @@ __device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d,
 // slab values are the same FMAs as in box_hit, and rounding is monotonic,
 // so each near / far value is exactly the one min / max would pick.
 struct Octant {
-    int nx, ny, nz, fx, fy, fz;  // float4 row offsets (in units of W floats / 4) of near and far planes
+    uint32_t nx, ny, nz, fx, fy, fz;  // byte offsets of the near and far plane rows in a node
 };
 
+template <int W>
 __device__ __forceinline__ Octant octant(f3 inv) {
+    constexpr uint32_t row = 4 * W;  // bytes per row of W floats
     Octant q;
-    q.nx = inv.x >= 0.f ? 0 : 3;
-    q.ny = inv.y >= 0.f ? 1 : 4;
-    q.nz = inv.z >= 0.f ? 2 : 5;
-    q.fx = 3 - q.nx;
-    q.fy = 5 - q.ny;
-    q.fz = 7 - q.nz;
+    q.nx = inv.x >= 0.f ? 0 : 3 * row;
+    q.ny = inv.y >= 0.f ? row : 4 * row;
+    q.nz = inv.z >= 0.f ? 2 * row : 5 * row;
+    q.fx = 3 * row - q.nx;
+    q.fy = 5 * row - q.ny;
+    q.fz = 7 * row - q.nz;
     return q;
 }
 
@@ -219,11 +235,11 @@ __device__ __forceinline__ Octant octant(f3 inv) {
 template <int W>
 __device__ __forceinline__ void wide_hits_minmax(const float4 *node, int ref, f3 inv, f3 oi, float t_lo, float t_hi,
                                                  float (&tn)[W], int (&cr)[W]) {
-    const float4 *nd = node + 2 * W * (size_t)ref;
+    const uint32_t nb = (uint32_t)ref * (32u * W);
     float v[7 * W];
 #pragma unroll
     for (int k = 0; k < 7 * W / 4; ++k) {
-        const float4 q = nd[k];
+        const float4 q = ld4(node, nb + 16u * k);
         v[4 * k] = q.x;
         v[4 * k + 1] = q.y;
         v[4 * k + 2] = q.z;
@@ -243,12 +259,12 @@ template <int W>
 __device__ __forceinline__ void wide_hits(const float4 *node, int ref, const Octant &q, f3 inv, f3 oi, float t_lo,
                                           float t_hi, float (&tn)[W], int (&cr)[W]) {
     constexpr int R = W / 4;  // float4 per row of W floats
-    const float4 *nd = node + 2 * W * (size_t)ref;
+    const uint32_t nb = (uint32_t)ref * (32u * W);
     float nx[W], ny[W], nz[W], fx[W], fy[W], fz[W];
-    auto row = [&](int r, float (&out)[W]) {
+    auto row = [&](uint32_t r, float (&out)[W]) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const float4 v = nd[r * R + k];
+            const float4 v = ld4(node, nb + r + 16u * k);
             out[4 * k] = v.x;
             out[4 * k + 1] = v.y;
             out[4 * k + 2] = v.z;
@@ -263,7 +279,7 @@ __device__ __forceinline__ void wide_hits(const float4 *node, int ref, const Oct
     row(q.fz, fz);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const float4 v = nd[6 * R + k];
+        const float4 v = ld4(node, nb + 6u * 4 * W + 16u * k);
         cr[4 * k] = __float_as_int(v.x);
         cr[4 * k + 1] = __float_as_int(v.y);
         cr[4 * k + 2] = __float_as_int(v.z);
@@ -368,8 +384,9 @@ __device__ __forceinline__ void traverse_closest(const DevScene &S, f3 o, f3 d, 
             if constexpr (W > 2) {
                 if (wide_step<W>(S, ref, sp, inv, oi, t_lo, tc, stk)) continue;
             } else {
-                const float4 *nd = S.node + 4 * (size_t)ref;
-                const float4 a = nd[0], b = nd[1], e = nd[2], r = nd[3];
+                const uint32_t nb = (uint32_t)ref * 64u;
+                const float4 a = ld4(S.node, nb), b = ld4(S.node, nb + 16u), e = ld4(S.node, nb + 32u),
+                             r = ld4(S.node, nb + 48u);
                 float n0, n1;
                 const bool h0 = box_hit(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, t_lo, tc, n0);
                 const bool h1 = box_hit(b.z, b.w, e.x, e.y, e.z, e.w, inv, oi, t_lo, tc, n1);
@@ -439,7 +456,7 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     const float t_hi = L - eps_self;
     if (!(t_hi > eps_self)) return false;
     const f3 oi = times(a, inv);
-    const Octant oq = octant(inv);
+    const Octant oq = octant<W>(inv);
     int ref = S.root;
     int sp = 0;
     for (;;) {
@@ -448,8 +465,9 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
             if constexpr (W > 2) {
                 if (wide_step_any<W>(S, ref, sp, oq, inv, oi, eps_self, t_hi, stk)) continue;
             } else {
-                const float4 *nd = S.node + 4 * (size_t)ref;
-                const float4 na = nd[0], nb = nd[1], ne = nd[2], nr = nd[3];
+                const uint32_t o = (uint32_t)ref * 64u;
+                const float4 na = ld4(S.node, o), nb = ld4(S.node, o + 16u), ne = ld4(S.node, o + 32u),
+                             nr = ld4(S.node, o + 48u);
                 float n0, n1;
                 const bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, eps_self, t_hi, n0);
                 const bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, eps_self, t_hi, n1);
@@ -468,11 +486,11 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
             const int first = v >> 3, cnt = (v & 7) + 1;
             stk.test(cnt);
             for (int i = 0; i < cnt; ++i) {
-                const float4 dp = S.disk[2 * (first + i)];
-                const float4 dn = S.disk[2 * (first + i) + 1];
-                if (__float_as_int(dp.w) == excl) continue;
+                const float4 dp = ld4(S.disk, (uint32_t)(first + i) * 32u);
+                const float4 dn = ld4(S.disk, (uint32_t)(first + i) * 32u + 16u);
                 float t, d2;
-                if (disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2) && t > eps_self && t < t_hi) return true;
+                const bool h = disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2);
+                if (h & (__float_as_int(dp.w) != excl) & (t > eps_self) & (t < t_hi)) return true;
             }
         }
         if (sp == 0) break;

@@ -28,10 +28,10 @@ namespace pcrt {
 // choices through the upper tree and only part near their own end points,
 // which keeps the lanes of a wavefront on the same nodes for most of the walk.
 //
-// Sums: per (record group, receiver) a fixed xor-butterfly over the lanes;
-// lane r of the wavefront keeps receiver r's running sum over the chunk's
-// record groups in order and writes it as the chunk's partial sum. The
-// result does not depend on timing.
+// Sums: each lane adds its own records' contributions to a receiver over the
+// chunk's record groups in order; one fixed xor-butterfly over the lanes then
+// gives the chunk's partial sum for that receiver. The result does not
+// depend on timing or on the hierarchy.
 __global__ void k_diffuse_keys(LaunchArgs A) {
     const uint32_t n_rec = A.D.T * A.D.K;
     const float *B = A.S.bounds;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kWave) void k_diffuse(LaunchArgs A) {
         const uint32_t g0 = c * kRayChunk;
         const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
         const float budget = (float)I.budget;
-        double acc[5] = {0, 0, 0, 0, 0};  // lane l < nr: receiver r0 + l
+        double acc[kDiffRxSlice][5] = {};  // this lane's records, per receiver of the slice
         for (uint32_t q = 0; q < n_groups; ++q) {
             const uint32_t ri = A.dsort.order[g0 * K + q * kWave + lane];
             const int id = A.rb.id[ri];
@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kWave) void k_diffuse(LaunchArgs A) {
                 n = xyz(A.S.nrm[id]);
                 if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
             }
-            for (uint32_t rr = 0; rr < nr; ++rr) {
+#pragma unroll
+            for (uint32_t rr = 0; rr < (uint32_t)kDiffRxSlice; ++rr) {
+                if (rr >= nr) break;
                 const uint32_t r = r0 + rr;
                 const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
                 bool vis = false;
@@ -151,21 +153,23 @@ __global__ __launch_bounds__(kWave) void k_diffuse(LaunchArgs A) {
                     vis = !occluded<W>(A.S, rx, x, id, eps, stk);
                 }
                 if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
-                if (!__ballot(vis)) continue;
-                double v5[5] = {0, 0, 0, 0, 0};
                 if (vis) {
                     ++n_vis;
+                    double v5[5];
                     diffuse_amplitude(A, ri, rx, budget, v5);
-                }
-                for (int a = 0; a < 5; ++a) {
-                    const double sv = wave_sum_d(v5[a]);
-                    if ((uint32_t)lane == rr) acc[a] += sv;
+                    for (int a = 0; a < 5; ++a) acc[rr][a] += v5[a];
                 }
             }
         }
-        if ((uint32_t)lane < nr) {
-            double *o = A.diff_part + ((size_t)c * n_rx + r0 + lane) * 5;
-            for (int a = 0; a < 5; ++a) o[a] = acc[a];
+#pragma unroll
+        for (uint32_t rr = 0; rr < (uint32_t)kDiffRxSlice; ++rr) {
+            if (rr >= nr) break;
+            double sv[5];
+            for (int a = 0; a < 5; ++a) sv[a] = wave_sum_d(acc[rr][a]);
+            if (lane == 0) {
+                double *o = A.diff_part + ((size_t)c * n_rx + r0 + rr) * 5;
+                for (int a = 0; a < 5; ++a) o[a] = sv[a];
+            }
         }
     }
     flush_visits(stk, A.counters, 13);
