@@ -445,8 +445,47 @@ __device__ __forceinline__ int closest_hit(const DevScene &S, f3 o, f3 d, int ex
     return bid;
 }
 
+// Any-hit step at a node of either layout: true if a child was entered (ref
+// is then that child, the other entered children are on the stack), false
+// if the segment enters none.
+template <int W>
+__device__ __forceinline__ bool step_any(const DevScene &S, int &ref, int &sp, const Octant &oq, f3 inv, f3 oi,
+                                         float t_lo, float t_hi, Stack &stk) {
+    if constexpr (W > 2) {
+        return wide_step_any<W>(S, ref, sp, oq, inv, oi, t_lo, t_hi, stk);
+    } else {
+        const uint32_t o = (uint32_t)ref * 64u;
+        const float4 na = ld4(S.node, o), nb = ld4(S.node, o + 16u), ne = ld4(S.node, o + 32u),
+                     nr = ld4(S.node, o + 48u);
+        float n0, n1;
+        const bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, t_lo, t_hi, n0);
+        const bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, t_lo, t_hi, n1);
+        const int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
+        if (h0 && h1) {
+            const bool f0 = n0 <= n1;
+            stk.put(sp++, f0 ? r1 : r0);
+            ref = f0 ? r0 : r1;
+            return true;
+        }
+        if (h0) { ref = r0; return true; }
+        if (h1) { ref = r1; return true; }
+        return false;
+    }
+}
+
+// "Nothing left to walk": never a node (>= 0) or leaf (>= -2^29 - 8) reference.
+constexpr int kNoRef = -0x7fffffff - 1;
+
 // True iff a disk != excl is hit with eps_self < t < |b - a| - eps_self on the
 // segment from a towards b.
+//
+// Leaves are parked: a lane that reaches a leaf keeps it (one at a time) and
+// walks on through nodes; the wavefront tests the parked leaves together once
+// at least half of its live lanes hold one, or when no lane can take a node
+// step. Node steps and disk tests then each run with more lanes busy than
+// when every lane tests a leaf as soon as it reaches it. Parking only delays
+// disk tests: the walk order, and so the stack bound, are those of the plain
+// depth-first walk, and the answer is the same.
 template <int W>
 __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl, float eps_self, Stack &stk) {
     const f3 dv = b - a;
@@ -457,32 +496,24 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
     if (!(t_hi > eps_self)) return false;
     const f3 oi = times(a, inv);
     const Octant oq = octant<W>(inv);
-    int ref = S.root;
-    int sp = 0;
+    int ref = S.root, sp = 0, park = kNoRef;
     for (;;) {
-        if (ref >= 0) {
-            stk.visit();
-            if constexpr (W > 2) {
-                if (wide_step_any<W>(S, ref, sp, oq, inv, oi, eps_self, t_hi, stk)) continue;
-            } else {
-                const uint32_t o = (uint32_t)ref * 64u;
-                const float4 na = ld4(S.node, o), nb = ld4(S.node, o + 16u), ne = ld4(S.node, o + 32u),
-                             nr = ld4(S.node, o + 48u);
-                float n0, n1;
-                const bool h0 = box_hit(na.x, na.y, na.z, na.w, nb.x, nb.y, inv, oi, eps_self, t_hi, n0);
-                const bool h1 = box_hit(nb.z, nb.w, ne.x, ne.y, ne.z, ne.w, inv, oi, eps_self, t_hi, n1);
-                const int r0 = __float_as_int(nr.x), r1 = __float_as_int(nr.y);
-                if (h0 && h1) {
-                    const bool f0 = n0 <= n1;
-                    stk.put(sp++, f0 ? r1 : r0);
-                    ref = f0 ? r0 : r1;
-                    continue;
-                }
-                if (h0) { ref = r0; continue; }
-                if (h1) { ref = r1; continue; }
+        for (;;) {
+            if (ref < 0 && ref != kNoRef && park == kNoRef) {
+                park = ref;
+                ref = sp > 0 ? stk.get(--sp) : kNoRef;
             }
-        } else {
-            const int v = -1 - ref;
+            const uint32_t n_live = (uint32_t)__popcll(__ballot(1));
+            const uint32_t n_park = (uint32_t)__popcll(__ballot(park != kNoRef));
+            if (!__ballot(ref >= 0) || 2 * n_park >= n_live) break;
+            if (ref >= 0) {
+                stk.visit();
+                if (!step_any<W>(S, ref, sp, oq, inv, oi, eps_self, t_hi, stk))
+                    ref = sp > 0 ? stk.get(--sp) : kNoRef;
+            }
+        }
+        if (park != kNoRef) {
+            const int v = -1 - park;
             const int first = v >> 3, cnt = (v & 7) + 1;
             stk.test(cnt);
             for (int i = 0; i < cnt; ++i) {
@@ -492,11 +523,10 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
                 const bool h = disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2);
                 if (h & (__float_as_int(dp.w) != excl) & (t > eps_self) & (t < t_hi)) return true;
             }
+            park = kNoRef;
         }
-        if (sp == 0) break;
-        ref = stk.get(--sp);
+        if (ref == kNoRef) return false;
     }
-    return false;
 }
 
 // ------------------------------------------------------------- field
