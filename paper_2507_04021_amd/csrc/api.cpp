@@ -262,6 +262,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.key_off = (uint32_t *)at(L.key_off);
     A.chunk_off = (uint32_t *)at(L.chunk_off);
     A.spec_part = (double *)at(L.spec_part);
+    A.spec_res = (p->flags & PCRT_SPECULAR) ? (float4 *)at(L.spec_res) : nullptr;
     A.diff_part = (double *)at(L.diff_part);
     A.los_part = (double *)at(L.los_part);
     A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
@@ -318,6 +319,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.scan_blk = b.take(sizeof(uint32_t) * ((nrec + 1023) / 1024 + 1));
         L.keylist = b.take(sizeof(uint32_t) * D.max_keys);
         L.spec_part = b.take(sizeof(double) * 5 * (size_t)D.max_key_chunks * D.n_rx);
+        L.spec_res = b.take(sizeof(float4) * (size_t)refine_grid(D) * kKeyChunk * kRefineRxSlice);
         if (rec) {
             const size_t pairs = (size_t)D.rec_keys * D.n_rx;
             L.sp_valid = b.take(pairs);

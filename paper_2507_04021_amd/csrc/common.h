@@ -11,7 +11,7 @@ namespace pcrt {
 
 constexpr int kMaxK = 8;          // max interactions per path
 constexpr int kWave = 64;         // wavefront width
-constexpr int kStackLds = 32;     // traversal stack entries kept in LDS per lane
+constexpr int kStackLds = 24;     // traversal stack entries kept in LDS per lane (6 KiB per wavefront)
 constexpr int kStackMax = 96;     // max stack entries (LDS + global spill)
 constexpr int kRayChunk = 128;    // rays per diffuse reduction chunk (item ray ranges are padded to this)
 constexpr int kKeyChunk = 64;     // specular keys per reduction chunk
@@ -362,9 +362,15 @@ __device__ __forceinline__ bool wide_step_any(const DevScene &S, int &ref, int &
     if (!(tb < INFINITY)) return false;
     int nref = cr[0];
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        if (j > 0) nref = jb == j ? cr[j] : nref;
-        if (tn[j] < INFINITY && j != jb) stk.put(sp++, cr[j]);
+    for (int j = 1; j < W; ++j) nref = jb == j ? cr[j] : nref;
+    if (sp + (W - 1) <= kStackLds) {  // every push lands in LDS: no spill test per push
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (tn[j] < INFINITY && j != jb) stk.lds[(sp++) * kWave] = cr[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (tn[j] < INFINITY && j != jb) stk.put(sp++, cr[j]);
     }
     ref = nref;
     return true;

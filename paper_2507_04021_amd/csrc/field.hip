@@ -91,8 +91,13 @@ constexpr int kDiffRxSlice = 1;
 // of the chunk against each receiver of the slice in turn and writes the
 // chunk's partial sums of those receivers itself, so no block barrier ever
 // makes it wait for another wavefront.
+//
+// Occupancy: six wavefronts per SIMD for the 2- and 4-wide walks (the
+// register budget that allows, with 6 KiB of LDS stack per wavefront, beat
+// five by 2-3 % on the office; seven and eight spilled and lost).
 template <int W>
-__global__ __launch_bounds__(kWave) void k_diffuse(LaunchArgs A) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 4 : 6, 8))) void k_diffuse(
+    LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
     const int lane = threadIdx.x;
     const uint32_t glane = blockIdx.x * kWave + lane;

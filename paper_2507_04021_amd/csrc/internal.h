@@ -100,12 +100,15 @@ struct SolveDims {
 };
 
 constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk
+// Receivers per specular refinement unit (with one key chunk). Measured on the
+// 1M-point office: 16 -> 8.70 ms, 8 -> 8.55 ms, 32 -> 10.05 ms.
+constexpr uint32_t kRefineRxSlice = 8;
 constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 labels x 3 doubles
 
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
         key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
-        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk;
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res;
     size_t total;
 };
 
@@ -144,6 +147,7 @@ struct LaunchArgs {
     uint32_t *key_off;   // [n_items + 1]
     uint32_t *chunk_off; // [n_items + 1]
     double *spec_part;
+    float4 *spec_res;      // refinement: per block, path amplitudes of its current unit's pairs
     double *diff_part;
     double *los_part;
     uint8_t *dvis;

@@ -160,14 +160,19 @@ __device__ __forceinline__ f3 rx_point(const LaunchArgs &A, uint32_t r) {
     return mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
 }
 
-// Validation and field of one (key, receiver) candidate whose first image
-// solution exists: a ray from each point to the next must hit a disk of the
-// expected surface, close in angle (t_a) and plane distance (t_d); otherwise
-// the plane is replaced by the hit disk's and the image solution recomputed,
-// at most kappa times. The last point must see the receiver.
+// One validation pass of a (key, receiver) candidate on its current planes
+// (the key's disk planes, some replaced after earlier passes): a ray from each
+// image point to the next must hit a disk of the expected surface, close in
+// angle (t_a) and plane distance (t_d). The first interaction that fails
+// those two tests asks for another pass with that plane replaced by the hit
+// disk's (kPassRetry: slot, disk), unless retries already equals kappa; any
+// other failure ends the candidate. If every interaction holds, the last
+// point must see the receiver, and the path's field is evaluated.
+enum { kPassDone = 0, kPassRetry = 1 };
+
 template <int KM, int W>
-__device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, KeyPlanes<KM> kp,
-                              Stack &stk, PairOut &po) {
+__device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, const KeyPlanes<KM> &kp,
+                             int retries, Stack &stk, PairOut &po, int &slot, int &disk) {
     po.valid = false;
     const uint32_t K = A.D.K;
     const int k = kp.k;
@@ -175,40 +180,35 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
     const f3 rx = rx_point(A, r);
     f3 x[KM + 1];
     int hid[KM];
-    int retries = 0;
-    for (;;) {
-        if (!refine_planes<KM>(k, tx, rx, kp.pp, kp.pn, A.thr.eps_self, x)) return;
-        int prev = -1;
-        bool retry = false, fail = false;
+    if (!refine_planes<KM>(k, tx, rx, kp.pp, kp.pn, A.thr.eps_self, x)) return kPassDone;
+    int prev = -1;
+    bool retry = false, fail = false;
 #pragma unroll
-        for (int m = 1; m <= KM; ++m) {
-            if (m > k || retry || fail) continue;
-            f3 u = normalize(x[m] - x[m - 1]);
-            float t;
-            bool sp;
-            int h = closest_hit<W>(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
-            if (h < 0) { fail = true; continue; }
-            float4 hp = A.S.pos[h];
-            if (__float_as_uint(hp.w) != kp.ks[m - 1]) { fail = true; continue; }
-            f3 hn = xyz(A.S.nrm[h]);
-            f3 qh = x[m - 1] + t * u;
-            bool ang_ok = fabsf(dot(hn, kp.pn[m - 1])) >= A.thr.cos_ta;
-            bool dist_ok = fabsf(dot(qh - kp.pp[m - 1], kp.pn[m - 1])) <= A.thr.t_d;
-            if (!(ang_ok && dist_ok)) {
-                if (retries >= A.thr.kappa) { fail = true; continue; }
-                ++retries;
-                kp.pp[m - 1] = xyz(hp);
-                kp.pn[m - 1] = hn;
-                retry = true;
-                continue;
-            }
-            hid[m - 1] = h;
-            prev = h;
+    for (int m = 1; m <= KM; ++m) {
+        if (m > k || retry || fail) continue;
+        f3 u = normalize(x[m] - x[m - 1]);
+        float t;
+        bool sp;
+        int h = closest_hit<W>(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.eps_tie, stk, t, sp);
+        if (h < 0) { fail = true; continue; }
+        float4 hp = A.S.pos[h];
+        if (__float_as_uint(hp.w) != kp.ks[m - 1]) { fail = true; continue; }
+        f3 hn = xyz(A.S.nrm[h]);
+        f3 qh = x[m - 1] + t * u;
+        bool ang_ok = fabsf(dot(hn, kp.pn[m - 1])) >= A.thr.cos_ta;
+        bool dist_ok = fabsf(dot(qh - kp.pp[m - 1], kp.pn[m - 1])) <= A.thr.t_d;
+        if (!(ang_ok && dist_ok)) {
+            if (retries >= A.thr.kappa) { fail = true; continue; }
+            slot = m - 1;
+            disk = h;
+            retry = true;
+            continue;
         }
-        if (fail) return;
-        if (retry) continue;
-        break;
+        hid[m - 1] = h;
+        prev = h;
     }
+    if (fail) return kPassDone;
+    if (retry) return kPassRetry;
     f3 xk = x[1];
     int hk = hid[0];
 #pragma unroll
@@ -217,7 +217,7 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
             xk = x[m];
             hk = hid[m - 1];
         }
-    if (occluded<W>(A.S, xk, rx, hk, A.thr.eps_self, stk)) return;
+    if (occluded<W>(A.S, xk, rx, hk, A.thr.eps_self, stk)) return kPassDone;
     float L = 0.f;
     c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
     float csv[KM];
@@ -254,34 +254,58 @@ __device__ void validate_pair(const LaunchArgs &A, uint32_t q, uint32_t r, const
                 A.sb.cs[p * K + m] = csv[m];
             }
     }
+    return kPassDone;
 }
 
 // Persistent single-wavefront blocks. A work unit is (key chunk, slice of up
 // to kRefineRxSlice receivers); units are handed out by an atomic counter,
-// slice-minor so that consecutive units reuse a chunk's key planes. The
-// wavefront deals the unit's (key, receiver) pairs to its lanes in tiles of
-// 64, solves the image method for each pair (cheap, no traversal) and
-// appends the pairs that have a solution to a queue in LDS, in pair order;
-// whenever 64 are queued, all 64 lanes validate one each. Most pairs fail
-// the image test, so this keeps the traversals -- the expensive part -- on
-// full wavefronts, and the small units balance the uneven candidate counts
-// of the chunks.
+// slice-minor so that consecutive units reuse a chunk's key planes.
 //
-// Sums: every batch's results go to LDS, and lane r adds those of receiver
-// r in queue order, i.e. in increasing key order; lane r then writes the
-// unit's partial sum of receiver r0 + r for chunk c. The result does not
-// depend on timing.
-constexpr int kRefineRxSlice = 8;
+// The wavefront deals the unit's (key, receiver) pairs to its lanes in tiles
+// of 64 and solves the image method for each pair (cheap, no traversal);
+// pairs with a solution join a queue in LDS. Whenever 64 are queued, or the
+// tiles are done, every lane takes one queued candidate through ONE
+// validation pass. A pass that asks for a plane replacement puts the
+// candidate back at the end of the queue with that replacement recorded
+// (the disk whose plane it takes), so a candidate that needs many passes
+// holds one lane for one pass at a time instead of keeping the rest of its
+// batch waiting. Most pairs fail the image test, and most candidates end
+// within a few passes, so the traversals -- the expensive part -- run on
+// full wavefronts.
+//
+// Sums: a path's amplitudes go to this block's result slots, indexed by the
+// pair within the unit, with a bit in LDS. When the unit is done, lane r adds
+// the paths of receiver r in increasing key order and writes the unit's
+// partial sum of receiver r0 + r for chunk c. The result does not depend on
+// timing or on the order in which passes ran.
+constexpr uint32_t kRefineQueue = 128;  // ring of queued candidates (at most 127 are live)
+
+template <int KM>
+struct QEntry {
+    uint32_t e;   // pair within the unit: key * nr + receiver
+    int retries;  // passes so far that ended in a plane replacement
+    int ovr[KM];  // per interaction: the disk whose plane replaced the key's, -1 if none
+};
+
+// Global-memory writes of some lanes of a single-wavefront block are visible
+// to its other lanes after this.
+__device__ __forceinline__ void block_sync_global() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 template <int KM, int W>
 __global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
+    constexpr uint32_t kUnitPairs = kKeyChunk * kRefineRxSlice;
     __shared__ int lds_stack[kStackLds * kWave];
-    __shared__ uint32_t queue[2 * kWave];  // pair indices within the unit
-    __shared__ float4 res[kWave];          // a batch's TE and TM amplitudes
-    __shared__ int res_rx[kWave];          // its receiver in the slice, -1 if not a path
+    __shared__ QEntry<KM> queue[kRefineQueue];
+    __shared__ uint32_t vbits[kUnitPairs / 32];  // pairs of the unit that are paths
     const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
+    float4 *res = A.spec_res + (size_t)blockIdx.x * kUnitPairs;
     const uint32_t n_rx = A.D.n_rx, n_items = A.D.n_items;
     const uint32_t n_chunks = A.chunk_off[n_items];
     const uint32_t n_slices = (n_rx + kRefineRxSlice - 1) / kRefineRxSlice;
@@ -309,48 +333,14 @@ __global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
         const uint32_t q0 = A.key_off[it] + (c - A.chunk_off[it]) * kKeyChunk;
         const uint32_t q1 = min(q0 + kKeyChunk, A.key_off[it + 1]);
         const uint32_t ne = (q1 - q0) * nr;  // pairs of this unit, e = key * nr + receiver
-        double acc[5] = {0, 0, 0, 0, 0};     // lane l < nr: receiver r0 + l
-        uint32_t qn = 0;                     // queued candidates (wave-uniform)
-        auto run_batch = [&](uint32_t nb) {
-            PairOut po;
-            po.valid = false;
-            int rr = -1;
-            if ((uint32_t)lane < nb) {
-                const uint32_t e = queue[lane];
-                const uint32_t q = q0 + e / nr;
-                rr = (int)(e % nr);
-                KeyPlanes<KM> kp;
-                load_planes<KM>(A, q, kp);
-                validate_pair<KM, W>(A, q, r0 + rr, I, kp, stk, po);
-                if (rec && q < A.D.rec_keys) {
-                    const size_t p = (size_t)q * n_rx + r0 + rr;
-                    A.sb.valid[p] = po.valid;
-                    A.sb.len[p] = po.valid ? po.len : 0.f;
-                    A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                n_valid += po.valid;
-            }
-            res[lane] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
-            res_rx[lane] = po.valid ? rr : -1;
-            wave_sync();
-            for (uint32_t j = 0; j < nb; ++j)
-                if (res_rx[j] == lane) {
-                    const float4 v = res[j];
-                    const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
-                    acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
-                    acc[1] += tr;
-                    acc[2] += ti;
-                    acc[3] += mr;
-                    acc[4] += mi;
-                }
-            wave_sync();
-        };
-        // one code path for the image test of a tile and for a batch, so
-        // that the validation is inlined once
-        for (uint32_t t = 0;;) {
+        if ((uint32_t)lane < kUnitPairs / 32) vbits[lane] = 0u;
+        wave_sync();
+        uint32_t head = 0, tail = 0;  // queue ring positions (wave-uniform)
+        uint32_t t = 0;               // next image-test tile
+        for (;;) {
             const bool more = t * kWave < ne;
-            if (more) {
+            if (more && tail - head < (uint32_t)kWave) {
+                // image test of one tile; candidates join the queue in pair order
                 const uint32_t e = t * kWave + lane;
                 bool cand = false;
                 if (e < ne) {
@@ -372,28 +362,83 @@ __global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
                 }
                 n_cand += cand;
                 const uint64_t m = __ballot(cand);
-                const uint32_t pos = qn + (uint32_t)__popcll(m & ((1ull << lane) - 1));
-                if (cand) queue[pos] = e;
-                qn += (uint32_t)__popcll(m);
-                wave_sync();
+                if (cand) {
+                    QEntry<KM> &qe = queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue];
+                    qe.e = e;
+                    qe.retries = 0;
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) qe.ovr[j] = -1;
+                }
+                tail += (uint32_t)__popcll(m);
                 ++t;
-            }
-            if (qn >= (uint32_t)kWave || (!more && qn > 0)) {
-                const uint32_t nb = min(qn, (uint32_t)kWave);
-                run_batch(nb);
-                const uint32_t left = qn - nb;
-                const uint32_t v = (uint32_t)lane < left ? queue[nb + lane] : 0u;
                 wave_sync();
-                if ((uint32_t)lane < left) queue[lane] = v;
-                wave_sync();
-                qn = left;
+                continue;
             }
-            if (!more && qn == 0) break;
+            if (tail == head) break;  // tiles done and queue empty
+            // one validation pass for up to 64 queued candidates
+            const uint32_t nb = min(tail - head, (uint32_t)kWave);
+            const bool have = (uint32_t)lane < nb;
+            QEntry<KM> me;
+            if (have) me = queue[(head + lane) % kRefineQueue];
+            head += nb;
+            wave_sync();  // taken entries are read before their ring slots are reused
+            bool again = false;
+            if (have) {
+                const uint32_t q = q0 + me.e / nr, rr = me.e % nr;
+                KeyPlanes<KM> kp;
+                load_planes<KM>(A, q, kp);
+#pragma unroll
+                for (int j = 0; j < KM; ++j)
+                    if (j < kp.k && me.ovr[j] >= 0) {
+                        kp.pp[j] = xyz(A.S.pos[me.ovr[j]]);
+                        kp.pn[j] = xyz(A.S.nrm[me.ovr[j]]);
+                    }
+                PairOut po;
+                int slot = 0, disk = -1;
+                const int out = validate_pass<KM, W>(A, q, r0 + rr, I, kp, me.retries, stk, po, slot, disk);
+                if (out == kPassRetry) {
+                    again = true;
+                    me.retries += 1;
+#pragma unroll
+                    for (int j = 0; j < KM; ++j)
+                        if (j == slot) me.ovr[j] = disk;
+                } else {
+                    if (rec && q < A.D.rec_keys) {
+                        const size_t p = (size_t)q * n_rx + r0 + rr;
+                        A.sb.valid[p] = po.valid;
+                        A.sb.len[p] = po.valid ? po.len : 0.f;
+                        A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                    if (po.valid) {
+                        ++n_valid;
+                        res[me.e] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
+                        atomicOr(&vbits[me.e >> 5], 1u << (me.e & 31));
+                    }
+                }
+            }
+            const uint64_t m = __ballot(again);
+            if (again) queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue] = me;
+            tail += (uint32_t)__popcll(m);
+            wave_sync();
         }
+        block_sync_global();  // result slots written by other lanes are visible
         if ((uint32_t)lane < nr) {
+            double acc[5] = {0, 0, 0, 0, 0};
+            for (uint32_t e = (uint32_t)lane; e < ne; e += nr)  // increasing key
+                if ((vbits[e >> 5] >> (e & 31)) & 1u) {
+                    const float4 v = res[e];
+                    const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
+                    acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+                    acc[1] += tr;
+                    acc[2] += ti;
+                    acc[3] += mr;
+                    acc[4] += mi;
+                }
             double *o = A.spec_part + ((size_t)c * n_rx + r0 + lane) * 5;
             for (int a = 0; a < 5; ++a) o[a] = acc[a];
         }
+        block_sync_global();  // sums read before the next unit clears the bits and reuses the slots
     }
     flush_visits(stk, A.counters, 11);
     n_cand = warp_sum_u(n_cand);
