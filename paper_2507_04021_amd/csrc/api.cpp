@@ -319,7 +319,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.scan_blk = b.take(sizeof(uint32_t) * ((nrec + 1023) / 1024 + 1));
         L.keylist = b.take(sizeof(uint32_t) * D.max_keys);
         L.spec_part = b.take(sizeof(double) * 5 * (size_t)D.max_key_chunks * D.n_rx);
-        L.spec_res = b.take(sizeof(float4) * (size_t)refine_grid(D) * kKeyChunk * kRefineRxSlice);
+        L.spec_res = b.take(sizeof(float4) * (size_t)refine_grid(D) * kRefineResPerBlock);
         if (rec) {
             const size_t pairs = (size_t)D.rec_keys * D.n_rx;
             L.sp_valid = b.take(pairs);

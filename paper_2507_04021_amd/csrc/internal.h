@@ -103,6 +103,8 @@ constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction ch
 // Receivers per specular refinement unit (with one key chunk). Measured on the
 // 1M-point office: 16 -> 8.70 ms, 8 -> 8.55 ms, 32 -> 10.05 ms.
 constexpr uint32_t kRefineRxSlice = 8;
+// Result slots per refinement block: two open units of kKeyChunk keys x kRefineRxSlice receivers.
+constexpr uint32_t kRefineResPerBlock = 2 * kKeyChunk * kRefineRxSlice;
 constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 labels x 3 doubles
 
 struct SolveLayout {

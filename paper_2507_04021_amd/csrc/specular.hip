@@ -171,12 +171,11 @@ __device__ __forceinline__ f3 rx_point(const LaunchArgs &A, uint32_t r) {
 enum { kPassDone = 0, kPassRetry = 1 };
 
 template <int KM, int W>
-__device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, const Item &I, const KeyPlanes<KM> &kp,
+__device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, f3 tx, const KeyPlanes<KM> &kp,
                              int retries, Stack &stk, PairOut &po, int &slot, int &disk) {
     po.valid = false;
     const uint32_t K = A.D.K;
     const int k = kp.k;
-    const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
     const f3 rx = rx_point(A, r);
     f3 x[KM + 1];
     int hid[KM];
@@ -261,30 +260,37 @@ __device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, const 
 // to kRefineRxSlice receivers); units are handed out by an atomic counter,
 // slice-minor so that consecutive units reuse a chunk's key planes.
 //
-// The wavefront deals the unit's (key, receiver) pairs to its lanes in tiles
+// The wavefront deals a unit's (key, receiver) pairs to its lanes in tiles
 // of 64 and solves the image method for each pair (cheap, no traversal);
-// pairs with a solution join a queue in LDS. Whenever 64 are queued, or the
-// tiles are done, every lane takes one queued candidate through ONE
+// pairs with a solution join a queue in LDS. Whenever 64 are queued, or no
+// tile is left to run, every lane takes one queued candidate through ONE
 // validation pass. A pass that asks for a plane replacement puts the
 // candidate back at the end of the queue with that replacement recorded
 // (the disk whose plane it takes), so a candidate that needs many passes
-// holds one lane for one pass at a time instead of keeping the rest of its
-// batch waiting. Most pairs fail the image test, and most candidates end
-// within a few passes, so the traversals -- the expensive part -- run on
-// full wavefronts.
+// holds one lane for one pass at a time. Up to two units are open at once:
+// while the last candidates of one unit still cycle through the queue, the
+// tiles of the next unit refill it, so the batches stay full.
 //
 // Sums: a path's amplitudes go to this block's result slots, indexed by the
-// pair within the unit, with a bit in LDS. When the unit is done, lane r adds
-// the paths of receiver r in increasing key order and writes the unit's
-// partial sum of receiver r0 + r for chunk c. The result does not depend on
-// timing or on the order in which passes ran.
+// open unit and the pair within it, with a bit in LDS. When a unit is done,
+// lane r adds the paths of receiver r in increasing key order and writes the
+// unit's partial sum of receiver r0 + r for chunk c. The result does not
+// depend on timing or on the order in which passes ran.
 constexpr uint32_t kRefineQueue = 128;  // ring of queued candidates (at most 127 are live)
+constexpr int kRefineOpen = 2;          // units open at once per wavefront
 
 template <int KM>
 struct QEntry {
-    uint32_t e;   // pair within the unit: key * nr + receiver
+    uint32_t e;   // pair within its unit: key * nr + receiver
+    int slot;     // open-unit slot
     int retries;  // passes so far that ended in a plane replacement
     int ovr[KM];  // per interaction: the disk whose plane replaced the key's, -1 if none
+};
+
+struct RefUnit {  // an open unit (wavefront-uniform)
+    uint32_t c, r0, nr, q0, ne, t, pending;  // pending: candidates queued or in a pass
+    f3 tx;
+    bool open;
 };
 
 // Global-memory writes of some lanes of a single-wavefront block are visible
@@ -295,60 +301,106 @@ __device__ __forceinline__ void block_sync_global() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Occupancy: four wavefronts per SIMD up to K = 5 (a 128-register budget,
+// with a few spills): on the office two gave 6.1 ms, three 4.8, four 4.7.
 template <int KM, int W>
-__global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ? 4 : 2, 8))) void k_refine(
+    LaunchArgs A) {
     constexpr uint32_t kUnitPairs = kKeyChunk * kRefineRxSlice;
+    static_assert(kRefineOpen == 2 && kRefineOpen * kUnitPairs == kRefineResPerBlock, "two open units");
     __shared__ int lds_stack[kStackLds * kWave];
     __shared__ QEntry<KM> queue[kRefineQueue];
-    __shared__ uint32_t vbits[kUnitPairs / 32];  // pairs of the unit that are paths
+    __shared__ uint32_t vbits[kRefineOpen][kUnitPairs / 32];  // pairs of an open unit that are paths
     const int lane = threadIdx.x;
     const uint64_t below = (1ull << lane) - 1;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
-    float4 *res = A.spec_res + (size_t)blockIdx.x * kUnitPairs;
+    float4 *res = A.spec_res + (size_t)blockIdx.x * kRefineOpen * kUnitPairs;
     const uint32_t n_rx = A.D.n_rx, n_items = A.D.n_items;
     const uint32_t n_chunks = A.chunk_off[n_items];
     const uint32_t n_slices = (n_rx + kRefineRxSlice - 1) / kRefineRxSlice;
     const uint32_t n_units = n_chunks * n_slices;
     const bool rec = A.flags & 8;
     uint32_t n_cand = 0, n_valid = 0;
+    RefUnit U[kRefineOpen];
+#pragma unroll
+    for (int k = 0; k < kRefineOpen; ++k) U[k] = RefUnit{0, 0, 0, 0, 0, 0, 0, mk(0.f, 0.f, 0.f), false};
+    bool exhausted = false;       // the unit counter has run out
+    uint32_t head = 0, tail = 0;  // queue ring positions (wavefront-uniform)
     for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(&A.work[1], 1u);
-        u = __builtin_amdgcn_readfirstlane(u);
-        if (u >= n_units) break;
-        const uint32_t c = u / n_slices;
-        const uint32_t r0 = (u % n_slices) * kRefineRxSlice;
-        const uint32_t nr = min((uint32_t)kRefineRxSlice, n_rx - r0);
-        // item of this chunk
-        int lo = 0, hi = (int)n_items - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (A.chunk_off[mid] <= c) lo = mid;
-            else hi = mid - 1;
+        // close the units whose tiles are done and whose candidates have all ended
+#pragma unroll
+        for (int k = 0; k < kRefineOpen; ++k) {
+            if (!(U[k].open && U[k].t * kWave >= U[k].ne && U[k].pending == 0)) continue;
+            block_sync_global();  // result slots written by other lanes are visible
+            if ((uint32_t)lane < U[k].nr) {
+                double acc[5] = {0, 0, 0, 0, 0};
+                for (uint32_t e = (uint32_t)lane; e < U[k].ne; e += U[k].nr)  // increasing key
+                    if ((vbits[k][e >> 5] >> (e & 31)) & 1u) {
+                        const float4 v = res[k * kUnitPairs + e];
+                        const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
+                        acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+                        acc[1] += tr;
+                        acc[2] += ti;
+                        acc[3] += mr;
+                        acc[4] += mi;
+                    }
+                double *o = A.spec_part + ((size_t)U[k].c * n_rx + U[k].r0 + lane) * 5;
+                for (int a = 0; a < 5; ++a) o[a] = acc[a];
+            }
+            block_sync_global();  // sums read before the slot is reused
+            U[k].open = false;
         }
-        const int it = lo;
-        const Item I = A.items[it];
-        const f3 tx = mk(I.tx[0], I.tx[1], I.tx[2]);
-        const uint32_t q0 = A.key_off[it] + (c - A.chunk_off[it]) * kKeyChunk;
-        const uint32_t q1 = min(q0 + kKeyChunk, A.key_off[it + 1]);
-        const uint32_t ne = (q1 - q0) * nr;  // pairs of this unit, e = key * nr + receiver
-        if ((uint32_t)lane < kUnitPairs / 32) vbits[lane] = 0u;
-        wave_sync();
-        uint32_t head = 0, tail = 0;  // queue ring positions (wave-uniform)
-        uint32_t t = 0;               // next image-test tile
-        for (;;) {
-            const bool more = t * kWave < ne;
-            if (more && tail - head < (uint32_t)kWave) {
-                // image test of one tile; candidates join the queue in pair order
-                const uint32_t e = t * kWave + lane;
+        const uint32_t live = tail - head;
+        if (live < (uint32_t)kWave) {
+            // image-test tile of an open unit with tiles left, else of a newly opened one
+            int s = -1;
+#pragma unroll
+            for (int k = 0; k < kRefineOpen; ++k)
+                if (s < 0 && U[k].open && U[k].t * kWave < U[k].ne) s = k;
+            if (s < 0 && !exhausted) {
+#pragma unroll
+                for (int k = 0; k < kRefineOpen; ++k) {
+                    if (s >= 0 || U[k].open) continue;
+                    uint32_t u = 0;
+                    if (lane == 0) u = atomicAdd(&A.work[1], 1u);
+                    u = __builtin_amdgcn_readfirstlane(u);
+                    if (u >= n_units) {
+                        exhausted = true;
+                        break;
+                    }
+                    const uint32_t c = u / n_slices;
+                    int lo = 0, hi = (int)n_items - 1;  // item of this chunk
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (A.chunk_off[mid] <= c) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const Item I = A.items[lo];
+                    U[k].c = c;
+                    U[k].r0 = (u % n_slices) * kRefineRxSlice;
+                    U[k].nr = min((uint32_t)kRefineRxSlice, n_rx - U[k].r0);
+                    U[k].q0 = A.key_off[lo] + (c - A.chunk_off[lo]) * kKeyChunk;
+                    const uint32_t q1 = min(U[k].q0 + kKeyChunk, A.key_off[lo + 1]);
+                    U[k].ne = (q1 - U[k].q0) * U[k].nr;
+                    U[k].t = 0;
+                    U[k].pending = 0;
+                    U[k].tx = mk(I.tx[0], I.tx[1], I.tx[2]);
+                    U[k].open = true;
+                    if ((uint32_t)lane < kUnitPairs / 32) vbits[k][lane] = 0u;
+                    wave_sync();
+                    s = k;
+                }
+            }
+            auto tile = [&](RefUnit &R, int slot) {
+                const uint32_t e = R.t * kWave + lane;
                 bool cand = false;
-                if (e < ne) {
-                    const uint32_t q = q0 + e / nr, r = r0 + e % nr;
+                if (e < R.ne) {
+                    const uint32_t q = R.q0 + e / R.nr, r = R.r0 + e % R.nr;
                     KeyPlanes<KM> kp;
                     load_planes<KM>(A, q, kp);
                     f3 x[KM + 1];
-                    cand = refine_planes<KM>(kp.k, tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
+                    cand = refine_planes<KM>(kp.k, R.tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
                     if (rec) {
                         if (q >= A.D.rec_keys) {
                             atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded
@@ -365,80 +417,79 @@ __global__ __launch_bounds__(kWave) void k_refine(LaunchArgs A) {
                 if (cand) {
                     QEntry<KM> &qe = queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue];
                     qe.e = e;
+                    qe.slot = slot;
                     qe.retries = 0;
 #pragma unroll
                     for (int j = 0; j < KM; ++j) qe.ovr[j] = -1;
                 }
                 tail += (uint32_t)__popcll(m);
-                ++t;
+                R.pending += (uint32_t)__popcll(m);
+                ++R.t;
                 wave_sync();
+            };
+            if (s == 0) {
+                tile(U[0], 0);
                 continue;
             }
-            if (tail == head) break;  // tiles done and queue empty
-            // one validation pass for up to 64 queued candidates
-            const uint32_t nb = min(tail - head, (uint32_t)kWave);
-            const bool have = (uint32_t)lane < nb;
-            QEntry<KM> me;
-            if (have) me = queue[(head + lane) % kRefineQueue];
-            head += nb;
-            wave_sync();  // taken entries are read before their ring slots are reused
-            bool again = false;
-            if (have) {
-                const uint32_t q = q0 + me.e / nr, rr = me.e % nr;
-                KeyPlanes<KM> kp;
-                load_planes<KM>(A, q, kp);
+            if (s == 1) {
+                tile(U[1], 1);
+                continue;
+            }
+        }
+        if (live == 0) break;  // no tile to run, nothing queued, every unit closed
+        // one validation pass for up to 64 queued candidates
+        const uint32_t nb = min(live, (uint32_t)kWave);
+        const bool have = (uint32_t)lane < nb;
+        QEntry<KM> me;
+        if (have) me = queue[(head + lane) % kRefineQueue];
+        head += nb;
+        wave_sync();  // taken entries are read before their ring slots are reused
+        bool again = false, ended = false;
+        if (have) {
+            const bool s1 = me.slot == 1;
+            const uint32_t nr = s1 ? U[1].nr : U[0].nr;
+            const uint32_t q = (s1 ? U[1].q0 : U[0].q0) + me.e / nr;
+            const uint32_t r = (s1 ? U[1].r0 : U[0].r0) + me.e % nr;
+            const f3 tx = s1 ? U[1].tx : U[0].tx;
+            KeyPlanes<KM> kp;
+            load_planes<KM>(A, q, kp);
+#pragma unroll
+            for (int j = 0; j < KM; ++j)
+                if (j < kp.k && me.ovr[j] >= 0) {
+                    kp.pp[j] = xyz(A.S.pos[me.ovr[j]]);
+                    kp.pn[j] = xyz(A.S.nrm[me.ovr[j]]);
+                }
+            PairOut po;
+            int slot = 0, disk = -1;
+            const int out = validate_pass<KM, W>(A, q, r, tx, kp, me.retries, stk, po, slot, disk);
+            if (out == kPassRetry) {
+                again = true;
+                me.retries += 1;
 #pragma unroll
                 for (int j = 0; j < KM; ++j)
-                    if (j < kp.k && me.ovr[j] >= 0) {
-                        kp.pp[j] = xyz(A.S.pos[me.ovr[j]]);
-                        kp.pn[j] = xyz(A.S.nrm[me.ovr[j]]);
-                    }
-                PairOut po;
-                int slot = 0, disk = -1;
-                const int out = validate_pass<KM, W>(A, q, r0 + rr, I, kp, me.retries, stk, po, slot, disk);
-                if (out == kPassRetry) {
-                    again = true;
-                    me.retries += 1;
-#pragma unroll
-                    for (int j = 0; j < KM; ++j)
-                        if (j == slot) me.ovr[j] = disk;
-                } else {
-                    if (rec && q < A.D.rec_keys) {
-                        const size_t p = (size_t)q * n_rx + r0 + rr;
-                        A.sb.valid[p] = po.valid;
-                        A.sb.len[p] = po.valid ? po.len : 0.f;
-                        A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                    if (po.valid) {
-                        ++n_valid;
-                        res[me.e] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
-                        atomicOr(&vbits[me.e >> 5], 1u << (me.e & 31));
-                    }
+                    if (j == slot) me.ovr[j] = disk;
+            } else {
+                ended = true;
+                if (rec && q < A.D.rec_keys) {
+                    const size_t p = (size_t)q * n_rx + r;
+                    A.sb.valid[p] = po.valid;
+                    A.sb.len[p] = po.valid ? po.len : 0.f;
+                    A.sb.amp[p] = po.valid ? make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                if (po.valid) {
+                    ++n_valid;
+                    res[me.slot * kUnitPairs + me.e] = make_float4(po.te.re, po.te.im, po.tm.re, po.tm.im);
+                    atomicOr(&vbits[me.slot][me.e >> 5], 1u << (me.e & 31));
                 }
             }
-            const uint64_t m = __ballot(again);
-            if (again) queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue] = me;
-            tail += (uint32_t)__popcll(m);
-            wave_sync();
         }
-        block_sync_global();  // result slots written by other lanes are visible
-        if ((uint32_t)lane < nr) {
-            double acc[5] = {0, 0, 0, 0, 0};
-            for (uint32_t e = (uint32_t)lane; e < ne; e += nr)  // increasing key
-                if ((vbits[e >> 5] >> (e & 31)) & 1u) {
-                    const float4 v = res[e];
-                    const double tr = v.x, ti = v.y, mr = v.z, mi = v.w;
-                    acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
-                    acc[1] += tr;
-                    acc[2] += ti;
-                    acc[3] += mr;
-                    acc[4] += mi;
-                }
-            double *o = A.spec_part + ((size_t)c * n_rx + r0 + lane) * 5;
-            for (int a = 0; a < 5; ++a) o[a] = acc[a];
-        }
-        block_sync_global();  // sums read before the next unit clears the bits and reuses the slots
+        U[0].pending -= (uint32_t)__popcll(__ballot(ended && me.slot == 0));
+        U[1].pending -= (uint32_t)__popcll(__ballot(ended && me.slot == 1));
+        const uint64_t m = __ballot(again);
+        if (again) queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue] = me;
+        tail += (uint32_t)__popcll(m);
+        wave_sync();
     }
     flush_visits(stk, A.counters, 11);
     n_cand = warp_sum_u(n_cand);
