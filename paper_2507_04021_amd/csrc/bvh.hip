@@ -225,6 +225,38 @@ __global__ void k_refit(int n, int L, const int2 *__restrict__ child, const int2
 }
 
 // Depth (number of internal ancestors) of each sorted leaf; max into *depth.
+// Node records when every internal node's box is already known (the
+// clustering builder records them at merge time): one thread per node, no
+// bottom-up climb. Same records as k_refit.
+__global__ void k_node_records(int n_int, int L, const int2 *__restrict__ child, const int2 *__restrict__ range,
+                               const float *__restrict__ dbox, const float *__restrict__ ibox,
+                               float4 *__restrict__ node) {
+    const int cur = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cur >= n_int) return;
+    const int2 ch = child[cur];
+    float b[2][6];
+    int ref[2];
+    const int cc[2] = {ch.x, ch.y};
+    for (int s = 0; s < 2; ++s) {
+        const int c = cc[s];
+        if (c < 0) {
+            const int p = ~c;
+            for (int a = 0; a < 6; ++a) b[s][a] = dbox[6 * (size_t)p + a];
+            ref[s] = leaf_ref(p, 1);
+        } else {
+            for (int a = 0; a < 6; ++a) b[s][a] = ibox[6 * (size_t)c + a];
+            const int2 rg = range[c];
+            const int cnt = rg.y - rg.x + 1;
+            ref[s] = cnt <= L ? leaf_ref(rg.x, cnt) : c;
+        }
+    }
+    float4 *nd = node + 4 * (size_t)cur;
+    nd[0] = make_float4(b[0][0], b[0][1], b[0][2], b[0][3]);
+    nd[1] = make_float4(b[0][4], b[0][5], b[1][0], b[1][1]);
+    nd[2] = make_float4(b[1][2], b[1][3], b[1][4], b[1][5]);
+    nd[3] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), 0.f, 0.f);
+}
+
 __global__ void k_depth(int n, const int *__restrict__ parent_int, const int *__restrict__ parent_leaf,
                         uint32_t *__restrict__ depth) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,7 +349,7 @@ __global__ void k_ploc_apply(const float *__restrict__ cbox, const int *__restri
                              const uint32_t *__restrict__ mpos, const uint32_t *__restrict__ kpos, uint32_t node_base,
                              float *__restrict__ obox, int *__restrict__ oid, uint32_t *__restrict__ osize,
                              int2 *__restrict__ child, uint32_t *__restrict__ nsize, int *__restrict__ parent_int,
-                             int *__restrict__ parent_leaf) {
+                             int *__restrict__ parent_leaf, float *__restrict__ ibox) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int j = nn[i];
@@ -341,8 +373,11 @@ __global__ void k_ploc_apply(const float *__restrict__ cbox, const int *__restri
     else parent_int[b] = node;
     const float *x = cbox + 6 * (size_t)i, *y = cbox + 6 * (size_t)j;
     for (int k = 0; k < 3; ++k) {
-        obox[6 * (size_t)p + k] = fminf(x[k], y[k]);
-        obox[6 * (size_t)p + 3 + k] = fmaxf(x[3 + k], y[3 + k]);
+        const float lo = fminf(x[k], y[k]), hi = fmaxf(x[3 + k], y[3 + k]);
+        obox[6 * (size_t)p + k] = lo;
+        obox[6 * (size_t)p + 3 + k] = hi;
+        ibox[6 * (size_t)node + k] = lo;  // the node's box: min / max are exact, so the same
+        ibox[6 * (size_t)node + 3 + k] = hi;  // values a refit over its disks would give
     }
     oid[p] = node;
     osize[p] = sz;
@@ -567,7 +602,8 @@ hipError_t build_ploc(const SceneLayout &L, char *ws, uint32_t n, const uint32_t
         exclusive_scan(kflag, m, pblk, s);
         exclusive_scan(mflag, m, pblk, s);  // merge count lands in pblk[cdiv(m, 1024)]
         hipLaunchKernelGGL(k_ploc_apply, dim3(g), dim3(256), 0, s, cbox[cur], cid[cur], csz[cur], nn, m, mflag, kflag,
-                           node_base, cbox[cur ^ 1], cid[cur ^ 1], csz[cur ^ 1], child, nsize, pint, pleaf);
+                           node_base, cbox[cur ^ 1], cid[cur ^ 1], csz[cur ^ 1], child, nsize, pint, pleaf,
+                           (float *)P(L.ibox));
         uint32_t merges = 0;
         hipError_t e = hipMemcpyAsync(&merges, pblk + cdiv(m, 1024), sizeof merges, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -669,9 +705,14 @@ hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, 
             hipLaunchKernelGGL(k_karras, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, c0, (int)n, child, range, pint,
                                pleaf);
         }
-        fill_u32((uint32_t *)P(L.flags), 0, n - 1, s);
-        hipLaunchKernelGGL(k_refit, dim3(blk), dim3(256), 0, s, (int)n, (int)leaf, child, range, pint, pleaf, dbox,
-                           (float *)P(L.ibox), (uint32_t *)P(L.flags), (float4 *)P(L.node));
+        if (L.builder == kBuildPloc) {
+            hipLaunchKernelGGL(k_node_records, dim3(cdiv(n - 1, 256)), dim3(256), 0, s, (int)(n - 1), (int)leaf,
+                               child, range, dbox, (const float *)P(L.ibox), (float4 *)P(L.node));
+        } else {
+            fill_u32((uint32_t *)P(L.flags), 0, n - 1, s);
+            hipLaunchKernelGGL(k_refit, dim3(blk), dim3(256), 0, s, (int)n, (int)leaf, child, range, pint, pleaf,
+                               dbox, (float *)P(L.ibox), (uint32_t *)P(L.flags), (float4 *)P(L.node));
+        }
         hipLaunchKernelGGL(k_depth, dim3(blk), dim3(256), 0, s, (int)n, pint, pleaf, stat + 3);
     }
     *root = broot;
