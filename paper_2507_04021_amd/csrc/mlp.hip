@@ -457,25 +457,68 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const uint16_t *dz, const uin
     if (threadIdx.x < OUT) P[OUT * IN + threadIdx.x] = bsum;
 }
 
-// Embedding gradient partial: thread (label, dim) sums its rows of the block in order.
+// Embedding gradient partial of one block of rows. Thread (g, d) -- row group
+// g = 0..15, embedding dimension d -- adds dx0[row][d] of rows b0 + g,
+// b0 + g + 16, ... in order into its group's LDS table acc[g][label][d]; the
+// 16 group tables are then added in group order. Fixed order, no atomics.
+constexpr int kEmbGroups = 16;
+constexpr int kMaxLabels = 64;
 __global__ __launch_bounds__(256) void k_mlp_embgrad(const uint16_t *label, const float *dx0, uint32_t n,
                                                      uint32_t n_labels, float *part) {
+    __shared__ float acc[kEmbGroups][kMaxLabels * kEmb];
+    for (uint32_t e = threadIdx.x; e < kEmbGroups * kMaxLabels * kEmb; e += blockDim.x) (&acc[0][0])[e] = 0.f;
+    __syncthreads();
+    const uint32_t g = threadIdx.x / kEmb, d = threadIdx.x % kEmb;
     const uint32_t b0 = blockIdx.x * kGradRows, b1 = min(b0 + kGradRows, n);
+    for (uint32_t r = b0 + g; r < b1; r += kEmbGroups) {
+        const uint32_t lab = label[r];
+        if (lab < n_labels) acc[g][lab * kEmb + d] += dx0[(size_t)r * kEmb + d];
+    }
+    __syncthreads();
     for (uint32_t e = threadIdx.x; e < n_labels * kEmb; e += blockDim.x) {
-        const uint32_t lab = e / kEmb, d = e % kEmb;
         float s = 0.f;
-        for (uint32_t r = b0; r < b1; ++r)
-            if (label[r] == lab) s += dx0[(size_t)r * kEmb + d];
+        for (int k = 0; k < kEmbGroups; ++k) s += acc[k][e];
         part[(size_t)blockIdx.x * n_labels * kEmb + e] = s;
     }
 }
 
-__global__ void k_sum_parts(const float *part, uint32_t n_parts, uint32_t width, uint32_t stride, float *out) {
+// Fixed-order sum of per-block partials, first stage: block (x, y) adds, for
+// columns 64 x .. 64 x + 63, the partials of split y (kSumSplits contiguous
+// ranges) -- each of its four wavefronts a quarter of the range in order,
+// then the four in wavefront order -- into part2[y][column].
+constexpr uint32_t kSumSplits = 16;
+__global__ __launch_bounds__(256) void k_sum_parts_split(const float *part, uint32_t n_parts, uint32_t width,
+                                                         uint32_t stride, float *part2) {
+    __shared__ float red[4][64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t i = blockIdx.x * 64 + lane;
+    const uint32_t p0 = (uint32_t)((uint64_t)blockIdx.y * n_parts / kSumSplits);
+    const uint32_t p1 = (uint32_t)((uint64_t)(blockIdx.y + 1) * n_parts / kSumSplits);
+    const uint32_t b0 = p0 + (uint32_t)((uint64_t)wave * (p1 - p0) / 4);
+    const uint32_t b1 = p0 + (uint32_t)((uint64_t)(wave + 1) * (p1 - p0) / 4);
+    float s = 0.f;
+    if (i < width)
+        for (uint32_t b = b0; b < b1; ++b) s += part[(size_t)b * stride + i];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && i < width)
+        part2[(size_t)blockIdx.y * width + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// Second stage: out[i] = sum over the splits in order.
+__global__ void k_sum_parts(const float *part2, uint32_t width, float *out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= width) return;
     float s = 0.f;
-    for (uint32_t b = 0; b < n_parts; ++b) s += part[(size_t)b * stride + i];
+    for (uint32_t y = 0; y < kSumSplits; ++y) s += part2[(size_t)y * width + i];
     out[i] = s;
+}
+
+void sum_parts(const float *part, uint32_t n_parts, uint32_t width, uint32_t stride, float *part2, float *out,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_parts_split, dim3((width + 63) / 64, kSumSplits), dim3(256), 0, s, part, n_parts, width,
+                       stride, part2);
+    hipLaunchKernelGGL(k_sum_parts, dim3((width + 255) / 256), dim3(256), 0, s, part2, width, out);
 }
 
 }  // namespace pcrt
@@ -484,7 +527,7 @@ using namespace pcrt;
 
 namespace {
 struct MlpLayout {
-    size_t x0, h1, h2, h3, dz1, dz2, dz3, dz4, dx0, part, total;
+    size_t x0, h1, h2, h3, dz1, dz2, dz3, dz4, dx0, part, part2, total;
     uint32_t n_blocks;
 };
 MlpLayout mlp_layout(uint32_t n, uint32_t n_labels) {
@@ -502,6 +545,7 @@ MlpLayout mlp_layout(uint32_t n, uint32_t n_labels) {
     L.dx0 = b.take(4ull * n * kEmb);
     size_t per = std::max<size_t>(kHid * kHid + kHid, (size_t)n_labels * kEmb);
     L.part = b.take(4ull * L.n_blocks * per);
+    L.part2 = b.take(4ull * kSumSplits * per);
     L.total = b.off;
     return L;
 }
@@ -567,7 +611,7 @@ pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *l
     M.dz3 = (uint16_t *)(w + L.dz3);
     M.dz4 = (uint16_t *)(w + L.dz4);
     M.dx0 = (float *)(w + L.dx0);
-    float *part = (float *)(w + L.part);
+    float *part = (float *)(w + L.part), *part2 = (float *)(w + L.part2);
     const uint32_t tiles = (n + kTileRows - 1) / kTileRows;
     hipLaunchKernelGGL(k_mlp_backward_chain, dim3(std::min<uint32_t>((tiles + 3) / 4, 2048)), dim3(256), 0, s, M);
     const uint32_t nb = L.n_blocks;
@@ -588,14 +632,12 @@ pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *l
         else
             hipLaunchKernelGGL((k_mlp_wgrad<kHid, kIn>), dim3(nb), dim3(256), 0, s, j.dz, j.h, n, part);
         const uint32_t wsz = j.out * j.in, stride = wsz + j.out;
-        hipLaunchKernelGGL(k_sum_parts, dim3((wsz + 255) / 256), dim3(256), 0, s, part, nb, wsz, stride,
-                           grad_w + j.w_off);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part + wsz, nb, (uint32_t)j.out, stride,
-                           grad_b + j.b_off);
+        sum_parts(part, nb, wsz, stride, part2, grad_w + j.w_off, s);
+        sum_parts(part + wsz, nb, (uint32_t)j.out, stride, part2, grad_b + j.b_off, s);
     }
     hipLaunchKernelGGL(k_mlp_embgrad, dim3(nb), dim3(256), 0, s, label, M.dx0, n, net->n_labels, part);
     const uint32_t ew = net->n_labels * kEmb;
-    hipLaunchKernelGGL(k_sum_parts, dim3((ew + 255) / 256), dim3(256), 0, s, part, nb, ew, ew, grad_emb);
+    sum_parts(part, nb, ew, ew, part2, grad_emb, s);
     return hipGetLastError() == hipSuccess ? PCRT_OK : PCRT_EDEVICE;
 }
 
