@@ -129,6 +129,7 @@ class Solution:
     h_te: np.ndarray
     h_tm: np.ndarray
     jac: np.ndarray | None   # float64[n_rx, n_labels, 3]: dG/d(eps_r, sigma, S)
+    cfr: np.ndarray | None = None  # complex128[n_rx, n_freq, 2]: channel frequency response (TE, TM)
 
     def paths(self, r: int):
         """{key: (length, a_TE, a_TM)} of the valid specular paths at receiver r."""
@@ -140,8 +141,12 @@ class Solution:
 
 
 def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SPECULAR,
-          thr=None, want_dvis=False, want_jac=False) -> Solution:
-    """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S)."""
+          thr=None, want_dvis=False, want_jac=False, cfr=None) -> Solution:
+    """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S).
+
+    cfr = (bandwidth_hz, n_freq): also the channel frequency response, every
+    path's centre-frequency amplitudes times exp(-j 2 pi (f_n - freq) L / c0)
+    at n_freq equally spaced frequencies f_n spanning bandwidth_hz around freq."""
     th = dict(DEFAULT_THR)
     if thr:
         th.update(thr)
@@ -170,13 +175,16 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     sh = np.empty((cap, n_rx, K), np.int64)
     orx = np.empty((n_rx, 8), np.float64)
     jac = np.empty((n_rx, n_labels, 3), np.float64) if want_jac else None
+    n_freq, bw = (int(cfr[1]), float(cfr[0])) if cfr else (0, 0.0)
+    ocfr = np.empty((n_rx, max(n_freq, 1), 4), np.float64) if cfr else None
     rc = _load().orc_solve(
         ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal), _p(scene.material), _p(scene.surface),
         _radius(scene), ctypes.c_int32(n_labels), _p(eps_r), _p(sig), _p(sca),
         _p(tx), ctypes.c_int32(n_rx), _p(rx), ctypes.c_double(freq), ctypes.c_int64(n_budget),
         ctypes.c_int64(nt), _p(ids), ctypes.c_int32(K), ctypes.c_int32(flags), _p(thr_arr),
         _p(seq), _p(rec), _p(dvis), ctypes.c_int64(cap), _p(keys), _p(klen), _p(krep), ctypes.byref(nk),
-        _p(sv), _p(sl), _p(sa), _p(sh), _p(orx), _p(jac))
+        _p(sv), _p(sl), _p(sa), _p(sh), _p(orx), _p(jac), ctypes.c_int32(n_freq), ctypes.c_double(bw),
+        _p(ocfr))
     if rc:
         raise ValueError("oracle solve failed (%d)" % rc)
     n = nk.value
@@ -185,7 +193,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     return Solution(seq, rec, dvis.astype(bool) if dvis is not None else None, key_list, krep[:n].copy(),
                     sv[:n].astype(bool), sl[:n].copy(), amp, sh[:n].copy(), orx[:, 0].copy(), orx[:, 1].copy(),
                     orx[:, 2].copy(), orx[:, 3].copy(), orx[:, 4] + 1j * orx[:, 5], orx[:, 6] + 1j * orx[:, 7],
-                    jac)
+                    jac, (ocfr[..., 0::2] + 1j * ocfr[..., 1::2]) if cfr else None)
 
 
 def trace(scene, tx, n_budget, ray_ids=None, K=2, thr=None):

@@ -271,6 +271,28 @@ static void path_field(const em_t *em, int k, const int *label, const double *co
     }
 }
 
+/* Channel frequency response: every path adds its two complex amplitudes
+ * (taken at the centre frequency f_c) times exp(-j 2 pi (f_n - f_c) tau),
+ * tau = len / c0, at n_freq equally spaced frequencies
+ * f_n = f_c + (n - (n_freq - 1) / 2) bw / (n_freq - 1) spanning bw. */
+typedef struct {
+    int n;
+    double bw;
+    double complex *h; /* [n_rx][n][2]: TE, TM */
+} cfr_t;
+
+static void cfr_add(cfr_t *c, int r, double complex a_te, double complex a_tm, double len)
+{
+    if (!c || c->n <= 0) return;
+    const double tau = len / ORC_C0;
+    for (int i = 0; i < c->n; ++i) {
+        const double df = c->n > 1 ? (i - 0.5 * (c->n - 1)) * c->bw / (c->n - 1) : 0.0;
+        const double complex w = cexp(-I * 2.0 * ORC_PI * df * tau);
+        c->h[((size_t)r * c->n + i) * 2 + 0] += a_te * w;
+        c->h[((size_t)r * c->n + i) * 2 + 1] += a_tm * w;
+    }
+}
+
 /* ------------------------------------------------------ bounce loop (a4-a5) */
 typedef struct {
     int n;                 /* interactions recorded */
@@ -490,6 +512,8 @@ static int key_cmp(const void *pa, const void *pb)
  *   spec_amp double[key_cap*n_rx*4] (TE re, im, TM re, im), spec_hid int64[key_cap*n_rx*K]
  *   out_rx   double[n_rx*8]: G_los, G_spec, G_diff, G, h_TE re, im, h_TM re, im
  *   jac      double[n_rx*n_labels*3]: dG/d(eps_r, sigma, S) per label
+ *   out_cfr  double[n_rx*n_freq*4]: channel frequency response (TE re, im,
+ *            TM re, im) at n_freq frequencies spanning bandwidth around freq
  * *n_keys receives the number of unique keys; returns -3 if key_cap is too small.
  */
 int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf,
@@ -498,7 +522,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
               int64_t n_trace, const int64_t *ray_ids, int32_t K, int32_t flags, const double *thr,
               int64_t *seq, double *rec, uint8_t *dvis, int64_t key_cap, uint32_t *keys, int32_t *key_len,
               int64_t *key_rep, int64_t *n_keys, uint8_t *spec_valid, double *spec_len, double *spec_amp,
-              int64_t *spec_hid, double *out_rx, double *jac)
+              int64_t *spec_hid, double *out_rx, double *jac, int32_t n_freq, double bandwidth, double *out_cfr)
 {
     if (K < 1 || K > ORC_KMAX) return -1;
     scene_t s;
@@ -520,6 +544,8 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     double complex *h_te = calloc((size_t)n_rx, sizeof(double complex));
     double complex *h_tm = calloc((size_t)n_rx, sizeof(double complex));
     if (jac) memset(jac, 0, sizeof(double) * (size_t)n_rx * (size_t)n_labels * 3);
+    cfr_t cfr = {out_cfr ? n_freq : 0, bandwidth, NULL};
+    if (cfr.n > 0) cfr.h = calloc((size_t)n_rx * (size_t)cfr.n * 2, sizeof(double complex));
 
     /* line of sight */
     if (flags & ORC_LOS) {
@@ -532,6 +558,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
             G_los[r] += 0.5 * (creal(a * conj(a)) * 2.0);
             h_te[r] += a;
             h_tm[r] += a;
+            cfr_add(&cfr, r, a, a, d);
         }
     }
 
@@ -565,6 +592,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
         double complex *ate = calloc((size_t)nslot, sizeof(double complex));
         double complex *atm = calloc((size_t)nslot, sizeof(double complex));
         double *pw = calloc((size_t)nslot, sizeof(double));
+        double *plen = calloc((size_t)nslot, sizeof(double));
         double *jl = jac ? calloc((size_t)nslot * (size_t)n_labels * 3, sizeof(double)) : NULL;
         uint8_t *vis = calloc((size_t)nslot, 1);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -588,6 +616,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                     double cos_s = vn / rs;
                     double amp0 = a_iso * sqrt(4.0 * cos_s / (double)n_budget) / rs;
                     vis[slot] = 1;
+                    plen[slot] = tr[q].L[k] + rs;
                     path_field(&em, k + 1, label, cs, kind, amp0, tr[q].L[k] + rs, &ate[slot], &atm[slot],
                                &pw[slot], jl ? jl + slot * n_labels * 3 : NULL);
                 }
@@ -602,10 +631,11 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                     G_diff[r] += pw[slot];
                     h_te[r] += ate[slot];
                     h_tm[r] += atm[slot];
+                    cfr_add(&cfr, r, ate[slot], atm[slot], plen[slot]);
                     if (jac)
                         for (int l = 0; l < 3 * n_labels; ++l) jac[r * n_labels * 3 + l] += jl[slot * n_labels * 3 + l];
                 }
-        free(ate); free(atm); free(pw); free(jl); free(vis);
+        free(ate); free(atm); free(pw); free(plen); free(jl); free(vis);
     } else if (dvis) {
         memset(dvis, 0, (size_t)(n_trace * K * n_rx));
     }
@@ -671,6 +701,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                         G_spec[r] += g;
                         h_te[r] += ate;
                         h_tm[r] += atm;
+                        cfr_add(&cfr, r, ate, atm, p->len);
                     }
                     if (spec_len) spec_len[o] = p->valid ? p->len : NAN;
                     if (spec_amp) {
@@ -698,6 +729,12 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
             o[6] = creal(h_tm[r]);
             o[7] = cimag(h_tm[r]);
         }
+    if (cfr.n > 0)
+        for (size_t i = 0; i < (size_t)n_rx * (size_t)cfr.n * 2; ++i) {
+            out_cfr[2 * i] = creal(cfr.h[i]);
+            out_cfr[2 * i + 1] = cimag(cfr.h[i]);
+        }
+    free(cfr.h);
     free(tr); free(dirs); free(rx); free(G_los); free(G_spec); free(G_diff); free(h_te); free(h_tm);
     scene_free(&s);
     return ret;

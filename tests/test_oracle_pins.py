@@ -470,3 +470,56 @@ def test_diffuse_phase_uses_unfolded_length(orc):
     te, tm = fresnel_bc(5.0, 0.1, f, cos_i)
     assert abs(np.angle(sol.h_te[0] / te * np.exp(1j * 2 * math.pi / lam * L))) < 1e-9
     assert abs(np.angle(sol.h_tm[0] / tm * np.exp(1j * 2 * math.pi / lam * L))) < 1e-9
+
+
+# ------------------------------- channel frequency / impulse response (CFR)
+# CFR reading: each path's centre-frequency amplitudes times
+# exp(-j 2 pi (f_n - f_c) L / c0) at n_freq equally spaced samples spanning
+# the bandwidth (the paper's learning experiment: 129 samples over 1.5 GHz at
+# 8 GHz, the CIR being the inverse DFT of those samples).
+def _cfr_freqs(fc, bw, n):
+    return fc + (np.arange(n) - 0.5 * (n - 1)) * bw / (n - 1)
+
+
+def test_cfr_centre_sample_is_the_coherent_field(orc, room_holefree):
+    """At the centre sample every path's weight is exactly 1, so it is the
+    solve's own coherent sum h_TE, h_TM (all three path kinds)."""
+    rxs = np.array([scenes.BOX_RX, [3.0, 2.0, 2.0]], np.float32)
+    sol = orc.solve(room_holefree, scenes.box_room_materials(scatter=0.3), scenes.BOX_TX, rxs, 8e9, 400, K=2,
+                    flags=LOS | SPEC | DIFF, cfr=(1.5e9, 129))
+    assert sol.cfr.shape == (2, 129, 2)
+    np.testing.assert_array_equal(sol.cfr[:, 64, 0], sol.h_te)
+    np.testing.assert_array_equal(sol.cfr[:, 64, 1], sol.h_tm)
+    # off-centre samples differ (the paths have different delays)
+    assert np.all(np.abs(sol.cfr[:, 0, 0] - sol.h_te) > 1e-3 * np.abs(sol.h_te))
+
+
+def test_cfr_line_of_sight_is_free_space_at_each_frequency(orc, room_holefree):
+    """One path: lambda_c / (4 pi d) exp(-j 2 pi f_n d / c0) -- the phase
+    follows each sample frequency, the amplitude stays at the centre's."""
+    fc, bw, n = 8e9, 1.5e9, 129
+    rx = np.array([[3.0, 2.0, 2.0]], np.float32)
+    sol = orc.solve(room_holefree, scenes.box_room_materials(), scenes.BOX_TX, rx, fc, 16, K=1, flags=LOS,
+                    cfr=(bw, n))
+    d = np.linalg.norm(rx[0].astype(float) - np.array(scenes.BOX_TX, np.float32).astype(float))
+    lam = C0 / fc
+    ref = lam / (4 * math.pi * d) * np.exp(-1j * 2 * math.pi * _cfr_freqs(fc, bw, n) * d / C0)
+    np.testing.assert_allclose(sol.cfr[0, :, 0], ref, rtol=0, atol=1e-12 * abs(ref[0]))
+    np.testing.assert_allclose(sol.cfr[0, :, 1], ref, rtol=0, atol=1e-12 * abs(ref[0]))
+
+
+def test_cfr_impulse_response_peaks_at_the_path_delays(orc):
+    """Line of sight plus one floor reflection: the inverse DFT of the 129
+    samples peaks at bins tau * N * bw / (N - 1) of the two path delays
+    (a wrong phase sign would put them at N minus that)."""
+    fc, bw, n = 8e9, 1.5e9, 129
+    floor = scenes.plane_patch(-1, 7, -1, 5, 0.1, 0.0708, z=0.0, material=0, surface=0)
+    tx = np.array([1.0, 1.0, 1.5], np.float32)
+    rx = np.array([4.0, 2.5, 1.2], np.float32)
+    sol = orc.solve(floor, np.array([[2.0, 0.01, 0.0]]), tx, [rx], fc, 4000, K=1, flags=LOS | SPEC, cfr=(bw, n))
+    taus = [np.linalg.norm(rx.astype(float) - tx.astype(float)) / C0,
+            np.linalg.norm(rx.astype(float) - tx.astype(float) * np.array([1, 1, -1])) / C0]
+    h = np.fft.ifft(sol.cfr[0, :, 0])
+    top = sorted(np.argsort(np.abs(h))[-2:])
+    want = sorted(int(round(t * n * bw / (n - 1))) % n for t in taus)
+    assert top == want, (top, want)
