@@ -321,6 +321,25 @@ pcrt_status pcrt_tape_forward(const pcrt_scene *scene, const pcrt_solve_params *
 pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                                const double *dL_dgain, void *stream);
 
+/* Channel frequency response of the recorded paths with the current coef
+ * rows (the material-learning experiment of Sec. IV-B): per receiver r and
+ * sample n, H_r(f_n) = sum over paths of a_p exp(-j 2 pi (f_n - f_c) L_p / c0),
+ * a_p the path's TE / TM amplitudes at the solve's frequency f_c, L_p its
+ * unfolded length, f_n = f_c + (n - (n_freq - 1) / 2) bandwidth_hz /
+ * (n_freq - 1) (the centre frequency alone when n_freq == 1). The channel
+ * impulse response is the inverse DFT of these samples. Paths: line of sight,
+ * valid specular paths, visible diffuse connections, summed in that fixed
+ * order in FP64. cfr: device double[n_rx][n_freq][4] = (H_TE re, im, H_TM
+ * re, im). n_freq in 1..65535, bandwidth_hz >= 0; EINVAL otherwise. */
+pcrt_status pcrt_tape_cfr(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, double bandwidth_hz,
+                          uint32_t n_freq, double *cfr, void *stream);
+
+/* Adjoint rows (as pcrt_tape_backward writes them) for a loss L(H) of that
+ * response: dL_dcfr device double[n_rx][n_freq][4] = dL/d of the four reals
+ * of each sample. pcrt_material_grad then gives dL/d(eps_r, sigma, S). */
+pcrt_status pcrt_tape_cfr_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                                   double bandwidth_hz, uint32_t n_freq, const double *dL_dcfr, void *stream);
+
 /* dL/d(eps_r, sigma, S) per label from the adjoint rows and the Fresnel
  * derivatives dGamma/deta (deta/deps_r = 1, deta/dsigma = -j/(omega eps0)).
  * Fixed-order FP64 reduction. mats: device pcrt_material[n_labels],

@@ -138,6 +138,8 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_tape_forward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.POINTER(Outputs), vp]
         L.pcrt_tape_backward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
         L.pcrt_material_grad.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, u32, vp, vp]
+        L.pcrt_tape_cfr.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.c_double, u32, vp, vp]
+        L.pcrt_tape_cfr_backward.argtypes = [vp, ctypes.POINTER(SolveParams), vp, ctypes.c_double, u32, vp, vp]
         _libs[variant] = L
         if variant == "prod":
             _lib = L
@@ -533,6 +535,31 @@ def tape_backward(res: SolveResult, dl_dg, stream=None):
     d = dl_dg.to(device=res.scene.device, dtype=torch.float64).contiguous()
     _check(L.pcrt_tape_backward(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), _ptr(d),
                                 _stream(stream)), L)
+    return d
+
+
+def tape_cfr(res: SolveResult, bandwidth_hz: float, n_freq: int, stream=None):
+    """Channel frequency response of a RECORD solve's paths with the tape's
+    current coefficient rows: complex128 [n_rx, n_freq, 2] (TE, TM) at n_freq
+    equally spaced frequencies spanning bandwidth_hz around the solve's."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    n_rx = res.params.n_rx
+    out = torch.empty(n_rx, n_freq, 4, dtype=torch.float64, device=res.scene.device)
+    _check(L.pcrt_tape_cfr(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), float(bandwidth_hz), int(n_freq),
+                           _ptr(out), _stream(stream)), L)
+    return torch.complex(out[..., 0::2], out[..., 1::2])
+
+
+def tape_cfr_backward(res: SolveResult, bandwidth_hz: float, n_freq: int, dl_dh, stream=None):
+    """Adjoint rows of the tape for dL/dH, given as a complex [n_rx, n_freq, 2]
+    tensor dL/dRe + j dL/dIm of each sample."""
+    torch = _torch()
+    L = lib(res.scene._variant)
+    g = dl_dh.to(device=res.scene.device, dtype=torch.complex128)
+    d = torch.stack([g[..., 0].real, g[..., 0].imag, g[..., 1].real, g[..., 1].imag], -1).contiguous()
+    _check(L.pcrt_tape_cfr_backward(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), float(bandwidth_hz),
+                                    int(n_freq), _ptr(d), _stream(stream)), L)
     return d
 
 

@@ -797,6 +797,34 @@ pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params 
     return ok();
 }
 
+pcrt_status pcrt_tape_cfr(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, double bandwidth_hz,
+                          uint32_t n_freq, double *cfr, void *stream) {
+    LaunchArgs A;
+    Plan P{};  // every field zero until set
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!cfr) return fail(PCRT_EINVAL, "cfr is required");
+    if (n_freq == 0 || n_freq > 65535) return fail(PCRT_EINVAL, "n_freq must be in 1..65535");
+    if (!(bandwidth_hz >= 0.0) || !std::isfinite(bandwidth_hz)) return fail(PCRT_EINVAL, "bandwidth_hz must be >= 0");
+    launch_tape_cfr(A, bandwidth_hz, n_freq, cfr, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_tape_cfr_backward(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
+                                   double bandwidth_hz, uint32_t n_freq, const double *dL_dcfr, void *stream) {
+    LaunchArgs A;
+    Plan P{};  // every field zero until set
+    pcrt_status st = tape_args(scene, p, ws, &A, &P);
+    if (st) return st;
+    if (!dL_dcfr) return fail(PCRT_EINVAL, "dL_dcfr is required");
+    if (n_freq == 0 || n_freq > 65535) return fail(PCRT_EINVAL, "n_freq must be in 1..65535");
+    if (!(bandwidth_hz >= 0.0) || !std::isfinite(bandwidth_hz)) return fail(PCRT_EINVAL, "bandwidth_hz must be >= 0");
+    launch_tape_cfr_backward(A, bandwidth_hz, n_freq, dL_dcfr, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
 pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws,
                                const pcrt_material *mats, uint32_t n_labels, double *dL_dmat, void *stream) {
     LaunchArgs A;

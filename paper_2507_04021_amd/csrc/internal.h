@@ -175,6 +175,8 @@ void launch_tape_fresnel(const LaunchArgs &A, const float *mats, uint32_t n_labe
 void launch_tape_forward(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                          hipStream_t s);
 void launch_tape_backward(const LaunchArgs &A, const double *dldg, hipStream_t s);
+void launch_tape_cfr(const LaunchArgs &A, double bw, uint32_t N, double *cfr, hipStream_t s);
+void launch_tape_cfr_backward(const LaunchArgs &A, double bw, uint32_t N, const double *dldh, hipStream_t s);
 void launch_material_grad(const LaunchArgs &A, const float *mats, uint32_t n_labels, double *out, hipStream_t s);
 void launch_raygen(uint32_t n_budget, const uint32_t *ids, uint32_t n, float *out, hipStream_t s);
 void launch_paths_copy(const LaunchArgs &A, uint32_t cap, uint32_t *key_ray, uint8_t *key_len, int32_t *key_seq,

@@ -368,6 +368,312 @@ void launch_tape_backward(const LaunchArgs &A, const double *dldg, hipStream_t s
     }
 }
 
+// ------------------------------------------- channel frequency response
+// H_r(f_n) = sum over the recorded paths of a_p exp(-j 2 pi (f_n - f_c) tau_p)
+// with a_p the path's TE / TM amplitudes at the solve's frequency f_c,
+// tau_p = L_p / c0 and f_n = f_c + (n - (N - 1) / 2) bw / (N - 1) (Sec. IV-B:
+// CFR samples over a bandwidth; the CIR is their inverse DFT). Paths per
+// receiver in a fixed order: line of sight, the valid specular paths by key,
+// the visible diffuse connections by record.
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd cdmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cdconj(cd a) { return {a.re, -a.im}; }
+
+struct CfrPath {
+    cd te, tm;
+    double tau;
+};
+
+__device__ __forceinline__ double cfr_df(uint32_t n, uint32_t N, double bw) {
+    return N > 1 ? ((double)n - 0.5 * (double)(N - 1)) * bw / (double)(N - 1) : 0.0;
+}
+
+// Path j of receiver r: 0 = line of sight, 1..nk = specular key j - 1, then
+// diffuse record j - 1 - nk. False if that path does not exist.
+__device__ bool cfr_path(const LaunchArgs &A, uint32_t j, uint32_t r, uint32_t nk, CfrPath &out) {
+    const uint32_t K = A.D.K, n_rx = A.D.n_rx, TK = A.D.T * A.D.K;
+    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+    if (j == 0) {
+        if (!(A.flags & 1)) return false;
+        const double *lp = A.los_part + (size_t)r * 5;
+        if (!(lp[0] > 0.0)) return false;
+        const Item I = A.items[0];
+        const float d = len(rx - mk(I.tx[0], I.tx[1], I.tx[2]));
+        out.te = {lp[1], lp[2]};
+        out.tm = {lp[3], lp[4]};
+        out.tau = (double)d / kC0;
+        return true;
+    }
+    if (j <= nk) {
+        const uint32_t q = j - 1;
+        const size_t p = (size_t)q * n_rx + r;
+        if (!A.sb.valid[p]) return false;
+        const uint32_t k = A.keylist[q] % K + 1;
+        c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
+        for (uint32_t m = 0; m < k; ++m) {
+            SlotCoef cf = load_coef(A.slot_coef, TK + p * K + m);
+            float f = sqrtf(fmaxf(0.f, 1.f - cf.S * cf.S));
+            pte = cmul(pte, {f * cf.te.re, f * cf.te.im});
+            ptm = cmul(ptm, {f * cf.tm.re, f * cf.tm.im});
+        }
+        const float L = A.sb.len[p];
+        const float a0 = A.fc.amp_iso / L;
+        const c32 ph = propagate(L, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+        const c32 te = cmul({a0 * pte.re, a0 * pte.im}, ph), tm = cmul({a0 * ptm.re, a0 * ptm.im}, ph);
+        out.te = {te.re, te.im};
+        out.tm = {tm.re, tm.im};
+        out.tau = (double)L / kC0;
+        return true;
+    }
+    const uint32_t ri = j - 1 - nk;
+    if (A.rb.id[ri] < 0 || !A.dvis[(size_t)ri * n_rx + r]) return false;
+    const uint32_t g = ri / K, k = ri % K;
+    c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
+    for (uint32_t m = 0; m <= k; ++m) {
+        SlotCoef cf = load_coef(A.slot_coef, (size_t)g * K + m);
+        float f = m < k ? sqrtf(fmaxf(0.f, 1.f - cf.S * cf.S)) : cf.S;
+        pte = cmul(pte, {f * cf.te.re, f * cf.te.im});
+        ptm = cmul(ptm, {f * cf.tm.re, f * cf.tm.im});
+    }
+    float a0, plen;
+    diffuse_geom(A, ri, rx, (float)A.items[0].budget, a0, plen);
+    const c32 ph = propagate(plen, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+    const c32 te = cmul({a0 * pte.re, a0 * pte.im}, ph), tm = cmul({a0 * ptm.re, a0 * ptm.im}, ph);
+    out.te = {te.re, te.im};
+    out.tm = {tm.re, tm.im};
+    out.tau = (double)plen / kC0;
+    return true;
+}
+
+// Block (receiver r, 256 frequencies): the lanes evaluate 256 paths at a time
+// into LDS, then each lane adds all of them, in path order, to its frequency.
+__global__ __launch_bounds__(256) void k_tape_cfr(LaunchArgs A, double bw, uint32_t N, double *cfr) {
+    __shared__ CfrPath P[256];
+    __shared__ int ok[256];
+    const uint32_t r = blockIdx.x, n = blockIdx.y * 256 + threadIdx.x;
+    const uint32_t nk = (A.flags & 2) ? n_keys_rec(A) : 0;
+    const uint32_t nd = (A.flags & 4) ? A.D.T * A.D.K : 0;
+    const uint32_t total = 1 + nk + nd;
+    const double w = -2.0 * M_PI * cfr_df(n, N, bw);
+    cd hte = {0.0, 0.0}, htm = {0.0, 0.0};
+    for (uint32_t b = 0; b < total; b += 256) {
+        const uint32_t j = b + threadIdx.x;
+        CfrPath pp{};
+        ok[threadIdx.x] = j < total && cfr_path(A, j, r, nk, pp);
+        P[threadIdx.x] = pp;
+        __syncthreads();
+        const uint32_t cnt = min(256u, total - b);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            if (!ok[i]) continue;
+            double sn, cs;
+            sincos(w * P[i].tau, &sn, &cs);
+            const cd e = {cs, sn};
+            const cd a = cdmul(P[i].te, e), c = cdmul(P[i].tm, e);
+            hte.re += a.re;
+            hte.im += a.im;
+            htm.re += c.re;
+            htm.im += c.im;
+        }
+        __syncthreads();
+    }
+    if (n < N) {
+        double *o = cfr + ((size_t)r * N + n) * 4;
+        o[0] = hte.re;
+        o[1] = hte.im;
+        o[2] = htm.re;
+        o[3] = htm.im;
+    }
+}
+
+void launch_tape_cfr(const LaunchArgs &A, double bw, uint32_t N, double *cfr, hipStream_t s) {
+    hipLaunchKernelGGL(k_tape_cfr, dim3(A.D.n_rx, (N + 255) / 256), dim3(256), 0, s, A, bw, N, cfr);
+}
+
+// dL/da_p (as gR + j gI per polarisation) of one path from dL/dH_r:
+// sum over n of dL/dH_r(f_n) exp(+j 2 pi (f_n - f_c) tau_p).
+__device__ __forceinline__ void cfr_path_grad(const double *dldh, uint32_t r, uint32_t N, double bw, double tau,
+                                              cd &gte, cd &gtm) {
+    gte = {0.0, 0.0};
+    gtm = {0.0, 0.0};
+    for (uint32_t n = 0; n < N; ++n) {
+        double sn, cs;
+        sincos(2.0 * M_PI * cfr_df(n, N, bw) * tau, &sn, &cs);
+        const double *g = dldh + ((size_t)r * N + n) * 4;
+        const cd a = cdmul({g[0], g[1]}, {cs, sn}), b = cdmul({g[2], g[3]}, {cs, sn});
+        gte.re += a.re;
+        gte.im += a.im;
+        gtm.re += b.re;
+        gtm.im += b.im;
+    }
+}
+
+// Adjoint rows of one chain a = G prod_m f_m Gamma_m (f_m = sqrt(1 - S_m^2)
+// for specular interactions, S_m for the diffuse end) from E = g conj(G)
+// per polarisation, g = dL/da: dL/dGamma_m = E conj(f_m prod_{n != m} f_n
+// Gamma_n), dL/dS_m = Re(E conj(f'_m Gamma_m prod_{n != m} f_n Gamma_n)).
+template <int KM>
+__device__ __forceinline__ void chain_adjoint_c(int k, const SlotCoef *cf, const bool *diff_end, cd Ete, cd Etm,
+                                                double (*adj)[5]) {
+    double f[KM], fp[KM];
+    cd Fte[KM], Ftm[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        if (m >= k) continue;
+        const double S = cf[m].S;
+        if (diff_end[m]) {
+            f[m] = S;
+            fp[m] = 1.0;
+        } else {
+            f[m] = sqrt(fmax(0.0, 1.0 - S * S));
+            fp[m] = f[m] > 0.0 ? -S / f[m] : 0.0;
+        }
+        Fte[m] = {f[m] * cf[m].te.re, f[m] * cf[m].te.im};
+        Ftm[m] = {f[m] * cf[m].tm.re, f[m] * cf[m].tm.im};
+    }
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        if (m >= k) continue;
+        cd Pte = {1.0, 0.0}, Ptm = {1.0, 0.0};
+#pragma unroll
+        for (int n = 0; n < KM; ++n) {
+            if (n >= k || n == m) continue;
+            Pte = cdmul(Pte, Fte[n]);
+            Ptm = cdmul(Ptm, Ftm[n]);
+        }
+        const cd gte = cdmul(Ete, cdconj({f[m] * Pte.re, f[m] * Pte.im}));
+        const cd gtm = cdmul(Etm, cdconj({f[m] * Ptm.re, f[m] * Ptm.im}));
+        adj[m][0] += gte.re;
+        adj[m][1] += gte.im;
+        adj[m][2] += gtm.re;
+        adj[m][3] += gtm.im;
+        const cd qte = cdmul({fp[m] * cf[m].te.re, fp[m] * cf[m].te.im}, Pte);
+        const cd qtm = cdmul({fp[m] * cf[m].tm.re, fp[m] * cf[m].tm.im}, Ptm);
+        adj[m][4] += cdmul(Ete, cdconj(qte)).re + cdmul(Etm, cdconj(qtm)).re;
+    }
+}
+
+// Traced-interaction slots: one thread per ray, all of its diffuse paths.
+template <int KM>
+__global__ __launch_bounds__(256) void k_tape_cfr_adjoint_trace(LaunchArgs A, double bw, uint32_t N,
+                                                                const double *dldh) {
+    const uint32_t K = A.D.K, n_rx = A.D.n_rx;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < A.D.T; g += gridDim.x * blockDim.x) {
+        double adj[KM][5];
+#pragma unroll
+        for (int m = 0; m < KM; ++m)
+            for (int a = 0; a < 5; ++a) adj[m][a] = 0.0;
+        if (A.flags & 4) {
+            const float budget = (float)A.items[0].budget;
+            SlotCoef cf[KM];
+            bool de[KM];
+#pragma unroll
+            for (int m = 0; m < KM; ++m)
+                if (m < (int)K) cf[m] = load_coef(A.slot_coef, (size_t)g * K + m);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (k >= (int)K) continue;
+                const uint32_t ri = g * K + k;
+                if (A.rb.id[ri] < 0) continue;
+                cd Ete = {0.0, 0.0}, Etm = {0.0, 0.0};
+                bool any = false;
+                for (uint32_t r = 0; r < n_rx; ++r) {
+                    if (!A.dvis[(size_t)ri * n_rx + r]) continue;
+                    float a0, plen;
+                    diffuse_geom(A, ri, mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]), budget, a0, plen);
+                    const c32 ph = propagate(plen, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+                    const cd G = {(double)a0 * ph.re, (double)a0 * ph.im};
+                    cd gte, gtm;
+                    cfr_path_grad(dldh, r, N, bw, (double)plen / kC0, gte, gtm);
+                    const cd ete = cdmul(gte, cdconj(G)), etm = cdmul(gtm, cdconj(G));
+                    Ete.re += ete.re;
+                    Ete.im += ete.im;
+                    Etm.re += etm.re;
+                    Etm.im += etm.im;
+                    any = true;
+                }
+                if (!any) continue;
+#pragma unroll
+                for (int m = 0; m < KM; ++m) de[m] = (m == k);
+                chain_adjoint_c<KM>(k + 1, cf, de, Ete, Etm, adj);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < KM; ++m) {
+            if (m >= (int)K) continue;
+            float4 *o = (float4 *)(A.slot_adj + 8 * ((size_t)g * K + m));
+            o[0] = make_float4((float)adj[m][0], (float)adj[m][1], (float)adj[m][2], (float)adj[m][3]);
+            o[1] = make_float4((float)adj[m][4], 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+// Specular-path slots: one thread per (key, RX) pair.
+template <int KM>
+__global__ __launch_bounds__(256) void k_tape_cfr_adjoint_spec(LaunchArgs A, double bw, uint32_t N,
+                                                               const double *dldh) {
+    const uint32_t K = A.D.K, n_rx = A.D.n_rx, TK = A.D.T * A.D.K;
+    const uint32_t nk = n_keys_rec(A);
+    const size_t n_pairs = (size_t)A.D.rec_keys * n_rx;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n_pairs; p += (size_t)gridDim.x * blockDim.x) {
+        double adj[KM][5];
+#pragma unroll
+        for (int m = 0; m < KM; ++m)
+            for (int a = 0; a < 5; ++a) adj[m][a] = 0.0;
+        const uint32_t q = (uint32_t)(p / n_rx), r = (uint32_t)(p % n_rx);
+        if ((A.flags & 2) && q < nk && A.sb.valid[p]) {
+            const uint32_t k = A.keylist[q] % K + 1;
+            SlotCoef cf[KM];
+            bool de[KM];
+#pragma unroll
+            for (int m = 0; m < KM; ++m) {
+                de[m] = false;
+                if (m < (int)k) cf[m] = load_coef(A.slot_coef, TK + p * K + m);
+            }
+            const float L = A.sb.len[p];
+            const float a0 = A.fc.amp_iso / L;
+            const c32 ph = propagate(L, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+            const cd G = {(double)a0 * ph.re, (double)a0 * ph.im};
+            cd gte, gtm;
+            cfr_path_grad(dldh, r, N, bw, (double)L / kC0, gte, gtm);
+            chain_adjoint_c<KM>((int)k, cf, de, cdmul(gte, cdconj(G)), cdmul(gtm, cdconj(G)), adj);
+        }
+#pragma unroll
+        for (int m = 0; m < KM; ++m) {
+            if (m >= (int)K) continue;
+            float4 *o = (float4 *)(A.slot_adj + 8 * (TK + p * K + m));
+            o[0] = make_float4((float)adj[m][0], (float)adj[m][1], (float)adj[m][2], (float)adj[m][3]);
+            o[1] = make_float4((float)adj[m][4], 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+void launch_tape_cfr_backward(const LaunchArgs &A, double bw, uint32_t N, const double *dldh, hipStream_t s) {
+    const uint32_t gt = std::min<uint32_t>((A.D.T + 255) / 256, 4096);
+    const size_t np = (size_t)A.D.rec_keys * A.D.n_rx;
+    const uint32_t gs = (uint32_t)std::min<size_t>((np + 255) / 256, 4096);
+    switch (A.D.K) {
+#define PCRT_TC_CASE(KK)                                                                                       \
+    case KK:                                                                                                   \
+        hipLaunchKernelGGL(k_tape_cfr_adjoint_trace<KK>, dim3(std::max<uint32_t>(gt, 1)), dim3(256), 0, s, A, bw, N, \
+                           dldh);                                                                              \
+        hipLaunchKernelGGL(k_tape_cfr_adjoint_spec<KK>, dim3(std::max<uint32_t>(gs, 1)), dim3(256), 0, s, A, bw, N, \
+                           dldh);                                                                              \
+        break;
+        PCRT_TC_CASE(1)
+        PCRT_TC_CASE(2)
+        PCRT_TC_CASE(3)
+        PCRT_TC_CASE(4)
+        PCRT_TC_CASE(5)
+        PCRT_TC_CASE(6)
+        PCRT_TC_CASE(7)
+        PCRT_TC_CASE(8)
+#undef PCRT_TC_CASE
+        default: break;
+    }
+}
+
 // Per-label gradient: for each slot, dL/d(eps_r, sigma) = Re(conj(g) dGamma/deta deta/dtheta)
 // summed over TE and TM (deta/deps_r = 1, deta/dsigma = -j/(omega eps0)), and
 // dL/dS = g_S. One 64-lane block per slot chunk; lane t owns an LDS row of

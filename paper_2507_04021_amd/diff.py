@@ -11,7 +11,7 @@ from __future__ import annotations
 import torch
 
 from . import (DIFFUSE, LOS, RECORD, SPECULAR, SolveResult, material_grad, materials_tensor, solve,
-               tape_backward, tape_forward, tape_fresnel)
+               tape_backward, tape_cfr, tape_cfr_backward, tape_forward, tape_fresnel)
 
 
 def record(scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR | DIFFUSE, **kw) -> SolveResult:
@@ -48,3 +48,36 @@ def gains(mats: torch.Tensor, rec: SolveResult) -> torch.Tensor:
 def db_mse_loss(g: torch.Tensor, target_db: torch.Tensor) -> torch.Tensor:
     """Mean over receivers of (10 log10 G_r - T_r)^2."""
     return torch.mean((10.0 * torch.log10(g) - target_db) ** 2)
+
+
+class MaterialCfr(torch.autograd.Function):
+    """Channel frequency response H(materials) on a recorded tape: input
+    (n_labels, 3) tensor of (eps_r, sigma, S); output complex128
+    [n_rx, n_freq, 2] (TE, TM) over bandwidth_hz around the solve's
+    frequency."""
+
+    @staticmethod
+    def forward(ctx, mats, rec, bandwidth_hz, n_freq):
+        m = tape_fresnel(rec, mats.detach())
+        h = tape_cfr(rec, bandwidth_hz, n_freq)
+        ctx.rec, ctx.mats_dev, ctx.bw, ctx.n = rec, m, bandwidth_hz, n_freq
+        ctx.shape, ctx.dtype, ctx.device = mats.shape, mats.dtype, mats.device
+        return h
+
+    @staticmethod
+    def backward(ctx, grad_h):
+        # for a real loss torch hands over dL/dRe + j dL/dIm of each sample
+        tape_cfr_backward(ctx.rec, ctx.bw, ctx.n, grad_h.detach())
+        gm = material_grad(ctx.rec, ctx.mats_dev)
+        return gm.to(device=ctx.device, dtype=ctx.dtype).reshape(ctx.shape), None, None, None
+
+
+def cfr(mats: torch.Tensor, rec: SolveResult, bandwidth_hz: float = 1.5e9, n_freq: int = 129) -> torch.Tensor:
+    return MaterialCfr.apply(mats, rec, bandwidth_hz, n_freq)
+
+
+def cir_loss(h: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """|h - h_hat|^2 / |h_hat|^2 (Eq. 5) of the impulse responses, evaluated on
+    the frequency samples: the inverse DFT is unitary up to one scale, which
+    cancels in the ratio (Parseval), so both polarisations' CFRs give it."""
+    return torch.sum(torch.abs(h - target) ** 2) / torch.sum(torch.abs(target) ** 2)
