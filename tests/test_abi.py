@@ -52,6 +52,10 @@ def test_scene_argument_errors(L):
     assert b"n_points" in L.pcrt_last_error()
     assert L.pcrt_scene_workspace_size(10, None, None) == EINVAL
     assert L.pcrt_scene_workspace_size(1 << 28, None, ctypes.byref(nb)) == EUNSUPPORTED
+    # node and disk arrays are addressed with 32-bit byte offsets: at most 2^26 points
+    assert L.pcrt_scene_workspace_size((1 << 26) + 1, None, ctypes.byref(nb)) == EUNSUPPORTED
+    assert b"2^26" in L.pcrt_last_error()
+    assert L.pcrt_scene_workspace_size(1 << 26, None, ctypes.byref(nb)) == 0
     assert L.pcrt_scene_workspace_size(1000, None, ctypes.byref(nb)) == 0 and nb.value > 1000 * 64
     o = P.BvhOpts(4, 2, 1)
     assert L.pcrt_scene_workspace_size(1000, ctypes.byref(o), ctypes.byref(nb)) == 0
@@ -104,6 +108,8 @@ def test_solve_argument_errors(L):
     ms = (ctypes.c_double * 6)()
     assert L.pcrt_stage_times(ms, 6) == EINVAL
     assert L.pcrt_scene_get_info(None, None) == EINVAL
+    assert L.pcrt_tape_cfr(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
+    assert L.pcrt_tape_cfr_backward(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
     assert L.pcrt_last_error()  # an explanation is always set on failure
 
 
