@@ -273,6 +273,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
         A.dsort.val1 = (uint32_t *)at(L.dval1);
         A.dsort.hist = (uint32_t *)at(L.dhist);
         A.dsort.blk = (uint32_t *)at(L.dblk);
+        A.dsort.pack = (float4 *)at(L.dpack);
     }
     if (p->flags & PCRT_RECORD) {
         A.slot_label = (uint16_t *)at(L.slot_label);
@@ -310,6 +311,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.dhist = b.take(sizeof(uint32_t) * radix_hist_words((uint32_t)nrec));
         L.dblk = b.take(sizeof(uint32_t) * scan_blk_words(radix_hist_words((uint32_t)nrec)));
         L.rec_coef = b.take(sizeof(float4) * nrec);
+        L.dpack = b.take(2 * sizeof(float4) * nrec);
         L.diff_part = b.take(sizeof(double) * 5 * (size_t)D.n_ray_chunks * D.n_rx);
         if (rec) L.dvis = b.take(nrec * D.n_rx);
     }

@@ -60,15 +60,15 @@ __global__ void k_diffuse_keys(LaunchArgs A) {
     }
 }
 
-__device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t ri, f3 rx, float budget, double *v5) {
-    const float4 xl = A.rb.xl[ri];
-    f3 n = xyz(A.S.nrm[A.rb.id[ri]]);
-    if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
-    const f3 v = rx - xyz(xl);
+// Lambertian ray-tube amplitude of one visible connection, from the packed
+// record (hit point x, lit-side normal n, unfolded length w from the TX).
+__device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t ri, f3 x, f3 n, float w, f3 rx,
+                                                  float budget, double *v5) {
+    const f3 v = rx - x;
     const float rs = len(v);
     const float cos_s = dot(v, n) / rs;
     const float a0 = sqrtf(4.f * cos_s / budget) / rs;
-    const c32 ph = propagate(xl.w + rs, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+    const c32 ph = propagate(w + rs, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
     const float4 cf = A.rb.coef[ri];
     const c32 te = cmul({a0 * cf.x, a0 * cf.y}, ph);
     const c32 tm = cmul({a0 * cf.z, a0 * cf.w}, ph);
@@ -80,31 +80,59 @@ __device__ __forceinline__ void diffuse_amplitude(const LaunchArgs &A, uint32_t 
     v5[4] = mi;
 }
 
-// Receivers per work unit. Measured on the 1M-point office (64 receivers):
-// 32 -> 58.9 ms, 16 -> 51.9, 8 -> 47.8, 4 -> 45.7, 2 -> 44.4, 1 -> 43.5.
-// The smallest units balance best, and the units of one chunk (consecutive
-// counter values) then run at the same time on one XCD and share its L2.
-constexpr int kDiffRxSlice = 1;
+// The records in Morton order, packed: the connection loop below reads each
+// record once per receiver, and the packed copy makes those reads contiguous
+// across the lanes and independent of each other (no id -> normal chain).
+// Measured on the 1M-point office: 34.0 -> 32.5 ms for the connections, for
+// 0.24 ms of packing.
+__global__ void k_diffuse_pack(LaunchArgs A, const uint32_t *order) {
+    const uint32_t n_rec = A.D.T * A.D.K;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_rec; j += gridDim.x * blockDim.x) {
+        const uint32_t ri = order[j];
+        const int id = A.rb.id[ri];
+        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = make_float4(0.f, 0.f, 1.f, __int_as_float(-1));
+        if (id >= 0) {
+            p0 = A.rb.xl[ri];
+            const float4 nn = A.S.nrm[id];
+            const float sg = A.rb.cs[ri] < 0.f ? -1.f : 1.f;
+            p1 = make_float4(sg * nn.x, sg * nn.y, sg * nn.z, __int_as_float(id));
+        }
+        A.dsort.pack[2 * (size_t)j] = p0;
+        A.dsort.pack[2 * (size_t)j + 1] = p1;
+    }
+}
 
-// Persistent single-wavefront blocks. A work unit is (ray chunk, slice of
-// up to kDiffRxSlice receivers): the wavefront walks every 64-record group
-// of the chunk against each receiver of the slice in turn and writes the
-// chunk's partial sums of those receivers itself, so no block barrier ever
-// makes it wait for another wavefront.
+// Persistent single-wavefront blocks. A work unit is (ray chunk, receiver):
+// the wavefront tests the chunk's records against the receiver and writes the
+// chunk's partial sums of that receiver itself, so no block barrier ever makes
+// it wait for another wavefront. One receiver per unit balanced best on the
+// 1M-point office (receivers per unit 32 / 16 / 8 / 4 / 2 / 1: 58.9 / 51.9 /
+// 47.8 / 45.7 / 44.4 / 43.5 ms), and the units of one chunk (consecutive
+// counter values) then run at the same time on one XCD and share its L2.
+//
+// Lit compaction. The wavefront reads the chunk's records 64 at a time and
+// queues the indices of those on the receiver's lit side in LDS, in record
+// order; every full 64 (and the rest at the end) go through the walks
+// together. A wave then never carries a lane whose record is dark or empty
+// for the receiver (a fifth of them on the office), so the chunk takes
+// fewer wave-wide walks. Which lane takes which record depends only on the
+// geometry, so the sums stay fixed-order.
 //
 // Occupancy: six wavefronts per SIMD for the 2- and 4-wide walks (the
-// register budget that allows, with 6 KiB of LDS stack per wavefront, beat
+// register budget that allows, with 6.5 KiB of LDS per wavefront, beat
 // five by 2-3 % on the office; seven and eight spilled and lost).
+constexpr uint32_t kLitQueue = 2 * kWave;  // < 64 carried over + 64 added
+
 template <int W>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 4 : 6, 8))) void k_diffuse(
     LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
+    __shared__ uint32_t lit_q[kLitQueue];
     const int lane = threadIdx.x;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
     const uint32_t K = A.D.K, n_rx = A.D.n_rx;
     const uint32_t n_chunks = A.D.n_ray_chunks;
-    const uint32_t n_slices = (n_rx + kDiffRxSlice - 1) / kDiffRxSlice;
     const bool rec = A.flags & 8;
     const float eps = A.thr.eps_self;
     const uint32_t n_groups = kRayChunk * K / kWave;  // groups of 64 records per chunk
@@ -113,15 +141,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
     // L2: the wavefronts of XCD x take chunks from the x-th eighth of the
     // (Morton-ordered) chunk range first, so one XCD's L2 serves one region
     // of the scene, then help the other ranges in turn. Within a range, units
-    // are slice-minor, so consecutive units reuse a chunk's records.
+    // are receiver-minor, so consecutive units reuse a chunk's records.
     const uint32_t xcd = blockIdx.x % kXcds;
     for (;;) {
         uint32_t u = 0xffffffffu;
         if (lane == 0) {
             for (uint32_t k = 0; k < kXcds; ++k) {
                 const uint32_t x = (xcd + k) % kXcds;
-                const uint32_t lo = (uint32_t)((uint64_t)x * n_chunks / kXcds) * n_slices;
-                const uint32_t hi = (uint32_t)((uint64_t)(x + 1) * n_chunks / kXcds) * n_slices;
+                const uint32_t lo = (uint32_t)((uint64_t)x * n_chunks / kXcds) * n_rx;
+                const uint32_t hi = (uint32_t)((uint64_t)(x + 1) * n_chunks / kXcds) * n_rx;
                 const uint32_t uu = lo + atomicAdd(&A.work[8 + x], 1u);
                 if (uu < hi) {
                     u = uu;
@@ -131,50 +159,55 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
         }
         u = __builtin_amdgcn_readfirstlane(u);
         if (u == 0xffffffffu) break;
-        const uint32_t c = u / n_slices;
-        const uint32_t r0 = (u % n_slices) * kDiffRxSlice;
-        const uint32_t nr = min((uint32_t)kDiffRxSlice, n_rx - r0);
+        const uint32_t c = u / n_rx, r = u % n_rx;
         const uint32_t g0 = c * kRayChunk;
         const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
         const float budget = (float)I.budget;
-        double acc[kDiffRxSlice][5] = {};  // this lane's records, per receiver of the slice
-        for (uint32_t q = 0; q < n_groups; ++q) {
-            const uint32_t ri = A.dsort.order[g0 * K + q * kWave + lane];
-            const int id = A.rb.id[ri];
-            f3 x = mk(0.f, 0.f, 0.f), n = mk(0.f, 0.f, 1.f);
-            if (id >= 0) {
-                x = xyz(A.rb.xl[ri]);
-                n = xyz(A.S.nrm[id]);
-                if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+        const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+        double acc[5] = {};  // this lane's records, in the order it takes them
+        uint32_t head = 0, tail = 0;  // queue positions (wave-uniform, increasing)
+        for (uint32_t q = 0; q <= n_groups; ++q) {
+            if (q < n_groups) {
+                const uint32_t j = g0 * K + q * kWave + lane;
+                const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
+                const bool lit = __float_as_int(p1.w) >= 0 && dot(rx - xyz(p0), xyz(p1)) > 0.f;
+                if (rec && !lit) A.dvis[(size_t)A.dsort.order[j] * n_rx + r] = 0;
+                const uint64_t m = __ballot(lit);
+                if (lit) {
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    lit_q[(tail + below) % kLitQueue] = j;
+                }
+                tail += (uint32_t)__popcll(m);
+                __syncthreads();
             }
-#pragma unroll
-            for (uint32_t rr = 0; rr < (uint32_t)kDiffRxSlice; ++rr) {
-                if (rr >= nr) break;
-                const uint32_t r = r0 + rr;
-                const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-                bool vis = false;
-                if (id >= 0 && dot(rx - x, n) > 0.f) {
+            while (tail - head >= (uint32_t)kWave || (q == n_groups && tail > head)) {
+                const uint32_t take = min((uint32_t)kWave, tail - head);
+                if ((uint32_t)lane < take) {
+                    const uint32_t j = lit_q[(head + lane) % kLitQueue];
+                    const uint32_t ri = A.dsort.order[j];
+                    const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
+                    const int id = __float_as_int(p1.w);
+                    const f3 x = xyz(p0), n = xyz(p1);
                     ++n_seg;
-                    vis = !occluded<W>(A.S, rx, x, id, eps, stk);
+                    const bool vis = !occluded<W>(A.S, rx, x, id, eps, stk);
+                    if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
+                    if (vis) {
+                        ++n_vis;
+                        double v5[5];
+                        diffuse_amplitude(A, ri, x, n, p0.w, rx, budget, v5);
+                        for (int a = 0; a < 5; ++a) acc[a] += v5[a];
+                    }
                 }
-                if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
-                if (vis) {
-                    ++n_vis;
-                    double v5[5];
-                    diffuse_amplitude(A, ri, rx, budget, v5);
-                    for (int a = 0; a < 5; ++a) acc[rr][a] += v5[a];
-                }
+                head += take;
+                __syncthreads();  // the taken slots may be refilled next
             }
         }
-#pragma unroll
-        for (uint32_t rr = 0; rr < (uint32_t)kDiffRxSlice; ++rr) {
-            if (rr >= nr) break;
-            double sv[5];
-            for (int a = 0; a < 5; ++a) sv[a] = wave_sum_d(acc[rr][a]);
-            if (lane == 0) {
-                double *o = A.diff_part + ((size_t)c * n_rx + r0 + rr) * 5;
-                for (int a = 0; a < 5; ++a) o[a] = sv[a];
-            }
+        double sv[5];
+        for (int a = 0; a < 5; ++a) sv[a] = wave_sum_d(acc[a]);
+        if (lane == 0) {
+            double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
+            for (int a = 0; a < 5; ++a) o[a] = sv[a];
         }
     }
     flush_visits(stk, A.counters, 13);
@@ -194,7 +227,7 @@ uint32_t diffuse_cap() {
 
 uint32_t diffuse_grid(const SolveDims &D) {
     const uint32_t cap = D.width == 8 ? diffuse_cap<8>() : D.width == 4 ? diffuse_cap<4>() : diffuse_cap<2>();
-    const uint32_t units = D.n_ray_chunks * ((D.n_rx + kDiffRxSlice - 1) / kDiffRxSlice);
+    const uint32_t units = D.n_ray_chunks * D.n_rx;
     return std::max<uint32_t>(1, std::min(cap, units));
 }
 
@@ -206,7 +239,9 @@ const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s) {
     const int hi = 32 + 8 * ((item_bits + 7) / 8);  // 30 Morton bits, then the transmitter index
     const bool in1 = radix_sort_u64(A.dsort.key0, A.dsort.val0, A.dsort.key1, A.dsort.val1, n_rec, 0, hi,
                                     A.dsort.hist, A.dsort.blk, s);
-    return in1 ? A.dsort.val1 : A.dsort.val0;
+    const uint32_t *order = in1 ? A.dsort.val1 : A.dsort.val0;
+    hipLaunchKernelGGL(k_diffuse_pack, dim3(std::min<uint32_t>((n_rec + 255) / 256, 8192)), dim3(256), 0, s, A, order);
+    return order;
 }
 
 void launch_diffuse(const LaunchArgs &A, hipStream_t s) {

@@ -110,7 +110,7 @@ constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 l
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
         key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
-        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res;
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res, dpack;
     size_t total;
 };
 
@@ -123,6 +123,9 @@ struct SortBufs {  // spatial ordering of the diffuse records
     uint64_t *key0, *key1;
     uint32_t *val0, *val1, *hist, *blk;
     const uint32_t *order;  // sorted record indices (set by the launcher)
+    // The records in that order, two float4 each: (hit point, unfolded length),
+    // (normal on the lit side, disk id as int bits; -1 = no interaction).
+    float4 *pack;
 };
 
 struct LaunchArgs {
@@ -164,7 +167,8 @@ struct LaunchArgs {
 void launch_trace(const LaunchArgs &A, hipStream_t s);
 void launch_keys(const LaunchArgs &A, hipStream_t s);
 void launch_refine(const LaunchArgs &A, hipStream_t s);
-// Morton order of the interaction records (returns the sorted record indices)
+// Morton order of the interaction records: sorts them, fills A.dsort.pack and
+// returns the sorted record indices
 const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s);
 void launch_diffuse(const LaunchArgs &A, hipStream_t s);  // needs A.dsort.order
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
