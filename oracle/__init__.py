@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcrt_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-LOS, SPECULAR, DIFFUSE, TRACE = 1, 2, 4, 8
+LOS, SPECULAR, DIFFUSE, TRACE, AVERAGE = 1, 2, 4, 8, 16
 DEFAULT_THR = dict(eps_tie=1e-4, eps_self=1e-3, t_a_deg=1.0, t_d=0.01, kappa=10)
 C0 = 299792458.0
 
@@ -97,6 +97,25 @@ def nearest(scene, o, d, excl=None, t_lo=1e-3, t_hi=np.inf, eps_tie=1e-4):
     return oid, ot, oq
 
 
+def average(scene, o, d, rho, lambda_d, excl=None, eps_self=1e-3, eps_tie=1e-4):
+    """Nearest disk, then the weighted average over its point set (voxel edge rho).
+    Returns (id int64[n], t float64[n], normal float64[n, 3] facing the ray)."""
+    o = np.ascontiguousarray(o, np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    excl = np.full(n, -1, np.int64) if excl is None else np.ascontiguousarray(excl, np.int64)
+    oid = np.empty(n, np.int64)
+    ot = np.empty(n, np.float64)
+    on = np.empty((n, 3), np.float64)
+    rc = _load().orc_average_batch(ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal), _radius(scene),
+                                   ctypes.c_double(float(np.float32(rho))), ctypes.c_double(lambda_d),
+                                   ctypes.c_int64(n), _p(o), _p(d), _p(excl), ctypes.c_double(eps_self),
+                                   ctypes.c_double(eps_tie), _p(oid), _p(ot), _p(on))
+    if rc:
+        raise ValueError("oracle average: bad scene (%d)" % rc)
+    return oid, ot, on
+
+
 def occluded(scene, a, b, excl=None, eps_self=1e-3):
     a = np.ascontiguousarray(a, np.float64).reshape(-1, 3)
     b = np.ascontiguousarray(b, np.float64).reshape(-1, 3)
@@ -141,8 +160,11 @@ class Solution:
 
 
 def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SPECULAR,
-          thr=None, want_dvis=False, want_jac=False, cfr=None) -> Solution:
+          thr=None, want_dvis=False, want_jac=False, cfr=None, average=None) -> Solution:
     """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S).
+
+    average = (rho, lambda_d): every interaction is the weighted average over
+    the intersected disks of the hit disk's point set (voxels of edge rho).
 
     cfr = (bandwidth_hz, n_freq): also the channel frequency response, every
     path's centre-frequency amplitudes times exp(-j 2 pi (f_n - freq) L / c0)
@@ -150,7 +172,10 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     th = dict(DEFAULT_THR)
     if thr:
         th.update(thr)
-    thr_arr = np.array([th["eps_tie"], th["eps_self"], th["t_a_deg"], th["t_d"], th["kappa"]], np.float64)
+    rho, lam = (float(np.float32(average[0])), float(average[1])) if average else (0.0, 0.0)
+    if average:
+        flags |= AVERAGE
+    thr_arr = np.array([th["eps_tie"], th["eps_self"], th["t_a_deg"], th["t_d"], th["kappa"], rho, lam], np.float64)
     mats = np.ascontiguousarray(mats, np.float64).reshape(-1, 3)
     n_labels = mats.shape[0]
     eps_r = np.ascontiguousarray(mats[:, 0])
@@ -196,11 +221,11 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
                     jac, (ocfr[..., 0::2] + 1j * ocfr[..., 1::2]) if cfr else None)
 
 
-def trace(scene, tx, n_budget, ray_ids=None, K=2, thr=None):
+def trace(scene, tx, n_budget, ray_ids=None, K=2, thr=None, average=None):
     """Interaction sequences (int64[n, K]) and records (x, y, z, L, cos) only."""
     n_labels = int(np.max(scene.material)) + 1
     sol = solve(scene, np.ones((n_labels, 3)), tx, np.zeros((0, 3), np.float32), 1e9, n_budget, ray_ids=ray_ids,
-                K=K, flags=TRACE, thr=thr)
+                K=K, flags=TRACE, thr=thr, average=average)
     return sol.seq, sol.rec
 
 

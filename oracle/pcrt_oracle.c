@@ -11,6 +11,9 @@
  *   - Input: augmented point cloud (position, normal, surface label, material
  *     label per point), TX and RX positions (Sec. II, opening paragraph).
  *   - Each point is a planar disk of radius r_p (Sec. II-C).
+ *   - Optionally, the points are grouped into voxels of edge rho (Sec. II-A)
+ *     and an interaction is the weighted average over the intersected disks
+ *     of the hit disk's voxel (Sec. II-C, Eq. 3-4).
  *   - Rays keep a constant count; every interaction continues as a specular
  *     reflection (Sec. II-B).
  *   - Diffuse scattering is the last interaction, validated by a ray from the
@@ -39,7 +42,8 @@
 #define ORC_PI 3.14159265358979323846
 #define ORC_KMAX 8
 
-enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4, ORC_TRACE = 8 /* trace even without paths */ };
+enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4, ORC_TRACE = 8 /* trace even without paths */,
+       ORC_AVERAGE = 16 /* weighted-average intersection over point sets */ };
 
 typedef struct {
     int64_t n;
@@ -189,6 +193,102 @@ static int occluded(const scene_t *s, const double *a, const double *b, int64_t 
     return 0;
 }
 
+/* ------------------------------------ discretised point sets (Sec. II-A) */
+/* The points are grouped by the voxel of edge rho that holds their centre:
+ * voxel = floor(p / rho) per axis, both in FP64 from the FP32 inputs. Each
+ * non-empty voxel is one point set. */
+typedef struct {
+    int64_t *of;  /* [n] set of each point */
+    int64_t *off; /* [n_sets + 1] first member of each set in mem */
+    int64_t *mem; /* [n] point indices grouped by set, ascending inside a set */
+    int64_t n_sets;
+} dps_t;
+
+typedef struct {
+    int64_t v[3], i;
+} vox_t;
+
+static int vox_cmp(const void *pa, const void *pb)
+{
+    const vox_t *a = (const vox_t *)pa, *b = (const vox_t *)pb;
+    for (int c = 0; c < 3; ++c)
+        if (a->v[c] != b->v[c]) return a->v[c] < b->v[c] ? -1 : 1;
+    return a->i < b->i ? -1 : (a->i > b->i);
+}
+
+static int dps_build(dps_t *g, const scene_t *s, double rho)
+{
+    int64_t n = s->n;
+    vox_t *v = (vox_t *)malloc(sizeof(vox_t) * (size_t)(n > 0 ? n : 1));
+    g->of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    g->off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    g->mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!v || !g->of || !g->off || !g->mem) { free(v); return -2; }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) v[i].v[c] = (int64_t)floor(s->p[3 * i + c] / rho);
+        v[i].i = i;
+    }
+    qsort(v, (size_t)n, sizeof(vox_t), vox_cmp);
+    g->n_sets = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == 0 || memcmp(v[j].v, v[j - 1].v, sizeof v[j].v)) g->off[g->n_sets++] = j;
+        g->mem[j] = v[j].i;
+        g->of[v[j].i] = g->n_sets - 1;
+    }
+    g->off[g->n_sets] = n;
+    free(v);
+    return 0;
+}
+
+static void dps_free(dps_t *g)
+{
+    free(g->of);
+    free(g->off);
+    free(g->mem);
+}
+
+/* Weighted-average intersection (Sec. II-C, Eq. 3-4). The averaging set is
+ * every disk of the hit disk's point set that the ray meets farther than
+ * eps_self from its origin (the excluded disk aside). Each member i has the
+ * weight
+ *   w_i = exp(-|q_i - p_i|^2 / (2 r^2)) * exp(-lambda_d |q_i - q_min|),
+ * q_min being the member intersection nearest to the origin; the point is the
+ * w-weighted mean of the q_i. All q_i lie on the ray, so the point is
+ * o + t d with t the weighted mean of the t_i. The normal used to reflect is
+ * the w-weighted sum of the member normals, each turned to face the incoming
+ * ray, normalised. */
+static void dps_average(const scene_t *s, const dps_t *g, const double *o, const double *d, int64_t excl,
+                        double eps_self, int64_t h, double lambda_d, double *t_out, double *n_out)
+{
+    const int64_t set = g->of[h], b = g->off[set], e = g->off[set + 1];
+    double t, q[3], d2, tmin = INFINITY, qmin[3] = {0, 0, 0};
+    for (int64_t j = b; j < e; ++j) {
+        int64_t i = g->mem[j];
+        if (i == excl) continue;
+        if (ray_disk(s, i, o, d, &t, q, &d2) && t > eps_self && t < tmin) {
+            tmin = t;
+            copy3(qmin, q);
+        }
+    }
+    double sw = 0.0, st = 0.0, sn[3] = {0, 0, 0};
+    for (int64_t j = b; j < e; ++j) {
+        int64_t i = g->mem[j];
+        if (i == excl) continue;
+        if (!(ray_disk(s, i, o, d, &t, q, &d2) && t > eps_self)) continue;
+        double dq[3];
+        sub3(dq, q, qmin);
+        double w = exp(-d2 / (2.0 * s->r * s->r)) * exp(-lambda_d * norm3(dq));
+        const double *n = s->nr + 3 * i;
+        double side = dot3(d, n) > 0.0 ? -1.0 : 1.0;
+        sw += w;
+        st += w * t;
+        for (int c = 0; c < 3; ++c) sn[c] += w * side * n[c];
+    }
+    *t_out = st / sw;
+    scale3(sn, 1.0 / norm3(sn));
+    copy3(n_out, sn);
+}
+
 /* --------------------------------------------------------- Fresnel (field) */
 /* eta = eps_r - j sigma/(omega eps0) (time convention e^{+j omega t});
  * w = sqrt(eta - sin^2) (principal branch);
@@ -306,7 +406,7 @@ typedef struct {
 /* Every interaction is treated as a specular reflection and the ray count stays
  * constant (Sec. II-B). A miss ends the ray. */
 static void trace_ray(const scene_t *s, const double *tx, const float *dir32, int K, const thr_t *th,
-                      trace_t *tr)
+                      const dps_t *g, double lambda_d, trace_t *tr)
 {
     double o[3], d[3];
     copy3(o, tx);
@@ -322,6 +422,10 @@ static void trace_ray(const scene_t *s, const double *tx, const float *dir32, in
         double n[3];
         copy3(n, s->nr + 3 * h);
         if (dot3(d, n) > 0.0) scale3(n, -1.0);
+        if (g) { /* the point set's weighted average replaces the nearest disk's point and normal */
+            dps_average(s, g, o, d, excl, th->eps_self, h, lambda_d, &t, n);
+            for (int c = 0; c < 3; ++c) q[c] = o[c] + t * d[c];
+        }
         L += t;
         tr->id[k] = h;
         copy3(tr->x[k], q);
@@ -478,6 +582,36 @@ int orc_occluded_batch(int64_t n_pts, const float *pos, const float *nrm, double
     return 0;
 }
 
+/* Nearest hit followed by the point-set average (Eq. 3-4) for a batch of
+ * queries: out_id = nearest disk (-1: miss), out_t = averaged distance,
+ * out_n = averaged normal facing the incoming ray. */
+int orc_average_batch(int64_t n_pts, const float *pos, const float *nrm, double r, double rho, double lambda_d,
+                      int64_t n_q, const double *o, const double *d, const int64_t *excl, double eps_self,
+                      double eps_tie, int64_t *out_id, double *out_t, double *out_n)
+{
+    scene_t s;
+    int rc = scene_init(&s, n_pts, pos, nrm, NULL, NULL, r);
+    if (rc) { scene_free(&s); return rc; }
+    dps_t g;
+    if (dps_build(&g, &s, rho)) { scene_free(&s); return -2; }
+    for (int64_t k = 0; k < n_q; ++k) {
+        double dd[3], t, q[3];
+        copy3(dd, d + 3 * k);
+        scale3(dd, 1.0 / norm3(dd));
+        int64_t h = nearest(&s, o + 3 * k, dd, excl[k], eps_self, INFINITY, eps_tie, &t, q);
+        out_id[k] = h;
+        if (h < 0) {
+            out_t[k] = NAN;
+            for (int c = 0; c < 3; ++c) out_n[3 * k + c] = NAN;
+            continue;
+        }
+        dps_average(&s, &g, o + 3 * k, dd, excl[k], eps_self, h, lambda_d, &out_t[k], out_n + 3 * k);
+    }
+    dps_free(&g);
+    scene_free(&s);
+    return 0;
+}
+
 /* ------------------------------------------------------------- full solve */
 typedef struct {
     int len;
@@ -501,7 +635,9 @@ static int key_cmp(const void *pa, const void *pb)
  * n_budget Fibonacci directions (the diffuse ray-tube weight always uses the
  * full budget).
  *
- * thr[5] = {eps_tie, eps_self, t_a (degrees), t_d, kappa}.
+ * thr[7] = {eps_tie, eps_self, t_a (degrees), t_d, kappa, rho, lambda_d}; rho
+ * (voxel edge of the point sets) and lambda_d (depth attenuation) are read
+ * with ORC_AVERAGE only.
  *
  * Outputs (NULL = not wanted):
  *   seq      int64[n_trace*K]   hit disk per (ray, k), -1 after the ray ends
@@ -531,6 +667,12 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     for (int64_t i = 0; i < n_pts; ++i)
         if (mat[i] >= (uint32_t)n_labels) { scene_free(&s); return -1; }
     thr_t th = {thr[0], thr[1], cos(thr[2] * ORC_PI / 180.0), thr[3], (int)thr[4]};
+    dps_t dps, *g = NULL;
+    if (flags & ORC_AVERAGE) {
+        if (!(thr[5] > 0.0) || !(thr[6] > 0.0)) { scene_free(&s); return -1; }
+        if (dps_build(&dps, &s, thr[5])) { scene_free(&s); return -2; }
+        g = &dps;
+    }
     em_t em = {n_labels, eps_r, sigma, scat, freq, 2.0 * ORC_PI * freq, ORC_C0 / freq, 0.0};
     em.k0 = 2.0 * ORC_PI / em.lambda;
     const double a_iso = em.lambda / (4.0 * ORC_PI);
@@ -568,7 +710,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     orc_fib_dirs(n_budget, ray_ids, n_trace, dirs);
     if (flags & (ORC_SPECULAR | ORC_DIFFUSE | ORC_TRACE)) {
 #pragma omp parallel for schedule(dynamic, 8)
-        for (int64_t q = 0; q < n_trace; ++q) trace_ray(&s, tx, dirs + 3 * q, K, &th, &tr[q]);
+        for (int64_t q = 0; q < n_trace; ++q) trace_ray(&s, tx, dirs + 3 * q, K, &th, g, g ? thr[6] : 0.0, &tr[q]);
     } else {
         for (int64_t q = 0; q < n_trace; ++q) tr[q].n = 0;
     }
@@ -736,6 +878,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
         }
     free(cfr.h);
     free(tr); free(dirs); free(rx); free(G_los); free(G_spec); free(G_diff); free(h_te); free(h_tm);
+    if (g) dps_free(g);
     scene_free(&s);
     return ret;
 }

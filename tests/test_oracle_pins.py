@@ -523,3 +523,83 @@ def test_cfr_impulse_response_peaks_at_the_path_delays(orc):
     top = sorted(np.argsort(np.abs(h))[-2:])
     want = sorted(int(round(t * n * bw / (n - 1))) % n for t in taus)
     assert top == want, (top, want)
+
+
+# ------------------------------------- point-set averaging (Sec. II-C, Eq. 3-4)
+RHO, LAM, RP = 0.0625, 100.0, 0.015
+
+
+def _disks(centres, normals, radius=RP):
+    return scenes.concat([scenes.single_disk(c, n, radius) for c, n in zip(centres, normals)])
+
+
+def _f(v):
+    """The FP64 value of an FP32 input, as the oracle reads it."""
+    return np.asarray(v, np.float32).astype(np.float64)
+
+
+def test_average_two_stacked_disks_closed_form(orc):
+    """Two +z disks in one voxel, the ray straight down through the upper centre:
+    t = (t_A + w_B t_B) / (1 + w_B) with w_B = exp(-a^2/(2 r^2)) exp(-lambda dz),
+    a = the in-plane offset of B's centre, dz = the depth between the two hits."""
+    pa, pb = _f([0.02, 0.02, 0.03]), _f([0.03, 0.02, 0.02])
+    s = _disks([pa, pb], [[0, 0, 1], [0, 0, 1]])
+    o = np.array([pa[0], pa[1], 1.0])
+    i, t, n = orc.average(s, o, [0, 0, -1], RHO, LAM)
+    ta, tb = 1.0 - pa[2], 1.0 - pb[2]
+    a2 = (pa[0] - pb[0]) ** 2 + (pa[1] - pb[1]) ** 2
+    r = float(np.float32(RP))
+    wb = math.exp(-a2 / (2 * r * r)) * math.exp(-LAM * (tb - ta))
+    assert i[0] == 0
+    assert t[0] == pytest.approx((ta + wb * tb) / (1 + wb), rel=1e-13)
+    assert np.allclose(n[0], [0, 0, 1], atol=1e-15)
+
+
+def test_average_large_lambda_keeps_the_nearest_member(orc):
+    pa, pb = _f([0.02, 0.02, 0.03]), _f([0.03, 0.02, 0.02])
+    s = _disks([pa, pb], [[0, 0, 1], [0, 0, 1]])
+    _, t, _ = orc.average(s, [pa[0], pa[1], 1.0], [0, 0, -1], RHO, 1e6)
+    assert t[0] == 1.0 - pa[2]
+
+
+def test_average_tilted_pair_and_flipped_member_reflect_like_the_plane(orc):
+    """Members tilted by +-20 deg about x at one centre average to the +z normal,
+    also when one of them is stored facing away from the ray (two-sided disks)."""
+    c = _f([0.03, 0.03, 0.03])
+    th = math.radians(20.0)
+    n1 = [0.0, math.sin(th), math.cos(th)]
+    for n2 in ([0.0, -math.sin(th), math.cos(th)], [0.0, math.sin(th), -math.cos(th)]):
+        s = _disks([c, c], [n1, n2])
+        _, t, n = orc.average(s, [c[0], c[1], 1.0], [0, 0, -1], RHO, LAM)
+        assert t[0] == pytest.approx(1.0 - c[2], rel=1e-14)
+        assert np.allclose(n[0], [0, 0, 1], atol=1e-7)
+
+
+def test_average_uses_the_voxel_of_the_hit_disk_only(orc):
+    """B overlaps A's footprint from across the voxel boundary x = rho: it is no
+    member of A's set. Moved inside the voxel, it changes the average."""
+    pa = _f([0.04, 0.03, 0.03])
+    r = 0.03
+    o = [0.05, 0.03, 1.0]
+    for xb, member in ((0.065, False), (0.060, True)):
+        pb = _f([xb, 0.03, 0.025])
+        s = _disks([pa, pb], [[0, 0, 1], [0, 0, 1]], radius=r)
+        i, t, _ = orc.average(s, o, [0, 0, -1], RHO, LAM)
+        assert i[0] == 0
+        if member:
+            assert t[0] > 1.0 - pa[2] + 1e-6
+        else:
+            assert t[0] == pytest.approx(1.0 - pa[2], rel=1e-14)
+
+
+def test_average_with_single_point_sets_is_the_nearest_hit(orc):
+    """Voxels far smaller than the spacing: every set holds one disk, so the full
+    solve with averaging reproduces the plain solve."""
+    s = scenes.random_disks(400, seed=11, extent=1.5, radius=0.2)
+    mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2], [2.0, 0.01, 0.5]])
+    rx = np.array([[0.3, -0.2, 0.1], [-0.5, 0.4, -0.3]], np.float32)
+    a = orc.solve(s, mats, [0, 0, 0], rx, 3.5e9, 500, K=3, flags=LOS | SPEC | DIFF)
+    b = orc.solve(s, mats, [0, 0, 0], rx, 3.5e9, 500, K=3, flags=LOS | SPEC | DIFF, average=(1e-4, LAM))
+    assert np.array_equal(a.seq, b.seq)
+    assert np.allclose(a.rec, b.rec, rtol=1e-12, atol=1e-12, equal_nan=True)
+    assert np.allclose(a.G, b.G, rtol=1e-10)
