@@ -446,7 +446,10 @@ static void trace_ray(const scene_t *s, const double *tx, const float *dir32, in
  * limit of the paper's iterative phase 1; phase 2 validates every interaction
  * with a ray from the previous point, thresholds t_a (angle) and t_d (plane
  * distance), and up to kappa retries that replace the failing plane with the
- * plane of the disk the validation ray hit. */
+ * plane of the disk the validation ray hit. With point sets (Sec. II-C), the
+ * planes are the representative's averaged interactions (point and normal),
+ * every validation hit is averaged over its point set in the same way, and a
+ * retry takes the averaged hit as the new plane. */
 typedef struct {
     int valid, retries;
     int64_t hid[ORC_KMAX];
@@ -492,12 +495,12 @@ static int refine_on_planes(int k, const double *tx, const double *rx, double pp
 }
 
 static void specular_one(const scene_t *s, const double *tx, const double *rx, int k, const uint32_t *key,
-                         const int64_t *rep_ids, const thr_t *th, spec_t *out)
+                         const trace_t *rep, const dps_t *g, double lambda_d, const thr_t *th, spec_t *out)
 {
     double pp[ORC_KMAX][3], pn[ORC_KMAX][3];
     for (int m = 0; m < k; ++m) {
-        copy3(pp[m], s->p + 3 * rep_ids[m]);
-        copy3(pn[m], s->nr + 3 * rep_ids[m]);
+        copy3(pp[m], g ? rep->x[m] : s->p + 3 * rep->id[m]);
+        copy3(pn[m], g ? rep->nk[m] : s->nr + 3 * rep->id[m]);
     }
     out->valid = 0;
     out->retries = 0;
@@ -511,15 +514,23 @@ static void specular_one(const scene_t *s, const double *tx, const double *rx, i
             scale3(u, 1.0 / norm3(u));
             int64_t h = nearest(s, out->x[m - 1], u, prev, th->eps_self, INFINITY, th->eps_tie, &t, q);
             if (h < 0 || s->surf[h] != key[m - 1]) return;
+            double hp[3], hn[3];
+            copy3(hp, s->p + 3 * h);
+            copy3(hn, s->nr + 3 * h);
+            if (g) { /* the validation hit, averaged over its point set */
+                dps_average(s, g, out->x[m - 1], u, prev, th->eps_self, h, lambda_d, &t, hn);
+                for (int c = 0; c < 3; ++c) q[c] = out->x[m - 1][c] + t * u[c];
+                copy3(hp, q);
+            }
             double w[3];
             sub3(w, q, pp[m - 1]);
-            int ang_ok = fabs(dot3(s->nr + 3 * h, pn[m - 1])) >= th->cos_ta;
+            int ang_ok = fabs(dot3(hn, pn[m - 1])) >= th->cos_ta;
             int dist_ok = fabs(dot3(w, pn[m - 1])) <= th->t_d;
             if (!(ang_ok && dist_ok)) {
                 if (out->retries >= th->kappa) return;
                 out->retries++;
-                copy3(pp[m - 1], s->p + 3 * h);
-                copy3(pn[m - 1], s->nr + 3 * h);
+                copy3(pp[m - 1], hp);
+                copy3(pn[m - 1], hn);
                 retry = 1;
                 break;
             }
@@ -817,7 +828,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                 int64_t ki = pi / n_rx;
                 int r = (int)(pi % n_rx);
                 const keyrec_t *key = &uk[ki];
-                specular_one(&s, tx, rx + 3 * r, key->len, key->s, tr[key->slot].id, &th, &sp[pi]);
+                specular_one(&s, tx, rx + 3 * r, key->len, key->s, &tr[key->slot], g, g ? thr[6] : 0.0, &th, &sp[pi]);
             }
             for (int64_t ki = 0; ki < nk; ++ki) {
                 if (keys)

@@ -603,3 +603,19 @@ def test_average_with_single_point_sets_is_the_nearest_hit(orc):
     assert np.array_equal(a.seq, b.seq)
     assert np.allclose(a.rec, b.rec, rtol=1e-12, atol=1e-12, equal_nan=True)
     assert np.allclose(a.G, b.G, rtol=1e-10)
+
+
+def test_average_on_exact_planes_keeps_the_specular_paths(orc, room_holefree):
+    """Noise-free room: every point set lies in one face plane with that face's
+    normal, so averaged interactions and averaged validation planes are the
+    exact face planes and the specular paths are those of the plain solve."""
+    mats = scenes.box_room_materials()
+    tx, rx = [1.5, 1.2, 1.4], np.array([[4.2, 2.9, 1.1], [0.8, 3.1, 2.0]], np.float32)
+    a = orc.solve(room_holefree, mats, tx, rx, 3.5e9, 3000, K=2, flags=SPEC)
+    b = orc.solve(room_holefree, mats, tx, rx, 3.5e9, 3000, K=2, flags=SPEC, average=(0.25, 100.0))
+    for r in range(len(rx)):
+        pa, pb = a.paths(r), b.paths(r)
+        assert set(pa) == set(pb) and len(pa) >= 5
+        for key in pa:
+            assert pb[key][0] == pytest.approx(pa[key][0], rel=1e-9)
+
