@@ -237,6 +237,40 @@ def cir_workload(iters):
                 scatter_rel_err=float(rel[:, 2].mean()))
 
 
+def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
+    """The office solve with the paper's point-set parameters (Table I: voxel
+    0.0625 m, point radius 0.015 m, depth attenuation 100 /m): weighted-average
+    interactions against plain nearest-disk interactions on the same scene."""
+    import dataclasses
+    import torch
+    import paper_2507_04021_amd as P
+    sc15 = dataclasses.replace(sc, radius=0.015)
+    scene = P.Scene.from_scene(sc15, leaf_size=leaf, width=width, builder=builder, dps_voxel=0.0625)
+    dev = torch.device("cuda")
+    mats_t = P.materials_tensor(mats, dev)
+    rx_t = torch.as_tensor(rx, device=dev)
+    out = {}
+    for name, fl in (("average", P.LOS | P.SPECULAR | P.DIFFUSE | P.AVERAGE), ("plain", P.LOS | P.SPECULAR | P.DIFFUSE)):
+        res = P.solve(scene, mats_t, tx, rx_t, 28e9, rays, K=5, flags=fl, lambda_d=100.0)
+        o = dict(gain=res.gain, h_te=res.h_te, h_tm=res.h_tm, parts=res.parts, seq=None, counters=res.counters)
+        torch.cuda.synchronize()
+        stage = {k: 0.0 for k in P.STAGES}
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.solve(scene, mats_t, tx, rx_t, 28e9, rays, K=5, flags=fl | P.TIMING, ws=res.ws, out=o, lambda_d=100.0)
+            for k, v in P.stage_times().items():
+                stage[k] += v
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        cnt = {k: int(o["counters"][i].item()) for k, i in P.CNT.items()}
+        out[name] = dict(ms_per_solve=ms, stage_ms={k: v / reps for k, v in stage.items()},
+                         counts={k: cnt[k] for k in ("interactions", "keys", "candidates", "specular", "diffuse")},
+                         gain_db_mean=float(10 * torch.log10(o["gain"]).mean().item()))
+    return dict(workload="office as above with point radius 0.015 m, voxel 0.0625 m, lambda_d 100 /m, %d rays, "
+                         "K=5, 64 RX, LOS+specular+diffuse" % rays,
+                n_point_sets=scene.info["n_point_sets"], build_ms=scene.info["build_ms"], **out)
+
+
 def mlp_workload(iters):
     """Learned materials: box room with one label per surface (8 labels);
     512 channel sets, 256 at 3.5 GHz and 256 at 28 GHz, each 1 TX + 8 RX at
@@ -447,6 +481,9 @@ def main():
         line["mlp"] = mlp_workload(args.mlp_iters)
         log("impulse-response learning workload...")
         line["cir"] = cir_workload(args.cir_iters)
+        log("point-set averaging workload...")
+        line["dps"] = dps_workload(sc, rx, tx, mats, args.rays, max(3, args.steps // 2), args.leaf, args.width,
+                                   args.builder)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on %d rays..." % args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(sc, rx, tx, mats, args.rays, K, args.cpu_sample)

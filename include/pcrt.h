@@ -72,6 +72,11 @@ typedef struct {
     uint32_t leaf_size;
     uint32_t width;
     uint32_t builder; /* PCRT_BUILD_*; 0 = default (PCRT_BUILD_PLOC) */
+    /* Discretised point sets (Sec. II-A): voxel edge rho in metres; each
+     * non-empty voxel floor(p / rho) (per axis, evaluated in FP64 from the
+     * FP32 centres) is one set. 0 = no sets; PCRT_AVERAGE solves need them.
+     * Voxel indices must stay within +-2^20 (else EUNSUPPORTED). */
+    float dps_voxel;
 } pcrt_bvh_opts;
 
 enum {
@@ -92,12 +97,15 @@ typedef struct {
     uint32_t stack_entries; /* bound on traversal stack entries: (width - 1) x levels */
     uint32_t builder;
     float bbox[6];         /* lo xyz, hi xyz of the disk bounds */
-    double build_ms;       /* device time of the build */
+    double build_ms;       /* device time of the build (point sets included) */
+    uint32_t n_point_sets; /* non-empty voxels (0 without dps_voxel) */
+    float dps_voxel;
 } pcrt_scene_info;
 
 typedef struct pcrt_scene pcrt_scene; /* opaque host handle */
 
-/* Bytes of device workspace a scene of n_points needs (BVH + disk copies). */
+/* Bytes of device workspace a scene of n_points needs (BVH, disk copies and,
+ * with dps_voxel > 0, the point sets). */
 pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *opts, size_t *bytes);
 
 /* Validate the points, copy them, build the hierarchy (Morton codes, radix
@@ -105,7 +113,8 @@ pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *op
  * outlive the scene. This call synchronises the stream once at the end to
  * read back validation results and statistics. Errors: EINVAL for NULL
  * pointers, n_points == 0, disk_radius <= 0, non-finite positions or zero
- * normals; ENOMEM for a small ws; EUNSUPPORTED for more than 2^26 points
+ * normals, a negative or non-finite dps_voxel; ENOMEM for a small ws;
+ * EUNSUPPORTED for voxel indices beyond +-2^20, more than 2^26 points
  * (the traversal kernels address the node and disk arrays with 32-bit byte
  * offsets), an unsupported leaf size, width or builder, or a hierarchy whose
  * traversal stack bound exceeds the supported maximum. stream: hipStream_t
@@ -139,7 +148,16 @@ enum {
     PCRT_SPECULAR = 2, /* specular paths (keys, refinement, validation) */
     PCRT_DIFFUSE = 4,  /* diffuse scattering as the last interaction */
     PCRT_RECORD = 8,   /* keep the per-path tape in the workspace (for the gradient and path output) */
-    PCRT_TIMING = 16   /* record HIP events between stages (read with pcrt_stage_times) */
+    PCRT_TIMING = 16,  /* record HIP events between stages (read with pcrt_stage_times) */
+    /* Weighted-average intersection (Sec. II-C, Eq. 3-4): every interaction
+     * is the weighted mean, over the hit disk's point set, of the ray's
+     * intersections farther than eps_self, with weights
+     * exp(-|q_i - p_i|^2 / (2 r_p^2)) exp(-lambda_d |q_i - q_min|) (q_min: the
+     * member intersection nearest to the origin); the ray reflects about the
+     * weighted sum of the member normals turned to face it. The nearest disk
+     * still names the interaction (material, surface label, sequence).
+     * Needs a scene built with dps_voxel > 0 (else EINVAL). */
+    PCRT_AVERAGE = 32
 };
 
 /* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
@@ -161,6 +179,7 @@ typedef struct {
     pcrt_thresholds thr;
     uint32_t key_capacity;
     uint32_t wave_rays; /* rays a wavefront takes per work fetch, multiple of 64 up to 1024 (0 = 64) */
+    float lambda_d;     /* depth attenuation of PCRT_AVERAGE, 1/m (0 = 100) */
 } pcrt_solve_params;
 
 /* Outputs (device pointers; NULL = not wanted unless marked required).

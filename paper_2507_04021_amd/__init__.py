@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcrt.so")
 LIB_COUNT_PATH = os.path.join(_HERE, "libpcrt_count.so")  # measurement build with visit counters
 
-LOS, SPECULAR, DIFFUSE, RECORD, TIMING = 1, 2, 4, 8, 16
+LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE = 1, 2, 4, 8, 16, 32
 STAGES = ("init", "trace", "keys", "refine", "diffuse_order", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
            tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
@@ -37,7 +37,8 @@ class Points(ctypes.Structure):
 
 
 class BvhOpts(ctypes.Structure):
-    _fields_ = [("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32), ("builder", ctypes.c_uint32)]
+    _fields_ = [("leaf_size", ctypes.c_uint32), ("width", ctypes.c_uint32), ("builder", ctypes.c_uint32),
+                ("dps_voxel", ctypes.c_float)]
 
 
 BUILD_LBVH, BUILD_PLOC = 1, 2
@@ -47,7 +48,8 @@ class SceneInfo(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_uint32), ("n_surfaces", ctypes.c_uint32), ("n_materials", ctypes.c_uint32),
                 ("depth", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("leaf_size", ctypes.c_uint32),
                 ("width", ctypes.c_uint32), ("stack_entries", ctypes.c_uint32), ("builder", ctypes.c_uint32),
-                ("bbox", ctypes.c_float * 6), ("build_ms", ctypes.c_double)]
+                ("bbox", ctypes.c_float * 6), ("build_ms", ctypes.c_double), ("n_point_sets", ctypes.c_uint32),
+                ("dps_voxel", ctypes.c_float)]
 
 
 class Thresholds(ctypes.Structure):
@@ -59,7 +61,8 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_float * 3), ("rx", ctypes.c_void_p), ("n_rx", ctypes.c_uint32),
                 ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
-                ("thr", Thresholds), ("key_capacity", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32)]
+                ("thr", Thresholds), ("key_capacity", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32),
+                ("lambda_d", ctypes.c_float)]
 
 
 class BatchItem(ctypes.Structure):
@@ -177,7 +180,9 @@ class Scene:
     """A point cloud of disks with its bounding-volume hierarchy on the GPU."""
 
     def __init__(self, pos, normal, material, surface, radius, leaf_size=4, width=4, builder=0, device="cuda",
-                 stream=None):
+                 stream=None, dps_voxel=0.0):
+        """dps_voxel > 0 also groups the points into voxels of that edge (the point
+        sets of the AVERAGE solves)."""
         torch = _torch()
         self.device = torch.device(device)
         pos = _dev(pos, torch.float32, self.device).reshape(-1, 3)
@@ -189,7 +194,7 @@ class Scene:
         n = pos.shape[0]
         self.n = n
         self.radius = float(radius)
-        opts = BvhOpts(leaf_size, width, builder)
+        opts = BvhOpts(leaf_size, width, builder, float(dps_voxel))
         nbytes = ctypes.c_size_t(0)
         _check(lib().pcrt_scene_workspace_size(n, ctypes.byref(opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
@@ -204,7 +209,7 @@ class Scene:
         self.info = dict(n_points=info.n_points, n_surfaces=info.n_surfaces, n_materials=info.n_materials,
                          depth=info.depth, n_nodes=info.n_nodes, leaf_size=info.leaf_size, width=info.width,
                          stack_entries=info.stack_entries, builder=info.builder, bbox=list(info.bbox),
-                         build_ms=info.build_ms)
+                         build_ms=info.build_ms, n_point_sets=info.n_point_sets, dps_voxel=info.dps_voxel)
 
     @classmethod
     def from_scene(cls, sc, **kw):
@@ -243,7 +248,8 @@ class SolveResult:
         return int(self.counters[CNT[name]].item())
 
 
-def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0, wave_rays=0):
+def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0, wave_rays=0,
+                lambda_d=0.0):
     th = Thresholds(0.0, 0.0, 0.0, 0.0, 0)
     if thr:
         for k, v in thr.items():
@@ -261,12 +267,16 @@ def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_c
     p.thr = th
     p.key_capacity = int(key_capacity)
     p.wave_rays = int(wave_rays)
+    p.lambda_d = float(lambda_d)
     return p
 
 
 def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
-          want_seq=False, stream=None, ws=None, out=None, key_capacity=0, wave_rays=0) -> SolveResult:
-    """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor."""
+          want_seq=False, stream=None, ws=None, out=None, key_capacity=0, wave_rays=0,
+          lambda_d=0.0) -> SolveResult:
+    """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor.
+    flags with AVERAGE: point-set averaged interactions (scene built with dps_voxel > 0), depth
+    attenuation lambda_d (0 = 100 per metre)."""
     torch = _torch()
     L = lib(scene._variant)
     dev = scene.device
@@ -277,7 +287,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
     if ray_subset is not None:
         sub_t = _dev(np.asarray(ray_subset, np.int64).astype(np.int32) if not isinstance(ray_subset, torch.Tensor)
                      else ray_subset, torch.int32, dev)
-    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays)
+    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays, lambda_d)
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:
@@ -365,14 +375,14 @@ def _items(tx, n_rays):
     return arr
 
 
-def _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr, wave_rays):
+def _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr, wave_rays, lambda_d=0.0):
     torch = _torch()
     dev = scene.device
     mats_t = mats if isinstance(mats, torch.Tensor) and mats.device.type == "cuda" else materials_tensor(mats, dev)
     rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
                 torch.float32, dev).reshape(-1, 3)
     items = _items(tx, n_rays)
-    p = make_params([0, 0, 0], rx_t, freq, 1, K, flags, None, thr, 0, wave_rays)
+    p = make_params([0, 0, 0], rx_t, freq, 1, K, flags, None, thr, 0, wave_rays, lambda_d)
     L = lib(scene._variant)
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_batch_workspace_size(scene.handle, ctypes.byref(p), items, len(items), ctypes.byref(nbytes)), L)
@@ -389,10 +399,10 @@ def _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr, wave_rays):
 
 
 def solve_batch(scene: Scene, mats, tx, n_rays, rx, freq, K=2, flags=LOS | SPECULAR, thr=None, wave_rays=0,
-                stream=None) -> BatchResult:
+                stream=None, lambda_d=0.0) -> BatchResult:
     """Many transmitters (tx[n, 3], n_rays[n]) against the same receivers in one launch sequence."""
     L, mats_t, rx_t, items, p, ws, out, o = _batch_setup(scene, mats, tx, n_rays, rx, freq, K, flags, thr,
-                                                         wave_rays)
+                                                         wave_rays, lambda_d)
     _check(L.pcrt_solve_batch(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), items, len(items),
                               _ptr(ws), ws.numel(), ctypes.byref(o), _stream(stream)), L)
     return BatchResult(out["gain"], out["h_te"], out["h_tm"], out["parts"], out["counters"], ws, p, items,

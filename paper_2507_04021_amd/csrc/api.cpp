@@ -131,6 +131,9 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     uint64_t nt = p->ray_subset ? p->n_subset : p->n_rays;
     if (nt * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
     if ((uint64_t)p->n_rx > kMaxPairs) return fail(PCRT_EUNSUPPORTED, "too many receivers");
+    if ((p->flags & PCRT_AVERAGE) && !sc->dev.dps_pt)
+        return fail(PCRT_EINVAL, "PCRT_AVERAGE needs a scene built with dps_voxel > 0");
+    if (!(p->lambda_d >= 0.f) || !std::isfinite(p->lambda_d)) return fail(PCRT_EINVAL, "lambda_d must be >= 0");
     return PCRT_OK;
 }
 
@@ -195,6 +198,7 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
                               round_up(D.n_items * D.n_rx, kWave)});
     P.L = solve_layout(D, p->flags);
     P.thr = make_thr(p->thr);
+    P.thr.lambda_d = p->lambda_d > 0.f ? p->lambda_d : 100.f;
     P.fc = make_fc(p->freq_hz);
     return P;
 }
@@ -244,6 +248,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.rb.cs = (float *)at(L.rec_cs);
     A.rb.coef = (p->flags & PCRT_DIFFUSE) ? (float4 *)at(L.rec_coef) : nullptr;
     A.rb.slot = (p->flags & PCRT_SPECULAR) ? (uint32_t *)at(L.rec_slot) : nullptr;
+    A.rb.nk = (p->flags & PCRT_AVERAGE) ? (float4 *)at(L.rec_nk) : nullptr;
     A.hb.key = (unsigned long long *)at(L.hkey);
     A.hb.rep = (uint32_t *)at(L.hrep);
     A.hb.cap = P.cap;
@@ -263,6 +268,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.chunk_off = (uint32_t *)at(L.chunk_off);
     A.spec_part = (double *)at(L.spec_part);
     A.spec_res = (p->flags & PCRT_SPECULAR) ? (float4 *)at(L.spec_res) : nullptr;
+    A.spec_ovr = ((p->flags & PCRT_SPECULAR) && (p->flags & PCRT_AVERAGE)) ? (float4 *)at(L.spec_ovr) : nullptr;
     A.diff_part = (double *)at(L.diff_part);
     A.los_part = (double *)at(L.los_part);
     A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
@@ -300,6 +306,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
     L.rec_id = b.take(sizeof(int) * nrec);
     L.rec_xl = b.take(sizeof(float4) * nrec);
     L.rec_cs = b.take(sizeof(float) * nrec);
+    if (flags & PCRT_AVERAGE) L.rec_nk = b.take(sizeof(float4) * nrec);
     L.key_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
     L.chunk_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
     L.los_part = b.take(sizeof(double) * 5 * (size_t)D.n_items * D.n_rx);
@@ -322,6 +329,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.keylist = b.take(sizeof(uint32_t) * D.max_keys);
         L.spec_part = b.take(sizeof(double) * 5 * (size_t)D.max_key_chunks * D.n_rx);
         L.spec_res = b.take(sizeof(float4) * (size_t)refine_grid(D) * kRefineResPerBlock);
+        if (flags & PCRT_AVERAGE) L.spec_ovr = b.take(sizeof(float4) * 2 * (size_t)refine_grid(D) * kRefineQueue * D.K);
         if (rec) {
             const size_t pairs = (size_t)D.rec_keys * D.n_rx;
             L.sp_valid = b.take(pairs);
@@ -377,7 +385,8 @@ pcrt_status pcrt_scene_workspace_size(uint32_t n_points, const pcrt_bvh_opts *op
     if (opts && opts->leaf_size > 8) return fail(PCRT_EUNSUPPORTED, "leaf_size must be in 1..8");
     const uint32_t builder = opts && opts->builder ? opts->builder : kDefaultBuilder;
     if (builder != kBuildLbvh && builder != kBuildPloc) return fail(PCRT_EUNSUPPORTED, "builder must be 1 or 2");
-    *bytes = scene_layout(n_points, width, builder).total;
+    const bool dps = opts && opts->dps_voxel > 0.f;
+    *bytes = scene_layout(n_points, width, builder, dps).total;
     return ok();
 }
 
@@ -396,7 +405,9 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     if (width != 2 && width != 4 && width != 8) return fail(PCRT_EUNSUPPORTED, "width must be 2, 4 or 8");
     const uint32_t builder = opts && opts->builder ? opts->builder : kDefaultBuilder;
     if (builder != kBuildLbvh && builder != kBuildPloc) return fail(PCRT_EUNSUPPORTED, "builder must be 1 or 2");
-    SceneLayout L = scene_layout(pts->n_points, width, builder);
+    const float rho = opts ? opts->dps_voxel : 0.f;
+    if (!(rho >= 0.f) || !std::isfinite(rho)) return fail(PCRT_EINVAL, "dps_voxel must be finite and >= 0");
+    SceneLayout L = scene_layout(pts->n_points, width, builder, rho > 0.f);
     if (ws_bytes < L.total) return fail(PCRT_ENOMEM, "scene workspace too small: need %zu bytes", L.total);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -407,11 +418,13 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     int broot = 0;
     HIP_TRY(build_scene(pts->pos, pts->normal, pts->material, pts->surface, pts->n_points, pts->disk_radius, leaf,
                         (char *)ws, L, s, &wide_levels, &wide_nodes, &broot));
+    if (rho > 0.f) HIP_TRY(build_point_sets(L, (char *)ws, pts->n_points, rho, s));
     HIP_TRY(hipEventRecord(e1, s));
-    uint32_t stat[8];
+    uint32_t stat[8], dstat[2] = {0, 0};
     float bounds[6];
     HIP_TRY(hipMemcpyAsync(stat, (char *)ws + L.stat, sizeof stat, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(bounds, (char *)ws + L.bounds, sizeof bounds, hipMemcpyDeviceToHost, s));
+    if (rho > 0.f) HIP_TRY(hipMemcpyAsync(dstat, (char *)ws + L.dps_stat, sizeof dstat, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -419,6 +432,7 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     hipEventDestroy(e1);
     if (stat[0] & 1) return fail(PCRT_EINVAL, "non-finite point position");
     if (stat[0] & 2) return fail(PCRT_EINVAL, "zero or non-finite normal");
+    if (dstat[0] & 1) return fail(PCRT_EUNSUPPORTED, "voxel index beyond +-2^20 (dps_voxel too small for the scene)");
     // a depth-first walk holds at most (width - 1) entries per level of its path
     const uint32_t n_pts = pts->n_points;
     const uint32_t stack_entries = n_pts <= leaf ? 0 : width == 2 ? stat[3] : (width - 1) * wide_levels;
@@ -439,6 +453,11 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     sc->dev.bounds = (const float *)(sc->ws + L.bounds);
     sc->dev.r2 = pts->disk_radius * pts->disk_radius;
     sc->dev.n = n;
+    if (rho > 0.f) {
+        sc->dev.dps_pt = (const float4 *)(sc->ws + L.dps_pt);
+        sc->dev.dps_off = (const uint32_t *)(sc->ws + L.dps_off);
+        sc->dev.dps_of = (const uint32_t *)(sc->ws + L.dps_of);
+    }
     // the wide hierarchy's root is node 0; the binary root is the builder's
     sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : (width > 2 ? 0 : broot));
     pcrt_scene_info &I = sc->info;
@@ -453,6 +472,8 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     I.builder = builder;
     memcpy(I.bbox, bounds, sizeof bounds);
     I.build_ms = ms;
+    I.n_point_sets = dstat[1];
+    I.dps_voxel = rho;
     *out = sc;
     return ok();
 }

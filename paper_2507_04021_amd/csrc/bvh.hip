@@ -520,7 +520,7 @@ __global__ void k_wide_emit(const float4 *__restrict__ bnode, const int *__restr
     }
 }
 
-SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder) {
+SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps) {
     Bump b;
     SceneLayout L;
     uint32_t ni = n > 1 ? n - 1 : 1;
@@ -570,6 +570,14 @@ SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder) {
         L.front1 = b.take(sizeof(int) * ni);
         L.wcnt = b.take(sizeof(uint32_t) * ni);
         L.wblk = b.take(sizeof(uint32_t) * scan_blk_words(ni));
+    }
+    if (dps) {  // point sets; their sort reuses the build's code / idx / hist buffers
+        L.dps_pt = b.take(sizeof(float4) * 2 * (size_t)n);
+        L.dps_off = b.take(sizeof(uint32_t) * ((size_t)n + 1));
+        L.dps_of = b.take(sizeof(uint32_t) * n);
+        L.dps_flag = b.take(sizeof(uint32_t) * n);
+        L.dps_blk = b.take(sizeof(uint32_t) * scan_blk_words(n));
+        L.dps_stat = b.take(sizeof(uint32_t) * 2);
     }
     L.total = b.off;
     return L;

@@ -69,6 +69,10 @@ struct DevScene {
     int root;
     float r2;
     uint32_t n;
+    // Discretised point sets (voxels of the point centres), null without them.
+    const float4 *dps_pt;     // 2 float4 per member, grouped by set: (p.xyz, id bits), (n.xyz, 0)
+    const uint32_t *dps_off;  // [n_sets + 1] first member of each set
+    const uint32_t *dps_of;   // by id: set of the point
 };
 
 // Node layout (64 B): n0 = (lo0.x, lo0.y, lo0.z, hi0.x), n1 = (hi0.y, hi0.z, lo1.x, lo1.y),
@@ -77,6 +81,7 @@ struct DevScene {
 struct Thr {
     float eps_tie, eps_self, cos_ta, t_d;
     int kappa;
+    float lambda_d;  // depth attenuation of the point-set average
 };
 
 struct Item {  // one transmitter of a (batched) solve, 32 B
@@ -152,6 +157,44 @@ __device__ __forceinline__ bool disk_hit(f3 o, f3 d, f3 p, f3 n, float r2, float
     const f3 e = q - p;
     d2 = dot(e, e);
     return (fabsf(a) >= kParallelEps) & (d2 <= r2);
+}
+
+// Weighted-average intersection over the point set of the hit disk h
+// (Sec. II-C, Eq. 3-4). The members are the disks of h's voxel that the ray
+// meets farther than eps_self from o (excl aside); member i weighs
+//   exp(-|q_i - p_i|^2 / (2 r^2)) * exp(-lambda_d * (t_i - t_min)),
+// t_min being the nearest member intersection (|q_i - q_min| = t_i - t_min:
+// both points lie on the ray and d is unit). t becomes the weighted mean
+// distance, n the weighted sum of the member normals turned to face the ray,
+// normalised. Members are visited in increasing id, which fixes the sums.
+__device__ __forceinline__ void dps_average(const DevScene &S, f3 o, f3 d, int excl, float eps_self,
+                                            float lambda_d, int h, float &t, f3 &n) {
+    const uint32_t g = S.dps_of[h];
+    const uint32_t b = S.dps_off[g], e = S.dps_off[g + 1];
+    float tmin = INFINITY;
+    for (uint32_t j = b; j < e; ++j) {
+        const float4 pp = S.dps_pt[2 * (size_t)j], pn = S.dps_pt[2 * (size_t)j + 1];
+        float tj, d2;
+        const bool hit = disk_hit(o, d, xyz(pp), xyz(pn), S.r2, tj, d2);
+        if (hit && __float_as_int(pp.w) != excl && tj > eps_self) tmin = fminf(tmin, tj);
+    }
+    const float inv2r2 = 0.5f / S.r2;
+    float sw = 0.f, st = 0.f;
+    f3 sn = mk(0.f, 0.f, 0.f);
+    for (uint32_t j = b; j < e; ++j) {
+        const float4 pp = S.dps_pt[2 * (size_t)j], pn = S.dps_pt[2 * (size_t)j + 1];
+        float tj, d2;
+        const bool hit = disk_hit(o, d, xyz(pp), xyz(pn), S.r2, tj, d2);
+        if (!(hit && __float_as_int(pp.w) != excl && tj > eps_self)) continue;
+        const float w = expf(-d2 * inv2r2) * expf(-lambda_d * (tj - tmin));
+        const f3 m = xyz(pn);
+        const float side = dot(d, m) > 0.f ? -w : w;
+        sw += w;
+        st += w * tj;
+        sn = sn + side * m;
+    }
+    t = st / sw;
+    n = normalize(sn);
 }
 
 // Nearest hit among disks != excl with t in (t_lo, inf), with the tie rule:

@@ -93,9 +93,8 @@ __global__ void k_diffuse_pack(LaunchArgs A, const uint32_t *order) {
         float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = make_float4(0.f, 0.f, 1.f, __int_as_float(-1));
         if (id >= 0) {
             p0 = A.rb.xl[ri];
-            const float4 nn = A.S.nrm[id];
-            const float sg = A.rb.cs[ri] < 0.f ? -1.f : 1.f;
-            p1 = make_float4(sg * nn.x, sg * nn.y, sg * nn.z, __int_as_float(id));
+            const f3 nn = record_normal(A, ri);
+            p1 = make_float4(nn.x, nn.y, nn.z, __int_as_float(id));
         }
         A.dsort.pack[2 * (size_t)j] = p0;
         A.dsort.pack[2 * (size_t)j + 1] = p1;

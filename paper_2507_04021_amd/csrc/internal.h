@@ -44,10 +44,13 @@ struct SceneLayout {
     size_t cbox[2] = {0, 0}, cid[2] = {0, 0}, csz[2] = {0, 0};  // clustering build (builder == kBuildPloc)
     size_t nn = 0, mflag = 0, kflag = 0, pblk = 0, nsize = 0, noff = 0, leaf_pos = 0, perm2 = 0, pleaf2 = 0;
     size_t wnode = 0, front0 = 0, front1 = 0, wcnt = 0, wblk = 0;  // wide collapse (width > 2)
+    size_t dps_pt = 0, dps_off = 0, dps_of = 0, dps_flag = 0, dps_blk = 0, dps_stat = 0;  // point sets
     size_t total;
 };
 
-SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder);
+SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps);
+// Point sets: voxel keys, sort, set boundaries (after build_scene, reusing its sort buffers).
+hipError_t build_point_sets(const SceneLayout &L, char *ws, uint32_t n, float rho, hipStream_t s);
 hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, int broot, uint32_t *levels, uint32_t *nodes);
 hipError_t build_scene(const float *pos, const float *nrm, const uint16_t *mat, const uint32_t *surf, uint32_t n,
                        float r, uint32_t leaf, char *ws, const SceneLayout &L, hipStream_t s, uint32_t *wide_levels,
@@ -67,6 +70,7 @@ struct RecBufs {
     float *cs;        // incidence cosine, sign = orientation of the hit normal (n_k = sign * n)
     float4 *coef;     // diffuse coefficient (TE re, im, TM re, im), incl. lambda/4pi and the chain before
     uint32_t *slot;   // key-table slot of the prefix key
+    float4 *nk;       // point-set average only: normal of the interaction, facing the incoming ray
 };
 
 struct HashBufs {
@@ -105,12 +109,13 @@ constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction ch
 constexpr uint32_t kRefineRxSlice = 8;
 // Result slots per refinement block: two open units of kKeyChunk keys x kRefineRxSlice receivers.
 constexpr uint32_t kRefineResPerBlock = 2 * kKeyChunk * kRefineRxSlice;
+constexpr uint32_t kRefineQueue = 128;  // refinement ring of queued candidates (at most 127 are live)
 constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 labels x 3 doubles
 
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
         key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
-        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res, dpack;
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res, dpack, rec_nk, spec_ovr;
     size_t total;
 };
 
@@ -153,6 +158,7 @@ struct LaunchArgs {
     uint32_t *chunk_off; // [n_items + 1]
     double *spec_part;
     float4 *spec_res;      // refinement: per block, path amplitudes of its current unit's pairs
+    float4 *spec_ovr;      // refinement with point-set averaging: per block and ring position, replaced planes
     double *diff_part;
     double *los_part;
     uint8_t *dvis;
@@ -163,6 +169,14 @@ struct LaunchArgs {
     double *grad_part;     // [n_slot_chunks][kMaxGradLabels][3]
     SortBufs dsort;
 };
+
+// Normal of interaction record ri, turned to face the ray that arrived there:
+// the point-set average's normal when it ran, else the hit disk's normal.
+__device__ __forceinline__ f3 record_normal(const LaunchArgs &A, uint32_t ri) {
+    if (A.rb.nk) return xyz(A.rb.nk[ri]);
+    const f3 n = xyz(A.S.nrm[A.rb.id[ri]]);
+    return A.rb.cs[ri] < 0.f ? (-1.f) * n : n;
+}
 
 void launch_trace(const LaunchArgs &A, hipStream_t s);
 void launch_keys(const LaunchArgs &A, hipStream_t s);

@@ -131,7 +131,9 @@ struct PairOut {
     c32 te, tm;
 };
 
-// The representative's interaction planes of key q (its first k hit disks).
+// The representative's interaction planes of key q: its first k hit disks'
+// planes, or with point-set averaging its first k averaged interactions
+// (point and normal from the records).
 template <int KM>
 struct KeyPlanes {
     f3 pp[KM], pn[KM];
@@ -139,7 +141,7 @@ struct KeyPlanes {
     int k;
 };
 
-template <int KM>
+template <int KM, bool AVG>
 __device__ __forceinline__ void load_planes(const LaunchArgs &A, uint32_t q, KeyPlanes<KM> &kp) {
     const uint32_t K = A.D.K;
     const uint32_t rec = A.keylist[q];
@@ -148,11 +150,17 @@ __device__ __forceinline__ void load_planes(const LaunchArgs &A, uint32_t q, Key
 #pragma unroll
     for (int m = 0; m < KM; ++m)
         if (m < kp.k) {
-            const int id = A.rb.id[(size_t)g * K + m];
+            const size_t ri = (size_t)g * K + m;
+            const int id = A.rb.id[ri];
             const float4 p4 = A.S.pos[id];
-            kp.pp[m] = xyz(p4);
             kp.ks[m] = __float_as_uint(p4.w);
-            kp.pn[m] = xyz(A.S.nrm[id]);
+            if (AVG) {
+                kp.pp[m] = xyz(A.rb.xl[ri]);
+                kp.pn[m] = xyz(A.rb.nk[ri]);
+            } else {
+                kp.pp[m] = xyz(p4);
+                kp.pn[m] = xyz(A.S.nrm[id]);
+            }
         }
 }
 
@@ -167,12 +175,15 @@ __device__ __forceinline__ f3 rx_point(const LaunchArgs &A, uint32_t r) {
 // those two tests asks for another pass with that plane replaced by the hit
 // disk's (kPassRetry: slot, disk), unless retries already equals kappa; any
 // other failure ends the candidate. If every interaction holds, the last
-// point must see the receiver, and the path's field is evaluated.
+// point must see the receiver, and the path's field is evaluated. With
+// point-set averaging the validation hit is averaged over its set first
+// (Sec. II-C): its point and normal are tested, and a retry takes them as the
+// new plane (rp, rn).
 enum { kPassDone = 0, kPassRetry = 1 };
 
-template <int KM, int W>
+template <int KM, int W, bool AVG>
 __device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, f3 tx, const KeyPlanes<KM> &kp,
-                             int retries, Stack &stk, PairOut &po, int &slot, int &disk) {
+                             int retries, Stack &stk, PairOut &po, int &slot, int &disk, f3 &rp, f3 &rn) {
     po.valid = false;
     const uint32_t K = A.D.K;
     const int k = kp.k;
@@ -193,6 +204,7 @@ __device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, f3 tx,
         float4 hp = A.S.pos[h];
         if (__float_as_uint(hp.w) != kp.ks[m - 1]) { fail = true; continue; }
         f3 hn = xyz(A.S.nrm[h]);
+        if (AVG) dps_average(A.S, x[m - 1], u, prev, A.thr.eps_self, A.thr.lambda_d, h, t, hn);
         f3 qh = x[m - 1] + t * u;
         bool ang_ok = fabsf(dot(hn, kp.pn[m - 1])) >= A.thr.cos_ta;
         bool dist_ok = fabsf(dot(qh - kp.pp[m - 1], kp.pn[m - 1])) <= A.thr.t_d;
@@ -200,6 +212,10 @@ __device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, f3 tx,
             if (retries >= A.thr.kappa) { fail = true; continue; }
             slot = m - 1;
             disk = h;
+            if (AVG) {
+                rp = qh;
+                rn = hn;
+            }
             retry = true;
             continue;
         }
@@ -276,7 +292,6 @@ __device__ int validate_pass(const LaunchArgs &A, uint32_t q, uint32_t r, f3 tx,
 // lane r adds the paths of receiver r in increasing key order and writes the
 // unit's partial sum of receiver r0 + r for chunk c. The result does not
 // depend on timing or on the order in which passes ran.
-constexpr uint32_t kRefineQueue = 128;  // ring of queued candidates (at most 127 are live)
 constexpr int kRefineOpen = 2;          // units open at once per wavefront
 
 template <int KM>
@@ -303,7 +318,7 @@ __device__ __forceinline__ void block_sync_global() {
 
 // Occupancy: four wavefronts per SIMD up to K = 5 (a 128-register budget,
 // with a few spills): on the office two gave 6.1 ms, three 4.8, four 4.7.
-template <int KM, int W>
+template <int KM, int W, bool AVG>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ? 4 : 2, 8))) void k_refine(
     LaunchArgs A) {
     constexpr uint32_t kUnitPairs = kKeyChunk * kRefineRxSlice;
@@ -316,6 +331,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ?
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
     float4 *res = A.spec_res + (size_t)blockIdx.x * kRefineOpen * kUnitPairs;
+    // point-set averaging: the current planes of a queued candidate with
+    // retries sit at its ring position, (point, normal) per interaction
+    constexpr bool avg = AVG;
+    float4 *qpl = avg ? A.spec_ovr + (size_t)blockIdx.x * kRefineQueue * KM * 2 : nullptr;
     const uint32_t n_rx = A.D.n_rx, n_items = A.D.n_items;
     const uint32_t n_chunks = A.chunk_off[n_items];
     const uint32_t n_slices = (n_rx + kRefineRxSlice - 1) / kRefineRxSlice;
@@ -398,7 +417,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ?
                 if (e < R.ne) {
                     const uint32_t q = R.q0 + e / R.nr, r = R.r0 + e % R.nr;
                     KeyPlanes<KM> kp;
-                    load_planes<KM>(A, q, kp);
+                    load_planes<KM, AVG>(A, q, kp);
                     f3 x[KM + 1];
                     cand = refine_planes<KM>(kp.k, R.tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
                     if (rec) {
@@ -441,33 +460,46 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ?
         const uint32_t nb = min(live, (uint32_t)kWave);
         const bool have = (uint32_t)lane < nb;
         QEntry<KM> me;
-        if (have) me = queue[(head + lane) % kRefineQueue];
+        const uint32_t at = (head + lane) % kRefineQueue;
+        if (have) me = queue[at];
         head += nb;
         wave_sync();  // taken entries are read before their ring slots are reused
         bool again = false, ended = false;
+        KeyPlanes<KM> kp;
         if (have) {
             const bool s1 = me.slot == 1;
             const uint32_t nr = s1 ? U[1].nr : U[0].nr;
             const uint32_t q = (s1 ? U[1].q0 : U[0].q0) + me.e / nr;
             const uint32_t r = (s1 ? U[1].r0 : U[0].r0) + me.e % nr;
             const f3 tx = s1 ? U[1].tx : U[0].tx;
-            KeyPlanes<KM> kp;
-            load_planes<KM>(A, q, kp);
+            load_planes<KM, AVG>(A, q, kp);
 #pragma unroll
             for (int j = 0; j < KM; ++j)
                 if (j < kp.k && me.ovr[j] >= 0) {
-                    kp.pp[j] = xyz(A.S.pos[me.ovr[j]]);
-                    kp.pn[j] = xyz(A.S.nrm[me.ovr[j]]);
+                    if (avg) {
+                        kp.pp[j] = xyz(qpl[((size_t)at * KM + j) * 2]);
+                        kp.pn[j] = xyz(qpl[((size_t)at * KM + j) * 2 + 1]);
+                    } else {
+                        kp.pp[j] = xyz(A.S.pos[me.ovr[j]]);
+                        kp.pn[j] = xyz(A.S.nrm[me.ovr[j]]);
+                    }
                 }
             PairOut po;
             int slot = 0, disk = -1;
-            const int out = validate_pass<KM, W>(A, q, r, tx, kp, me.retries, stk, po, slot, disk);
+            f3 rp = mk(0.f, 0.f, 0.f), rn = mk(0.f, 0.f, 1.f);
+            const int out = validate_pass<KM, W, AVG>(A, q, r, tx, kp, me.retries, stk, po, slot, disk, rp, rn);
             if (out == kPassRetry) {
                 again = true;
                 me.retries += 1;
 #pragma unroll
                 for (int j = 0; j < KM; ++j)
-                    if (j == slot) me.ovr[j] = disk;
+                    if (j == slot) {
+                        me.ovr[j] = disk;
+                        if (AVG) {
+                            kp.pp[j] = rp;
+                            kp.pn[j] = rn;
+                        }
+                    }
             } else {
                 ended = true;
                 if (rec && q < A.D.rec_keys) {
@@ -487,9 +519,21 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ?
         U[0].pending -= (uint32_t)__popcll(__ballot(ended && me.slot == 0));
         U[1].pending -= (uint32_t)__popcll(__ballot(ended && me.slot == 1));
         const uint64_t m = __ballot(again);
-        if (again) queue[(tail + (uint32_t)__popcll(m & below)) % kRefineQueue] = me;
+        if (again) {
+            const uint32_t to = (tail + (uint32_t)__popcll(m & below)) % kRefineQueue;
+            queue[to] = me;
+            if (avg) {  // the replaced planes travel with the candidate
+#pragma unroll
+                for (int j = 0; j < KM; ++j)
+                    if (me.ovr[j] >= 0) {
+                        qpl[((size_t)to * KM + j) * 2] = make_float4(kp.pp[j].x, kp.pp[j].y, kp.pp[j].z, 0.f);
+                        qpl[((size_t)to * KM + j) * 2 + 1] = make_float4(kp.pn[j].x, kp.pn[j].y, kp.pn[j].z, 0.f);
+                    }
+            }
+        }
         tail += (uint32_t)__popcll(m);
-        wave_sync();
+        if (avg) block_sync_global();  // plane rows written by some lanes are read by others later
+        else wave_sync();
     }
     flush_visits(stk, A.counters, 11);
     n_cand = warp_sum_u(n_cand);
@@ -513,7 +557,7 @@ void launch_keys(const LaunchArgs &A, hipStream_t s) {
 
 template <int KM, int W>
 uint32_t refine_cap() {
-    static const uint32_t cap = resident_blocks((const void *)k_refine<KM, W>, kWave);
+    static const uint32_t cap = resident_blocks((const void *)k_refine<KM, W, false>, kWave);
     return cap;
 }
 
@@ -537,18 +581,26 @@ uint32_t refine_grid(const SolveDims &D) {
     return std::max<uint32_t>(1, std::min(cap, units));
 }
 
+template <int W, bool AVG>
+void launch_refine_wa(const LaunchArgs &A, dim3 grid, hipStream_t s) {
+    switch (A.D.K) {
+        case 1: hipLaunchKernelGGL((k_refine<1, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 2: hipLaunchKernelGGL((k_refine<2, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 3: hipLaunchKernelGGL((k_refine<3, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 4: hipLaunchKernelGGL((k_refine<4, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 5: hipLaunchKernelGGL((k_refine<5, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 6: hipLaunchKernelGGL((k_refine<6, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        case 7: hipLaunchKernelGGL((k_refine<7, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+        default: hipLaunchKernelGGL((k_refine<8, W, AVG>), grid, dim3(kWave), 0, s, A); break;
+    }
+}
+
+// Point-set averaging has kernels of its own, so that the plain refinement
+// keeps its register allocation.
 template <int W>
 void launch_refine_w(const LaunchArgs &A, dim3 grid, hipStream_t s) {
-    switch (A.D.K) {
-        case 1: hipLaunchKernelGGL((k_refine<1, W>), grid, dim3(kWave), 0, s, A); break;
-        case 2: hipLaunchKernelGGL((k_refine<2, W>), grid, dim3(kWave), 0, s, A); break;
-        case 3: hipLaunchKernelGGL((k_refine<3, W>), grid, dim3(kWave), 0, s, A); break;
-        case 4: hipLaunchKernelGGL((k_refine<4, W>), grid, dim3(kWave), 0, s, A); break;
-        case 5: hipLaunchKernelGGL((k_refine<5, W>), grid, dim3(kWave), 0, s, A); break;
-        case 6: hipLaunchKernelGGL((k_refine<6, W>), grid, dim3(kWave), 0, s, A); break;
-        case 7: hipLaunchKernelGGL((k_refine<7, W>), grid, dim3(kWave), 0, s, A); break;
-        default: hipLaunchKernelGGL((k_refine<8, W>), grid, dim3(kWave), 0, s, A); break;
-    }
+    if (A.rb.nk) launch_refine_wa<W, true>(A, grid, s);
+    else launch_refine_wa<W, false>(A, grid, s);
 }
 
 void launch_refine(const LaunchArgs &A, hipStream_t s) {

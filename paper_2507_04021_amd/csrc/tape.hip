@@ -88,10 +88,8 @@ __device__ __forceinline__ SlotCoef load_coef(const float *coef, size_t s) {
 // factor a0 = lambda/(4 pi) sqrt(4 cos_s / N) / r_s and the phase length.
 __device__ __forceinline__ bool diffuse_geom(const LaunchArgs &A, uint32_t ri, f3 rx, float budget, float &a0,
                                              float &plen) {
-    const int id = A.rb.id[ri];
     const float4 xl = A.rb.xl[ri];
-    f3 n = xyz(A.S.nrm[id]);
-    if (A.rb.cs[ri] < 0.f) n = (-1.f) * n;
+    const f3 n = record_normal(A, ri);
     const f3 v = rx - xyz(xl);
     const float rs = len(v);
     const float cos_s = dot(v, n) / rs;

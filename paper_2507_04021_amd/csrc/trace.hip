@@ -36,7 +36,8 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
                                           uint32_t &n_ray, uint32_t &n_spill) {
     const uint32_t K = A.D.K;
     const bool want_diff = A.flags & 4, want_spec = A.flags & 2;
-    const bool want_geom = A.flags & (4 | 8);  // points/lengths/cosines feed diffuse and the tape
+    const bool want_geom = A.flags & (4 | 8 | 32);  // points/lengths/cosines: diffuse, tape, averaged planes
+    const bool avg = A.flags & 32;             // weighted-average intersection over point sets
     const int it = find_item(A.items, A.D.n_items, g);
     const Item I = A.items[it];
     const uint32_t local = g - I.ray_off;
@@ -61,6 +62,10 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
         if (h < 0) break;
         const float4 pn = A.S.nrm[h];
         f3 n = xyz(pn);
+        if (avg) {  // the point set's weighted average replaces the disk's point and normal
+            dps_average(A.S, o, d, excl, A.thr.eps_self, A.thr.lambda_d, h, t, n);
+            A.rb.nk[rb + k] = make_float4(n.x, n.y, n.z, 0.f);
+        }
         float dn = dot(d, n);
         float sgn = dn > 0.f ? -1.f : 1.f;
         float cosi = fabsf(dn);

@@ -340,6 +340,25 @@ def single_disk(center, normal, radius, material=0, surface=0) -> Scene:
                  material + 1, surface + 1, dict(kind="disk"))
 
 
+def noisy(sc: Scene, seed: int, pos_sigma: float = 0.005, normal_jitter_deg: float = 3.0,
+          radius: float | None = None) -> Scene:
+    """A copy with the office's scanner-like noise: isotropic Gaussian position
+    noise and a Gaussian tangent-plane tilt of the normals."""
+    rng = np.random.default_rng(seed)
+    pos = sc.pos.astype(np.float64) + rng.normal(0.0, pos_sigma, size=sc.pos.shape)
+    nrm = sc.normal.astype(np.float64)
+    a = np.where(np.abs(nrm[:, 0:1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    t1 = np.cross(nrm, a)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    g = rng.normal(0.0, math.tan(math.radians(normal_jitter_deg)), size=(sc.n, 2))
+    nrm = nrm + g[:, :1] * t1 + g[:, 1:] * t2
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    info = dict(sc.info, noise=(seed, pos_sigma, normal_jitter_deg))
+    return _pack(pos, nrm, sc.material, sc.surface, sc.radius if radius is None else radius, sc.n_labels,
+                 sc.n_surfaces, info)
+
+
 def concat(scenes) -> Scene:
     pos = np.concatenate([s.pos for s in scenes])
     nrm = np.concatenate([s.normal for s in scenes])

@@ -97,6 +97,16 @@ def test_scene_argument_errors(L):
     assert L.pcrt_scene_create(ctypes.byref(pts), None, ctypes.c_void_p(fake), 16, None,
                                ctypes.byref(h)) == ENOMEM
     assert b"need" in L.pcrt_last_error()
+    # point sets: a negative or non-finite voxel edge is refused; a positive one adds 44+ bytes per point
+    for bad in (-0.1, float("nan"), float("inf")):
+        opts = P.BvhOpts(4, 4, 2, bad)
+        assert L.pcrt_scene_create(ctypes.byref(pts), ctypes.byref(opts), ctypes.c_void_p(fake), 1 << 30, None,
+                                   ctypes.byref(h)) == EINVAL
+        assert b"dps_voxel" in L.pcrt_last_error()
+    plain, sets = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(P.BvhOpts(4, 4, 2)), ctypes.byref(plain)) == 0
+    assert L.pcrt_scene_workspace_size(1000, ctypes.byref(P.BvhOpts(4, 4, 2, 0.0625)), ctypes.byref(sets)) == 0
+    assert sets.value >= plain.value + 1000 * 44
 
 
 def test_solve_argument_errors(L):
@@ -119,3 +129,30 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(P, "_libs", {})
     with pytest.raises(ImportError):
         P.lib()
+
+
+STRUCTS = [("pcrt_points", "Points"), ("pcrt_bvh_opts", "BvhOpts"), ("pcrt_scene_info", "SceneInfo"),
+           ("pcrt_thresholds", "Thresholds"), ("pcrt_solve_params", "SolveParams"), ("pcrt_batch_item", "BatchItem"),
+           ("pcrt_tuning", "Tuning"), ("pcrt_mlp", "Mlp"), ("pcrt_tape", "Tape"), ("pcrt_outputs", "Outputs")]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Size and every field offset of the binding's ctypes mirrors equal what a
+    C compiler makes of include/pcrt.h."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pcrt.h"', "int main(void) {"]
+    for cname, pname in STRUCTS:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in getattr(P, pname)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, pname in STRUCTS:
+        cls = getattr(P, pname)
+        assert int(got["%s size" % cname]) == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert int(got["%s %s" % (cname, f[0])]) == getattr(cls, f[0]).offset, (cname, f[0])

@@ -52,10 +52,13 @@ def test_cfr_matches_oracle(env, orc, flags, scatter):
         scale = np.abs(ref[r]).max()
         err = np.abs(h[r] - ref[r]).max()
         assert err <= 5e-4 * scale, (r, err, scale)
-    # the centre sample is the tape's coherent field
+    # the centre sample is the tape's coherent field. Both sums add the same
+    # paths in FP64, but each kernel evaluates the FP32 path amplitudes in
+    # its own code, where the compiler may contract products differently:
+    # a few FP32 ulps per amplitude (~1e-7 relative), hence 1e-6.
     _, h_te, h_tm, _ = P.tape_forward(rec)
     hte = torch.view_as_complex(h_te.reshape(-1, 2).contiguous()).cpu().numpy()
-    np.testing.assert_allclose(h[:, NF // 2, 0], hte, rtol=1e-12, atol=1e-12 * np.abs(hte).max())
+    np.testing.assert_allclose(h[:, NF // 2, 0], hte, rtol=1e-6, atol=1e-6 * np.abs(hte).max())
 
 
 def test_cfr_gradient_matches_finite_differences(env, orc):

@@ -1,0 +1,178 @@
+"""Point sets and the weighted-average intersection (Sec. II-A, II-C, Eq. 3-4):
+GPU library vs the CPU oracle, through the C ABI.
+
+Bars:
+  - set count: identical to the number of distinct voxels floor(p / rho) of
+    the FP32 centres (integer work);
+  - interaction sequences: >= 99.9 % of rays identical (an FP32 vs FP64 rim
+    or tie decision may legitimately send a ray elsewhere);
+  - incidence cosines of the averaged normals on identical rays: within
+    2e-5 for >= 99.9 % of the interactions. The averaged normal is a sum of
+    a few unit vectors with FP32 weights: a few ulp of FP32 (1.2e-7 each)
+    over ~10 terms, doubled by the normalisation, stays below 1e-5; the
+    rest allows a member whose rim test flips between FP32 and FP64;
+  - diffuse visibility on identical rays: >= 99.9 % identical;
+  - per-receiver power parts: 2e-3 relative (the 0.1 % of rays that may
+    differ each carry ~1/N of the diffuse power).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2507_04021_amd import scenes
+
+pytestmark = pytest.mark.gpu
+LOS, SPEC, DIFF, REC, AVG = 1, 2, 4, 8, 32
+RHO, LAM = 0.0625, 100.0
+
+
+def step(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    import paper_2507_04021_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def room():
+    return scenes.noisy(scenes.box_room(spacing=0.025, radius=0.02, size=(3.0, 2.0, 2.5)), seed=3)
+
+
+def voxel_count(sc, rho):
+    v = np.floor(sc.pos.astype(np.float64) / np.float64(np.float32(rho)))
+    return len(np.unique(v, axis=0))
+
+
+@pytest.mark.parametrize("rho", [RHO, 0.01, 0.5])
+def test_point_set_count(P, room, rho):
+    step("point sets rho=%g" % rho)
+    sg = P.Scene.from_scene(room, dps_voxel=rho)
+    assert sg.info["n_point_sets"] == voxel_count(room, rho)
+    assert sg.info["dps_voxel"] == pytest.approx(rho)
+
+
+def test_average_needs_point_sets(P, room):
+    step("average without point sets")
+    sg = P.Scene.from_scene(room)
+    assert sg.info["n_point_sets"] == 0
+    with pytest.raises(P.PcrtError) as e:
+        P.solve(sg, scenes.box_room_materials(), [1.5, 1.0, 1.2], [[0.5, 0.5, 1.0]], 3.5e9, 100, K=2,
+                flags=LOS | SPEC | AVG)
+    assert e.value.code == -1  # PCRT_EINVAL
+
+
+@pytest.mark.parametrize("leaf,width,builder", [(2, 4, 2), (4, 2, 1), (1, 8, 2)])
+def test_average_solve_parity(P, orc, room, leaf, width, builder):
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    tx = [1.1, 0.7, 1.3]
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    N, K = 3000, 3
+    step("average solve leaf=%d width=%d builder=%d" % (leaf, width, builder))
+    sg = P.Scene.from_scene(room, leaf_size=leaf, width=width, builder=builder, dps_voxel=RHO)
+    r = P.solve(sg, mats, tx, rx, 3.5e9, N, K=K, flags=LOS | SPEC | DIFF | REC | AVG, want_seq=True,
+                lambda_d=LAM)
+    ref = orc.solve(room, mats, tx, rx, 3.5e9, N, K=K, flags=LOS | SPEC | DIFF, want_dvis=True,
+                    average=(RHO, LAM))
+    seq = r.seq.cpu().numpy()
+    same = np.all(seq == ref.seq, 1)
+    assert same.mean() >= 0.999
+    tape = P.tape(r)
+    cos = tape["cos"][:N * K].cpu().numpy().reshape(N, K)
+    has = same[:, None] & (ref.seq >= 0)
+    err = np.abs(cos[has] - ref.rec[..., 4][has])
+    assert has.sum() > N
+    assert (err <= 2e-5).mean() >= 0.999
+    vis = P.diffuse_vis(r).cpu().numpy().astype(bool)
+    assert (vis[same] == ref.dvis[same]).mean() >= 0.999
+    parts = r.parts.cpu().numpy()
+    for c, ref_part in enumerate((ref.G_los, ref.G_spec, ref.G_diff)):
+        assert np.allclose(parts[:, c], ref_part, rtol=2e-3, atol=1e-30)
+    # specular paths refined on averaged planes and validated on averaged hits
+    pth = P.paths(r)
+    gp = {}
+    for q in range(pth["n_keys"]):
+        key = tuple(int(room.surface[i]) for i in pth["key_seq"][q, :int(pth["key_len"][q])])
+        for j in range(len(rx)):
+            if pth["valid"][q, j]:
+                gp[(j, key)] = float(pth["length"][q, j])
+    op = {(j, k): v[0] for j in range(len(rx)) for k, v in ref.paths(j).items()}
+    step("paths: gpu %d oracle %d common %d" % (len(gp), len(op), len(set(gp) & set(op))))
+    assert len(op) > 0
+    assert len(set(gp) ^ set(op)) <= max(1, len(op) // 50)
+    for k in set(gp) & set(op):
+        assert abs(gp[k] - op[k]) <= 2e-6 * op[k]
+
+
+def test_average_changes_the_result(P, orc, room):
+    """The averaging is live: on the first interaction (same nearest disk in both
+    modes) the incidence cosine moves wherever the set holds more than one
+    intersected disk; the GPU moves as many as the oracle does."""
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    tx, N = [1.1, 0.7, 1.3], 2000
+    step("average vs plain")
+    sg = P.Scene.from_scene(room, dps_voxel=RHO)
+    a = P.solve(sg, mats, tx, [[2.2, 1.4, 1.0]], 3.5e9, N, K=3, flags=LOS | DIFF | REC, want_seq=True)
+    b = P.solve(sg, mats, tx, [[2.2, 1.4, 1.0]], 3.5e9, N, K=3, flags=LOS | DIFF | REC | AVG, want_seq=True,
+                lambda_d=LAM)
+    first = np.arange(N) * 3
+    ca, cb = P.tape(a)["cos"].cpu().numpy()[first], P.tape(b)["cos"].cpu().numpy()[first]
+    _, ra = orc.trace(room, tx, N, K=1)
+    _, rb = orc.trace(room, tx, N, K=1, average=(RHO, LAM))
+    moved_gpu = np.mean(np.abs(ca - cb) > 1e-4)
+    moved_orc = np.mean(np.abs(ra[:, 0, 4] - rb[:, 0, 4]) > 1e-4)
+    assert moved_orc > 0.1
+    assert abs(moved_gpu - moved_orc) <= 0.01
+    assert abs(a.gain.item() - b.gain.item()) > 1e-6 * abs(a.gain.item())
+
+
+def test_average_batch_matches_single(P, room):
+    """Batched transmitters with averaging give each single solve's gains."""
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    step("average batch")
+    sg = P.Scene.from_scene(room, dps_voxel=RHO)
+    tx = np.array([[1.1, 0.7, 1.3], [2.0, 1.2, 0.9]], np.float32)
+    rx = [[2.2, 1.4, 1.0], [0.6, 1.5, 1.6]]
+    fl = LOS | SPEC | DIFF | AVG
+    g = P.solve_batch(sg, mats, tx, [1500, 700], rx, 3.5e9, K=3, flags=fl, lambda_d=LAM).gain.cpu().numpy()
+    for i in range(2):
+        s = P.solve(sg, mats, tx[i], rx, 3.5e9, [1500, 700][i], K=3, flags=fl, lambda_d=LAM).gain.cpu().numpy()
+        assert np.allclose(g[i], s, rtol=1e-12)
+
+
+def test_average_specular_paths_parity(P, orc):
+    """Milder noise (1 mm, 0.5 deg) leaves many valid specular paths: the GPU
+    finds the oracle's paths, with the same lengths, when planes and
+    validation hits are averaged."""
+    calm = scenes.noisy(scenes.box_room(spacing=0.025, radius=0.02, size=(3.0, 2.0, 2.5)), seed=3,
+                        pos_sigma=0.001, normal_jitter_deg=0.5)
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    step("average specular paths")
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    r = P.solve(sg, mats, [1.1, 0.7, 1.3], rx, 3.5e9, 3000, K=3, flags=SPEC | REC | AVG, lambda_d=LAM)
+    ref = orc.solve(calm, mats, [1.1, 0.7, 1.3], rx, 3.5e9, 3000, K=3, flags=SPEC, average=(RHO, LAM))
+    pth = P.paths(r)
+    gp = {}
+    for q in range(pth["n_keys"]):
+        key = tuple(int(calm.surface[i]) for i in pth["key_seq"][q, :int(pth["key_len"][q])])
+        for j in range(len(rx)):
+            if pth["valid"][q, j]:
+                gp[(j, key)] = (float(pth["length"][q, j]), complex(pth["amp_te"][q, j]))
+    op = {(j, k): (v[0], v[1]) for j in range(len(rx)) for k, v in ref.paths(j).items()}
+    step("paths: gpu %d oracle %d common %d" % (len(gp), len(op), len(set(gp) & set(op))))
+    assert len(op) >= 50
+    assert len(set(gp) ^ set(op)) <= max(1, len(op) // 50)
+    k0 = 2 * np.pi * 3.5e9 / 299792458.0
+    for k in set(gp) & set(op):
+        assert abs(gp[k][0] - op[k][0]) <= 2e-6 * op[k][0]
+        # 1e-4 in magnitude plus the phase of a 4 um FP32 path-length error
+        assert abs(gp[k][1] - op[k][1]) <= (1e-4 + k0 * 4e-6) * abs(op[k][1])
