@@ -69,17 +69,16 @@ def algorithmic_bytes(cnt, K, n_rx, stage, width=2):
 
     Traversal: 32 W bytes per node of width W visited + 32 B per disk tested
     (counted by the instrumented build). Streams: the trace kernel writes a
-    48 B record per interaction; the diffuse kernel reads that record (40 B)
-    plus the hit normal (16 B) once per (interaction, receiver group of 64
-    lanes) and writes 40 B of FP64 partial sums per (ray chunk, receiver).
+    48 B record per interaction; the diffuse kernel reads every record slot's
+    packed copy (32 B) and its index (4 B) once per receiver and writes 40 B
+    of FP64 partial sums per (ray chunk of 256, receiver).
     """
     nb = 32 * width
     if stage == "trace":
         return cnt["trace_nodes"] * nb + cnt["trace_disks"] * 32 + cnt["interactions"] * 48
     if stage == "diffuse":
-        groups = max(1, (n_rx + 63) // 64)
-        chunks = (cnt["rays"] + 127) // 128
-        return (cnt["diffuse_nodes"] * nb + cnt["diffuse_disks"] * 32 + cnt["interactions"] * 56 * groups
+        chunks = (cnt["rays"] + 255) // 256
+        return (cnt["diffuse_nodes"] * nb + cnt["diffuse_disks"] * 32 + chunks * 256 * K * n_rx * 36
                 + chunks * n_rx * 40)
     if stage == "refine":
         return cnt["refine_nodes"] * nb + cnt["refine_disks"] * 32

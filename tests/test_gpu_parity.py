@@ -125,7 +125,7 @@ def test_random_scene_full_parity(P, orc, n_disks, seed, leaf, width, builder):
 
 @pytest.mark.parametrize("n_rays,n_rx", [(1, 1), (129, 3), (1000, 65), (777, 300)])
 def test_ragged_sizes(P, orc, n_rays, n_rx):
-    """Ray counts off the 128-ray chunk, receiver counts off the 64/256-lane groups."""
+    """Ray counts off the 256-ray chunk, receiver counts off the 64/256-lane groups."""
     s = scenes.random_disks(400, seed=9, extent=1.5, radius=0.25)
     mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2], [2.0, 0.01, 0.5]])
     rng = np.random.default_rng(n_rx)
