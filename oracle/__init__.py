@@ -116,6 +116,24 @@ def average(scene, o, d, rho, lambda_d, excl=None, eps_self=1e-3, eps_tie=1e-4):
     return oid, ot, on
 
 
+def visibility(scene, rho, rx, eps_self=1e-3):
+    """Point sets of voxel edge rho: (reception points float32[n_sets, 3],
+    visibility uint8[n_rx, n_sets] from the receivers rx)."""
+    rx = _f32(rx).reshape(-1, 3)
+    L = _load()
+    ns = ctypes.c_int64(0)
+    args = (ctypes.c_int64(scene.n), _p(scene.pos), _p(scene.normal), _radius(scene),
+            ctypes.c_double(float(np.float32(rho))), ctypes.c_int32(rx.shape[0]), _p(rx), ctypes.c_double(eps_self),
+            ctypes.byref(ns))
+    if L.orc_visibility(*args, None, None):
+        raise ValueError("oracle visibility: bad scene")
+    recv = np.empty((ns.value, 3), np.float32)
+    vis = np.empty((rx.shape[0], ns.value), np.uint8)
+    if L.orc_visibility(*args, _p(recv), _p(vis)):
+        raise ValueError("oracle visibility: bad scene")
+    return recv, vis
+
+
 def occluded(scene, a, b, excl=None, eps_self=1e-3):
     a = np.ascontiguousarray(a, np.float64).reshape(-1, 3)
     b = np.ascontiguousarray(b, np.float64).reshape(-1, 3)

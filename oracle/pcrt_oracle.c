@@ -13,7 +13,9 @@
  *   - Each point is a planar disk of radius r_p (Sec. II-C).
  *   - Optionally, the points are grouped into voxels of edge rho (Sec. II-A)
  *     and an interaction is the weighted average over the intersected disks
- *     of the hit disk's voxel (Sec. II-C, Eq. 3-4).
+ *     of the hit disk's voxel (Sec. II-C, Eq. 3-4). Each set's reception
+ *     point and its visibility from every receiver form the visibility
+ *     matrix (Sec. II-A, II-B).
  *   - Rays keep a constant count; every interaction continues as a specular
  *     reflection (Sec. II-B).
  *   - Diffuse scattering is the last interaction, validated by a ray from the
@@ -617,6 +619,68 @@ int orc_average_batch(int64_t n_pts, const float *pos, const float *nrm, double 
             continue;
         }
         dps_average(&s, &g, o + 3 * k, dd, excl[k], eps_self, h, lambda_d, &out_t[k], out_n + 3 * k);
+    }
+    dps_free(&g);
+    scene_free(&s);
+    return 0;
+}
+
+/* ------------------------------------------ visibility matrix (Sec. II-B) */
+/* Reception point of a point set: the mean of its members' centres (summed in
+ * FP64 in ascending index, then rounded to FP32 like every scene coordinate).
+ * Visibility of reception point j from receiver r: the open segment between
+ * them meets no disk outside set j farther than eps_self from both ends (the
+ * set's own disks surround its reception point and are not tested). */
+static void reception_point(const scene_t *s, const dps_t *g, int64_t j, double *c)
+{
+    double acc[3] = {0, 0, 0};
+    for (int64_t m = g->off[j]; m < g->off[j + 1]; ++m)
+        for (int k = 0; k < 3; ++k) acc[k] += s->p[3 * g->mem[m] + k];
+    const double n = (double)(g->off[j + 1] - g->off[j]);
+    for (int k = 0; k < 3; ++k) c[k] = (double)(float)(acc[k] / n);
+}
+
+static int occluded_but_set(const scene_t *s, const dps_t *g, const double *a, const double *b, int64_t set,
+                            double eps_self)
+{
+    double d[3];
+    sub3(d, b, a);
+    double len = norm3(d);
+    scale3(d, 1.0 / len);
+    double t, q[3], d2;
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (g->of[i] == set) continue;
+        if (ray_disk(s, i, a, d, &t, q, &d2) && t > eps_self && t < len - eps_self) return 1;
+    }
+    return 0;
+}
+
+/* Point sets of voxel edge rho: *n_sets; with out_recv (float[n_sets][3]) the
+ * reception points; with out_vis (uint8[n_rx][n_sets]) the visibility matrix
+ * from the receivers rx32 (float[n_rx][3]). */
+int orc_visibility(int64_t n_pts, const float *pos, const float *nrm, double r, double rho, int32_t n_rx,
+                   const float *rx32, double eps_self, int64_t *n_sets, float *out_recv, uint8_t *out_vis)
+{
+    scene_t s;
+    int rc = scene_init(&s, n_pts, pos, nrm, NULL, NULL, r);
+    if (rc) { scene_free(&s); return rc; }
+    dps_t g;
+    if (dps_build(&g, &s, rho)) { scene_free(&s); return -2; }
+    *n_sets = g.n_sets;
+    if (out_recv || out_vis) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t j = 0; j < g.n_sets; ++j) {
+            double c[3];
+            reception_point(&s, &g, j, c);
+            if (out_recv)
+                for (int k = 0; k < 3; ++k) out_recv[3 * j + k] = (float)c[k];
+            if (out_vis)
+                for (int32_t q = 0; q < n_rx; ++q) {
+                    double a[3];
+                    from_f32(a, rx32 + 3 * q);
+                    out_vis[(int64_t)q * g.n_sets + j] = (uint8_t)!occluded_but_set(&s, &g, a, c, j, eps_self);
+                }
+        }
     }
     dps_free(&g);
     scene_free(&s);

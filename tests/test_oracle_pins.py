@@ -619,3 +619,47 @@ def test_average_on_exact_planes_keeps_the_specular_paths(orc, room_holefree):
         for key in pa:
             assert pb[key][0] == pytest.approx(pa[key][0], rel=1e-9)
 
+
+
+# ------------------------------------ visibility matrix (Sec. II-A, II-B)
+def test_reception_points_are_set_means(orc):
+    s = scenes.random_disks(3000, seed=21, extent=1.0, radius=0.05)
+    recv, vis = orc.visibility(s, 0.5, [[0.0, 0.0, 0.0]])
+    p = s.pos.astype(np.float64)
+    v = np.floor(p / np.float64(np.float32(0.5)))
+    keys, inv = np.unique(v, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    mean = np.stack([np.bincount(inv, weights=p[:, k]) for k in range(3)], 1) / np.bincount(inv)[:, None]
+    assert recv.shape == (len(keys), 3) and vis.shape == (1, len(keys))
+    assert np.allclose(recv, mean.astype(np.float32), rtol=0, atol=2e-7)
+
+
+def test_visibility_behind_a_blocker_closed_form(orc):
+    """A floor patch at z = 0 and one blocking disk (z = 0.5) under a receiver at
+    z = 1, all disks of radius 0.15: a reception point is hidden iff the segment
+    crosses z = 0.5 within 0.15 of the blocker's centre (points clear of the rim)."""
+    R = 0.15
+    floor = scenes.plane_patch(0.0, 1.2, 0.0, 1.2, 0.1, R)
+    sc = scenes.concat([floor, scenes.single_disk([0.6, 0.6, 0.5], [0, 0, 1], R)])
+    rx = np.array([[0.5, 0.5, 1.0]], np.float32)
+    recv, vis = orc.visibility(sc, 0.25, rx)
+    mid = rx[0].astype(np.float64) + 0.5 * (recv.astype(np.float64) - rx[0])
+    dist = np.linalg.norm(mid[:, :2] - [0.6, 0.6], axis=1)
+    on_floor = np.abs(recv[:, 2]) < 1e-6
+    sel = on_floor & (np.abs(dist - R) > 1e-3)
+    assert sel.sum() >= 20
+    assert np.array_equal(vis[0, sel].astype(bool), dist[sel] > R)
+    assert (dist[sel] <= R).any() and (dist[sel] > R).any()
+
+
+def test_visibility_ignores_the_own_set_only(orc):
+    """A disk 2 cm above a reception point on the segment towards the receiver:
+    no occluder while it belongs to the same voxel, an occluder once it sits in
+    the voxel above."""
+    base = [scenes.single_disk([0.10 + 0.01 * i, 0.10, 0.05], [0, 0, 1], 0.02) for i in range(3)]
+    rx = np.array([[0.11, 0.10, 1.0]], np.float32)
+    for z, visible in ((0.07, True), (0.13, False)):
+        sc = scenes.concat(base + [scenes.single_disk([0.11, 0.10, z], [0, 0, 1], 0.02)])
+        recv, vis = orc.visibility(sc, 0.125, rx)
+        j = int(np.argmin(np.abs(recv[:, 2] - 0.05) + np.abs(recv[:, 0] - 0.11)))
+        assert bool(vis[0, j]) == visible
