@@ -13,6 +13,7 @@ dominant kernel's roofline, the oracle's CPU baseline on a bounded sample).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -265,6 +266,22 @@ def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
         out[name] = dict(ms_per_solve=ms, stage_ms={k: v / reps for k, v in stage.items()},
                          counts={k: cnt[k] for k in ("interactions", "keys", "candidates", "specular", "diffuse")},
                          gain_db_mean=float(10 * torch.log10(o["gain"]).mean().item()))
+    # visibility matrix: every receiver against every set's reception point
+    vis = P.visibility(scene, rx_t)
+    nb = ctypes.c_size_t(0)
+    P.lib().pcrt_visibility_workspace_size(scene.handle, ctypes.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        P.visibility(scene, rx_t, ws=ws, out=vis)
+    e1.record()
+    torch.cuda.synchronize()
+    vms = e0.elapsed_time(e1) / reps
+    n_seg = len(rx) * scene.info["n_point_sets"]
+    out["visibility_matrix"] = dict(ms=vms, segments=n_seg, segments_per_s=n_seg / (vms / 1e3),
+                                    visible_fraction=float(vis.float().mean().item()))
     return dict(workload="office as above with point radius 0.015 m, voxel 0.0625 m, lambda_d 100 /m, %d rays, "
                          "K=5, 64 RX, LOS+specular+diffuse" % rays,
                 n_point_sets=scene.info["n_point_sets"], build_ms=scene.info["build_ms"], **out)

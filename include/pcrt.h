@@ -124,6 +124,26 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
 pcrt_status pcrt_scene_get_info(const pcrt_scene *scene, pcrt_scene_info *info);
 pcrt_status pcrt_scene_destroy(pcrt_scene *scene);
 
+/* ------------------------------------------ visibility matrix (Sec. II-A, II-B) */
+/* Reception point of each point set: the mean of its members' centres (summed
+ * in FP64 in increasing point index, rounded to FP32). out: device
+ * float[n_point_sets][3]. Errors: EINVAL without point sets or NULL pointers. */
+pcrt_status pcrt_reception_points(const pcrt_scene *scene, float *out, void *stream);
+
+/* Device workspace of pcrt_visibility (traversal stack spill; >= 256 bytes). */
+pcrt_status pcrt_visibility_workspace_size(const pcrt_scene *scene, size_t *bytes);
+
+/* Visibility matrix: vis[r][j] = 1 when receiver r sees reception point j,
+ * i.e. the open segment between them meets no disk outside set j farther
+ * than eps_self (0 = 1e-3 m) from both ends; else 0. rx: device
+ * float[n_rx][3]; vis: device uint8[n_rx][n_point_sets], overwritten. The
+ * result does not depend on the hierarchy options. Asynchronous on stream,
+ * allocates nothing. Errors: EINVAL without point sets, for NULL pointers,
+ * n_rx == 0 or a negative eps_self; ENOMEM for a small ws; EUNSUPPORTED for
+ * n_rx x n_point_sets >= 2^32. */
+pcrt_status pcrt_visibility(const pcrt_scene *scene, const float *rx, uint32_t n_rx, float eps_self, void *ws,
+                            size_t ws_bytes, uint8_t *vis, void *stream);
+
 /* ------------------------------------------------------------------ solve */
 /* Material of one label: relative permittivity, conductivity (S/m) and
  * scattering coefficient S in [0, 1]. Specular reflections carry

@@ -117,6 +117,9 @@ def lib(variant=None) -> ctypes.CDLL:
                                         ctypes.POINTER(vp)]
         L.pcrt_scene_get_info.argtypes = [vp, ctypes.POINTER(SceneInfo)]
         L.pcrt_scene_destroy.argtypes = [vp]
+        L.pcrt_reception_points.argtypes = [vp, vp, vp]
+        L.pcrt_visibility_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+        L.pcrt_visibility.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_float, vp, sz, vp, vp]
         L.pcrt_solve_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]
         L.pcrt_solve.argtypes = [vp, vp, u32, ctypes.POINTER(SolveParams), vp, sz, ctypes.POINTER(Outputs), vp]
         L.pcrt_paths_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, u32, vp, vp, vp, vp, vp, vp, vp,
@@ -221,6 +224,34 @@ class Scene:
         if h is not None and _libs:
             lib(self._variant).pcrt_scene_destroy(h)
             self.handle = None
+
+
+def reception_points(scene: Scene, stream=None):
+    """float32[n_point_sets, 3] device tensor: the mean centre of each point set."""
+    torch = _torch()
+    L = lib(scene._variant)
+    out = torch.empty(max(scene.info["n_point_sets"], 1), 3, dtype=torch.float32, device=scene.device)
+    _check(L.pcrt_reception_points(scene.handle, _ptr(out), _stream(stream)), L)
+    return out[:scene.info["n_point_sets"]]
+
+
+def visibility(scene: Scene, rx, eps_self=0.0, ws=None, out=None, stream=None):
+    """uint8[n_rx, n_point_sets] device tensor: 1 where the receiver sees the
+    set's reception point (the set's own disks aside)."""
+    torch = _torch()
+    L = lib(scene._variant)
+    rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
+                torch.float32, scene.device).reshape(-1, 3)
+    nb = ctypes.c_size_t(0)
+    _check(L.pcrt_visibility_workspace_size(scene.handle, ctypes.byref(nb)), L)
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=scene.device)
+    n = scene.info["n_point_sets"]
+    if out is None:
+        out = torch.empty(rx_t.shape[0], max(n, 1), dtype=torch.uint8, device=scene.device)
+    _check(L.pcrt_visibility(scene.handle, _ptr(rx_t), rx_t.shape[0], float(eps_self), _ptr(ws), ws.numel(),
+                             _ptr(out), _stream(stream)), L)
+    return out[:, :n]
 
 
 def materials_tensor(mats, device="cuda"):

@@ -478,6 +478,45 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     return ok();
 }
 
+static size_t visibility_spill_bytes(const pcrt_scene *sc) {
+    const uint32_t depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;
+    return sizeof(int) * (size_t)depth * visibility_grid(sc->info.width) * kWave;
+}
+
+pcrt_status pcrt_visibility_workspace_size(const pcrt_scene *scene, size_t *bytes) {
+    if (!scene || !bytes) return fail(PCRT_EINVAL, "scene and bytes are required");
+    *bytes = std::max<size_t>(256, visibility_spill_bytes(scene));
+    return ok();
+}
+
+pcrt_status pcrt_visibility(const pcrt_scene *scene, const float *rx, uint32_t n_rx, float eps_self, void *ws,
+                            size_t ws_bytes, uint8_t *vis, void *stream) {
+    if (!scene || !rx || !vis || !ws) return fail(PCRT_EINVAL, "scene, rx, ws and vis are required");
+    if (!scene->dev.dps_pt) return fail(PCRT_EINVAL, "the scene has no point sets (dps_voxel = 0)");
+    if (n_rx == 0) return fail(PCRT_EINVAL, "n_rx must be > 0");
+    if (!(eps_self >= 0.f) || !std::isfinite(eps_self)) return fail(PCRT_EINVAL, "eps_self must be >= 0");
+    const size_t need = std::max<size_t>(256, visibility_spill_bytes(scene));
+    if (ws_bytes < need) return fail(PCRT_ENOMEM, "visibility workspace too small: need %zu bytes", need);
+    if ((uint64_t)n_rx * scene->info.n_point_sets > 0xffffffffull)
+        return fail(PCRT_EUNSUPPORTED, "n_rx x point sets must stay below 2^32");
+    DevScene S = scene->dev;
+    S.spill = (int *)ws;
+    S.spill_lanes = visibility_grid(scene->info.width) * kWave;
+    launch_visibility(S, rx, n_rx, (const float4 *)(scene->ws + scene->L.dps_recv), scene->info.n_point_sets,
+                      eps_self > 0.f ? eps_self : 1e-3f, vis, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+pcrt_status pcrt_reception_points(const pcrt_scene *scene, float *out, void *stream) {
+    if (!scene || !out) return fail(PCRT_EINVAL, "scene and out are required");
+    if (!scene->dev.dps_pt) return fail(PCRT_EINVAL, "the scene has no point sets (dps_voxel = 0)");
+    launch_recv_copy((const float4 *)(scene->ws + scene->L.dps_recv), scene->info.n_point_sets, out,
+                     (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
 pcrt_status pcrt_scene_get_info(const pcrt_scene *scene, pcrt_scene_info *info) {
     if (!scene || !info) return fail(PCRT_EINVAL, "scene and info are required");
     *info = scene->info;

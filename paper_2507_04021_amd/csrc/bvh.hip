@@ -578,6 +578,7 @@ SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps)
         L.dps_flag = b.take(sizeof(uint32_t) * n);
         L.dps_blk = b.take(sizeof(uint32_t) * scan_blk_words(n));
         L.dps_stat = b.take(sizeof(uint32_t) * 2);
+        L.dps_recv = b.take(sizeof(float4) * n);
     }
     L.total = b.off;
     return L;

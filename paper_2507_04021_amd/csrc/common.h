@@ -60,7 +60,7 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t off) {
 
 struct DevScene {
     const float4 *node;  // binary nodes (4 float4: child boxes + refs) or wide nodes (2W float4)
-    const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, 0)
+    const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, point set bits or 0)
     const float4 *pos;   // by id: (p.xyz, surface bits)
     const float4 *nrm;   // by id: (n.xyz, material bits)
     const float *bounds; // scene bounds of the disk centres: lo xyz, hi xyz
@@ -536,7 +536,8 @@ constexpr int kNoRef = -0x7fffffff - 1;
 // when every lane tests a leaf as soon as it reaches it. Parking only delays
 // disk tests: the walk order, and so the stack bound, are those of the plain
 // depth-first walk, and the answer is the same.
-template <int W>
+// excl: a disk id, or with BY_SET a point set whose disks are all ignored.
+template <int W, bool BY_SET = false>
 __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl, float eps_self, Stack &stk) {
     const f3 dv = b - a;
     const float L = len(dv);
@@ -571,7 +572,8 @@ __device__ __forceinline__ bool occluded(const DevScene &S, f3 a, f3 b, int excl
                 const float4 dn = ld4(S.disk, (uint32_t)(first + i) * 32u + 16u);
                 float t, d2;
                 const bool h = disk_hit(a, d, xyz(dp), xyz(dn), S.r2, t, d2);
-                if (h & (__float_as_int(dp.w) != excl) & (t > eps_self) & (t < t_hi)) return true;
+                const int who = BY_SET ? __float_as_int(dn.w) : __float_as_int(dp.w);
+                if (h & (who != excl) & (t > eps_self) & (t < t_hi)) return true;
             }
             park = kNoRef;
         }

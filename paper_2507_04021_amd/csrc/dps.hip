@@ -61,6 +61,34 @@ __global__ void k_set_fill(const uint64_t *__restrict__ key, const uint32_t *__r
     }
 }
 
+// Reception point of each set (Sec. II-A): the mean of its members' centres,
+// summed in FP64 in member order and rounded to FP32.
+__global__ void k_set_recv(const float4 *__restrict__ pt, const uint32_t *__restrict__ off,
+                           const uint32_t *__restrict__ stat, float4 *__restrict__ recv) {
+    const uint32_t n_sets = stat[1];
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_sets; g += gridDim.x * blockDim.x) {
+        double x = 0.0, y = 0.0, z = 0.0;
+        const uint32_t b = off[g], e = off[g + 1];
+        for (uint32_t m = b; m < e; ++m) {
+            const float4 p = pt[2 * (size_t)m];
+            x += p.x;
+            y += p.y;
+            z += p.z;
+        }
+        const double c = (double)(e - b);
+        recv[g] = make_float4((float)(x / c), (float)(y / c), (float)(z / c), 0.f);
+    }
+}
+
+// The set of every leaf-ordered disk goes into the spare word of its normal,
+// so walks that must ignore one set test it without another load.
+__global__ void k_disk_sets(float4 *__restrict__ disk, uint32_t n, const uint32_t *__restrict__ of) {
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int id = __float_as_int(disk[2 * (size_t)k].w);
+        disk[2 * (size_t)k + 1].w = __int_as_float((int)of[id]);
+    }
+}
+
 hipError_t build_point_sets(const SceneLayout &L, char *ws, uint32_t n, float rho, hipStream_t s) {
     auto P = [&](size_t o) { return ws + o; };
     uint64_t *k0 = (uint64_t *)P(L.code0), *k1 = (uint64_t *)P(L.code1);
@@ -78,6 +106,9 @@ hipError_t build_point_sets(const SceneLayout &L, char *ws, uint32_t n, float rh
     hipLaunchKernelGGL(k_set_fill, g, b, 0, s, key, id, flag, n, (const float4 *)P(L.pos_id),
                        (const float4 *)P(L.nrm_id), (float4 *)P(L.dps_pt), (uint32_t *)P(L.dps_off),
                        (uint32_t *)P(L.dps_of), stat);
+    hipLaunchKernelGGL(k_set_recv, g, b, 0, s, (const float4 *)P(L.dps_pt), (const uint32_t *)P(L.dps_off),
+                       (const uint32_t *)stat, (float4 *)P(L.dps_recv));
+    hipLaunchKernelGGL(k_disk_sets, g, b, 0, s, (float4 *)P(L.disk), n, (const uint32_t *)P(L.dps_of));
     return hipGetLastError();
 }
 

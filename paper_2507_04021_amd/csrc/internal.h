@@ -44,11 +44,16 @@ struct SceneLayout {
     size_t cbox[2] = {0, 0}, cid[2] = {0, 0}, csz[2] = {0, 0};  // clustering build (builder == kBuildPloc)
     size_t nn = 0, mflag = 0, kflag = 0, pblk = 0, nsize = 0, noff = 0, leaf_pos = 0, perm2 = 0, pleaf2 = 0;
     size_t wnode = 0, front0 = 0, front1 = 0, wcnt = 0, wblk = 0;  // wide collapse (width > 2)
-    size_t dps_pt = 0, dps_off = 0, dps_of = 0, dps_flag = 0, dps_blk = 0, dps_stat = 0;  // point sets
+    size_t dps_pt = 0, dps_off = 0, dps_of = 0, dps_flag = 0, dps_blk = 0, dps_stat = 0, dps_recv = 0;  // point sets
     size_t total;
 };
 
 SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps);
+// Visibility of the point sets' reception points from receivers (one uint8 per pair).
+uint32_t visibility_grid(uint32_t width);
+void launch_visibility(const DevScene &S, const float *rx, uint32_t n_rx, const float4 *recv, uint32_t n_sets,
+                       float eps_self, uint8_t *out, hipStream_t s);
+void launch_recv_copy(const float4 *recv, uint32_t n, float *out, hipStream_t s);
 // Point sets: voxel keys, sort, set boundaries (after build_scene, reusing its sort buffers).
 hipError_t build_point_sets(const SceneLayout &L, char *ws, uint32_t n, float rho, hipStream_t s);
 hipError_t build_wide(const SceneLayout &L, char *ws, hipStream_t s, int broot, uint32_t *levels, uint32_t *nodes);

@@ -118,6 +118,9 @@ def test_solve_argument_errors(L):
     ms = (ctypes.c_double * 6)()
     assert L.pcrt_stage_times(ms, 6) == EINVAL
     assert L.pcrt_scene_get_info(None, None) == EINVAL
+    assert L.pcrt_reception_points(None, None, None) == EINVAL
+    assert L.pcrt_visibility_workspace_size(None, ctypes.byref(nb)) == EINVAL
+    assert L.pcrt_visibility(None, None, 1, 0.0, None, 0, None, None) == EINVAL
     assert L.pcrt_tape_cfr(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
     assert L.pcrt_tape_cfr_backward(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
     assert L.pcrt_last_error()  # an explanation is always set on failure

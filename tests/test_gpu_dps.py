@@ -176,3 +176,44 @@ def test_average_specular_paths_parity(P, orc):
         assert abs(gp[k][0] - op[k][0]) <= 2e-6 * op[k][0]
         # 1e-4 in magnitude plus the phase of a 4 um FP32 path-length error
         assert abs(gp[k][1] - op[k][1]) <= (1e-4 + k0 * 4e-6) * abs(op[k][1])
+
+
+# ------------------------------------------- visibility matrix (Sec. II-A, II-B)
+def test_reception_points_match_oracle(P, orc, room):
+    """Both sides sum the members in FP64 in the same order: identical FP32."""
+    step("reception points")
+    sg = P.Scene.from_scene(room, dps_voxel=RHO)
+    g = P.reception_points(sg).cpu().numpy()
+    o, _ = orc.visibility(room, RHO, [[1.0, 1.0, 1.0]])
+    assert np.array_equal(g, o)
+
+
+def test_visibility_matrix_parity(P, orc, room):
+    """Receiver-to-reception-point visibility: >= 99.9 % identical to the
+    oracle (FP32 vs FP64 rim decisions may differ), and bitwise the same for
+    every node width, leaf size and builder."""
+    rx = np.array([[1.1, 0.7, 1.3], [2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    _, ref = orc.visibility(room, RHO, rx)
+    base = None
+    for leaf, width, builder in ((2, 4, 2), (4, 2, 1), (1, 8, 2), (8, 4, 1)):
+        step("visibility leaf=%d width=%d builder=%d" % (leaf, width, builder))
+        sg = P.Scene.from_scene(room, leaf_size=leaf, width=width, builder=builder, dps_voxel=RHO)
+        v = P.visibility(sg, rx).cpu().numpy()
+        assert v.shape == ref.shape
+        assert (v == ref).mean() >= 0.999
+        assert 0.2 < ref.mean() < 0.95
+        if base is None:
+            base = v
+        else:
+            assert np.array_equal(v, base)
+
+
+def test_visibility_errors(P, room):
+    step("visibility errors")
+    sg = P.Scene.from_scene(room)
+    with pytest.raises(P.PcrtError) as e:
+        P.visibility(sg, [[1.0, 1.0, 1.0]])
+    assert e.value.code == -1
+    with pytest.raises(P.PcrtError) as e:
+        P.reception_points(sg)
+    assert e.value.code == -1
