@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcrt_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-LOS, SPECULAR, DIFFUSE, TRACE, AVERAGE = 1, 2, 4, 8, 16
+LOS, SPECULAR, DIFFUSE, TRACE, AVERAGE, DPS_LAUNCH = 1, 2, 4, 8, 16, 32
 DEFAULT_THR = dict(eps_tie=1e-4, eps_self=1e-3, t_a_deg=1.0, t_d=0.01, kappa=10)
 C0 = 299792458.0
 
@@ -178,11 +178,17 @@ class Solution:
 
 
 def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SPECULAR,
-          thr=None, want_dvis=False, want_jac=False, cfr=None, average=None) -> Solution:
+          thr=None, want_dvis=False, want_jac=False, cfr=None, average=None, dps_launch=None) -> Solution:
     """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S).
 
     average = (rho, lambda_d): every interaction is the weighted average over
     the intersected disks of the hit disk's point set (voxels of edge rho).
+
+    dps_launch = rho: ray j goes from the transmitter towards the reception
+    point of point set j (ray_ids are set indices, n_budget the set count),
+    and a (key, receiver) pair is a specular candidate only where the
+    receiver sees the reception point of the set its representative ends in.
+    No diffuse paths in this mode.
 
     cfr = (bandwidth_hz, n_freq): also the channel frequency response, every
     path's centre-frequency amplitudes times exp(-j 2 pi (f_n - freq) L / c0)
@@ -193,6 +199,11 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     rho, lam = (float(np.float32(average[0])), float(average[1])) if average else (0.0, 0.0)
     if average:
         flags |= AVERAGE
+    if dps_launch:
+        if average and float(np.float32(dps_launch)) != rho:
+            raise ValueError("one voxel edge for averaging and launch")
+        rho = float(np.float32(dps_launch))
+        flags |= DPS_LAUNCH
     thr_arr = np.array([th["eps_tie"], th["eps_self"], th["t_a_deg"], th["t_d"], th["kappa"], rho, lam], np.float64)
     mats = np.ascontiguousarray(mats, np.float64).reshape(-1, 3)
     n_labels = mats.shape[0]

@@ -45,7 +45,8 @@
 #define ORC_KMAX 8
 
 enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4, ORC_TRACE = 8 /* trace even without paths */,
-       ORC_AVERAGE = 16 /* weighted-average intersection over point sets */ };
+       ORC_AVERAGE = 16 /* weighted-average intersection over point sets */,
+       ORC_DPS_LAUNCH = 32 /* rays towards the reception points, visibility-gated specular candidates */ };
 
 typedef struct {
     int64_t n;
@@ -742,11 +743,16 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     for (int64_t i = 0; i < n_pts; ++i)
         if (mat[i] >= (uint32_t)n_labels) { scene_free(&s); return -1; }
     thr_t th = {thr[0], thr[1], cos(thr[2] * ORC_PI / 180.0), thr[3], (int)thr[4]};
-    dps_t dps, *g = NULL;
-    if (flags & ORC_AVERAGE) {
-        if (!(thr[5] > 0.0) || !(thr[6] > 0.0)) { scene_free(&s); return -1; }
+    dps_t dps, *sets = NULL, *g = NULL; /* g: the sets when interactions are averaged */
+    if (flags & (ORC_AVERAGE | ORC_DPS_LAUNCH)) {
+        if (!(thr[5] > 0.0) || ((flags & ORC_AVERAGE) && !(thr[6] > 0.0))) { scene_free(&s); return -1; }
+        if ((flags & ORC_DPS_LAUNCH) && (flags & ORC_DIFFUSE)) { scene_free(&s); return -1; }
         if (dps_build(&dps, &s, thr[5])) { scene_free(&s); return -2; }
-        g = &dps;
+        sets = &dps;
+        if (flags & ORC_AVERAGE) g = &dps;
+        if (flags & ORC_DPS_LAUNCH)
+            for (int64_t q = 0; q < n_trace; ++q)
+                if (ray_ids[q] < 0 || ray_ids[q] >= dps.n_sets) { dps_free(&dps); scene_free(&s); return -1; }
     }
     em_t em = {n_labels, eps_r, sigma, scat, freq, 2.0 * ORC_PI * freq, ORC_C0 / freq, 0.0};
     em.k0 = 2.0 * ORC_PI / em.lambda;
@@ -782,7 +788,19 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     /* trace every requested ray */
     trace_t *tr = (trace_t *)malloc(sizeof(trace_t) * (size_t)(n_trace > 0 ? n_trace : 1));
     float *dirs = (float *)malloc(sizeof(float) * 3 * (size_t)(n_trace > 0 ? n_trace : 1));
-    orc_fib_dirs(n_budget, ray_ids, n_trace, dirs);
+    if (flags & ORC_DPS_LAUNCH) {
+        /* one ray towards each requested set's reception point (Sec. II-B):
+         * the direction in FP64, rounded to FP32 like the sphere directions */
+        for (int64_t q = 0; q < n_trace; ++q) {
+            double c[3], d[3];
+            reception_point(&s, sets, ray_ids[q], c);
+            sub3(d, c, tx);
+            scale3(d, 1.0 / norm3(d));
+            for (int k = 0; k < 3; ++k) dirs[3 * q + k] = (float)d[k];
+        }
+    } else {
+        orc_fib_dirs(n_budget, ray_ids, n_trace, dirs);
+    }
     if (flags & (ORC_SPECULAR | ORC_DIFFUSE | ORC_TRACE)) {
 #pragma omp parallel for schedule(dynamic, 8)
         for (int64_t q = 0; q < n_trace; ++q) trace_ray(&s, tx, dirs + 3 * q, K, &th, g, g ? thr[6] : 0.0, &tr[q]);
@@ -892,6 +910,17 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                 int64_t ki = pi / n_rx;
                 int r = (int)(pi % n_rx);
                 const keyrec_t *key = &uk[ki];
+                if (flags & ORC_DPS_LAUNCH) {
+                    /* candidate only where the receiver sees the reception point of the
+                     * set the representative's path ends in (the visibility matrix) */
+                    const int64_t j = sets->of[tr[key->slot].id[key->len - 1]];
+                    double c[3];
+                    reception_point(&s, sets, j, c);
+                    if (occluded_but_set(&s, sets, rx + 3 * r, c, j, th.eps_self)) {
+                        sp[pi].valid = 0;
+                        continue;
+                    }
+                }
                 specular_one(&s, tx, rx + 3 * r, key->len, key->s, &tr[key->slot], g, g ? thr[6] : 0.0, &th, &sp[pi]);
             }
             for (int64_t ki = 0; ki < nk; ++ki) {
@@ -953,7 +982,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
         }
     free(cfr.h);
     free(tr); free(dirs); free(rx); free(G_los); free(G_spec); free(G_diff); free(h_te); free(h_tm);
-    if (g) dps_free(g);
+    if (sets) dps_free(sets);
     scene_free(&s);
     return ret;
 }

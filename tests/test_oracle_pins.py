@@ -663,3 +663,40 @@ def test_visibility_ignores_the_own_set_only(orc):
         recv, vis = orc.visibility(sc, 0.125, rx)
         j = int(np.argmin(np.abs(recv[:, 2] - 0.05) + np.abs(recv[:, 0] - 0.11)))
         assert bool(vis[0, j]) == visible
+
+
+# ------------------------------- launch at the reception points (Sec. II-B)
+def test_dps_launch_hits_the_reception_points(orc):
+    """Flat, hole-free floor under the transmitter: the ray towards a set's
+    reception point meets the floor exactly there (the mean of coplanar
+    centres lies on the plane)."""
+    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, 0.05, 0.04)
+    recv, _ = orc.visibility(floor, 0.0625, [[1.0, 1.0, 1.0]])
+    ns = len(recv)
+    sol = orc.solve(floor, np.array([[5.0, 0.1, 0.0]]), [1.0, 1.0, 1.0], np.zeros((1, 3), np.float32), 3.5e9, ns,
+                    K=1, flags=SPEC, dps_launch=0.0625)
+    hit = sol.seq[:, 0] >= 0
+    assert hit.all()
+    err = np.abs(sol.rec[:, 0, :3] - recv.astype(np.float64)).max()
+    assert err < 1e-6  # FP32 direction rounding over ~1.4 m
+
+
+def test_dps_launch_gates_specular_candidates(orc):
+    """One-bounce floor path TX -> (1.25, 1, 0) -> RX. The key's representative
+    is the ray of set 0 (reception point near the origin); a small disk on the
+    segment from RX to that reception point, far from the path, removes the
+    candidate in this mode."""
+    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, 0.05, 0.04)
+    tx, rx = np.array([1.0, 1.0, 1.0], np.float32), np.array([[1.5, 1.0, 1.0]], np.float32)
+    mats = np.array([[5.0, 0.1, 0.0], [3.0, 0.1, 0.0]])
+    recv0, _ = orc.visibility(floor, 0.0625, rx)
+    c0 = recv0[0].astype(np.float64)
+    mid = 0.5 * (rx[0] + c0)
+    axis = (c0 - rx[0]) / np.linalg.norm(c0 - rx[0])
+    blocker = scenes.single_disk(mid, axis, 0.04, material=1, surface=1)
+    for sc, expect in ((floor, True), (scenes.concat([floor, blocker]), False)):
+        recv, vis = orc.visibility(sc, 0.0625, rx)
+        sol = orc.solve(sc, mats, tx, rx, 3.5e9, len(recv), K=1, flags=SPEC, dps_launch=0.0625)
+        assert sol.key_rep[sol.keys.index((0,))] == 0
+        assert bool(vis[0, 0]) == expect
+        assert ((0,) in sol.paths(0)) == expect
