@@ -282,6 +282,27 @@ def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
     n_seg = len(rx) * scene.info["n_point_sets"]
     out["visibility_matrix"] = dict(ms=vms, segments=n_seg, segments_per_s=n_seg / (vms / 1e3),
                                     visible_fraction=float(vis.float().mean().item()))
+    # the paper's launch: one ray per set towards its reception point, candidates gated by the matrix
+    ns = scene.info["n_point_sets"]
+    fl = P.LOS | P.SPECULAR | P.AVERAGE | P.DPS_LAUNCH
+    res = P.solve(scene, mats_t, tx, rx_t, 28e9, ns, K=5, flags=fl, lambda_d=100.0, dps_vis=vis)
+    o = dict(gain=res.gain, h_te=res.h_te, h_tm=res.h_tm, parts=res.parts, seq=None, counters=res.counters)
+    torch.cuda.synchronize()
+    stage = {k: 0.0 for k in P.STAGES}
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.solve(scene, mats_t, tx, rx_t, 28e9, ns, K=5, flags=fl | P.TIMING, ws=res.ws, out=o, lambda_d=100.0,
+                dps_vis=vis)
+        for k, v in P.stage_times().items():
+            stage[k] += v
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    cnt = {k: int(o["counters"][i].item()) for k, i in P.CNT.items()}
+    out["reception_point_launch"] = dict(
+        workload="%d rays (one per set), K=5, 64 RX, LOS+specular, averaged interactions, candidates gated by the "
+                 "visibility matrix" % ns,
+        ms_per_solve=ms, stage_ms={k: v / reps for k, v in stage.items()},
+        counts={k: cnt[k] for k in ("interactions", "keys", "candidates", "specular")})
     return dict(workload="office as above with point radius 0.015 m, voxel 0.0625 m, lambda_d 100 /m, %d rays, "
                          "K=5, 64 RX, LOS+specular+diffuse" % rays,
                 n_point_sets=scene.info["n_point_sets"], build_ms=scene.info["build_ms"], **out)

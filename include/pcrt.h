@@ -177,7 +177,15 @@ enum {
      * weighted sum of the member normals turned to face it. The nearest disk
      * still names the interaction (material, surface label, sequence).
      * Needs a scene built with dps_voxel > 0 (else EINVAL). */
-    PCRT_AVERAGE = 32
+    PCRT_AVERAGE = 32,
+    /* The paper's launch (Sec. II-B): ray j goes from the transmitter towards
+     * the reception point of point set j (n_rays must equal the scene's
+     * n_point_sets; a ray_subset lists set indices, others end at once), and
+     * a (key, receiver) pair is a specular candidate only where dps_vis says
+     * the receiver sees the reception point of the set the key's
+     * representative ray ends in. Needs point sets and dps_vis (EINVAL);
+     * PCRT_DIFFUSE is refused (EUNSUPPORTED), as are batches. */
+    PCRT_DPS_LAUNCH = 64
 };
 
 /* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
@@ -200,6 +208,7 @@ typedef struct {
     uint32_t key_capacity;
     uint32_t wave_rays; /* rays a wavefront takes per work fetch, multiple of 64 up to 1024 (0 = 64) */
     float lambda_d;     /* depth attenuation of PCRT_AVERAGE, 1/m (0 = 100) */
+    const uint8_t *dps_vis; /* PCRT_DPS_LAUNCH: device uint8[n_rx][n_point_sets] from pcrt_visibility for rx */
 } pcrt_solve_params;
 
 /* Outputs (device pointers; NULL = not wanted unless marked required).

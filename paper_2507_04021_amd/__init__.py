@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcrt.so")
 LIB_COUNT_PATH = os.path.join(_HERE, "libpcrt_count.so")  # measurement build with visit counters
 
-LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE = 1, 2, 4, 8, 16, 32
+LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE, DPS_LAUNCH = 1, 2, 4, 8, 16, 32, 64
 STAGES = ("init", "trace", "keys", "refine", "diffuse_order", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
            tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
@@ -62,7 +62,7 @@ class SolveParams(ctypes.Structure):
                 ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
                 ("thr", Thresholds), ("key_capacity", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32),
-                ("lambda_d", ctypes.c_float)]
+                ("lambda_d", ctypes.c_float), ("dps_vis", ctypes.c_void_p)]
 
 
 class BatchItem(ctypes.Structure):
@@ -280,7 +280,7 @@ class SolveResult:
 
 
 def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0, wave_rays=0,
-                lambda_d=0.0):
+                lambda_d=0.0, dps_vis=None):
     th = Thresholds(0.0, 0.0, 0.0, 0.0, 0)
     if thr:
         for k, v in thr.items():
@@ -299,15 +299,18 @@ def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_c
     p.key_capacity = int(key_capacity)
     p.wave_rays = int(wave_rays)
     p.lambda_d = float(lambda_d)
+    p.dps_vis = dps_vis.data_ptr() if dps_vis is not None else None
     return p
 
 
 def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
           want_seq=False, stream=None, ws=None, out=None, key_capacity=0, wave_rays=0,
-          lambda_d=0.0) -> SolveResult:
+          lambda_d=0.0, dps_vis=None) -> SolveResult:
     """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor.
     flags with AVERAGE: point-set averaged interactions (scene built with dps_voxel > 0), depth
-    attenuation lambda_d (0 = 100 per metre)."""
+    attenuation lambda_d (0 = 100 per metre). flags with DPS_LAUNCH: one ray per point set towards its
+    reception point (n_rays = the scene's n_point_sets) and specular candidates gated by dps_vis
+    (the uint8[n_rx, n_point_sets] tensor from visibility() for the same receivers)."""
     torch = _torch()
     L = lib(scene._variant)
     dev = scene.device
@@ -318,7 +321,9 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
     if ray_subset is not None:
         sub_t = _dev(np.asarray(ray_subset, np.int64).astype(np.int32) if not isinstance(ray_subset, torch.Tensor)
                      else ray_subset, torch.int32, dev)
-    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays, lambda_d)
+    if dps_vis is not None:
+        dps_vis = dps_vis.contiguous()
+    p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays, lambda_d, dps_vis)
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:
@@ -337,7 +342,7 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
     _check(L.pcrt_solve(scene.handle, _ptr(mats_t), mats_t.shape[0], ctypes.byref(p), _ptr(ws), ws.numel(),
                         ctypes.byref(o), _stream(stream)), L)
     return SolveResult(out["gain"], out["h_te"], out["h_tm"], out["parts"], out.get("seq"), out["counters"], ws, p,
-                       scene, (mats_t, rx_t, sub_t))
+                       scene, (mats_t, rx_t, sub_t, dps_vis))
 
 
 def paths(res: SolveResult, stream=None):

@@ -134,6 +134,12 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     if ((p->flags & PCRT_AVERAGE) && !sc->dev.dps_pt)
         return fail(PCRT_EINVAL, "PCRT_AVERAGE needs a scene built with dps_voxel > 0");
     if (!(p->lambda_d >= 0.f) || !std::isfinite(p->lambda_d)) return fail(PCRT_EINVAL, "lambda_d must be >= 0");
+    if (p->flags & PCRT_DPS_LAUNCH) {
+        if (!sc->dev.dps_pt) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs a scene built with dps_voxel > 0");
+        if (p->flags & PCRT_DIFFUSE) return fail(PCRT_EUNSUPPORTED, "PCRT_DPS_LAUNCH has no diffuse paths");
+        if (p->n_rays != sc->info.n_point_sets) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH: n_rays must be n_point_sets");
+        if ((p->flags & PCRT_SPECULAR) && !p->dps_vis) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs dps_vis");
+    }
     return PCRT_OK;
 }
 
@@ -239,6 +245,7 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.n_labels = n_labels;
     A.n_surf1 = sc->info.n_surfaces + 1;
     A.flags = p->flags;
+    A.dps_vis = (p->flags & PCRT_DPS_LAUNCH) ? p->dps_vis : nullptr;
     A.thr = P.thr;
     A.fc = P.fc;
     A.D = P.D;
@@ -457,6 +464,8 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
         sc->dev.dps_pt = (const float4 *)(sc->ws + L.dps_pt);
         sc->dev.dps_off = (const uint32_t *)(sc->ws + L.dps_off);
         sc->dev.dps_of = (const uint32_t *)(sc->ws + L.dps_of);
+        sc->dev.dps_recv = (const float4 *)(sc->ws + L.dps_recv);
+        sc->dev.n_sets = dstat[1];
     }
     // the wide hierarchy's root is node 0; the binary root is the builder's
     sc->dev.root = n == 1 ? leaf_ref(0, 1) : (n <= leaf ? leaf_ref(0, (int)n) : (width > 2 ? 0 : broot));
@@ -612,6 +621,7 @@ static pcrt_status check_batch(const pcrt_solve_params *p, const pcrt_batch_item
     if (n_items > 65536) return fail(PCRT_EUNSUPPORTED, "at most 65536 items");
     if (p->ray_subset) return fail(PCRT_EINVAL, "ray_subset is not supported in a batch");
     if (p->flags & PCRT_RECORD) return fail(PCRT_EUNSUPPORTED, "tapes are kept for single-transmitter solves only");
+    if (p->flags & PCRT_DPS_LAUNCH) return fail(PCRT_EUNSUPPORTED, "the reception-point launch is for single solves");
     uint64_t total = 0;
     for (uint32_t i = 0; i < n_items; ++i) {
         if (!std::isfinite(items[i].tx[0]) || !std::isfinite(items[i].tx[1]) || !std::isfinite(items[i].tx[2]))

@@ -74,6 +74,8 @@ struct DevScene {
     const float4 *dps_pt;     // 2 float4 per member, grouped by set: (p.xyz, id bits), (n.xyz, 0)
     const uint32_t *dps_off;  // [n_sets + 1] first member of each set
     const uint32_t *dps_of;   // by id: set of the point
+    const float4 *dps_recv;   // [n_sets] reception points (set means)
+    uint32_t n_sets;
 };
 
 // Node layout (64 B): n0 = (lo0.x, lo0.y, lo0.z, hi0.x), n1 = (hi0.y, hi0.z, lo1.x, lo1.y),
@@ -710,6 +712,15 @@ __device__ __forceinline__ f3 fib_dir(uint32_t j, uint32_t N) {
     double sp, cp;
     sincos(phi, &sp, &cp);
     return {(float)(rho * cp), (float)(rho * sp), (float)z};
+}
+
+// Unit direction from o towards c, FP64 then rounded to FP32 (no contraction,
+// so both implementations round the same products).
+__device__ __forceinline__ f3 aim_dir(const float *o, float4 c) {
+#pragma clang fp contract(off)
+    const double dx = (double)c.x - (double)o[0], dy = (double)c.y - (double)o[1], dz = (double)c.z - (double)o[2];
+    const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    return {(float)(dx * il), (float)(dy * il), (float)(dz * il)};
 }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {  // splitmix64 finaliser

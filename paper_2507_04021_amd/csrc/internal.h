@@ -154,6 +154,7 @@ struct LaunchArgs {
     HashBufs hb;
     SpecBufs sb;
     uint32_t wave_rays; // rays a wavefront takes per work fetch (multiple of 64)
+    const uint8_t *dps_vis;  // launch at the reception points: [n_rx][n_sets] receiver sees reception point
     uint32_t *work;     // [8] atomic work counters
     uint64_t *counters; // [16]
     uint32_t *scan;

@@ -420,6 +420,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KM <= 5 ?
                     load_planes<KM, AVG>(A, q, kp);
                     f3 x[KM + 1];
                     cand = refine_planes<KM>(kp.k, R.tx, rx_point(A, r), kp.pp, kp.pn, A.thr.eps_self, x);
+                    // launch at the reception points: only where the receiver sees the reception
+                    // point of the set the representative ray ends in (the visibility matrix)
+                    if (cand && A.dps_vis)
+                        cand = A.dps_vis[(size_t)r * A.S.n_sets + A.S.dps_of[A.rb.id[A.keylist[q]]]] != 0;
                     if (rec) {
                         if (q >= A.D.rec_keys) {
                             atomicOr((unsigned long long *)&A.counters[6], 4ull);  // tape capacity exceeded

@@ -47,7 +47,17 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
         return;
     }
     const uint32_t j = A.subset ? A.subset[local] : local;
-    f3 d = normalize(fib_dir(j, I.budget));
+    f3 d;
+    if (A.flags & 64) {  // towards reception point j (Sec. II-B): FP64 direction, rounded to FP32
+        if (j >= A.S.n_sets) {
+            for (uint32_t k = 0; k < K; ++k) A.rb.id[rb + k] = -1;
+            n_ray += 1;
+            return;
+        }
+        d = normalize(aim_dir(I.tx, A.S.dps_recv[j]));
+    } else {
+        d = normalize(fib_dir(j, I.budget));
+    }
     f3 o = mk(I.tx[0], I.tx[1], I.tx[2]);
     float L = 0.f;
     int excl = -1;

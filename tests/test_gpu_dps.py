@@ -217,3 +217,64 @@ def test_visibility_errors(P, room):
     with pytest.raises(P.PcrtError) as e:
         P.reception_points(sg)
     assert e.value.code == -1
+
+
+# ------------------------------ launch at the reception points (Sec. II-B)
+@pytest.fixture(scope="module")
+def calm():
+    return scenes.noisy(scenes.box_room(spacing=0.025, radius=0.02, size=(3.0, 2.0, 2.5)), seed=3,
+                        pos_sigma=0.001, normal_jitter_deg=0.5)
+
+
+@pytest.mark.parametrize("avg", [False, True])
+def test_dps_launch_parity(P, orc, calm, avg):
+    """One ray per point set towards its reception point, specular candidates
+    gated by the visibility matrix: sequences and specular paths as the
+    oracle's (bars as in the averaging tests)."""
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    tx = [1.1, 0.7, 1.3]
+    step("dps launch avg=%s" % avg)
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    ns = sg.info["n_point_sets"]
+    vis = P.visibility(sg, rx)
+    fl = LOS | SPEC | REC | P.DPS_LAUNCH | (AVG if avg else 0)
+    r = P.solve(sg, mats, tx, rx, 3.5e9, ns, K=3, flags=fl, want_seq=True, lambda_d=LAM, dps_vis=vis)
+    ref = orc.solve(calm, mats, tx, rx, 3.5e9, ns, K=3, flags=LOS | SPEC, dps_launch=RHO,
+                    average=(RHO, LAM) if avg else None)
+    seq = r.seq.cpu().numpy()
+    same = np.all(seq == ref.seq, 1)
+    assert same.mean() >= 0.999
+    pth = P.paths(r)
+    gp = {}
+    for q in range(pth["n_keys"]):
+        key = tuple(int(calm.surface[i]) for i in pth["key_seq"][q, :int(pth["key_len"][q])])
+        for j in range(len(rx)):
+            if pth["valid"][q, j]:
+                gp[(j, key)] = float(pth["length"][q, j])
+    op = {(j, k): v[0] for j in range(len(rx)) for k, v in ref.paths(j).items()}
+    step("paths: gpu %d oracle %d common %d" % (len(gp), len(op), len(set(gp) & set(op))))
+    assert len(op) >= 30
+    assert len(set(gp) ^ set(op)) <= max(1, len(op) // 50)
+    for k in set(gp) & set(op):
+        assert abs(gp[k] - op[k]) <= 2e-6 * op[k]
+    assert np.allclose(r.parts.cpu().numpy()[:, 0], ref.G_los, rtol=1e-4)
+
+
+def test_dps_launch_errors(P, calm):
+    step("dps launch errors")
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    ns = sg.info["n_point_sets"]
+    rx = [[2.2, 1.4, 1.0]]
+    vis = P.visibility(sg, rx)
+    mats = scenes.box_room_materials()
+    for kw, code in ((dict(n_rays=ns, flags=LOS | SPEC | P.DPS_LAUNCH), -1),
+                     (dict(n_rays=ns + 1, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis), -1),
+                     (dict(n_rays=ns, flags=LOS | DIFF | P.DPS_LAUNCH, dps_vis=vis), -4)):
+        with pytest.raises(P.PcrtError) as e:
+            P.solve(sg, mats, [1.1, 0.7, 1.3], rx, 3.5e9, K=2, **kw)
+        assert e.value.code == code
+    plain = P.Scene.from_scene(calm)
+    with pytest.raises(P.PcrtError) as e:
+        P.solve(plain, mats, [1.1, 0.7, 1.3], rx, 3.5e9, ns, K=2, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis)
+    assert e.value.code == -1
