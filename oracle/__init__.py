@@ -188,7 +188,9 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     point of point set j (ray_ids are set indices, n_budget the set count),
     and a (key, receiver) pair is a specular candidate only where the
     receiver sees the reception point of the set its representative ends in.
-    No diffuse paths in this mode.
+    Diffuse paths are then one per unique (labels before the last interaction,
+    point set of the last), gated the same way, each standing for an area
+    rho^2 around its representative's interaction.
 
     cfr = (bandwidth_hz, n_freq): also the channel frequency response, every
     path's centre-frequency amplitudes times exp(-j 2 pi (f_n - freq) L / c0)

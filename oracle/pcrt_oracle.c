@@ -746,7 +746,6 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     dps_t dps, *sets = NULL, *g = NULL; /* g: the sets when interactions are averaged */
     if (flags & (ORC_AVERAGE | ORC_DPS_LAUNCH)) {
         if (!(thr[5] > 0.0) || ((flags & ORC_AVERAGE) && !(thr[6] > 0.0))) { scene_free(&s); return -1; }
-        if ((flags & ORC_DPS_LAUNCH) && (flags & ORC_DIFFUSE)) { scene_free(&s); return -1; }
         if (dps_build(&dps, &s, thr[5])) { scene_free(&s); return -2; }
         sets = &dps;
         if (flags & ORC_AVERAGE) g = &dps;
@@ -821,8 +820,68 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
             }
     }
 
-    /* diffuse connections from every interaction to every RX (Sec. II-B.1) */
-    if (flags & ORC_DIFFUSE) {
+    if ((flags & ORC_DIFFUSE) && (flags & ORC_DPS_LAUNCH)) {
+        /* Diffuse paths of the reception-point launch (Sec. II-B.1, II-B.4): one path
+         * per unique (surface labels of the interactions before the last, point set of
+         * the last); its representative (smallest ray id) gives the geometry. A path
+         * reaches receiver r when r sees the set's reception point (the visibility
+         * matrix) and lies on the lit side of the representative's interaction. It
+         * stands for the field scattered by an area rho^2 there: a Lambertian patch lit
+         * from the (image) transmitter at the unfolded length L,
+         *   amp0 = lambda/(4 pi) sqrt(rho^2 cos_i cos_s / pi) / (L r_s),
+         * which for the footprint of one ray tube, 4 pi L^2 / (N cos_i), is the ray-tube
+         * amplitude of the per-interaction connections. */
+        const double area = thr[5] * thr[5];
+        int64_t total = 0;
+        for (int64_t q = 0; q < n_trace; ++q) total += tr[q].n;
+        keyrec_t *kr = (keyrec_t *)malloc(sizeof(keyrec_t) * (size_t)(total > 0 ? total : 1));
+        int64_t e = 0;
+        for (int64_t q = 0; q < n_trace; ++q)
+            for (int k = 1; k <= tr[q].n; ++k) {
+                memset(&kr[e], 0, sizeof(keyrec_t));
+                kr[e].len = k;
+                for (int m = 0; m < k - 1; ++m) kr[e].s[m] = s.surf[tr[q].id[m]];
+                kr[e].s[k - 1] = (uint32_t)sets->of[tr[q].id[k - 1]];
+                kr[e].ray_id = ray_ids[q];
+                kr[e].slot = q;
+                ++e;
+            }
+        qsort(kr, (size_t)total, sizeof(keyrec_t), key_cmp);
+        for (int64_t i = 0; i < total; ++i) {
+            if (i > 0 && kr[i].len == kr[i - 1].len && !memcmp(kr[i].s, kr[i - 1].s, sizeof(uint32_t) * (size_t)kr[i].len))
+                continue;
+            const trace_t *t = &tr[kr[i].slot];
+            const int k = kr[i].len;
+            const int64_t set = kr[i].s[k - 1];
+            double c[3];
+            reception_point(&s, sets, set, c);
+            int label[ORC_KMAX], kind[ORC_KMAX];
+            double cs[ORC_KMAX];
+            for (int m = 0; m < k; ++m) {
+                label[m] = s.mat[t->id[m]];
+                cs[m] = t->cs[m];
+                kind[m] = (m == k - 1);
+            }
+            for (int r = 0; r < n_rx; ++r) {
+                if (occluded_but_set(&s, sets, rx + 3 * r, c, set, th.eps_self)) continue;
+                double v[3];
+                sub3(v, rx + 3 * r, t->x[k - 1]);
+                double vn = dot3(v, t->nk[k - 1]);
+                if (!(vn > 0.0)) continue;
+                double rs = norm3(v);
+                double amp0 = a_iso * sqrt(area * cs[k - 1] * (vn / rs) / ORC_PI) / (t->L[k - 1] * rs);
+                double complex ate = 0, atm = 0;
+                path_field(&em, k, label, cs, kind, amp0, t->L[k - 1] + rs, &ate, &atm, &G_diff[r],
+                           jac ? jac + (int64_t)r * n_labels * 3 : NULL);
+                h_te[r] += ate;
+                h_tm[r] += atm;
+                cfr_add(&cfr, r, ate, atm, t->L[k - 1] + rs);
+            }
+        }
+        free(kr);
+        if (dvis) memset(dvis, 0, (size_t)(n_trace * K * n_rx));
+    } else if (flags & ORC_DIFFUSE) {
+        /* diffuse connections from every interaction to every RX (Sec. II-B.1) */
         int64_t nslot = n_trace * K * (int64_t)n_rx;
         double complex *ate = calloc((size_t)nslot, sizeof(double complex));
         double complex *atm = calloc((size_t)nslot, sizeof(double complex));

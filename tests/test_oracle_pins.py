@@ -700,3 +700,29 @@ def test_dps_launch_gates_specular_candidates(orc):
         assert sol.key_rep[sol.keys.index((0,))] == 0
         assert bool(vis[0, 0]) == expect
         assert ((0,) in sol.paths(0)) == expect
+
+
+def test_dps_diffuse_floor_closed_form(orc):
+    """Reception-point launch over a flat floor, one interaction: every set
+    gives one diffuse path at its reception point, with amplitude
+    lambda/(4 pi) sqrt(rho^2 cos_i cos_s / pi) / (L r_s) times S Gamma(cos_i);
+    the total power is summed here from those closed forms."""
+    rho, freq = 0.0625, 3.5e9
+    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, 0.05, 0.04)
+    tx, rx = np.array([1.0, 1.0, 1.0]), np.array([[1.5, 1.0, 1.0]], np.float32)
+    eps_r, sigma, S = 5.0, 0.1, 0.4
+    recv, vis = orc.visibility(floor, rho, rx)
+    assert vis.all()
+    sol = orc.solve(floor, np.array([[eps_r, sigma, S]]), tx, rx, freq, len(recv), K=1, flags=DIFF,
+                    dps_launch=rho)
+    c = recv.astype(np.float64)
+    L = np.linalg.norm(c - tx, axis=1)
+    rs = np.linalg.norm(c - rx[0].astype(np.float64), axis=1)
+    cos_i, cos_s = tx[2] / L, float(rx[0, 2]) / rs
+    gte, gtm, _, _ = orc.fresnel(eps_r, sigma, freq, cos_i)
+    lam = C0 / freq
+    rho32 = float(np.float32(rho))
+    amp0 = lam / (4 * np.pi) * np.sqrt(rho32 ** 2 * cos_i * cos_s / np.pi) / (L * rs)
+    G = np.sum(0.5 * amp0 ** 2 * S ** 2 * (np.abs(gte) ** 2 + np.abs(gtm) ** 2))
+    assert sol.G_diff[0] == pytest.approx(G, rel=1e-5)
+    assert sol.G_spec[0] == 0.0 and sol.G_los[0] == 0.0
