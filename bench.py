@@ -284,7 +284,7 @@ def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
                                     visible_fraction=float(vis.float().mean().item()))
     # the paper's launch: one ray per set towards its reception point, candidates gated by the matrix
     ns = scene.info["n_point_sets"]
-    fl = P.LOS | P.SPECULAR | P.AVERAGE | P.DPS_LAUNCH
+    fl = P.LOS | P.SPECULAR | P.DIFFUSE | P.AVERAGE | P.DPS_LAUNCH
     res = P.solve(scene, mats_t, tx, rx_t, 28e9, ns, K=5, flags=fl, lambda_d=100.0, dps_vis=vis)
     o = dict(gain=res.gain, h_te=res.h_te, h_tm=res.h_tm, parts=res.parts, seq=None, counters=res.counters)
     torch.cuda.synchronize()
@@ -299,10 +299,10 @@ def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
     ms = (time.perf_counter() - t0) * 1e3 / reps
     cnt = {k: int(o["counters"][i].item()) for k, i in P.CNT.items()}
     out["reception_point_launch"] = dict(
-        workload="%d rays (one per set), K=5, 64 RX, LOS+specular, averaged interactions, candidates gated by the "
-                 "visibility matrix" % ns,
+        workload="%d rays (one per set), K=5, 64 RX, LOS+specular+diffuse, averaged interactions, candidates "
+                 "gated by the visibility matrix, diffuse paths deduplicated per voxel (area rho^2)" % ns,
         ms_per_solve=ms, stage_ms={k: v / reps for k, v in stage.items()},
-        counts={k: cnt[k] for k in ("interactions", "keys", "candidates", "specular")})
+        counts={k: cnt[k] for k in ("interactions", "keys", "candidates", "specular", "diffuse")})
     return dict(workload="office as above with point radius 0.015 m, voxel 0.0625 m, lambda_d 100 /m, %d rays, "
                          "K=5, 64 RX, LOS+specular+diffuse" % rays,
                 n_point_sets=scene.info["n_point_sets"], build_ms=scene.info["build_ms"], **out)

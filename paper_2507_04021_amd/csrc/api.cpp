@@ -136,9 +136,16 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     if (!(p->lambda_d >= 0.f) || !std::isfinite(p->lambda_d)) return fail(PCRT_EINVAL, "lambda_d must be >= 0");
     if (p->flags & PCRT_DPS_LAUNCH) {
         if (!sc->dev.dps_pt) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs a scene built with dps_voxel > 0");
-        if (p->flags & PCRT_DIFFUSE) return fail(PCRT_EUNSUPPORTED, "PCRT_DPS_LAUNCH has no diffuse paths");
+        if ((p->flags & PCRT_DIFFUSE) && (p->flags & PCRT_RECORD))
+            return fail(PCRT_EUNSUPPORTED, "PCRT_DPS_LAUNCH keeps no tape of its diffuse paths");
         if (p->n_rays != sc->info.n_point_sets) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH: n_rays must be n_point_sets");
-        if ((p->flags & PCRT_SPECULAR) && !p->dps_vis) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs dps_vis");
+        if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && !p->dps_vis)
+            return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs dps_vis");
+        if (p->flags & PCRT_DIFFUSE) {
+            double bits = (p->max_interactions - 1) * std::log2((double)sc->info.n_surfaces + 1.0) +
+                          std::log2((double)sc->info.n_point_sets + 1.0);
+            if (bits >= 63.0) return fail(PCRT_EUNSUPPORTED, "voxel diffuse keys do not fit 64 bits");
+        }
     }
     return PCRT_OK;
 }
@@ -246,6 +253,16 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.n_surf1 = sc->info.n_surfaces + 1;
     A.flags = p->flags;
     A.dps_vis = (p->flags & PCRT_DPS_LAUNCH) ? p->dps_vis : nullptr;
+    if ((p->flags & PCRT_DPS_LAUNCH) && (p->flags & PCRT_DIFFUSE)) {
+        A.rb.dslot = (uint32_t *)at(L.rec_dslot);
+        A.dhb.key = (unsigned long long *)at(L.dhkey);
+        A.dhb.rep = (uint32_t *)at(L.dhrep);
+        A.dhb.cap = dps_key_cap(P.D);
+        A.dkeylist = (uint32_t *)at(L.dkeylist);
+        A.dkey_off = (uint32_t *)at(L.dkey_off);
+        A.dchunk_off = (uint32_t *)at(L.dchunk_off);
+        A.dcnt = (uint64_t *)at(L.dcnt);
+    }
     A.thr = P.thr;
     A.fc = P.fc;
     A.D = P.D;
@@ -328,6 +345,20 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.dpack = b.take(2 * sizeof(float4) * nrec);
         L.diff_part = b.take(sizeof(double) * 5 * (size_t)D.n_ray_chunks * D.n_rx);
         if (rec) L.dvis = b.take(nrec * D.n_rx);
+        if (flags & PCRT_DPS_LAUNCH) {  // voxel diffuse keys of the reception-point launch
+            const size_t cap = dps_key_cap(D);
+            L.rec_dslot = b.take(sizeof(uint32_t) * nrec);
+            L.dhkey = b.take(sizeof(uint64_t) * cap);
+            L.dhrep = b.take(sizeof(uint32_t) * cap);
+            L.dkeylist = b.take(sizeof(uint32_t) * nrec);
+            L.dkey_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
+            L.dchunk_off = b.take(sizeof(uint32_t) * (D.n_items + 1));
+            L.dcnt = b.take(sizeof(uint64_t) * PCRT_CNT_COUNT);
+            if (!spec) {  // the compaction's scan buffers
+                L.scan = b.take(sizeof(uint32_t) * nrec);
+                L.scan_blk = b.take(sizeof(uint32_t) * ((nrec + 1023) / 1024 + 1));
+            }
+        }
     }
     if (spec) {
         L.rec_slot = b.take(sizeof(uint32_t) * nrec);
@@ -592,6 +623,11 @@ static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats
         fill_u64((uint64_t *)A.hb.key, 0, (size_t)P.cap * P.D.n_items, s);
         fill_u32(A.hb.rep, 0xffffffffu, (size_t)P.cap * P.D.n_items, s);
     }
+    const bool dps_diff = (p->flags & PCRT_DPS_LAUNCH) && (p->flags & PCRT_DIFFUSE);
+    if (dps_diff) {
+        fill_u64((uint64_t *)A.dhb.key, 0, A.dhb.cap, s);
+        fill_u32(A.dhb.rep, 0xffffffffu, A.dhb.cap, s);
+    }
     stage_mark(tm, 1, s);
     if (p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) {
         launch_trace(A, s);
@@ -605,9 +641,10 @@ static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats
     stage_mark(tm, 3, s);
     if (p->flags & PCRT_SPECULAR) launch_refine(A, s);
     stage_mark(tm, 4, s);
-    if (p->flags & PCRT_DIFFUSE) A.dsort.order = launch_diffuse_order(A, s);
+    if ((p->flags & PCRT_DIFFUSE) && !dps_diff) A.dsort.order = launch_diffuse_order(A, s);
     stage_mark(tm, 5, s);
-    if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
+    if (dps_diff) launch_dps_diffuse(A, scene->info.dps_voxel * scene->info.dps_voxel, s);
+    else if (p->flags & PCRT_DIFFUSE) launch_diffuse(A, s);
     stage_mark(tm, 6, s);
     launch_los_and_combine(A, out->gain, out->h_te, out->h_tm, out->gain_parts, s);
     if (p->flags & PCRT_RECORD) launch_tape_slots(A, s);

@@ -252,6 +252,78 @@ void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
     }
 }
 
+// Diffuse paths of the reception-point launch (Sec. II-B.1, II-B.4): one per
+// unique voxel diffuse key (surface labels before the last interaction, point
+// set of the last), its representative's record giving the geometry. A path
+// reaches receiver r when r sees the set's reception point (the visibility
+// matrix) and lies on the lit side of the interaction; it stands for the field
+// scattered by an area rho^2 there, a Lambertian patch lit from the (image)
+// transmitter at the unfolded length L:
+//   a0 = sqrt(rho^2 cos_i cos_s / pi) / (L r_s)   (times lambda/4pi S and the chain, in coef)
+// Block: one chunk of keys x 64 receivers; each thread adds its receiver's
+// paths over the chunk in key order (keys are in record order), FP64.
+__global__ __launch_bounds__(kWave) void k_dps_diffuse(LaunchArgs A, float area) {
+    const uint32_t n_rx = A.D.n_rx, CH = kRayChunk * A.D.K;
+    const uint32_t n_keys = A.dkey_off[A.D.n_items];
+    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + threadIdx.x;
+    const float inv_pi = (float)(1.0 / kPi);
+    double acc[5] = {0, 0, 0, 0, 0};
+    uint32_t n_vis = 0;
+    if (r < n_rx) {
+        const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+        const uint32_t k1 = min(n_keys, (c + 1) * CH);
+        for (uint32_t q = c * CH; q < k1; ++q) {
+            const uint32_t ri = A.dkeylist[q];
+            const int id = A.rb.id[ri];
+            if (!A.dps_vis[(size_t)r * A.S.n_sets + A.S.dps_of[id]]) continue;
+            const float4 xl = A.rb.xl[ri];
+            const f3 v = rx - xyz(xl);
+            const float vn = dot(v, record_normal(A, ri));
+            if (!(vn > 0.f)) continue;
+            const float rs = len(v);
+            const float a0 = sqrtf(area * fabsf(A.rb.cs[ri]) * (vn / rs) * inv_pi) / (xl.w * rs);
+            const c32 ph = propagate(xl.w + rs, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+            const float4 cf = A.rb.coef[ri];
+            const c32 te = cmul({a0 * cf.x, a0 * cf.y}, ph);
+            const c32 tm = cmul({a0 * cf.z, a0 * cf.w}, ph);
+            const double tr = te.re, ti = te.im, mr = tm.re, mi = tm.im;
+            acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+            acc[1] += tr;
+            acc[2] += ti;
+            acc[3] += mr;
+            acc[4] += mi;
+            ++n_vis;
+        }
+        double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
+        for (int a = 0; a < 5; ++a) o[a] = acc[a];
+    }
+    n_vis = warp_sum_u(n_vis);
+    if (threadIdx.x == 0 && n_vis) atomicAdd((unsigned long long *)&A.counters[5], (unsigned long long)n_vis);
+}
+
+uint32_t dps_key_cap(const SolveDims &D) {  // twice the records, a power of two
+    const uint64_t want = 2ull * D.T * D.K + 1;
+    uint32_t cap = 1;
+    while (cap < want && cap < (1u << 31)) cap <<= 1;
+    return cap;
+}
+
+void launch_dps_diffuse(const LaunchArgs &A, float area, hipStream_t s) {
+    // compact the voxel diffuse keys with the specular key machinery on the other table
+    LaunchArgs B = A;
+    B.hb = A.dhb;
+    B.rb.slot = A.rb.dslot;
+    B.keylist = A.dkeylist;
+    B.key_off = A.dkey_off;
+    B.chunk_off = A.dchunk_off;
+    B.counters = A.dcnt;
+    fill_u32(B.key_off, 0, A.D.n_items + 1, s);
+    fill_u32(B.chunk_off, 0, A.D.n_items + 1, s);
+    launch_keys(B, s);
+    const dim3 g(A.D.n_ray_chunks, (A.D.n_rx + kWave - 1) / kWave);
+    hipLaunchKernelGGL(k_dps_diffuse, g, dim3(kWave), 0, s, A, area);
+}
+
 template <int W>
 __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];

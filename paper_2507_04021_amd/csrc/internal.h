@@ -76,6 +76,7 @@ struct RecBufs {
     float4 *coef;     // diffuse coefficient (TE re, im, TM re, im), incl. lambda/4pi and the chain before
     uint32_t *slot;   // key-table slot of the prefix key
     float4 *nk;       // point-set average only: normal of the interaction, facing the incoming ray
+    uint32_t *dslot;  // reception-point launch with diffuse: key-table slot of the voxel diffuse key
 };
 
 struct HashBufs {
@@ -120,7 +121,8 @@ constexpr uint32_t kMaxGradLabels = 64;   // label-gradient LDS: 64 lanes x 64 l
 struct SolveLayout {
     size_t items, counters, work, rec_id, rec_xl, rec_cs, rec_coef, rec_slot, hkey, hrep, scan, scan_blk, keylist,
         key_off, chunk_off, spec_part, diff_part, los_part, sp_valid, sp_len, sp_amp, sp_hit, sp_cs, dvis, spill,
-        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res, dpack, rec_nk, spec_ovr;
+        slot_label, slot_cos, slot_coef, slot_adj, grad_part, dkey0, dkey1, dval0, dval1, dhist, dblk, spec_res, dpack, rec_nk, spec_ovr,
+        rec_dslot, dhkey, dhrep, dkeylist, dkey_off, dchunk_off, dcnt;
     size_t total;
 };
 
@@ -155,6 +157,9 @@ struct LaunchArgs {
     SpecBufs sb;
     uint32_t wave_rays; // rays a wavefront takes per work fetch (multiple of 64)
     const uint8_t *dps_vis;  // launch at the reception points: [n_rx][n_sets] receiver sees reception point
+    HashBufs dhb;            // ... and its voxel diffuse keys (labels before the last interaction, last set)
+    uint32_t *dkeylist, *dkey_off, *dchunk_off;
+    uint64_t *dcnt;
     uint32_t *work;     // [8] atomic work counters
     uint64_t *counters; // [16]
     uint32_t *scan;
@@ -191,6 +196,9 @@ void launch_refine(const LaunchArgs &A, hipStream_t s);
 // returns the sorted record indices
 const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s);
 void launch_diffuse(const LaunchArgs &A, hipStream_t s);  // needs A.dsort.order
+// Reception-point launch: compact the voxel diffuse keys, then their fields (area rho^2 each).
+void launch_dps_diffuse(const LaunchArgs &A, float area, hipStream_t s);
+uint32_t dps_key_cap(const SolveDims &D);
 void launch_los_and_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                             hipStream_t s);
 void launch_combine(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts, hipStream_t s);

@@ -102,10 +102,14 @@ __device__ __forceinline__ void trace_one(const LaunchArgs &A, uint32_t g, Stack
             pte = {R * cte.re, R * cte.im};
             ptm = {R * ctm.re, R * ctm.im};
         }
-        if (want_spec) {
+        if (A.rb.dslot) {  // voxel diffuse key: labels before this interaction, then this point set
+            const uint64_t encd = enc * (uint64_t)A.S.n_sets + (uint64_t)A.S.dps_of[h] + 1ull;
+            A.rb.dslot[rb + k] = key_insert(A.dhb, 0u, encd, j, A.counters + 6);
+        }
+        if (want_spec || A.rb.dslot) {
             uint32_t su = __float_as_uint(A.S.pos[h].w);
             enc = enc * (uint64_t)A.n_surf1 + (uint64_t)(su + 1);
-            A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
+            if (want_spec) A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
         }
         d = normalize(d - (2.f * dn) * n);
         o = q;

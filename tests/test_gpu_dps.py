@@ -269,8 +269,9 @@ def test_dps_launch_errors(P, calm):
     vis = P.visibility(sg, rx)
     mats = scenes.box_room_materials()
     for kw, code in ((dict(n_rays=ns, flags=LOS | SPEC | P.DPS_LAUNCH), -1),
+                     (dict(n_rays=ns, flags=LOS | DIFF | P.DPS_LAUNCH), -1),
                      (dict(n_rays=ns + 1, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis), -1),
-                     (dict(n_rays=ns, flags=LOS | DIFF | P.DPS_LAUNCH, dps_vis=vis), -4)):
+                     (dict(n_rays=ns, flags=LOS | DIFF | REC | P.DPS_LAUNCH, dps_vis=vis), -4)):
         with pytest.raises(P.PcrtError) as e:
             P.solve(sg, mats, [1.1, 0.7, 1.3], rx, 3.5e9, K=2, **kw)
         assert e.value.code == code
@@ -278,3 +279,44 @@ def test_dps_launch_errors(P, calm):
     with pytest.raises(P.PcrtError) as e:
         P.solve(plain, mats, [1.1, 0.7, 1.3], rx, 3.5e9, ns, K=2, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("avg", [False, True])
+def test_dps_launch_diffuse_parity(P, orc, calm, avg):
+    """Voxel-deduplicated diffuse paths (area rho^2 each), gated by the
+    visibility matrix: per-receiver diffuse power as the oracle's. The 0.1 %
+    of rays an FP32 rim decision may send elsewhere can change a key's
+    representative, hence 1e-3."""
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    tx = [1.1, 0.7, 1.3]
+    step("dps launch diffuse avg=%s" % avg)
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    ns = sg.info["n_point_sets"]
+    vis = P.visibility(sg, rx)
+    fl = LOS | SPEC | DIFF | P.DPS_LAUNCH | (AVG if avg else 0)
+    r = P.solve(sg, mats, tx, rx, 3.5e9, ns, K=3, flags=fl, lambda_d=LAM, dps_vis=vis)
+    ref = orc.solve(calm, mats, tx, rx, 3.5e9, ns, K=3, flags=LOS | SPEC | DIFF, dps_launch=RHO,
+                    average=(RHO, LAM) if avg else None)
+    parts = r.parts.cpu().numpy()
+    assert (ref.G_diff > 0).all()
+    assert np.allclose(parts[:, 2], ref.G_diff, rtol=1e-3)
+    assert np.allclose(r.gain.cpu().numpy(), ref.G, rtol=1e-3)
+    assert r.counter("diffuse") > 1000
+
+
+def test_dps_diffuse_floor_exact(P, orc):
+    """Flat floor, one interaction: each set's ray lands on its reception point
+    and every path is a closed form; GPU and oracle agree to FP32 rounding."""
+    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, 0.05, 0.04)
+    rx = np.array([[1.5, 1.0, 1.0], [0.3, 1.7, 0.6]], np.float32)
+    step("dps diffuse floor")
+    sg = P.Scene.from_scene(floor, dps_voxel=RHO)
+    ns = sg.info["n_point_sets"]
+    vis = P.visibility(sg, rx)
+    mats = np.array([[5.0, 0.1, 0.4]])
+    r = P.solve(sg, mats, [1.0, 1.0, 1.0], rx, 3.5e9, ns, K=1, flags=DIFF | P.DPS_LAUNCH, dps_vis=vis)
+    ref = orc.solve(floor, mats, [1.0, 1.0, 1.0], rx, 3.5e9, ns, K=1, flags=DIFF, dps_launch=RHO)
+    # one set in 1000 may change its key through an FP32 tie decision (each path is ~1/ns of the power)
+    assert np.allclose(r.parts.cpu().numpy()[:, 2], ref.G_diff, rtol=2e-3)
+    assert abs(r.counter("diffuse") - 2 * ns) <= max(2, 2 * ns // 1000)
