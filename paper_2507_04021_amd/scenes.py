@@ -309,6 +309,31 @@ def office(seed: int = 2507, target_points: int = 1_000_000, n_boxes: int = 20,
     return _pack(pos, nrm, mat, surf, r, 8, n_surf, info)
 
 
+def office_edges(sc: Scene):
+    """Convex edges of the office furniture, for single-bounce diffraction:
+    per box the four vertical edges and the four top edges (the edges on the
+    floor and the room's corners are concave). Returns (rows float32[n, 12]:
+    a xyz, b xyz, outward normal of face 0, of face n; labels int32[n, 2]:
+    material of face 0 and face n)."""
+    rows, labels = [], []
+    for i, b in enumerate(sc.info["boxes"]):
+        ca, sa = math.cos(b["yaw"]), math.sin(b["yaw"])
+        ex, ey, ez = np.array([ca, sa, 0.0]), np.array([-sa, ca, 0.0]), np.array([0.0, 0.0, 1.0])
+        c = np.array([b["c"][0], b["c"][1], 0.0])
+        hx, hy, hz = b["half"][0], b["half"][1], b["h"]
+        mat = 5 + i % 3
+        for sx in (-1.0, 1.0):
+            for sy in (-1.0, 1.0):
+                p = c + sx * hx * ex + sy * hy * ey
+                rows.append(np.concatenate([p, p + hz * ez, sx * ex, sy * ey]))
+                labels.append((mat, mat))
+        for nrm, tng, dn, dt in ((ex, ey, hx, hy), (-ex, ey, hx, hy), (ey, ex, hy, hx), (-ey, ex, hy, hx)):
+            p = c + dn * nrm + hz * ez
+            rows.append(np.concatenate([p - dt * tng, p + dt * tng, nrm, ez]))
+            labels.append((mat, mat))
+    return np.array(rows, np.float32), np.array(labels, np.int32)
+
+
 # ---------------------------------------------------------------------------
 # Small scenes for unit tests.
 # ---------------------------------------------------------------------------

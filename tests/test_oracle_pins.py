@@ -726,3 +726,71 @@ def test_dps_diffuse_floor_closed_form(orc):
     G = np.sum(0.5 * amp0 ** 2 * S ** 2 * (np.abs(gte) ** 2 + np.abs(gtm) ** 2))
     assert sol.G_diff[0] == pytest.approx(G, rel=1e-5)
     assert sol.G_spec[0] == 0.0 and sol.G_los[0] == 0.0
+
+
+# --------------------------------------- edge diffraction (Sec. II-B.3, UTD)
+def test_diffraction_point_obeys_kellers_cone():
+    """The edge point found by unfolding makes equal angles with the edge for
+    the incident and diffracted rays, and no sampled edge point is shorter."""
+    from oracle import diffraction as dif
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a, b = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        p, q = rng.uniform(-2, 2, 3), rng.uniform(-2, 2, 3)
+        t = dif.edge_point(a, b, p, q)
+        D = a + t * (b - a)
+        e = (b - a) / np.linalg.norm(b - a)
+        assert (D - p) @ e / np.linalg.norm(D - p) == pytest.approx((q - D) @ e / np.linalg.norm(q - D), abs=1e-12)
+        ts = np.linspace(t - 0.5, t + 0.5, 2001)
+        L = [np.linalg.norm(p - (a + s * (b - a))) + np.linalg.norm(q - (a + s * (b - a))) for s in ts]
+        assert min(L) >= np.linalg.norm(p - D) + np.linalg.norm(q - D) - 1e-12
+
+
+@pytest.mark.parametrize("n", [1.5, 2.0, 1.75])
+def test_diffraction_coefficient_far_from_boundaries_is_kellers(n):
+    """For large kL away from the shadow and reflection boundaries every
+    transition function tends to one, and the perfectly conducting wedge
+    coefficient is Keller's: e^{-j pi/4} sin(pi/n) / (n sqrt(2 pi k) sin b0)
+    [1/(cos(pi/n) - cos((phi - phi')/n)) -+ 1/(cos(pi/n) - cos((phi + phi')/n))]."""
+    from oracle import diffraction as dif
+    k, L, sb = 50.0, 2e5, 0.8
+    for phip, phi in ((0.4, 0.9 * n * np.pi), (0.7 * n * np.pi, 0.3)):
+        for r in (-1.0, 1.0):
+            d = dif.coefficient(n, k, L, phi, phip, sb, r, r)
+            g = (1 / (np.cos(np.pi / n) - np.cos((phi - phip) / n))
+                 + r / (np.cos(np.pi / n) - np.cos((phi + phip) / n)))
+            keller = np.exp(-1j * np.pi / 4) * np.sin(np.pi / n) / (n * np.sqrt(2 * np.pi * k) * sb) * g
+            assert abs(d - keller) <= 1e-4 * abs(keller)
+
+
+@pytest.mark.parametrize("r", [-1.0, 1.0])
+def test_half_plane_total_field_is_continuous_at_the_boundaries(r):
+    """Half-plane (n = 2), perfectly conducting, normal incidence: the incident
+    field vanishes across phi = pi + phi' and the reflected one across
+    phi = pi - phi'; geometric optics plus the diffracted field stays
+    continuous there."""
+    from oracle import diffraction as dif
+    k, sp, s, phip = 2 * np.pi / 0.1, 3.0, 2.0, np.radians(50.0)
+    S = sp * np.array([np.cos(phip), np.sin(phip)])
+    Si = sp * np.array([np.cos(phip), -np.sin(phip)])  # image in face 0
+
+    def total(phi):
+        O = s * np.array([np.cos(phi), np.sin(phi)])
+        u = 0j
+        if phi < np.pi + phip:
+            R = np.linalg.norm(S - O)
+            u += np.exp(-1j * k * R) / R
+        if phi < np.pi - phip:
+            R = np.linalg.norm(Si - O)
+            u += r * np.exp(-1j * k * R) / R
+        L = s * sp / (s + sp)
+        d = dif.coefficient(2.0, k, L, phi, phip, 1.0, r, r)
+        return u + np.exp(-1j * k * sp) / sp * d * np.sqrt(sp / (s * (s + sp))) * np.exp(-1j * k * s)
+
+    # the one-sided limits at each boundary, from a Richardson step on the
+    # difference across it (the fields vary smoothly away from the boundary)
+    for bnd in (np.pi + phip, np.pi - phip):
+        go_jump = 1.0 / (sp + s)  # the geometric-optics term that switches off there (|field| ~ 1/(s + s'))
+        J = lambda d: total(bnd - d) - total(bnd + d)  # noqa: E731
+        J0 = 2 * J(1e-4) - J(2e-4)
+        assert abs(J0) <= 1e-3 * go_jump
