@@ -308,6 +308,33 @@ def dps_workload(sc, rx, tx, mats, rays, reps, leaf, width, builder):
                 n_point_sets=scene.info["n_point_sets"], build_ms=scene.info["build_ms"], **out)
 
 
+def diffraction_workload(sc, rx, tx, mats, reps, leaf, width, builder):
+    """Single-bounce edge diffraction over the office furniture's 160 convex
+    edges to the 64 receivers (one HIP-event-timed call per repetition)."""
+    import torch
+    import paper_2507_04021_amd as P
+    from paper_2507_04021_amd import scenes
+    scene = P.Scene.from_scene(sc, leaf_size=leaf, width=width, builder=builder)
+    rows, labels = scenes.office_edges(sc)
+    e_t = P.edges_tensor(rows, labels)
+    mats_t = P.materials_tensor(mats)
+    rx_t = torch.as_tensor(rx, device="cuda")
+    out, _ = P.diffraction(scene, e_t, mats_t, tx, rx_t, 28e9)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        out, _ = P.diffraction(scene, e_t, mats_t, tx, rx_t, 28e9)
+    e1.record()
+    torch.cuda.synchronize()
+    _, amp = P.diffraction(scene, e_t, mats_t, tx, rx_t, 28e9, want_pairs=True)
+    o = out.cpu().numpy()
+    return dict(workload="office furniture, %d convex edges x %d RX, 28 GHz, UTD wedge coefficient" % (len(rows), len(rx)),
+                ms=e0.elapsed_time(e1) / reps, pairs=len(rows) * len(rx),
+                paths=int((np.abs(amp[..., 0]) > 0).sum()),
+                gain_db_mean=float(np.mean(10 * np.log10(np.maximum(o[:, 0], 1e-30)))))
+
+
 def mlp_workload(iters):
     """Learned materials: box room with one label per surface (8 labels);
     512 channel sets, 256 at 3.5 GHz and 256 at 28 GHz, each 1 TX + 8 RX at
@@ -518,6 +545,9 @@ def main():
         line["mlp"] = mlp_workload(args.mlp_iters)
         log("impulse-response learning workload...")
         line["cir"] = cir_workload(args.cir_iters)
+        log("edge diffraction workload...")
+        line["diffraction"] = diffraction_workload(sc, rx, tx, mats, max(3, args.steps // 2), args.leaf, args.width,
+                                                   args.builder)
         log("point-set averaging workload...")
         line["dps"] = dps_workload(sc, rx, tx, mats, args.rays, max(3, args.steps // 2), args.leaf, args.width,
                                    args.builder)

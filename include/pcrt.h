@@ -325,6 +325,38 @@ pcrt_status pcrt_autotune(const pcrt_scene *const *scenes, uint32_t n_scenes, co
                           uint32_t reps, void *solve_ws, size_t solve_ws_bytes, const pcrt_outputs *out, void *stream,
                           pcrt_tuning *table, pcrt_tuning *best);
 
+/* ------------------------------------------- edge diffraction (Sec. II-B.3) */
+/* One straight wedge edge from a to b; n0, n1: outward normals of its two faces
+ * (face 0 and face n); label0, label1: their material labels. The wedge is the
+ * region behind both faces (a convex edge, exterior angle n pi with 1 < n <= 2). */
+typedef struct {
+    float a[3], b[3], n0[3], n1[3];
+    uint16_t label0, label1;
+} pcrt_edge;
+
+/* Device workspace of pcrt_diffraction (stack spill + per-pair amplitudes). */
+pcrt_status pcrt_diffraction_workspace_size(const pcrt_scene *scene, uint32_t n_edges, uint32_t n_rx, size_t *bytes);
+
+/* Single-bounce diffracted paths from tx (host float[3]) to every receiver
+ * over every edge: the edge point minimising the path length (strictly inside
+ * the edge; source and receiver in the wedge's exterior), visible from both
+ * ends (the segments are cut 2 r_p short at the edge, where the faces' own
+ * disks meet, and eps_self (0 = 1e-3 m) at the other end), with the field of
+ * the uniform theory of diffraction for a wedge (Kouyoumjian-Pathak) whose
+ * two reflection terms carry the faces' Fresnel coefficients (Luebbers);
+ * TE takes the perpendicular and TM the parallel coefficients. The paper
+ * leaves this field to its EM back end. Amplitudes are normalised like the
+ * other path types (isotropic antennas, lambda/4pi). edges, mats (pcrt_material
+ * [n_labels]; labels beyond it read label n_labels - 1), rx (float[n_rx][3]):
+ * device. out: device double[n_rx][5] = G, h_TE re, im, h_TM re, im (sums over
+ * edges in edge order). pair_amp: optional device float[n_rx][n_edges][4]
+ * (TE re, im, TM re, im; 0 where no path). Asynchronous, allocates nothing.
+ * Errors: EINVAL for NULL pointers, zero sizes, freq <= 0; ENOMEM for a small ws. */
+pcrt_status pcrt_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                             const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                             uint32_t n_rx, double freq_hz, float eps_self, void *ws, size_t ws_bytes, double *out,
+                             float *pair_amp, void *stream);
+
 /* ------------------------------------------------------ differentiation */
 /* The tape of a PCRT_RECORD solve lives in its workspace. It holds the path
  * geometry, which does not depend on the materials, as interaction slots:

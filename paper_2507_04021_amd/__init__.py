@@ -65,6 +65,11 @@ class SolveParams(ctypes.Structure):
                 ("lambda_d", ctypes.c_float), ("dps_vis", ctypes.c_void_p)]
 
 
+class Edge(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_float * 3), ("b", ctypes.c_float * 3), ("n0", ctypes.c_float * 3),
+                ("n1", ctypes.c_float * 3), ("label0", ctypes.c_uint16), ("label1", ctypes.c_uint16)]
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [("tx", ctypes.c_float * 3), ("n_rays", ctypes.c_uint32)]
 
@@ -118,6 +123,9 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_scene_get_info.argtypes = [vp, ctypes.POINTER(SceneInfo)]
         L.pcrt_scene_destroy.argtypes = [vp]
         L.pcrt_reception_points.argtypes = [vp, vp, vp]
+        L.pcrt_diffraction_workspace_size.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(sz)]
+        L.pcrt_diffraction.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
+                                       vp, ctypes.c_uint32, ctypes.c_double, ctypes.c_float, vp, sz, vp, vp, vp]
         L.pcrt_visibility_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
         L.pcrt_visibility.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_float, vp, sz, vp, vp]
         L.pcrt_solve_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]
@@ -252,6 +260,52 @@ def visibility(scene: Scene, rx, eps_self=0.0, ws=None, out=None, stream=None):
     _check(L.pcrt_visibility(scene.handle, _ptr(rx_t), rx_t.shape[0], float(eps_self), _ptr(ws), ws.numel(),
                              _ptr(out), _stream(stream)), L)
     return out[:, :n]
+
+
+def edges_tensor(rows, labels, device="cuda"):
+    """Device array of pcrt_edge from rows float[n, 12] (a, b, n0, n1) and labels int[n, 2]."""
+    torch = _torch()
+    rows = np.ascontiguousarray(rows, np.float32).reshape(-1, 12)
+    labels = np.ascontiguousarray(labels, np.int64).reshape(-1, 2)
+    arr = (Edge * len(rows))()
+    for i in range(len(rows)):
+        arr[i].a[:] = rows[i, 0:3].tolist()
+        arr[i].b[:] = rows[i, 3:6].tolist()
+        arr[i].n0[:] = rows[i, 6:9].tolist()
+        arr[i].n1[:] = rows[i, 9:12].tolist()
+        arr[i].label0, arr[i].label1 = int(labels[i, 0]), int(labels[i, 1])
+    raw = np.frombuffer(bytes(arr), np.uint8)
+    return torch.as_tensor(raw.copy(), device=device), len(rows)
+
+
+def diffraction(scene: Scene, edges, mats, tx, rx, freq, eps_self=0.0, want_pairs=False, ws=None, stream=None):
+    """Single-bounce diffracted paths over edges (from edges_tensor, or (rows, labels)).
+    Returns (out float64[n_rx, 5]: G, h_TE re, im, h_TM re, im; pair amplitudes complex
+    [n_rx, n_edges, 2] or None)."""
+    torch = _torch()
+    L = lib(scene._variant)
+    dev = scene.device
+    e_t, n_e = edges if isinstance(edges, tuple) and isinstance(edges[0], torch.Tensor) else \
+        edges_tensor(edges[0], edges[1], dev)
+    mats_t = mats if isinstance(mats, torch.Tensor) and mats.device.type == "cuda" else materials_tensor(mats, dev)
+    rx_t = _dev(np.asarray(rx, np.float32).reshape(-1, 3) if not isinstance(rx, torch.Tensor) else rx,
+                torch.float32, dev).reshape(-1, 3)
+    n_rx = rx_t.shape[0]
+    nb = ctypes.c_size_t(0)
+    _check(L.pcrt_diffraction_workspace_size(scene.handle, n_e, n_rx, ctypes.byref(nb)), L)
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    out = torch.empty(n_rx, 5, dtype=torch.float64, device=dev)
+    pairs = torch.empty(n_rx, n_e, 4, dtype=torch.float32, device=dev) if want_pairs else None
+    txa = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(tx, np.float32).reshape(3)])
+    _check(L.pcrt_diffraction(scene.handle, _ptr(e_t), n_e, _ptr(mats_t), mats_t.shape[0], txa, _ptr(rx_t), n_rx,
+                              float(freq), float(eps_self), _ptr(ws), ws.numel(), _ptr(out), _ptr(pairs),
+                              _stream(stream)), L)
+    amp = None
+    if want_pairs:
+        p = pairs.cpu().numpy().astype(np.float64)
+        amp = np.stack([p[..., 0] + 1j * p[..., 1], p[..., 2] + 1j * p[..., 3]], -1)
+    return out, amp
 
 
 def materials_tensor(mats, device="cuda"):

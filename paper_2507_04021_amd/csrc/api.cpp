@@ -548,6 +548,45 @@ pcrt_status pcrt_visibility(const pcrt_scene *scene, const float *rx, uint32_t n
     return ok();
 }
 
+static size_t diffraction_ws(const pcrt_scene *sc, uint32_t n_edges, uint32_t n_rx, size_t *spill) {
+    const uint32_t depth = sc->info.stack_entries > (uint32_t)kStackLds ? sc->info.stack_entries - kStackLds : 0;
+    *spill = ((sizeof(int) * (size_t)depth * diffraction_blocks(n_edges, n_rx) * kWave) + 255) & ~size_t(255);
+    return *spill + sizeof(float4) * (size_t)n_edges * n_rx;
+}
+
+pcrt_status pcrt_diffraction_workspace_size(const pcrt_scene *scene, uint32_t n_edges, uint32_t n_rx, size_t *bytes) {
+    if (!scene || !bytes) return fail(PCRT_EINVAL, "scene and bytes are required");
+    if (n_edges == 0 || n_rx == 0) return fail(PCRT_EINVAL, "n_edges and n_rx must be > 0");
+    if ((uint64_t)n_edges * n_rx > (1ull << 30)) return fail(PCRT_EUNSUPPORTED, "at most 2^30 (edge, receiver) pairs");
+    size_t spill;
+    *bytes = diffraction_ws(scene, n_edges, n_rx, &spill);
+    return ok();
+}
+
+pcrt_status pcrt_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                             const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                             uint32_t n_rx, double freq_hz, float eps_self, void *ws, size_t ws_bytes, double *out,
+                             float *pair_amp, void *stream) {
+    if (!scene || !edges || !mats || !tx || !rx || !ws || !out)
+        return fail(PCRT_EINVAL, "scene, edges, mats, tx, rx, ws and out are required");
+    if (n_edges == 0 || n_rx == 0 || n_labels == 0) return fail(PCRT_EINVAL, "n_edges, n_rx and n_labels must be > 0");
+    if ((uint64_t)n_edges * n_rx > (1ull << 30)) return fail(PCRT_EUNSUPPORTED, "at most 2^30 (edge, receiver) pairs");
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(PCRT_EINVAL, "freq_hz must be > 0");
+    if (!(eps_self >= 0.f) || !std::isfinite(eps_self)) return fail(PCRT_EINVAL, "eps_self must be >= 0");
+    if (!std::isfinite(tx[0]) || !std::isfinite(tx[1]) || !std::isfinite(tx[2])) return fail(PCRT_EINVAL, "tx must be finite");
+    size_t spill;
+    const size_t need = diffraction_ws(scene, n_edges, n_rx, &spill);
+    if (ws_bytes < need) return fail(PCRT_ENOMEM, "diffraction workspace too small: need %zu bytes", need);
+    DevScene S = scene->dev;
+    S.spill = (int *)ws;
+    S.spill_lanes = diffraction_blocks(n_edges, n_rx) * kWave;
+    float4 *amp = pair_amp ? (float4 *)pair_amp : (float4 *)((char *)ws + spill);
+    launch_diffraction(S, edges, n_edges, (const float *)mats, n_labels, tx, rx, n_rx, freq_hz,
+                       eps_self > 0.f ? eps_self : 1e-3f, amp, out, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
 pcrt_status pcrt_reception_points(const pcrt_scene *scene, float *out, void *stream) {
     if (!scene || !out) return fail(PCRT_EINVAL, "scene and out are required");
     if (!scene->dev.dps_pt) return fail(PCRT_EINVAL, "the scene has no point sets (dps_voxel = 0)");

@@ -8,6 +8,7 @@
 #include <cstddef>
 
 #include "common.h"
+#include "pcrt.h"
 
 namespace pcrt {
 
@@ -49,6 +50,11 @@ struct SceneLayout {
 };
 
 SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps);
+// Single-bounce edge diffraction: per-pair amplitudes, then per-receiver sums.
+uint32_t diffraction_blocks(uint32_t n_edges, uint32_t n_rx);
+void launch_diffraction(const DevScene &S, const pcrt_edge *edges, uint32_t n_edges, const float *mats,
+                        uint32_t n_labels, const float tx[3], const float *rx, uint32_t n_rx, double freq,
+                        float eps_self, float4 *amp, double *out, hipStream_t s);
 // Visibility of the point sets' reception points from receivers (one uint8 per pair).
 uint32_t visibility_grid(uint32_t width);
 void launch_visibility(const DevScene &S, const float *rx, uint32_t n_rx, const float4 *recv, uint32_t n_sets,

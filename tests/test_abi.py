@@ -121,6 +121,8 @@ def test_solve_argument_errors(L):
     assert L.pcrt_reception_points(None, None, None) == EINVAL
     assert L.pcrt_visibility_workspace_size(None, ctypes.byref(nb)) == EINVAL
     assert L.pcrt_visibility(None, None, 1, 0.0, None, 0, None, None) == EINVAL
+    assert L.pcrt_diffraction_workspace_size(None, 1, 1, ctypes.byref(nb)) == EINVAL
+    assert L.pcrt_diffraction(None, None, 1, None, 1, None, None, 1, 1e9, 0.0, None, 0, None, None, None) == EINVAL
     assert L.pcrt_tape_cfr(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
     assert L.pcrt_tape_cfr_backward(None, ctypes.byref(p), None, 1.5e9, 129, None, None) == EINVAL
     assert L.pcrt_last_error()  # an explanation is always set on failure
@@ -136,7 +138,8 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
 
 STRUCTS = [("pcrt_points", "Points"), ("pcrt_bvh_opts", "BvhOpts"), ("pcrt_scene_info", "SceneInfo"),
            ("pcrt_thresholds", "Thresholds"), ("pcrt_solve_params", "SolveParams"), ("pcrt_batch_item", "BatchItem"),
-           ("pcrt_tuning", "Tuning"), ("pcrt_mlp", "Mlp"), ("pcrt_tape", "Tape"), ("pcrt_outputs", "Outputs")]
+           ("pcrt_tuning", "Tuning"), ("pcrt_mlp", "Mlp"), ("pcrt_tape", "Tape"), ("pcrt_outputs", "Outputs"),
+           ("pcrt_edge", "Edge")]
 
 
 def test_binding_structs_match_the_header(tmp_path):
