@@ -320,3 +320,32 @@ def test_dps_diffuse_floor_exact(P, orc):
     # one set in 1000 may change its key through an FP32 tie decision (each path is ~1/ns of the power)
     assert np.allclose(r.parts.cpu().numpy()[:, 2], ref.G_diff, rtol=2e-3)
     assert abs(r.counter("diffuse") - 2 * ns) <= max(2, 2 * ns // 1000)
+
+
+def test_average_tape_and_gradient(P, orc, calm):
+    """The recorded tape of an averaged solve reproduces its gains, and the
+    material gradient through it matches the oracle's analytic Jacobian of
+    the averaged solve (the averaged cosines and normals enter both)."""
+    import torch
+    from paper_2507_04021_amd import diff
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    tx, N, K, f = [1.1, 0.7, 1.3], 3000, 2, 3.5e9
+    fl = LOS | SPEC | DIFF
+    step("averaged tape and gradient")
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    rec = diff.record(sg, mats, tx, rx, f, N, K=K, flags=fl | AVG, lambda_d=LAM)
+    g0 = rec.gain.clone()
+    P.tape_fresnel(rec, mats)
+    assert torch.allclose(P.tape_forward(rec)[0], g0, rtol=2e-6, atol=0)
+    ref = orc.solve(calm, mats, tx, rx, f, N, K=K, flags=fl, want_jac=True, average=(RHO, LAM))
+    assert np.allclose(g0.cpu().numpy(), ref.G, rtol=2e-3)
+    target = 10 * np.log10(ref.G) + np.array([0.5, -0.3, 0.2])
+    m = torch.tensor(mats, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = diff.db_mse_loss(diff.gains(m, rec), torch.tensor(target, device="cuda"))
+    loss.backward()
+    g_gpu = m.grad.cpu().numpy()
+    dl_dg = 2 * (10 * np.log10(ref.G) - target) * 10 / (ref.G * np.log(10)) / len(ref.G)
+    g_orc = np.einsum("r,rlp->lp", dl_dg, ref.jac)
+    scale = np.abs(g_orc).max()
+    assert np.all(np.abs(g_gpu - g_orc) <= 5e-3 * np.abs(g_orc) + 1e-3 * scale), (g_gpu, g_orc)
