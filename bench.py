@@ -430,7 +430,7 @@ def main():
                     help="also run one plain 1 GiB device copy (calibrates the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (rays would shard by "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (rays would shard by "
               "strided ranges with one all-reduce of per-receiver sums; not implemented).", file=sys.stderr)
         sys.exit(2)
 

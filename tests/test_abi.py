@@ -162,3 +162,14 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got["%s size" % cname]) == ctypes.sizeof(cls), cname
         for f in cls._fields_:
             assert int(got["%s %s" % (cname, f[0])]) == getattr(cls, f[0]).offset, (cname, f[0])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching the GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
