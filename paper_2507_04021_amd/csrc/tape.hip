@@ -445,30 +445,42 @@ __device__ bool cfr_path(const LaunchArgs &A, uint32_t j, uint32_t r, uint32_t n
     return true;
 }
 
-// Block (receiver r, 256 frequencies): the lanes evaluate 256 paths at a time
-// into LDS, then each lane adds all of them, in path order, to its frequency.
-__global__ __launch_bounds__(256) void k_tape_cfr(LaunchArgs A, double bw, uint32_t N, double *cfr) {
-    __shared__ CfrPath P[256];
-    __shared__ int ok[256];
-    const uint32_t r = blockIdx.x, n = blockIdx.y * 256 + threadIdx.x;
+// Block (receiver r, 64 frequencies), 16 wavefronts: the path list is cut
+// into 16 contiguous ranges, one per wavefront. A wavefront's lanes evaluate 64
+// paths of its range at a time into LDS, then each lane adds them, in path
+// order, to its frequency; the block then adds the 16 range sums in range
+// order. The order of the FP64 sums is fixed, so results are reproducible.
+constexpr int kCfrWaves = 16;
+__global__ __launch_bounds__(kCfrWaves * kWave) void k_tape_cfr(LaunchArgs A, double bw, uint32_t N, double *cfr) {
+    __shared__ CfrPath P[kCfrWaves][kWave];
+    __shared__ int ok[kCfrWaves][kWave];
+    static_assert(sizeof(P) >= sizeof(double) * kCfrWaves * kWave * 4, "range sums reuse the path buffer");
+    double(*part)[kWave][4] = reinterpret_cast<double(*)[kWave][4]>(&P[0][0]);  // after the last round
+    const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const uint32_t r = blockIdx.x, n = blockIdx.y * kWave + lane;
     const uint32_t nk = (A.flags & 2) ? n_keys_rec(A) : 0;
     const uint32_t nd = (A.flags & 4) ? A.D.T * A.D.K : 0;
     const uint32_t total = 1 + nk + nd;
+    const uint32_t lo = (uint32_t)((uint64_t)total * wv / kCfrWaves);
+    const uint32_t hi = (uint32_t)((uint64_t)total * (wv + 1) / kCfrWaves);
+    // every wavefront runs the same number of rounds (the longest range), so
+    // the block-wide barriers below are reached by all of them
+    const uint32_t rounds = (total / kCfrWaves + 1 + kWave - 1) / kWave;
     const double w = -2.0 * M_PI * cfr_df(n, N, bw);
     cd hte = {0.0, 0.0}, htm = {0.0, 0.0};
-    for (uint32_t b = 0; b < total; b += 256) {
-        const uint32_t j = b + threadIdx.x;
+    for (uint32_t q = 0; q < rounds; ++q) {
+        const uint32_t b = lo + q * kWave, j = b + lane;
         CfrPath pp{};
-        ok[threadIdx.x] = j < total && cfr_path(A, j, r, nk, pp);
-        P[threadIdx.x] = pp;
+        ok[wv][lane] = j < hi && cfr_path(A, j, r, nk, pp);
+        P[wv][lane] = pp;
         __syncthreads();
-        const uint32_t cnt = min(256u, total - b);
+        const uint32_t cnt = b < hi ? min((uint32_t)kWave, hi - b) : 0u;
         for (uint32_t i = 0; i < cnt; ++i) {
-            if (!ok[i]) continue;
+            if (!ok[wv][i]) continue;
             double sn, cs;
-            sincos(w * P[i].tau, &sn, &cs);
+            sincos(w * P[wv][i].tau, &sn, &cs);
             const cd e = {cs, sn};
-            const cd a = cdmul(P[i].te, e), c = cdmul(P[i].tm, e);
+            const cd a = cdmul(P[wv][i].te, e), c = cdmul(P[wv][i].tm, e);
             hte.re += a.re;
             hte.im += a.im;
             htm.re += c.re;
@@ -476,35 +488,42 @@ __global__ __launch_bounds__(256) void k_tape_cfr(LaunchArgs A, double bw, uint3
         }
         __syncthreads();
     }
-    if (n < N) {
-        double *o = cfr + ((size_t)r * N + n) * 4;
-        o[0] = hte.re;
-        o[1] = hte.im;
-        o[2] = htm.re;
-        o[3] = htm.im;
+    part[wv][lane][0] = hte.re;
+    part[wv][lane][1] = hte.im;
+    part[wv][lane][2] = htm.re;
+    part[wv][lane][3] = htm.im;
+    __syncthreads();
+    if (wv < 4 && n < N) {  // wavefront c adds component c over the ranges, in range order
+        double v = 0.0;
+        for (int k = 0; k < kCfrWaves; ++k) v += part[k][lane][wv];
+        cfr[((size_t)r * N + n) * 4 + wv] = v;
     }
 }
 
 void launch_tape_cfr(const LaunchArgs &A, double bw, uint32_t N, double *cfr, hipStream_t s) {
-    hipLaunchKernelGGL(k_tape_cfr, dim3(A.D.n_rx, (N + 255) / 256), dim3(256), 0, s, A, bw, N, cfr);
+    hipLaunchKernelGGL(k_tape_cfr, dim3(A.D.n_rx, (N + kWave - 1) / kWave), dim3(kCfrWaves * kWave), 0, s, A, bw, N,
+                       cfr);
 }
 
 // dL/da_p (as gR + j gI per polarisation) of one path from dL/dH_r:
-// sum over n of dL/dH_r(f_n) exp(+j 2 pi (f_n - f_c) tau_p).
+// sum over n of dL/dH_r(f_n) exp(+j 2 pi (f_n - f_c) tau_p). Called by all
+// lanes of a wavefront for the same path: lane l adds samples l, l + 64, ...,
+// then a fixed butterfly adds the lanes, so every lane holds the same sums.
 __device__ __forceinline__ void cfr_path_grad(const double *dldh, uint32_t r, uint32_t N, double bw, double tau,
-                                              cd &gte, cd &gtm) {
-    gte = {0.0, 0.0};
-    gtm = {0.0, 0.0};
-    for (uint32_t n = 0; n < N; ++n) {
+                                              uint32_t lane, cd &gte, cd &gtm) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t n = lane; n < N; n += kWave) {
         double sn, cs;
         sincos(2.0 * M_PI * cfr_df(n, N, bw) * tau, &sn, &cs);
         const double *g = dldh + ((size_t)r * N + n) * 4;
         const cd a = cdmul({g[0], g[1]}, {cs, sn}), b = cdmul({g[2], g[3]}, {cs, sn});
-        gte.re += a.re;
-        gte.im += a.im;
-        gtm.re += b.re;
-        gtm.im += b.im;
+        acc[0] += a.re;
+        acc[1] += a.im;
+        acc[2] += b.re;
+        acc[3] += b.im;
     }
+    gte = {wave_sum_d(acc[0]), wave_sum_d(acc[1])};
+    gtm = {wave_sum_d(acc[2]), wave_sum_d(acc[3])};
 }
 
 // Adjoint rows of one chain a = G prod_m f_m Gamma_m (f_m = sqrt(1 - S_m^2)
@@ -552,12 +571,14 @@ __device__ __forceinline__ void chain_adjoint_c(int k, const SlotCoef *cf, const
     }
 }
 
-// Traced-interaction slots: one thread per ray, all of its diffuse paths.
+// Traced-interaction slots: one wavefront per ray, all of its diffuse paths;
+// the lanes share each path's frequency sum, and all of them evaluate the
+// (identical) chain; lane 0 writes.
 template <int KM>
 __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_trace(LaunchArgs A, double bw, uint32_t N,
                                                                 const double *dldh) {
-    const uint32_t K = A.D.K, n_rx = A.D.n_rx;
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < A.D.T; g += gridDim.x * blockDim.x) {
+    const uint32_t K = A.D.K, n_rx = A.D.n_rx, lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+    for (uint32_t g = blockIdx.x * wpb + threadIdx.x / kWave; g < A.D.T; g += gridDim.x * wpb) {
         double adj[KM][5];
 #pragma unroll
         for (int m = 0; m < KM; ++m)
@@ -583,7 +604,7 @@ __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_trace(LaunchArgs A, do
                     const c32 ph = propagate(plen, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
                     const cd G = {(double)a0 * ph.re, (double)a0 * ph.im};
                     cd gte, gtm;
-                    cfr_path_grad(dldh, r, N, bw, (double)plen / kC0, gte, gtm);
+                    cfr_path_grad(dldh, r, N, bw, (double)plen / kC0, lane, gte, gtm);
                     const cd ete = cdmul(gte, cdconj(G)), etm = cdmul(gtm, cdconj(G));
                     Ete.re += ete.re;
                     Ete.im += ete.im;
@@ -599,7 +620,7 @@ __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_trace(LaunchArgs A, do
         }
 #pragma unroll
         for (int m = 0; m < KM; ++m) {
-            if (m >= (int)K) continue;
+            if (m >= (int)K || lane != 0) continue;
             float4 *o = (float4 *)(A.slot_adj + 8 * ((size_t)g * K + m));
             o[0] = make_float4((float)adj[m][0], (float)adj[m][1], (float)adj[m][2], (float)adj[m][3]);
             o[1] = make_float4((float)adj[m][4], 0.f, 0.f, 0.f);
@@ -607,14 +628,14 @@ __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_trace(LaunchArgs A, do
     }
 }
 
-// Specular-path slots: one thread per (key, RX) pair.
+// Specular-path slots: one wavefront per (key, RX) pair, as above.
 template <int KM>
 __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_spec(LaunchArgs A, double bw, uint32_t N,
                                                                const double *dldh) {
     const uint32_t K = A.D.K, n_rx = A.D.n_rx, TK = A.D.T * A.D.K;
-    const uint32_t nk = n_keys_rec(A);
+    const uint32_t nk = n_keys_rec(A), lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
     const size_t n_pairs = (size_t)A.D.rec_keys * n_rx;
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n_pairs; p += (size_t)gridDim.x * blockDim.x) {
+    for (size_t p = blockIdx.x * (size_t)wpb + threadIdx.x / kWave; p < n_pairs; p += (size_t)gridDim.x * wpb) {
         double adj[KM][5];
 #pragma unroll
         for (int m = 0; m < KM; ++m)
@@ -634,12 +655,12 @@ __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_spec(LaunchArgs A, dou
             const c32 ph = propagate(L, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
             const cd G = {(double)a0 * ph.re, (double)a0 * ph.im};
             cd gte, gtm;
-            cfr_path_grad(dldh, r, N, bw, (double)L / kC0, gte, gtm);
+            cfr_path_grad(dldh, r, N, bw, (double)L / kC0, lane, gte, gtm);
             chain_adjoint_c<KM>((int)k, cf, de, cdmul(gte, cdconj(G)), cdmul(gtm, cdconj(G)), adj);
         }
 #pragma unroll
         for (int m = 0; m < KM; ++m) {
-            if (m >= (int)K) continue;
+            if (m >= (int)K || lane != 0) continue;
             float4 *o = (float4 *)(A.slot_adj + 8 * (TK + p * K + m));
             o[0] = make_float4((float)adj[m][0], (float)adj[m][1], (float)adj[m][2], (float)adj[m][3]);
             o[1] = make_float4((float)adj[m][4], 0.f, 0.f, 0.f);
@@ -648,9 +669,9 @@ __global__ __launch_bounds__(256) void k_tape_cfr_adjoint_spec(LaunchArgs A, dou
 }
 
 void launch_tape_cfr_backward(const LaunchArgs &A, double bw, uint32_t N, const double *dldh, hipStream_t s) {
-    const uint32_t gt = std::min<uint32_t>((A.D.T + 255) / 256, 4096);
+    const uint32_t gt = std::min<uint32_t>((A.D.T + 3) / 4, 16384);  // four wavefronts per block
     const size_t np = (size_t)A.D.rec_keys * A.D.n_rx;
-    const uint32_t gs = (uint32_t)std::min<size_t>((np + 255) / 256, 4096);
+    const uint32_t gs = (uint32_t)std::min<size_t>((np + 3) / 4, 16384);
     switch (A.D.K) {
 #define PCRT_TC_CASE(KK)                                                                                       \
     case KK:                                                                                                   \

@@ -61,6 +61,25 @@ def test_cfr_matches_oracle(env, orc, flags, scatter):
     np.testing.assert_allclose(h[:, NF // 2, 0], hte, rtol=1e-6, atol=1e-6 * np.abs(hte).max())
 
 
+def test_cfr_is_reproducible_across_calls_and_frequency_tilings(env):
+    """The path sums run in a fixed order that does not depend on the sample
+    count: repeated calls agree bitwise, and the centre sample of 129 equals
+    the single-sample response bitwise (its phase factor is exactly 1)."""
+    torch, P, diff, s, sg, rx = env
+    mats = _mats(7, 0.3)
+    rec = diff.record(sg, mats, scenes.BOX_TX, rx, FC, NR, K=K, flags=LOS | SPEC | DIFF)
+    P.tape_fresnel(rec, mats)
+    a = P.tape_cfr(rec, BW, NF).cpu().numpy()
+    b = P.tape_cfr(rec, BW, NF).cpu().numpy()
+    assert np.array_equal(a, b)
+    one = P.tape_cfr(rec, BW, 1).cpu().numpy()
+    assert one.shape == (3, 1, 2)
+    assert np.array_equal(one[:, 0], a[:, NF // 2])
+    # 65 samples: two frequency tiles, the second with one sample
+    h65 = P.tape_cfr(rec, BW, 65).cpu().numpy()
+    assert np.array_equal(h65[:, 32], a[:, NF // 2])
+
+
 def test_cfr_gradient_matches_finite_differences(env, orc):
     torch, P, diff, s, sg, rx = env
     flags, scatter = LOS | SPEC | DIFF, 0.3
