@@ -116,18 +116,18 @@ def train(mlp: MaterialMLP, sets, iters=300, batch=16, lr=3e-3, seed=0, log_ever
     for it in range(iters):
         idx = rng.choice(len(sets), size=min(batch, len(sets)), replace=False)
         acc = {k: torch.zeros_like(v) for k, v in mlp.p.items()}
-        tot = 0.0
+        tot = torch.zeros((), dtype=torch.float64, device=mlp.device)  # read once per iteration: no sync per set
         for i in idx:
             rec, f, tgt = sets[i]
             loss, g = mlp.loss_and_grads(rec, f, tgt)
-            tot += float(loss)
+            tot += loss
             for k in acc:
                 acc[k] += g[k]
         for k, v in mlp.p.items():
             v.grad = acc[k] / len(idx)
         opt.step()
         mlp.pack()
-        hist.append(tot / len(idx))
+        hist.append(float(tot) / len(idx))
         if log_every and it % log_every == 0:
             print("iter %d loss %.4f" % (it, hist[-1]), flush=True)
     return hist
