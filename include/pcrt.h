@@ -409,8 +409,10 @@ pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params 
  * (n_freq - 1) (the centre frequency alone when n_freq == 1). The channel
  * impulse response is the inverse DFT of these samples. Paths: line of sight,
  * valid specular paths, visible diffuse connections, in that order, cut into
- * 16 contiguous ranges; each range is summed in order and the range sums are
- * added in range order, in FP64, so results are reproducible. cfr: device double[n_rx][n_freq][4] = (H_TE re, im, H_TM
+ * 16 contiguous ranges, each range into rounds of 64 paths and each round into
+ * 4 interleaved subsets; each subset is summed in path order and the subset
+ * and range sums are added in order, in FP64. The order does not depend on
+ * n_freq, so results are reproducible. cfr: device double[n_rx][n_freq][4] = (H_TE re, im, H_TM
  * re, im). n_freq in 1..65535, bandwidth_hz >= 0; EINVAL otherwise. */
 pcrt_status pcrt_tape_cfr(const pcrt_scene *scene, const pcrt_solve_params *p, void *ws, double bandwidth_hz,
                           uint32_t n_freq, double *cfr, void *stream);

@@ -445,19 +445,21 @@ __device__ bool cfr_path(const LaunchArgs &A, uint32_t j, uint32_t r, uint32_t n
     return true;
 }
 
-// Block (receiver r, 64 frequencies), 16 wavefronts: the path list is cut
+// Block (receiver r, 16 frequencies), 16 wavefronts: the path list is cut
 // into 16 contiguous ranges, one per wavefront. A wavefront's lanes evaluate 64
-// paths of its range at a time into LDS, then each lane adds them, in path
-// order, to its frequency; the block then adds the 16 range sums in range
-// order. The order of the FP64 sums is fixed, so results are reproducible.
-constexpr int kCfrWaves = 16;
+// paths of its range at a time into LDS; lane l then adds, to frequency l % 16,
+// every 4th of them starting at l / 16, in path order (four interleaved
+// subsets, so small sample counts still fill the chip). The block adds the
+// subsets and then the ranges, both in order. The order of the FP64 sums is
+// fixed and independent of the sample count, so results are reproducible.
+constexpr int kCfrWaves = 16, kCfrF = 16, kCfrQ = kWave / kCfrF;
 __global__ __launch_bounds__(kCfrWaves * kWave) void k_tape_cfr(LaunchArgs A, double bw, uint32_t N, double *cfr) {
     __shared__ CfrPath P[kCfrWaves][kWave];
     __shared__ int ok[kCfrWaves][kWave];
-    static_assert(sizeof(P) >= sizeof(double) * kCfrWaves * kWave * 4, "range sums reuse the path buffer");
+    static_assert(sizeof(P) >= sizeof(double) * kCfrWaves * kWave * 4, "subset sums reuse the path buffer");
     double(*part)[kWave][4] = reinterpret_cast<double(*)[kWave][4]>(&P[0][0]);  // after the last round
     const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    const uint32_t r = blockIdx.x, n = blockIdx.y * kWave + lane;
+    const uint32_t sub = lane / kCfrF, r = blockIdx.x, n = blockIdx.y * kCfrF + lane % kCfrF;
     const uint32_t nk = (A.flags & 2) ? n_keys_rec(A) : 0;
     const uint32_t nd = (A.flags & 4) ? A.D.T * A.D.K : 0;
     const uint32_t total = 1 + nk + nd;
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(kCfrWaves * kWave) void k_tape_cfr(LaunchArgs A, do
         P[wv][lane] = pp;
         __syncthreads();
         const uint32_t cnt = b < hi ? min((uint32_t)kWave, hi - b) : 0u;
-        for (uint32_t i = 0; i < cnt; ++i) {
+        for (uint32_t i = sub; i < cnt; i += kCfrQ) {
             if (!ok[wv][i]) continue;
             double sn, cs;
             sincos(w * P[wv][i].tau, &sn, &cs);
@@ -493,15 +495,17 @@ __global__ __launch_bounds__(kCfrWaves * kWave) void k_tape_cfr(LaunchArgs A, do
     part[wv][lane][2] = htm.re;
     part[wv][lane][3] = htm.im;
     __syncthreads();
-    if (wv < 4 && n < N) {  // wavefront c adds component c over the ranges, in range order
+    if (threadIdx.x < kCfrF * 4) {  // thread (component c, frequency f): subsets, then ranges, in order
+        const uint32_t f = threadIdx.x % kCfrF, c = threadIdx.x / kCfrF, nn = blockIdx.y * kCfrF + f;
         double v = 0.0;
-        for (int k = 0; k < kCfrWaves; ++k) v += part[k][lane][wv];
-        cfr[((size_t)r * N + n) * 4 + wv] = v;
+        for (int k = 0; k < kCfrWaves; ++k)
+            for (int u = 0; u < kCfrQ; ++u) v += part[k][u * kCfrF + f][c];
+        if (nn < N) cfr[((size_t)r * N + nn) * 4 + c] = v;
     }
 }
 
 void launch_tape_cfr(const LaunchArgs &A, double bw, uint32_t N, double *cfr, hipStream_t s) {
-    hipLaunchKernelGGL(k_tape_cfr, dim3(A.D.n_rx, (N + kWave - 1) / kWave), dim3(kCfrWaves * kWave), 0, s, A, bw, N,
+    hipLaunchKernelGGL(k_tape_cfr, dim3(A.D.n_rx, (N + kCfrF - 1) / kCfrF), dim3(kCfrWaves * kWave), 0, s, A, bw, N,
                        cfr);
 }
 
