@@ -32,6 +32,15 @@
  * double precision; FP32 input arrays are promoted on entry. Parallelism is
  * OpenMP over independent rays / (key, receiver) pairs only; every reduction
  * is serial in a fixed order.
+ *
+ * Pins: tests/test_oracle_pins.py checks these functions against closed forms,
+ * brute force on tiny inputs, textbook special cases and invariants. Parity
+ * unpinned (conventions the paper leaves open, with no independent value to
+ * check them against; the GPU library is only compared with them): the tie
+ * window eps_tie and the self-hit distance eps_self of the nearest-hit rule,
+ * the pick between coplanar disks at the tiny room's holes and door edge, and,
+ * under ORC_AVERAGE, that the refinement takes its planes from the key's
+ * representative's averaged records.
  */
 #include <complex.h>
 #include <math.h>
