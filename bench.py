@@ -423,7 +423,7 @@ def main():
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--mlp-iters", type=int, default=300)
-    ap.add_argument("--cir-iters", type=int, default=1000)
+    ap.add_argument("--cir-iters", type=int, default=5000, help="Adam iterations of the impulse-response learning (the paper runs 5000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and gradient workloads")
     ap.add_argument("--copy-calib", action="store_true",
