@@ -61,6 +61,23 @@ def test_cfr_matches_oracle(env, orc, flags, scatter):
     np.testing.assert_allclose(h[:, NF // 2, 0], hte, rtol=1e-6, atol=1e-6 * np.abs(hte).max())
 
 
+def test_cfr_many_samples_matches_oracle(env, orc):
+    """1000 samples: 63 tiles of 16 samples, the last ragged (8), against the
+    oracle at every sample, with the tolerance derived above."""
+    torch, P, diff, s, sg, rx = env
+    mats = _mats(7, 0.3)
+    flags = LOS | SPEC | DIFF
+    rec = diff.record(sg, mats, scenes.BOX_TX, rx, FC, NR, K=K, flags=flags)
+    P.tape_fresnel(rec, mats)
+    nf = 1000
+    h = P.tape_cfr(rec, BW, nf).cpu().numpy()
+    ref = orc.solve(s, mats, scenes.BOX_TX, rx, FC, NR, K=K, flags=flags, cfr=(BW, nf)).cfr
+    assert h.shape == ref.shape == (3, nf, 2)
+    for r in range(3):
+        scale = np.abs(ref[r]).max()
+        assert np.abs(h[r] - ref[r]).max() <= 5e-4 * scale, r
+
+
 def test_cfr_is_reproducible_across_calls_and_frequency_tilings(env):
     """The path sums run in a fixed order that does not depend on the sample
     count: repeated calls agree bitwise, and the centre sample of 129 equals
