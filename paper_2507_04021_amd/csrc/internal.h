@@ -115,7 +115,7 @@ struct SolveDims {
     uint32_t width;        // node width of the scene's hierarchy (2, 4, 8)
 };
 
-constexpr uint32_t kSlotChunk = 4096;   // slots per label-gradient reduction chunk
+constexpr uint32_t kSlotChunk = 512;    // slots per label-gradient reduction chunk (one 64-lane block each)
 // Receivers per specular refinement unit (with one key chunk). Measured on the
 // 1M-point office: 16 -> 8.70 ms, 8 -> 8.55 ms, 32 -> 10.05 ms.
 constexpr uint32_t kRefineRxSlice = 8;

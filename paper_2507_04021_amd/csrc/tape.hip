@@ -740,8 +740,19 @@ __global__ __launch_bounds__(64) void k_label_grad(LaunchArgs A, const float *ma
 __global__ void k_label_grad_final(LaunchArgs A, uint32_t n_labels, double *out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_labels * 3) return;
+    // chunk order; eight loads are issued ahead of their adds
+    const uint32_t n = A.D.n_slot_chunks;
+    const size_t pitch = (size_t)kMaxGradLabels * 3;
     double s = 0.0;
-    for (uint32_t c = 0; c < A.D.n_slot_chunks; ++c) s += A.grad_part[(size_t)c * kMaxGradLabels * 3 + i];
+    uint32_t c = 0;
+    for (; c + 8 <= n; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = A.grad_part[(c + k) * pitch + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; c < n; ++c) s += A.grad_part[c * pitch + i];
     out[i] = s;
 }
 
