@@ -17,6 +17,7 @@ import ctypes
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -131,7 +132,7 @@ def batch_workload(reps):
     tx, n = scenes.trajectory(seed=4021, n=256)
     choice, rows = P.autotune(s, mats, scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 1 << 20, K=2, flags=P.LOS | P.SPECULAR,
                               leaf_sizes=(1, 2, 4, 8), widths=(2, 4, 8), wave_rays=(64, 128, 256), builders=(1, 2),
-                              reps=3, cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"))
+                              reps=3, cache_path=os.path.join(tempfile.gettempdir(), "pcrt_bench_tuning.json"))
     sg = P.Scene.from_scene(s, leaf_size=choice["leaf_size"], width=choice["width"], builder=choice["builder"])
     graph = P.BatchGraph(sg, mats, tx, n, [scenes.BOX_RX], 3.5e9, K=2, flags=P.LOS | P.SPECULAR,
                          wave_rays=choice["wave_rays"])
