@@ -173,7 +173,7 @@ def grad_workload(reps):
 
 
 def cir_workload(iters):
-    """Material learning from impulse responses (Sec. IV-B on a synthetic
+    """Material learning from impulse responses (Sec. III-B on a synthetic
     scene): box room, one label per surface (8 labels x (eps_r, sigma, S)),
     1 TX + 6 RX at seeded random positions (seed 5), 6000 rays, K = 2,
     LOS + specular + diffuse, CFR of 129 samples over 1.5 GHz at 8 GHz;

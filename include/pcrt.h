@@ -183,8 +183,10 @@ enum {
      * n_point_sets; a ray_subset lists set indices, others end at once), and
      * a (key, receiver) pair is a specular candidate only where dps_vis says
      * the receiver sees the reception point of the set the key's
-     * representative ray ends in. Needs point sets and dps_vis (EINVAL);
-     * PCRT_DIFFUSE is refused (EUNSUPPORTED), as are batches. */
+     * representative ray ends in. Needs point sets and dps_vis (EINVAL).
+     * With PCRT_DIFFUSE, diffuse paths are deduplicated per voxel, each an
+     * area rho^2 (Sec. II-B.4); PCRT_DIFFUSE together with PCRT_RECORD is
+     * refused (EUNSUPPORTED: no tape of those paths), as are batches. */
     PCRT_DPS_LAUNCH = 64
 };
 
@@ -238,6 +240,18 @@ enum {
     PCRT_CNT_TIE_SPILL = 8,    /* nearest-hit queries that needed the exact second pass */
     PCRT_CNT_COUNT = 16
 };
+
+/* Decode the status word of a solve (counters[PCRT_CNT_STATUS] of a host copy
+ * of the 16 counters, read back once the solve has finished). Returns PCRT_OK
+ * when no bit is set; otherwise the reason text (pcrt_last_error) names every
+ * set condition and the status is that of the first of:
+ *   bit 1  a material label >= n_labels was met (label 0 was used) -> EINVAL
+ *   bit 0  the key table overflowed: some specular (or voxel diffuse) keys
+ *          were dropped, so their paths are missing from every output -> EOVERFLOW
+ *   bit 2  a PCRT_RECORD solve found more keys than key_capacity: those
+ *          paths are in the gains but not on the tape (nor in gradients) -> EOVERFLOW
+ * counters_host_copy: host uint64[16]; NULL -> EINVAL. No device work. */
+pcrt_status pcrt_status_poll(const uint64_t *counters_host_copy);
 
 /* Workspace bytes for one solve with these parameters (plus, with
  * PCRT_RECORD, the tape). */
@@ -402,7 +416,7 @@ pcrt_status pcrt_tape_backward(const pcrt_scene *scene, const pcrt_solve_params 
                                const double *dL_dgain, void *stream);
 
 /* Channel frequency response of the recorded paths with the current coef
- * rows (the material-learning experiment of Sec. IV-B): per receiver r and
+ * rows (the material-learning experiment of Sec. III-B): per receiver r and
  * sample n, H_r(f_n) = sum over paths of a_p exp(-j 2 pi (f_n - f_c) L_p / c0),
  * a_p the path's TE / TM amplitudes at the solve's frequency f_c, L_p its
  * unfolded length, f_n = f_c + (n - (n_freq - 1) / 2) bandwidth_hz /

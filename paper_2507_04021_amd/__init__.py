@@ -135,6 +135,7 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_diffuse_vis_copy.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp]
         L.pcrt_raygen.argtypes = [u32, vp, u32, vp, vp]
         L.pcrt_stage_times.argtypes = [ctypes.POINTER(ctypes.c_double), u32]
+        L.pcrt_status_poll.argtypes = [vp]
         L.pcrt_batch_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), vp, u32, ctypes.POINTER(sz)]
         L.pcrt_solve_batch.argtypes = [vp, vp, u32, ctypes.POINTER(SolveParams), vp, u32, vp, sz,
                                        ctypes.POINTER(Outputs), vp]
@@ -332,6 +333,15 @@ class SolveResult:
     def counter(self, name):
         return int(self.counters[CNT[name]].item())
 
+    def check_status(self):
+        """Raise PcrtError if the solve's device status word has a bit set
+        (key table overflow, invalid material label, tape capacity exceeded).
+        Reads the counters back, so it waits for the solve."""
+        host = np.ascontiguousarray(self.counters.cpu().numpy().astype(np.uint64))
+        L = lib(self.scene._variant)
+        _check(L.pcrt_status_poll(host.ctypes.data_as(ctypes.c_void_p)), L)
+        self._status_ok = True
+
 
 def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_capacity=0, wave_rays=0,
                 lambda_d=0.0, dps_vis=None):
@@ -403,6 +413,7 @@ def paths(res: SolveResult, stream=None):
     """Specular path list of a RECORD solve as numpy arrays."""
     torch = _torch()
     L = lib(res.scene._variant)
+    res.check_status()
     p = res.params
     K, n_rx = p.max_interactions, p.n_rx
     nk = ctypes.c_uint32(0)
@@ -536,10 +547,15 @@ def autotune(sc, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, leaf_siz
     """Sweep BVH builder x leaf size x node width x rays per wavefront fetch
     with the library's tuner (one scene per builder, leaf size and width,
     built here); the winner is stored in a JSON cache keyed by the workload."""
+    import hashlib
     import json
     torch = _torch()
-    key = "n=%d rays=%d K=%d flags=%d rx=%d dev=%s" % (sc.n, n_rays, K, flags, np.asarray(rx).reshape(-1, 3).shape[0],
-                                                      torch.cuda.get_device_name(device))
+    # the cached choice is only valid for the same library build and candidate sets
+    with open(LIB_PATH, "rb") as f:
+        build_id = hashlib.sha1(f.read()).hexdigest()[:16]
+    key = "n=%d rays=%d K=%d flags=%d rx=%d dev=%s lib=%s cands=%s" % (
+        sc.n, n_rays, K, flags, np.asarray(rx).reshape(-1, 3).shape[0], torch.cuda.get_device_name(device), build_id,
+        repr((tuple(builders), tuple(leaf_sizes), tuple(widths), tuple(wave_rays), reps)))
     cache_path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "pcrt_tuning.json")
     try:
         cache = json.load(open(cache_path))
@@ -589,6 +605,8 @@ def tape(res: SolveResult):
     cos, coef [n_slots, 8], adj [n_slots, 8]) and sizes."""
     torch = _torch()
     L = lib(res.scene._variant)
+    if not getattr(res, "_status_ok", False):  # once per recording: a tape with dropped paths is refused
+        res.check_status()
     t = Tape()
     _check(L.pcrt_tape_get(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), ctypes.byref(t)), L)
     base = res.ws.data_ptr()

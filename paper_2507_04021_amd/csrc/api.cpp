@@ -77,6 +77,7 @@ struct Plan {
     uint32_t n_trace;
     Thr thr;
     FieldConst fc;
+    uint64_t slots_wanted;  // tape slots before the 32-bit check (RECORD only)
 };
 
 Thr make_thr(const pcrt_thresholds &t) {
@@ -197,8 +198,11 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
     if (p->flags & PCRT_RECORD) {
         uint32_t want = p->key_capacity ? p->key_capacity : 262144u;
         D.rec_keys = (p->flags & PCRT_SPECULAR) ? std::min(D.max_keys, want) : 0;
-        D.n_slots = D.T * K + D.rec_keys * D.n_rx * K;
-        D.n_slot_chunks = (D.n_slots + kSlotChunk - 1) / kSlotChunk;
+        // slot indices are 32-bit in the tape kernels: the count is formed in
+        // 64 bits and a plan beyond 2^32 - 1 slots is refused (plan_check)
+        P.slots_wanted = (uint64_t)D.T * K + (uint64_t)D.rec_keys * D.n_rx * K;
+        D.n_slots = (uint32_t)std::min<uint64_t>(P.slots_wanted, 0xffffffffull);
+        D.n_slot_chunks = (uint32_t)((P.slots_wanted + kSlotChunk - 1) / kSlotChunk);
     } else {
         D.rec_keys = D.n_slots = D.n_slot_chunks = 0;
     }
@@ -219,6 +223,16 @@ Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p, std::vector<Ite
 Plan make_plan(const pcrt_scene *sc, const pcrt_solve_params *p) {
     std::vector<Item> items = single_items(p);
     return make_plan(sc, p, items);
+}
+
+// Limits that depend on the whole plan (checked wherever a plan is used).
+pcrt_status plan_check(const Plan &P) {
+    if (P.slots_wanted > 0xffffffffull)
+        return fail(PCRT_EUNSUPPORTED,
+                    "the tape would need %llu interaction slots (at most 2^32 - 1): lower key_capacity, "
+                    "receivers or max_interactions",
+                    (unsigned long long)P.slots_wanted);
+    return PCRT_OK;
 }
 
 struct ItemBatch {
@@ -612,6 +626,8 @@ pcrt_status pcrt_solve_workspace_size(const pcrt_scene *scene, const pcrt_solve_
     if (st) return st;
     if (!bytes) return fail(PCRT_EINVAL, "bytes is NULL");
     Plan P = make_plan(scene, p);
+    st = plan_check(P);
+    if (st) return st;
     place_hash(P, p->flags);
     *bytes = P.L.total;
     return ok();
@@ -639,6 +655,8 @@ static pcrt_status solve_impl(const pcrt_scene *scene, const pcrt_material *mats
                               const pcrt_solve_params *p, std::vector<Item> &items, void *ws, size_t ws_bytes,
                               const pcrt_outputs *out, hipStream_t s) {
     Plan P = make_plan(scene, p, items);
+    pcrt_status st = plan_check(P);
+    if (st) return st;
     place_hash(P, p->flags);
     if (ws_bytes < P.L.total) return fail(PCRT_ENOMEM, "solve workspace too small: need %zu bytes", P.L.total);
     char *w = (char *)ws;
@@ -856,6 +874,8 @@ pcrt_status pcrt_paths_copy(const pcrt_scene *scene, const pcrt_solve_params *p,
         return fail(PCRT_EINVAL, "paths need a solve with RECORD and SPECULAR");
     if (!ws) return fail(PCRT_EINVAL, "ws is required");
     Plan P = make_plan(scene, p);
+    st = plan_check(P);
+    if (st) return st;
     place_hash(P, p->flags);
     hipStream_t s = (hipStream_t)stream;
     LaunchArgs A = make_args(scene, nullptr, 0, p, P, (char *)ws, nullptr);
@@ -875,6 +895,8 @@ pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_para
         return fail(PCRT_EINVAL, "visibility needs a solve with RECORD and DIFFUSE");
     if (!ws || !vis) return fail(PCRT_EINVAL, "ws and vis are required");
     Plan P = make_plan(scene, p);
+    st = plan_check(P);
+    if (st) return st;
     place_hash(P, p->flags);
     size_t bytes = (size_t)P.n_trace * P.D.K * P.D.n_rx;
     HIP_TRY(hipMemcpyAsync(vis, (const char *)ws + P.L.dvis, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -888,6 +910,8 @@ static pcrt_status tape_args(const pcrt_scene *scene, const pcrt_solve_params *p
     if (!(p->flags & PCRT_RECORD)) return fail(PCRT_EINVAL, "the tape needs a solve with PCRT_RECORD");
     if (!ws) return fail(PCRT_EINVAL, "ws is required");
     *P = make_plan(scene, p);
+    st = plan_check(*P);
+    if (st) return st;
     place_hash(*P, p->flags);
     *A = make_args(scene, nullptr, 0, p, *P, (char *)ws, nullptr);
     return PCRT_OK;
@@ -984,6 +1008,19 @@ pcrt_status pcrt_material_grad(const pcrt_scene *scene, const pcrt_solve_params 
     launch_material_grad(A, (const float *)mats, n_labels, dL_dmat, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return ok();
+}
+
+pcrt_status pcrt_status_poll(const uint64_t *counters_host_copy) {
+    if (!counters_host_copy) return fail(PCRT_EINVAL, "counters_host_copy is NULL");
+    const uint64_t w = counters_host_copy[PCRT_CNT_STATUS];
+    if (!w) return ok();
+    std::string why;
+    if (w & 2) why += "a material label >= n_labels was met (label 0 used); ";
+    if (w & 1) why += "the key table overflowed (keys dropped from the paths); ";
+    if (w & 4) why += "more keys than key_capacity (paths left off the tape and the gradients); ";
+    if (w & ~7ull) why += "unknown status bits; ";
+    why.resize(why.size() - 2);
+    return fail((w & 2) ? PCRT_EINVAL : PCRT_EOVERFLOW, "device status 0x%llx: %s", (unsigned long long)w, why.c_str());
 }
 
 pcrt_status pcrt_stage_times(double *ms, uint32_t n) {

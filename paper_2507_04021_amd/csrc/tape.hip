@@ -369,7 +369,7 @@ void launch_tape_backward(const LaunchArgs &A, const double *dldg, hipStream_t s
 // ------------------------------------------- channel frequency response
 // H_r(f_n) = sum over the recorded paths of a_p exp(-j 2 pi (f_n - f_c) tau_p)
 // with a_p the path's TE / TM amplitudes at the solve's frequency f_c,
-// tau_p = L_p / c0 and f_n = f_c + (n - (N - 1) / 2) bw / (N - 1) (Sec. IV-B:
+// tau_p = L_p / c0 and f_n = f_c + (n - (N - 1) / 2) bw / (N - 1) (Sec. III-B:
 // CFR samples over a bandwidth; the CIR is their inverse DFT). Paths per
 // receiver in a fixed order: line of sight, the valid specular paths by key,
 // the visible diffuse connections by record.

@@ -15,8 +15,11 @@ from . import (DIFFUSE, LOS, RECORD, SPECULAR, SolveResult, material_grad, mater
 
 
 def record(scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR | DIFFUSE, **kw) -> SolveResult:
-    """Trace once and keep the tape (a RECORD solve)."""
-    return solve(scene, mats, tx, rx, freq, n_rays, K=K, flags=flags | RECORD, **kw)
+    """Trace once and keep the tape (a RECORD solve). Raises PcrtError when
+    the solve's status word reports dropped keys or paths left off the tape."""
+    res = solve(scene, mats, tx, rx, freq, n_rays, K=K, flags=flags | RECORD, **kw)
+    res.check_status()
+    return res
 
 
 class MaterialGain(torch.autograd.Function):
@@ -36,6 +39,9 @@ class MaterialGain(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_g):
+        # the adjoint reads the tape's coefficient rows, which any later
+        # forward on the same recording overwrites: restore this forward's
+        tape_fresnel(ctx.rec, ctx.mats_dev)
         tape_backward(ctx.rec, grad_g.detach())
         gm = material_grad(ctx.rec, ctx.mats_dev)
         return gm.to(device=ctx.device, dtype=ctx.dtype).reshape(ctx.shape), None
@@ -66,7 +72,9 @@ class MaterialCfr(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_h):
-        # for a real loss torch hands over dL/dRe + j dL/dIm of each sample
+        # for a real loss torch hands over dL/dRe + j dL/dIm of each sample;
+        # the coefficient rows are restored first, as in MaterialGain.backward
+        tape_fresnel(ctx.rec, ctx.mats_dev)
         tape_cfr_backward(ctx.rec, ctx.bw, ctx.n, grad_h.detach())
         gm = material_grad(ctx.rec, ctx.mats_dev)
         return gm.to(device=ctx.device, dtype=ctx.dtype).reshape(ctx.shape), None, None, None

@@ -173,3 +173,24 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_status_poll_decodes_every_bit(L):
+    """pcrt_status_poll: host-only decoding of the device status word."""
+    EOVERFLOW = -5
+    c = (ctypes.c_uint64 * 16)()
+    assert L.pcrt_status_poll(c) == 0
+    assert L.pcrt_status_poll(None) == EINVAL
+    c[6] = 1
+    assert L.pcrt_status_poll(c) == EOVERFLOW and b"key table" in L.pcrt_last_error()
+    c[6] = 4
+    assert L.pcrt_status_poll(c) == EOVERFLOW and b"key_capacity" in L.pcrt_last_error()
+    c[6] = 2
+    assert L.pcrt_status_poll(c) == EINVAL and b"material label" in L.pcrt_last_error()
+    c[6] = 7  # every condition is named; the invalid label decides the code
+    assert L.pcrt_status_poll(c) == EINVAL
+    msg = L.pcrt_last_error()
+    assert b"key table" in msg and b"key_capacity" in msg and b"material label" in msg
+    c[6] = 0
+    c[0] = 123  # other counters are not status
+    assert L.pcrt_status_poll(c) == 0

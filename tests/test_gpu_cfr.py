@@ -1,6 +1,6 @@
 """Channel frequency response on the recorded tape (GPU) vs the FP64 oracle,
 and its material gradient vs finite differences (the material-learning
-experiment of Sec. IV-B on a synthetic scene).
+experiment of Sec. III-B on a synthetic scene).
 
 Workload: the box room with one material label per surface (8 labels), 1 TX,
 3 RX, 6000 rays, K = 2, line of sight + specular + diffuse, centre frequency
