@@ -167,6 +167,7 @@ class Solution:
     h_tm: np.ndarray
     jac: np.ndarray | None   # float64[n_rx, n_labels, 3]: dG/d(eps_r, sigma, S)
     cfr: np.ndarray | None = None  # complex128[n_rx, n_freq, 2]: channel frequency response (TE, TM)
+    dpow: np.ndarray | None = None  # float64[n_trace, K, n_rx]: lit connections' power, occluded or not
 
     def paths(self, r: int):
         """{key: (length, a_TE, a_TM)} of the valid specular paths at receiver r."""
@@ -178,7 +179,8 @@ class Solution:
 
 
 def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SPECULAR,
-          thr=None, want_dvis=False, want_jac=False, cfr=None, average=None, dps_launch=None) -> Solution:
+          thr=None, want_dvis=False, want_jac=False, cfr=None, average=None, dps_launch=None,
+          want_dpow=False) -> Solution:
     """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S).
 
     average = (rho, lambda_d): every interaction is the weighted average over
@@ -220,6 +222,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     seq = np.empty((nt, K), np.int64)
     rec = np.empty((nt, K, 5), np.float64)
     dvis = np.empty((nt, K, n_rx), np.uint8) if want_dvis else None
+    dpow = np.zeros((nt, K, n_rx), np.float64) if want_dpow else None
     cap = max(1, nt * K) if flags & SPECULAR else 1
     keys = np.empty((cap, K), np.uint32)
     klen = np.empty(cap, np.int32)
@@ -238,7 +241,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
         _radius(scene), ctypes.c_int32(n_labels), _p(eps_r), _p(sig), _p(sca),
         _p(tx), ctypes.c_int32(n_rx), _p(rx), ctypes.c_double(freq), ctypes.c_int64(n_budget),
         ctypes.c_int64(nt), _p(ids), ctypes.c_int32(K), ctypes.c_int32(flags), _p(thr_arr),
-        _p(seq), _p(rec), _p(dvis), ctypes.c_int64(cap), _p(keys), _p(klen), _p(krep), ctypes.byref(nk),
+        _p(seq), _p(rec), _p(dvis), _p(dpow), ctypes.c_int64(cap), _p(keys), _p(klen), _p(krep), ctypes.byref(nk),
         _p(sv), _p(sl), _p(sa), _p(sh), _p(orx), _p(jac), ctypes.c_int32(n_freq), ctypes.c_double(bw),
         _p(ocfr))
     if rc:
@@ -249,7 +252,7 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
     return Solution(seq, rec, dvis.astype(bool) if dvis is not None else None, key_list, krep[:n].copy(),
                     sv[:n].astype(bool), sl[:n].copy(), amp, sh[:n].copy(), orx[:, 0].copy(), orx[:, 1].copy(),
                     orx[:, 2].copy(), orx[:, 3].copy(), orx[:, 4] + 1j * orx[:, 5], orx[:, 6] + 1j * orx[:, 7],
-                    jac, (ocfr[..., 0::2] + 1j * ocfr[..., 1::2]) if cfr else None)
+                    jac, (ocfr[..., 0::2] + 1j * ocfr[..., 1::2]) if cfr else None, dpow)
 
 
 def trace(scene, tx, n_budget, ray_ids=None, K=2, thr=None, average=None):

@@ -728,6 +728,9 @@ static int key_cmp(const void *pa, const void *pb)
  *   seq      int64[n_trace*K]   hit disk per (ray, k), -1 after the ray ends
  *   rec      double[n_trace*K*5] x, y, z, L, cos per (ray, k)
  *   dvis     uint8[n_trace*K*n_rx] diffuse connection valid (lit side and unoccluded)
+ *   dpow     double[n_trace*K*n_rx] power 1/2(|a_TE|^2 + |a_TM|^2) of every connection on
+ *            the lit side, occluded or not (0 elsewhere): lets a comparison price the
+ *            connections on which two runs disagree about occlusion
  *   keys     uint32[key_cap*K], key_len int32[key_cap], key_rep int64[key_cap]
  *   spec_valid uint8[key_cap*n_rx], spec_len double[key_cap*n_rx],
  *   spec_amp double[key_cap*n_rx*4] (TE re, im, TM re, im), spec_hid int64[key_cap*n_rx*K]
@@ -741,7 +744,8 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
               double r_p, int32_t n_labels, const double *eps_r, const double *sigma, const double *scat,
               const float *tx32, int32_t n_rx, const float *rx32, double freq, int64_t n_budget,
               int64_t n_trace, const int64_t *ray_ids, int32_t K, int32_t flags, const double *thr,
-              int64_t *seq, double *rec, uint8_t *dvis, int64_t key_cap, uint32_t *keys, int32_t *key_len,
+              int64_t *seq, double *rec, uint8_t *dvis, double *dpow, int64_t key_cap, uint32_t *keys,
+              int32_t *key_len,
               int64_t *key_rep, int64_t *n_keys, uint8_t *spec_valid, double *spec_len, double *spec_amp,
               int64_t *spec_hid, double *out_rx, double *jac, int32_t n_freq, double bandwidth, double *out_cfr)
 {
@@ -892,6 +896,7 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     } else if (flags & ORC_DIFFUSE) {
         /* diffuse connections from every interaction to every RX (Sec. II-B.1) */
         int64_t nslot = n_trace * K * (int64_t)n_rx;
+        if (dpow) memset(dpow, 0, sizeof(double) * (size_t)nslot);
         double complex *ate = calloc((size_t)nslot, sizeof(double complex));
         double complex *atm = calloc((size_t)nslot, sizeof(double complex));
         double *pw = calloc((size_t)nslot, sizeof(double));
@@ -914,10 +919,17 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                     sub3(v, rx + 3 * r, tr[q].x[k]);
                     double vn = dot3(v, tr[q].nk[k]);
                     if (!(vn > 0.0)) continue;
-                    if (occluded(&s, tr[q].x[k], rx + 3 * r, tr[q].id[k], th.eps_self)) continue;
+                    const int occ = occluded(&s, tr[q].x[k], rx + 3 * r, tr[q].id[k], th.eps_self);
                     double rs = norm3(v);
                     double cos_s = vn / rs;
                     double amp0 = a_iso * sqrt(4.0 * cos_s / (double)n_budget) / rs;
+                    if (dpow) { /* the connection's power as if unoccluded */
+                        double complex a1 = 0, a2 = 0;
+                        double p1 = 0.0;
+                        path_field(&em, k + 1, label, cs, kind, amp0, tr[q].L[k] + rs, &a1, &a2, &p1, NULL);
+                        dpow[slot] = p1;
+                    }
+                    if (occ) continue;
                     vis[slot] = 1;
                     plen[slot] = tr[q].L[k] + rs;
                     path_field(&em, k + 1, label, cs, kind, amp0, tr[q].L[k] + rs, &ate[slot], &atm[slot],

@@ -333,13 +333,28 @@ class SolveResult:
     def counter(self, name):
         return int(self.counters[CNT[name]].item())
 
+    def fetch_status(self, stream=None):
+        """Start copying the counters to pinned host memory without waiting;
+        check_status() then waits only for this copy."""
+        torch = _torch()
+        self._status_host = torch.empty(16, dtype=torch.int64, pin_memory=True)
+        self._status_host.copy_(self.counters, non_blocking=True)
+        self._status_event = torch.cuda.Event()
+        self._status_event.record(stream if stream is not None else torch.cuda.current_stream())
+
     def check_status(self):
         """Raise PcrtError if the solve's device status word has a bit set
         (key table overflow, invalid material label, tape capacity exceeded).
-        Reads the counters back, so it waits for the solve."""
-        host = np.ascontiguousarray(self.counters.cpu().numpy().astype(np.uint64))
+        Waits for the solve (or for the copy fetch_status started)."""
+        if getattr(self, "_status_ok", False):
+            return
+        if getattr(self, "_status_event", None) is not None:
+            self._status_event.synchronize()
+            host = self._status_host.numpy().astype(np.uint64)
+        else:
+            host = np.ascontiguousarray(self.counters.cpu().numpy().astype(np.uint64))
         L = lib(self.scene._variant)
-        _check(L.pcrt_status_poll(host.ctypes.data_as(ctypes.c_void_p)), L)
+        _check(L.pcrt_status_poll(np.ascontiguousarray(host).ctypes.data_as(ctypes.c_void_p)), L)
         self._status_ok = True
 
 
@@ -605,8 +620,7 @@ def tape(res: SolveResult):
     cos, coef [n_slots, 8], adj [n_slots, 8]) and sizes."""
     torch = _torch()
     L = lib(res.scene._variant)
-    if not getattr(res, "_status_ok", False):  # once per recording: a tape with dropped paths is refused
-        res.check_status()
+    res.check_status()  # once per recording: a tape with dropped paths is refused
     t = Tape()
     _check(L.pcrt_tape_get(res.scene.handle, ctypes.byref(res.params), _ptr(res.ws), ctypes.byref(t)), L)
     base = res.ws.data_ptr()

@@ -15,10 +15,12 @@ from . import (DIFFUSE, LOS, RECORD, SPECULAR, SolveResult, material_grad, mater
 
 
 def record(scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR | DIFFUSE, **kw) -> SolveResult:
-    """Trace once and keep the tape (a RECORD solve). Raises PcrtError when
-    the solve's status word reports dropped keys or paths left off the tape."""
+    """Trace once and keep the tape (a RECORD solve). The solve's status word
+    is fetched without waiting; the first backward (or tape access) on this
+    recording raises PcrtError if it reports dropped keys or paths left off
+    the tape."""
     res = solve(scene, mats, tx, rx, freq, n_rays, K=K, flags=flags | RECORD, **kw)
-    res.check_status()
+    res.fetch_status()
     return res
 
 
@@ -41,6 +43,7 @@ class MaterialGain(torch.autograd.Function):
     def backward(ctx, grad_g):
         # the adjoint reads the tape's coefficient rows, which any later
         # forward on the same recording overwrites: restore this forward's
+        ctx.rec.check_status()
         tape_fresnel(ctx.rec, ctx.mats_dev)
         tape_backward(ctx.rec, grad_g.detach())
         gm = material_grad(ctx.rec, ctx.mats_dev)
@@ -74,6 +77,7 @@ class MaterialCfr(torch.autograd.Function):
     def backward(ctx, grad_h):
         # for a real loss torch hands over dL/dRe + j dL/dIm of each sample;
         # the coefficient rows are restored first, as in MaterialGain.backward
+        ctx.rec.check_status()
         tape_fresnel(ctx.rec, ctx.mats_dev)
         tape_cfr_backward(ctx.rec, ctx.bw, ctx.n, grad_h.detach())
         gm = material_grad(ctx.rec, ctx.mats_dev)

@@ -92,5 +92,11 @@ def test_autotune_sweep(env, tmp_path):
     assert {(r["leaf_size"], r["width"]) for r in rows} == {(1, 2), (1, 8), (4, 2), (4, 8)}
     assert choice["ms"] == min(r["ms"] for r in rows)
     again, rows2 = P.autotune(s, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 20000, K=2,
+                              leaf_sizes=(1, 4), widths=(2, 8), wave_rays=(64, 256), reps=2,
                               cache_path=str(tmp_path / "tune.json"))
-    assert rows2 is None and again == choice  # the stored choice is reused
+    assert rows2 is None and again == choice  # the stored choice is reused for the same candidates
+    # other candidates are another key: a fresh sweep over them
+    other, rows3 = P.autotune(s, scenes.box_room_materials(), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 20000, K=2,
+                              leaf_sizes=(2,), widths=(4,), wave_rays=(64,), reps=1,
+                              cache_path=str(tmp_path / "tune.json"))
+    assert rows3 is not None and len(rows3) == 1 and (other["leaf_size"], other["width"]) == (2, 4)

@@ -434,3 +434,46 @@ def test_office_node_width_bitwise(P, office):
         for a, b in zip((r.seq, r.gain, r.h_te, r.h_tm, r.parts), want):
             assert np.array_equal(a.cpu().numpy(), b)
         del g, r
+
+
+# ------------------- validation thresholds and kappa retries (Table I)
+@pytest.mark.parametrize("kind,v,at_x,thr", [("offset", 0.005, 1.3, {}), ("offset", 0.015, 1.3, {}),
+                                             ("offset", 0.015, 1.3, dict(kappa=0)),
+                                             ("offset", 0.015, 1.3, dict(t_d=0.02)), ("tilt", 0.5, 1.3, {}),
+                                             ("tilt", 1.5, 1.3, {}), ("tilt", 1.5, 1.3, dict(kappa=0)),
+                                             ("tilt", 1.5, 1.3, dict(t_a_deg=2.0)), ("tilt", 0.5, 2.5, {}),
+                                             ("tilt", 0.5, 2.5, dict(kappa=1))])
+def test_thresholds_and_retries_match_the_oracle(P, orc, kind, v, at_x, thr):
+    """The hand-built floors of the oracle's threshold pins (a representative
+    disk lifted or tilted, one launch ray that meets it): the GPU accepts,
+    retries on the hit disk's plane or rejects exactly as the oracle does,
+    with the same length (2e-6) and amplitude (1e-4 at 3.5 GHz). kappa = 0 is
+    PCRT_KAPPA_NONE in the C ABI (0 there means the default, 10)."""
+    sc = scenes.plane_patch(-1.0, 3.0, -1.0, 1.0, 0.05, 0.036)
+    tx, rx, N = np.array([0.0, 0.0, 1.0], np.float32), np.array([[2.0, 0.0, 1.0]], np.float32), 20000
+    i = int(np.argmin(np.linalg.norm(sc.pos[:, :2] - np.array([at_x, 0.0]), axis=1)))
+    dirs = orc.fib_dirs(N).astype(np.float64)
+    ids, _, q = orc.nearest(sc, np.tile(tx.astype(np.float64), (N, 1)), dirs)
+    js = np.nonzero(ids == i)[0]
+    j = int(js[np.argmin(np.linalg.norm(q[js] - sc.pos[i].astype(np.float64), axis=1))])
+    if kind == "offset":
+        sc.pos[i, 2] = v
+    else:
+        a = math.radians(v)
+        sc.normal[i] = [math.sin(a), 0.0, math.cos(a)]
+    mats = np.array([[5.0, 0.1, 0.0]])
+    ref = orc.solve(sc, mats, tx, rx, 3.5e9, N, ray_ids=[j], K=1, flags=SPEC, thr=thr)
+    gthr = dict(thr)
+    if gthr.get("kappa") == 0:
+        gthr["kappa"] = P.KAPPA_NONE
+    step("thresholds %s %.3f at %.1f thr=%s" % (kind, v, at_x, thr))
+    sg = P.Scene.from_scene(sc, leaf_size=2, width=4)
+    r = gpu_solve(P, sg, mats, tx, rx, 3.5e9, N, 1, SPEC | REC, ids=[j], thr=gthr)
+    assert int(r.seq.cpu().numpy()[0, 0]) == int(ref.seq[0, 0]) == i
+    gp, _ = gpu_paths_by_key(P, r, sc)
+    op = oracle_paths_by_key(ref, 1)
+    assert set(gp) == set(op)
+    for k, (L, te, tm) in op.items():
+        gl, gte, gtm = gp[k]
+        assert abs(gl - L) <= 2e-6 * L
+        assert abs(gte - te) <= 1e-4 * abs(te) and abs(gtm - tm) <= 1e-4 * abs(tm)

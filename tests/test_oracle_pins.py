@@ -343,6 +343,19 @@ def test_diffuse_ray_tube_matches_quadrature(orc, case):
     assert sol0.G_diff[0] == 0.0
 
 
+def test_connection_power_output_sums_to_the_diffuse_gain(orc, room_holefree):
+    """The per-connection power output prices every lit connection whether
+    or not it is occluded; over the visible ones it sums to G_diff, and it is
+    positive wherever a connection is visible."""
+    mats = scenes.box_room_materials(scatter=0.3)
+    rx = np.array([scenes.BOX_RX, [2.0, 3.0, 2.0]], np.float32)
+    sol = orc.solve(room_holefree, mats, scenes.BOX_TX, rx, 3.5e9, 500, K=3, flags=DIFF, want_dvis=True,
+                    want_dpow=True)
+    assert np.all(sol.dpow[sol.dvis] > 0)
+    assert np.allclose((sol.dpow * sol.dvis).sum(axis=(0, 1)), sol.G_diff, rtol=1e-12, atol=0)
+    assert np.all(sol.dpow[sol.seq < 0] == 0)
+
+
 def test_scattering_removes_specular(orc):
     floor = scenes.plane_patch(-1, 7, -1, 5, 0.1, 0.0708)
     sol = orc.solve(floor, np.array([[2.0, 0.01, 1.0]]), scenes.BOX_TX, [scenes.BOX_RX], 3.5e9, 2000, K=1,
@@ -702,30 +715,44 @@ def test_dps_launch_gates_specular_candidates(orc):
         assert ((0,) in sol.paths(0)) == expect
 
 
-def test_dps_diffuse_floor_closed_form(orc):
-    """Reception-point launch over a flat floor, one interaction: every set
-    gives one diffuse path at its reception point, with amplitude
-    lambda/(4 pi) sqrt(rho^2 cos_i cos_s / pi) / (L r_s) times S Gamma(cos_i);
-    the total power is summed here from those closed forms."""
-    rho, freq = 0.0625, 3.5e9
-    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, 0.05, 0.04)
-    tx, rx = np.array([1.0, 1.0, 1.0]), np.array([[1.5, 1.0, 1.0]], np.float32)
-    eps_r, sigma, S = 5.0, 0.1, 0.4
-    recv, vis = orc.visibility(floor, rho, rx)
-    assert vis.all()
-    sol = orc.solve(floor, np.array([[eps_r, sigma, S]]), tx, rx, freq, len(recv), K=1, flags=DIFF,
-                    dps_launch=rho)
-    c = recv.astype(np.float64)
-    L = np.linalg.norm(c - tx, axis=1)
-    rs = np.linalg.norm(c - rx[0].astype(np.float64), axis=1)
-    cos_i, cos_s = tx[2] / L, float(rx[0, 2]) / rs
-    gte, gtm, _, _ = orc.fresnel(eps_r, sigma, freq, cos_i)
+def test_voxel_diffuse_converges_to_the_lambertian_integral(orc):
+    """Reception-point launch over a flat, hole-free 2 x 2 m floor, one
+    interaction: each point set (voxel of edge rho) gives one diffuse path
+    standing for an area rho^2 (Sec. II-B.4), so the total diffuse power is a
+    midpoint-rule sum over the voxels. As rho halves it must converge, with
+    error falling as rho^2, to the integral over the floor of the Lambertian
+    scattered power (lambda/4 pi)^2 S^2 |Gamma|^2 cos_i cos_s / (pi r_i^2 r_s^2)
+    dA, evaluated here by adaptive quadrature with boundary-condition Fresnel
+    weights. A wrong area power, a dropped cosine or pi, or the wrong length
+    in the spreading changes the limit."""
+    h = 1.0 / 32  # grid spacing: every voxel edge below is a multiple, so each set's mean is its voxel centre
+    floor = scenes.plane_patch(0.0, 2.0, 0.0, 2.0, h, 0.72 * h)
+    tx, rx = np.array([1.0, 1.0, 1.0], np.float32), np.array([[1.5, 1.0, 1.0]], np.float32)
+    freq, eps_r, sigma, S = 3.5e9, 5.0, 0.1, 0.4
     lam = C0 / freq
-    rho32 = float(np.float32(rho))
-    amp0 = lam / (4 * np.pi) * np.sqrt(rho32 ** 2 * cos_i * cos_s / np.pi) / (L * rs)
-    G = np.sum(0.5 * amp0 ** 2 * S ** 2 * (np.abs(gte) ** 2 + np.abs(gtm) ** 2))
-    assert sol.G_diff[0] == pytest.approx(G, rel=1e-5)
-    assert sol.G_spec[0] == 0.0 and sol.G_los[0] == 0.0
+    t64, r64 = tx.astype(np.float64), rx[0].astype(np.float64)
+
+    def integrand(y, x):
+        vi, vs = np.array([x, y, 0.0]) - t64, r64 - np.array([x, y, 0.0])
+        ri, rs = np.linalg.norm(vi), np.linalg.norm(vs)
+        ci, cs = -vi[2] / ri, vs[2] / rs
+        te, tm = fresnel_bc(eps_r, sigma, freq, ci)
+        return ci * cs / (math.pi * ri * ri * rs * rs) * 0.5 * (abs(te) ** 2 + abs(tm) ** 2)
+    I, _ = integrate.dblquad(integrand, 0.0, 2.0, 0.0, 2.0, epsabs=1e-14, epsrel=1e-11)
+    g_ref = (lam / (4 * math.pi)) ** 2 * S ** 2 * I
+    G = []
+    for rho in (0.25, 0.125, 0.0625):
+        recv, vis = orc.visibility(floor, rho, rx)
+        assert vis.all() and len(recv) == round(2.0 / rho) ** 2
+        sol = orc.solve(floor, np.array([[eps_r, sigma, S]]), tx, rx, freq, len(recv), K=1, flags=DIFF,
+                        dps_launch=rho)
+        assert sol.G_spec[0] == 0.0 and sol.G_los[0] == 0.0
+        G.append(sol.G_diff[0])
+    err = np.array(G) / g_ref - 1
+    assert abs(err[0]) < 1e-2
+    assert 3.6 < err[0] / err[1] < 4.4 and 3.6 < err[1] / err[2] < 4.4  # second-order convergence
+    rich = (4 * G[2] - G[1]) / 3  # Richardson limit of the midpoint sums
+    assert abs(rich / g_ref - 1) < 1e-5
 
 
 # --------------------------------------- edge diffraction (Sec. II-B.3, UTD)
@@ -794,3 +821,139 @@ def test_half_plane_total_field_is_continuous_at_the_boundaries(r):
         J = lambda d: total(bnd - d) - total(bnd + d)  # noqa: E731
         J0 = 2 * J(1e-4) - J(2e-4)
         assert abs(J0) <= 1e-3 * go_jump
+
+
+# ------------------ validation thresholds t_a, t_d and kappa retries (Table I)
+VAL_TX = np.array([0.0, 0.0, 1.0], np.float32)
+VAL_RX = np.array([[2.0, 0.0, 1.0]], np.float32)
+VAL_N = 20000
+
+
+def _representative_ray(orc, sc, at_x):
+    i = int(np.argmin(np.linalg.norm(sc.pos[:, :2] - np.array([at_x, 0.0]), axis=1)))
+    dirs = orc.fib_dirs(VAL_N).astype(np.float64)
+    ids, _, q = orc.nearest(sc, np.tile(VAL_TX.astype(np.float64), (VAL_N, 1)), dirs)
+    js = np.nonzero(ids == i)[0]
+    assert js.size
+    return i, int(js[np.argmin(np.linalg.norm(q[js] - sc.pos[i].astype(np.float64), axis=1))])
+
+
+def _image_length(p, n, tx, rx):
+    """Reflection path length over the infinite plane (p, n): |rx - image(tx)|."""
+    n = n / np.linalg.norm(n)
+    img = tx - 2.0 * ((tx - p) @ n) * n
+    return float(np.linalg.norm(rx - img))
+
+
+@pytest.mark.parametrize("alter,thr,expect", [
+    # plane offsets: the validation hit lies dz from the refined plane (t_d = 0.01 m)
+    (("offset", 0.005, 1.3), {}, "own"),
+    (("offset", 0.015, 1.3), {}, "retry"),
+    (("offset", 0.015, 1.3), dict(kappa=0), "none"),
+    (("offset", 0.015, 1.3), dict(kappa=1), "retry"),
+    (("offset", 0.015, 1.3), dict(t_d=0.02), "own"),
+    # tilts about y (t_a = 1 degree): the hit's normal differs by the tilt
+    (("tilt", 0.5, 1.3), {}, "own"),
+    (("tilt", 1.5, 1.3), {}, "retry"),
+    (("tilt", 1.5, 1.3), dict(kappa=0), "none"),
+    (("tilt", 1.5, 1.3), dict(t_a_deg=2.0), "own"),
+    # a 0.5 degree tilt 1.5 m away: the angle passes, the plane distance (13 mm) does not
+    (("tilt", 0.5, 2.5), {}, "retry"),
+    (("tilt", 0.5, 2.5), dict(kappa=0), "none"),
+])
+def test_validation_thresholds_and_retries(orc, alter, thr, expect):
+    """Table I thresholds on a hand-built floor. The refinement plane is the
+    representative ray's disk, altered here (lifted by dz or tilted); the
+    validation ray then meets a flat floor disk. Accepted ("own"): the path
+    length is the image-method length over the altered disk's plane.
+    Rejected with retries left ("retry"): that plane is replaced by the hit
+    disk's (the flat floor) and the path is the flat image path, 2 sqrt 2 m.
+    Rejected with kappa = 0 ("none"): no path. A retry rule that re-solves on
+    the same plane, an off-by-one in the retry count, t_a read in radians or
+    the distance taken from the hit's own plane each fail a case."""
+    kind, v, at_x = alter
+    sc = scenes.plane_patch(-1.0, 3.0, -1.0, 1.0, 0.05, 0.036)
+    i, j = _representative_ray(orc, sc, at_x)
+    if kind == "offset":
+        sc.pos[i, 2] = v
+    else:
+        a = math.radians(v)
+        sc.normal[i] = [math.sin(a), 0.0, math.cos(a)]
+    mats = np.array([[5.0, 0.1, 0.0]])
+    f = 3.5e9
+    sol = orc.solve(sc, mats, VAL_TX, VAL_RX, f, VAL_N, ray_ids=[j], K=1, flags=SPEC, thr=thr)
+    assert sol.seq[0, 0] == i and sol.keys == [(0,)]
+    paths = sol.paths(0)
+    tx, rx = VAL_TX.astype(np.float64), VAL_RX[0].astype(np.float64)
+    if expect == "none":
+        assert paths == {}
+        return
+    if expect == "own":
+        L_ref = _image_length(sc.pos[i].astype(np.float64), sc.normal[i].astype(np.float64), tx, rx)
+        assert abs(L_ref - 2 * math.sqrt(2)) > 1e-3  # distinguishable from the flat path
+    else:
+        L_ref = 2 * math.sqrt(2)
+    L, ate, atm = paths[(0,)]
+    assert abs(L - L_ref) < 1e-9
+    # amplitude: boundary-condition Fresnel at the refined plane's incidence cosine
+    n = np.array([0.0, 0.0, 1.0]) if expect == "retry" else sc.normal[i].astype(np.float64)
+    n /= np.linalg.norm(n)
+    p = np.array([0.0, 0.0, 0.0]) if expect == "retry" else sc.pos[i].astype(np.float64)
+    img = tx - 2.0 * ((tx - p) @ n) * n
+    u = (rx - img) / np.linalg.norm(rx - img)
+    te, tm = fresnel_bc(5.0, 0.1, f, abs(u @ n))
+    lam = C0 / f
+    base = lam / (4 * math.pi) / L_ref * np.exp(-1j * 2 * math.pi / lam * L_ref)
+    assert abs(ate - base * te) < 1e-9 * abs(base) and abs(atm - base * tm) < 1e-9 * abs(base)
+
+
+# --------- diffraction assembly: continuity with the oracle's own GO paths
+def _side_limit(x, y, deg=3):
+    """Value at 0 of a cubic least-squares fit of complex samples y(x)."""
+    return np.polyval(np.polyfit(x, y.real, deg), 0.0) + 1j * np.polyval(np.polyfit(x, y.imag, deg), 0.0)
+
+
+@pytest.mark.parametrize("mat", ["pec", "concrete"])
+@pytest.mark.parametrize("phip_deg,boundary", [(50, "shadow"), (50, "refl0"), (310, "refln"), (310, "shadow"),
+                                               (35, "refl0"), (325, "refln")])
+def test_diffraction_assembly_continuous_with_the_oracle_paths(orc, mat, phip_deg, boundary):
+    """A half-plane of disks (z = 0, x < 0, edge along y) and receivers on a
+    1.5 m circle around the edge point, across the incident shadow boundary
+    and the reflection boundaries of the top (face 0) and bottom (face n)
+    faces. The oracle's own line-of-sight and specular paths (pinned above)
+    switch on or off at the boundary; with diffraction() added the field is
+    continuous there. The one-sided limits come from cubic fits over samples
+    0.02-0.08 rad from the boundary (outside the disks' jagged rim), and their
+    difference must be below 0.5 % of the switching path's own jump. The
+    field model (lambda/4 pi, the spherical spreading factor, the TE-soft /
+    TM-hard mapping, face n's coefficient at n pi - phi) all enter the
+    cancellation. The edge is a wedge of interior angle 2e-4 rad (normals
+    cannot state a zero-thickness plate's side)."""
+    from oracle import diffraction as dif
+    plate = scenes.plane_patch(-3.0, 0.0, -2.0, 2.0, 0.02, 0.0144)
+    mats = np.array([[1.0, 1e7, 0.0]]) if mat == "pec" else np.array([[5.0, 0.1, 0.0]])
+    f, sp, s = 3.5e9, 1.5, 1.5
+    dl = 1e-4
+    edges = (np.array([[0.0, -1.9, 0.0, 0.0, 1.9, 0.0, math.sin(dl), 0.0, math.cos(dl), math.sin(dl), 0.0,
+                        -math.cos(dl)]]), np.array([[0, 0]]))
+    phip = math.radians(phip_deg)
+    dirv = lambda ph: np.array([-math.cos(ph), 0.0, math.sin(ph)])  # noqa: E731  (angle from face 0)
+    tx = (sp * dirv(phip)).astype(np.float32)
+    bnd = dict(shadow=(math.pi + phip) % (2 * math.pi), refl0=math.pi - phip, refln=3 * math.pi - phip)[boundary]
+    d = np.array([0.02, 0.03, 0.04, 0.05, 0.06, 0.07, 0.08])
+    rx = np.array([s * dirv(p) for p in np.concatenate([bnd - d[::-1], bnd + d])], np.float32)
+    los = orc.solve(plate, mats, tx, rx, f, 4000, K=1, flags=LOS)
+    spec = orc.solve(plate, mats, tx, rx, f, 4000, K=1, flags=SPEC)
+    _, hte, htm, _ = dif.diffraction(plate, edges, mats, tx, rx, f)
+    m = len(d)
+    lit_first = boundary != "refln" if boundary != "shadow" else phip_deg < 180
+    switching = los if boundary == "shadow" else spec
+    g_sw = switching.G_los if boundary == "shadow" else switching.G_spec
+    assert np.all((g_sw[:m] > 0) == lit_first) and np.all((g_sw[m:] > 0) != lit_first)
+    other_g = spec.G_spec if boundary == "shadow" else los.G_los
+    assert np.all(other_g > 0) or np.all(other_g == 0)  # the other path type does not switch here
+    for go, hd in ((switching.h_te, hte), (switching.h_tm, htm)):
+        jump = _side_limit(-d[::-1], go[:m] + hd[:m]) - _side_limit(d, go[m:] + hd[m:])
+        go_jump = _side_limit(-d[::-1], go[:m]) - _side_limit(d, go[m:])
+        assert abs(go_jump) > 1e-4
+        assert abs(jump) <= 5e-3 * abs(go_jump), (abs(jump), abs(go_jump))
