@@ -371,6 +371,25 @@ pcrt_status pcrt_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, ui
                              uint32_t n_rx, double freq_hz, float eps_self, void *ws, size_t ws_bytes, double *out,
                              float *pair_amp, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as pcrt_diffraction, with its workspace taken from
+ * a fixed 16 MiB scratch array that the library holds on every device it runs
+ * on until the process ends (the stack spill and, when pair_amp is NULL, the
+ * per-pair amplitudes). Allocates nothing, including on its first call on a
+ * device, where it looks up that device's scratch address. The caller still
+ * passes edges, materials, receivers, out and (optionally) pair_amp. All calls
+ * on one device share its scratch, so calls that overlap on one device (on
+ * different streams, or from different threads without ordering) race; calls
+ * ordered on one stream do not. Nothing in the scratch needs to start at zero.
+ * Errors: as pcrt_diffraction; EUNSUPPORTED when the scratch needed
+ * (diffraction workspace size, minus the amplitudes when pair_amp is given)
+ * exceeds 16 MiB; EDEVICE if the scratch address cannot be found. */
+pcrt_status pcrt_diffraction_noalloc(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                                     const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                                     uint32_t n_rx, double freq_hz, float eps_self, double *out, float *pair_amp,
+                                     void *stream);
+
 /* ------------------------------------------------------ differentiation */
 /* The tape of a PCRT_RECORD solve lives in its workspace. It holds the path
  * geometry, which does not depend on the materials, as interaction slots:

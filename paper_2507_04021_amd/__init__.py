@@ -126,6 +126,9 @@ def lib(variant=None) -> ctypes.CDLL:
         L.pcrt_diffraction_workspace_size.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(sz)]
         L.pcrt_diffraction.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
                                        vp, ctypes.c_uint32, ctypes.c_double, ctypes.c_float, vp, sz, vp, vp, vp]
+        L.pcrt_diffraction_noalloc.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_float), vp, ctypes.c_uint32, ctypes.c_double,
+                                               ctypes.c_float, vp, vp, vp]
         L.pcrt_visibility_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
         L.pcrt_visibility.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_float, vp, sz, vp, vp]
         L.pcrt_solve_workspace_size.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -577,28 +578,97 @@ pcrt_status pcrt_diffraction_workspace_size(const pcrt_scene *scene, uint32_t n_
     return ok();
 }
 
-pcrt_status pcrt_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
-                             const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
-                             uint32_t n_rx, double freq_hz, float eps_self, void *ws, size_t ws_bytes, double *out,
-                             float *pair_amp, void *stream) {
-    if (!scene || !edges || !mats || !tx || !rx || !ws || !out)
+}  // extern "C"
+
+static pcrt_status check_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                                     const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                                     uint32_t n_rx, double freq_hz, float eps_self, const double *out) {
+    if (!scene || !edges || !mats || !tx || !rx || !out)
         return fail(PCRT_EINVAL, "scene, edges, mats, tx, rx, ws and out are required");
     if (n_edges == 0 || n_rx == 0 || n_labels == 0) return fail(PCRT_EINVAL, "n_edges, n_rx and n_labels must be > 0");
     if ((uint64_t)n_edges * n_rx > (1ull << 30)) return fail(PCRT_EUNSUPPORTED, "at most 2^30 (edge, receiver) pairs");
     if (!(freq_hz > 0) || !std::isfinite(freq_hz)) return fail(PCRT_EINVAL, "freq_hz must be > 0");
     if (!(eps_self >= 0.f) || !std::isfinite(eps_self)) return fail(PCRT_EINVAL, "eps_self must be >= 0");
     if (!std::isfinite(tx[0]) || !std::isfinite(tx[1]) || !std::isfinite(tx[2])) return fail(PCRT_EINVAL, "tx must be finite");
-    size_t spill;
-    const size_t need = diffraction_ws(scene, n_edges, n_rx, &spill);
-    if (ws_bytes < need) return fail(PCRT_ENOMEM, "diffraction workspace too small: need %zu bytes", need);
+    return PCRT_OK;
+}
+
+// ws holds the traversal stack spill, then (unless the caller takes the
+// per-pair amplitudes in pair_amp) the amplitudes; spill bytes come first.
+static pcrt_status diffraction_impl(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                                    const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                                    uint32_t n_rx, double freq_hz, float eps_self, char *ws, size_t spill,
+                                    double *out, float *pair_amp, hipStream_t stream) {
     DevScene S = scene->dev;
     S.spill = (int *)ws;
     S.spill_lanes = diffraction_blocks(n_edges, n_rx) * kWave;
-    float4 *amp = pair_amp ? (float4 *)pair_amp : (float4 *)((char *)ws + spill);
+    float4 *amp = pair_amp ? (float4 *)pair_amp : (float4 *)(ws + spill);
     launch_diffraction(S, edges, n_edges, (const float *)mats, n_labels, tx, rx, n_rx, freq_hz,
-                       eps_self > 0.f ? eps_self : 1e-3f, amp, out, (hipStream_t)stream);
+                       eps_self > 0.f ? eps_self : 1e-3f, amp, out, stream);
     HIP_TRY(hipGetLastError());
     return ok();
+}
+
+// Scratch of pcrt_diffraction_noalloc: one array per device, in the code
+// object, so that call allocates nothing. Host code never uses the array's
+// name as an address: the device address is looked up once per device.
+static constexpr size_t kNoallocScratch = 16u << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratch];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static pcrt_status scratch_ptr(char **p) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PCRT_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PCRT_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *p = (char *)g_scratch_ptr[dev];
+    return PCRT_OK;
+}
+
+extern "C" {
+
+pcrt_status pcrt_diffraction(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                             const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                             uint32_t n_rx, double freq_hz, float eps_self, void *ws, size_t ws_bytes, double *out,
+                             float *pair_amp, void *stream) {
+    pcrt_status st = check_diffraction(scene, edges, n_edges, mats, n_labels, tx, rx, n_rx, freq_hz, eps_self, out);
+    if (st) return st;
+    if (!ws) return fail(PCRT_EINVAL, "scene, edges, mats, tx, rx, ws and out are required");
+    size_t spill;
+    const size_t need = diffraction_ws(scene, n_edges, n_rx, &spill);
+    if (ws_bytes < need) return fail(PCRT_ENOMEM, "diffraction workspace too small: need %zu bytes", need);
+    return diffraction_impl(scene, edges, n_edges, mats, n_labels, tx, rx, n_rx, freq_hz, eps_self, (char *)ws, spill,
+                            out, pair_amp, (hipStream_t)stream);
+}
+
+pcrt_status pcrt_diffraction_noalloc(const pcrt_scene *scene, const pcrt_edge *edges, uint32_t n_edges,
+                                     const pcrt_material *mats, uint32_t n_labels, const float tx[3], const float *rx,
+                                     uint32_t n_rx, double freq_hz, float eps_self, double *out, float *pair_amp,
+                                     void *stream) {
+    pcrt_status st = check_diffraction(scene, edges, n_edges, mats, n_labels, tx, rx, n_rx, freq_hz, eps_self, out);
+    if (st) return st;
+    size_t spill;
+    const size_t full = diffraction_ws(scene, n_edges, n_rx, &spill);
+    const size_t need = pair_amp ? spill : full;
+    if (need > kNoallocScratch)
+        return fail(PCRT_EUNSUPPORTED,
+                    "pcrt_diffraction_noalloc: %zu scratch bytes needed, its fixed scratch holds %zu; "
+                    "use pcrt_diffraction with a workspace",
+                    need, kNoallocScratch);
+    char *ptr = nullptr;
+    st = scratch_ptr(&ptr);
+    if (st) return st;
+    return diffraction_impl(scene, edges, n_edges, mats, n_labels, tx, rx, n_rx, freq_hz, eps_self, ptr, spill, out,
+                            pair_amp, (hipStream_t)stream);
 }
 
 pcrt_status pcrt_reception_points(const pcrt_scene *scene, float *out, void *stream) {
