@@ -93,3 +93,34 @@ def cir_loss(h: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
     the frequency samples: the inverse DFT is unitary up to one scale, which
     cancels in the ratio (Parseval), so both polarisations' CFRs give it."""
     return torch.sum(torch.abs(h - target) ** 2) / torch.sum(torch.abs(target) ** 2)
+
+
+def fit_per_label(sets, init, iters=300, batch=8, lr=0.05, seed=0):
+    """Per-label Fresnel materials fitted through the recorded tapes: Adam on
+    the dB MSE over channel sets [(rec, freq, target_db)], the gradient from
+    the adjoint kernels. Parameters are kept in range by eps_r = 1 +
+    softplus(u), sigma = exp(v), S = sigmoid(w). Returns float64 [n_labels, 3]
+    and the loss history."""
+    import numpy as np
+    init = torch.as_tensor(init, dtype=torch.float64)
+    u0 = torch.log(torch.expm1(torch.clamp(init[:, 0] - 1.0, min=1e-3)))
+    v0 = torch.log(torch.clamp(init[:, 1], min=1e-9))
+    s0 = torch.clamp(init[:, 2], 1e-4, 1 - 1e-4)
+    w0 = torch.log(s0 / (1 - s0))
+    raw = torch.stack([u0, v0, w0], 1).to("cuda").requires_grad_(True)
+    opt = torch.optim.Adam([raw], lr=lr)
+    rng = np.random.default_rng(seed)
+
+    def mats_of(r):
+        return torch.stack([1.0 + torch.nn.functional.softplus(r[:, 0]), torch.exp(r[:, 1]),
+                            torch.sigmoid(r[:, 2])], 1)
+    hist = []
+    for _ in range(iters):
+        idx = rng.choice(len(sets), size=min(batch, len(sets)), replace=False)
+        opt.zero_grad()
+        m = mats_of(raw)
+        loss = sum(db_mse_loss(gains(m, sets[i][0]), sets[i][2]) for i in idx) / len(idx)
+        loss.backward()
+        opt.step()
+        hist.append(loss.detach())
+    return mats_of(raw).detach().cpu().numpy(), [float(h) for h in hist]

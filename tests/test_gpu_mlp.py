@@ -128,7 +128,16 @@ def test_mlp_training_through_the_tracer_beats_nominal_materials(env):
     hist = M.train(net, train, iters=250, batch=8, lr=5e-3)
     e_mlp = float(torch.cat([M.db_error(net.gains(rec, f), tgt) for rec, f, tgt in held]).mean())
     e_nom = err_nominal(held)
-    print("[gpu-test] held-out mean |dG| dB: nominal %.3f, trained network %.3f (loss %.3f -> %.3f)"
-          % (e_nom, e_mlp, hist[0], hist[-1]), flush=True)
+    # third comparator: the per-label Fresnel model fitted through the same tapes (gradient kernels)
+    print("[gpu-test] fitting per-label materials", flush=True)
+    fitted, fhist = diff.fit_per_label(train, nominal, iters=200, batch=8, lr=0.05)
+    e_fit = []
+    for rec, f, tgt in held:
+        P.tape_fresnel(rec, fitted)
+        e_fit.append(M.db_error(P.tape_forward(rec)[0], tgt))
+    e_fit = float(torch.cat(e_fit).mean())
+    print("[gpu-test] held-out mean |dG| dB: nominal %.3f, fitted per-label %.3f, trained network %.3f "
+          "(loss %.3f -> %.3f)" % (e_nom, e_fit, e_mlp, hist[0], hist[-1]), flush=True)
     assert hist[-1] < 0.2 * hist[0]
     assert e_mlp < 0.5 * e_nom
+    assert e_fit < 0.5 * e_nom and fhist[-1] < 0.2 * fhist[0]
