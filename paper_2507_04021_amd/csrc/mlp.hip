@@ -12,11 +12,24 @@
 //   A[i][k]: lane l holds i = l % 16, k = 8 (l / 16) + j, j = 0..7
 //   B[k][n]: lane l holds n = l % 16, k = 8 (l / 16) + j
 //   C[i][n]: lane l holds n = l % 16, i = 4 (l / 16) + r, r = 0..3
-// The forward pass runs all four layers per 16-row tile in one kernel with the
-// weights in LDS; activations change layout (C -> A) through a per-wave LDS
-// tile. The backward pass recomputes the forward per tile, back-propagates to
-// the pre-activation gradients (also MFMA), and a GEMM over fixed row blocks
-// forms the weight gradients, reduced in a fixed order.
+//
+// Forward: every layer is computed transposed, Y^T = W X^T, with the weights
+// as the A operand (held in registers for the wavefront's whole life) and
+// 16 rows as the B operand. The result leaves lane (n, g = l / 16) holding
+// row n's outputs 16 t + 4 g + r (t = 0..3 output tiles, r = 0..3). A
+// contraction does not care in which order its K index runs, so the next
+// layer takes its K index in exactly that order: K step ks, element j is
+// input 16 (2 ks + j / 4) + 4 g + j % 4, which lane (n, g) already holds. The
+// weights are loaded in the same permuted order, and the activations never
+// leave the registers between layers.
+// Backward: the forward recompute and the gradient chain dH = W^T dZ run the
+// same way; the weight gradients dW = dZ^T H contract over rows, so their
+// operands are transposed through LDS, and each wavefront accumulates its
+// share of every weight gradient in registers, written once as a partial
+// that a fixed-order reduction adds up.
+//
+// GELU uses erf by Abramowitz & Stegun 7.1.26 (absolute error below 1.5e-7
+// in erf): far below the BF16 rounding of the activations (2^-8 relative).
 #include <cstring>
 
 #include "common.h"
@@ -33,8 +46,6 @@ constexpr int kW1 = kHid * kIn, kW2 = kHid * kHid, kW3 = kHid * kHid, kW4 = kOut
 constexpr int kWAll = kW1 + kW2 + kW3 + kW4;       // 11264 bf16
 constexpr int kBAll = kHid * 3 + kOut;             // 208 floats
 constexpr int kTileRows = 16;
-constexpr int kHPad = kHid + 8;                    // LDS row pitch (bf16) of activation tiles
-constexpr int kGradRows = 1024;                    // rows per weight-gradient block
 
 __device__ __forceinline__ float bf(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
 __device__ __forceinline__ uint16_t to_bf(float f) {  // round to nearest even
@@ -47,10 +58,40 @@ __device__ __forceinline__ __bf16 as_b(uint16_t u) { return __builtin_bit_cast(_
 
 // Lanes of one wavefront hand tiles to each other through LDS: order the
 // writes before the following reads (wave-scope fence + scheduling barrier).
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2. With x = |z| / sqrt 2,
+// erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x)
+// (Abramowitz & Stegun 7.1.26), so h = (1 - erf(x)) / 2 = Phi(-|z|) and
+// GELU(z) = max(z, 0) - |z| h. Returns h; e receives exp(-z^2 / 2).
+__device__ __forceinline__ float norm_tail(float z, float &e) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
+    const float poly =  // the coefficients halved
+        fmaf(fmaf(fmaf(fmaf(0.5307027145f, t, -0.7265760135f), t, 0.7107068705f), t, -0.142248368f), t, 0.127414796f) *
+        t;
+    e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);  // 2^(-z^2 log2(e) / 2)
+    return poly * e;
 }
+__device__ __forceinline__ float gelu(float z) {
+    float e;
+    const float h = norm_tail(z, e);
+    return fmaf(-fabsf(z), h, fmaxf(z, 0.f));
+}
+// GELU'(z) = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi).
+__device__ __forceinline__ float gelu_grad(float z) {
+    float e;
+    const float h = norm_tail(z, e);
+    return fmaf(z * 0.39894228040143268f, e, z >= 0.f ? 1.0f - h : h);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two floats to two bf16 (round to nearest even), low half first.
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+    const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ bf16x8 bf8_of(u32x4 p) { return __builtin_bit_cast(bf16x8, p); }
 
 // (u + j v) tanh(r)/r and its Jacobian (a = d re/du, b = d re/dv = d im/du, d = d im/dv).
 __device__ __forceinline__ void radial(float u, float v, float &re, float &im, float &a, float &b, float &d) {
@@ -82,404 +123,464 @@ struct MlpArgs {
     float logf;
     float *out;          // [n][8]
     const float *gout;   // [n][8]
-    uint16_t *x0, *h1, *h2, *h3;       // saved bf16 activations [n][32], [n][64] x3
-    uint16_t *dz1, *dz2, *dz3, *dz4;   // bf16 pre-activation gradients [n][64] x3, [n][16]
-    float *dx0;                        // [n][16] input (embedding) gradients
-    float *part;                       // weight-gradient partials
-    uint32_t n_blocks;
+    float *part;         // per-wavefront gradient partials [kBwdWaves][part_stride]
+    uint32_t part_stride;
 };
 
-// LDS copy of the weights, forward (row = output) and, for the backward
-// chain, transposed (row = input).
-struct WLds {
-    uint16_t w1[kHid][kIn], w2[kHid][kHid], w3[kHid][kHid], w4[kOut][kHid];
-    float b[kBAll];
-};
-struct WtLds {
-    uint16_t w1t[kIn][kHid], w2t[kHid][kHid], w3t[kHid][kHid], w4t[kHid][kOut + 16];  // w4t padded to K = 32
+// Per-lane MFMA A fragments of the weights in the transposed formulation
+// (lane (i, g): output 16 t + i, K elements j = 0..7 of K step ks), and the
+// biases of the outputs the lane holds (16 t + 4 g + r at index 4 t + r).
+struct RegNet {
+    bf16x8 w1[4], w2[4][2], w3[4][2], w4[2];
+    f32x4 b1[4], b2[4], b3[4], b4;  // the MFMA accumulators start from these
 };
 
-__device__ void load_weights(const MlpArgs &M, WLds &W) {
-    const uint16_t *src = M.w;
-    uint16_t *dst = &W.w1[0][0];
-    for (int i = threadIdx.x; i < kWAll; i += blockDim.x) dst[i] = src[i];  // the four arrays are contiguous
-    for (int i = threadIdx.x; i < kBAll; i += blockDim.x) W.b[i] = M.b[i];
-}
+// Input index of K step ks, element j, lane group g, for the hidden layers
+// (the order in which the previous layer's outputs sit in the registers).
+__device__ __forceinline__ int perm_k(int ks, int g, int j) { return 16 * (2 * ks + (j >> 2)) + 4 * g + (j & 3); }
 
-__device__ void load_weights_t(const WLds &W, WtLds &T) {
-    for (int i = threadIdx.x; i < kIn * kHid; i += blockDim.x) T.w1t[i % kIn][i / kIn] = W.w1[i / kIn][i % kIn];
-    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) {
-        T.w2t[i % kHid][i / kHid] = W.w2[i / kHid][i % kHid];
-        T.w3t[i % kHid][i / kHid] = W.w3[i / kHid][i % kHid];
-    }
-    for (int i = threadIdx.x; i < kHid * (kOut + 16); i += blockDim.x) {
-        int in = i / (kOut + 16), o = i % (kOut + 16);
-        T.w4t[in][o] = o < kOut ? W.w4[o][in] : (uint16_t)0;
-    }
-}
-
-__device__ __forceinline__ bf16x8 frag16(const uint16_t *p) {  // 8 consecutive bf16 from LDS
-    bf16x8 v;
+__device__ __forceinline__ bf16x8 wfrag(const uint16_t *W, int ld, int row, int ks, int g, bool natural) {
+    u32x4 p;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = as_b(p[j]);
-    return v;
+    for (int q = 0; q < 4; ++q) {
+        const int j = 2 * q;
+        const int k0 = natural ? 8 * g + j : perm_k(ks, g, j), k1 = natural ? 8 * g + j + 1 : perm_k(ks, g, j + 1);
+        p[q] = (uint32_t)W[row * ld + k0] | ((uint32_t)W[row * ld + k1] << 16);
+    }
+    return bf8_of(p);
 }
 
-// Input features of this lane's A fragment (row = tile row l % 16, columns
-// 8 kb .. 8 kb + 7) as bf16 bits.
-__device__ __forceinline__ void input_bits(const MlpArgs &M, uint32_t row, int kb, uint16_t *xb) {
-    uint16_t lab = row < M.n ? M.label[row] : (uint16_t)0xffff;
-    const bool live = lab != 0xffff && lab < M.n_labels;
+__device__ __forceinline__ void load_regnet(const MlpArgs &M, int lane, RegNet &R) {
+    const int i = lane & 15, g = lane >> 4;
+    const uint16_t *w1 = M.w, *w2 = w1 + kW1, *w3 = w2 + kW2, *w4 = w3 + kW3;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        int k = 8 * kb + j;
-        float x = 0.f;
-        if (live) {
-            if (k < kEmb) x = M.emb[(size_t)lab * kEmb + k];
-            else if (k == kEmb) x = M.cosv[row];
-            else if (k == kEmb + 1) x = M.logf;
+    for (int t = 0; t < 4; ++t) {
+        R.w1[t] = wfrag(w1, kIn, 16 * t + i, 0, g, true);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            R.w2[t][ks] = wfrag(w2, kHid, 16 * t + i, ks, g, false);
+            R.w3[t][ks] = wfrag(w3, kHid, 16 * t + i, ks, g, false);
         }
-        xb[j] = to_bf(x);
-    }
-}
-
-__device__ __forceinline__ bf16x8 bits_frag(const uint16_t *xb) {
-    bf16x8 v;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = as_b(xb[j]);
-    return v;
-}
-
-// One hidden layer: acc[n] (C layout, 64 outputs) from an activation tile in
-// LDS (row pitch kHPad) or, for layer 1, from the input fragment.
-template <int KSTEPS>
-__device__ __forceinline__ void layer_mfma(const uint16_t *Hrow /* this lane's A row in LDS */, const bf16x8 *a_in,
-                                          const uint16_t (*Wrows)[KSTEPS * 32], int lane, f32x4 *acc) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-        bf16x8 a = a_in ? a_in[ks] : frag16(Hrow + ks * 32 + 8 * (lane >> 4));
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            bf16x8 bv = frag16(&Wrows[nt * 16 + (lane & 15)][ks * 32 + 8 * (lane >> 4)]);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[nt], 0, 0, 0);
-        }
-    }
-}
-
-// acc (C layout) + bias -> GELU -> bf16 tile in LDS (and optionally the
-// pre-activation values kept in LDS for the backward pass).
-__device__ __forceinline__ void store_act(const f32x4 *acc, const float *bias, uint16_t (*H)[kHPad], float (*Z)[kHid],
-                                          int lane) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int row = 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-            float z = acc[nt][r] + bias[col];
-            if (Z) Z[row][col] = z;
-            H[row][col] = to_bf(gelu(z));
+            R.b1[t][r] = M.b[16 * t + 4 * g + r];
+            R.b2[t][r] = M.b[kHid + 16 * t + 4 * g + r];
+            R.b3[t][r] = M.b[2 * kHid + 16 * t + 4 * g + r];
         }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) R.w4[ks] = wfrag(w4, kHid, i, ks, g, false);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R.b4[r] = M.b[3 * kHid + 4 * g + r];
 }
 
-// Output layer: z4 (16 wide) for the tile into LDS.
-__device__ __forceinline__ void out_layer(const WLds &W, uint16_t (*H)[kHPad], float (*Z4)[kOut], int lane) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 a = frag16(&H[lane & 15][ks * 32 + 8 * (lane >> 4)]);
-        bf16x8 bv = frag16(&W.w4[lane & 15][ks * 32 + 8 * (lane >> 4)]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc, 0, 0, 0);
+// Input B fragment of one row for lane group g (natural K order): g = 0, 1
+// the embedding's halves, g = 2 (cos, log f, 0, ...), g = 3 zeros; an empty
+// slot or a row past the end gives zeros.
+__device__ __forceinline__ bf16x8 input_frag(const MlpArgs &M, uint32_t row, uint16_t lab, int g) {
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (lab < M.n_labels) {
+        if (g < 2) {
+            const float4 *e = (const float4 *)(M.emb + (size_t)lab * kEmb + 8 * g);
+            const float4 a = e[0], b = e[1];
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else if (g == 2) {
+            v[0] = M.cosv[row];
+            v[1] = M.logf;
+        }
     }
+    return bf8_of(u32x4{pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]), pack_bf2(v[4], v[5]), pack_bf2(v[6], v[7])});
+}
+
+// GELU of one layer's outputs (C layout, bias included) into the next layer's two B
+// fragments (K order perm_k); z, if given, receives the pre-activations.
+__device__ __forceinline__ void act_frags(const f32x4 (&acc)[4], bf16x8 (&h)[2], f32x4 (*z)[4] = nullptr) {
+    float v[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float pre = acc[t][r];  // the accumulation started from the bias
+            if (z) (*z)[t][r] = pre;
+            v[4 * t + r] = gelu(pre);
+        }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+        h[ks] = bf8_of(u32x4{pack_bf2(v[8 * ks + 0], v[8 * ks + 1]), pack_bf2(v[8 * ks + 2], v[8 * ks + 3]),
+                             pack_bf2(v[8 * ks + 4], v[8 * ks + 5]), pack_bf2(v[8 * ks + 6], v[8 * ks + 7])});
+}
+
+#define MFMA16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16((a), (b), (c), 0, 0, 0)
+
+// The three hidden layers and the output layer of one 16-row tile; x: the
+// input fragment. Returns z4 (C layout: lane (n, g) holds outputs 4 g + r).
+__device__ __forceinline__ f32x4 net_forward(const RegNet &R, bf16x8 x, bf16x8 (*hs)[2] = nullptr,
+                                             f32x4 (*zs)[4] = nullptr) {
+    f32x4 acc[4];
+    bf16x8 h[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w1[t], x, R.b1[t]);
+    act_frags(acc, h, zs ? &zs[0] : nullptr);
+    if (hs) { hs[0][0] = h[0]; hs[0][1] = h[1]; }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w2[t][1], h[1], MFMA16(R.w2[t][0], h[0], R.b2[t]));
+    act_frags(acc, h, zs ? &zs[1] : nullptr);
+    if (hs) { hs[1][0] = h[0]; hs[1][1] = h[1]; }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w3[t][1], h[1], MFMA16(R.w3[t][0], h[0], R.b3[t]));
+    act_frags(acc, h, zs ? &zs[2] : nullptr);
+    if (hs) { hs[2][0] = h[0]; hs[2][1] = h[1]; }
+    return MFMA16(R.w4[1], h[1], MFMA16(R.w4[0], h[0], R.b4));
+}
+
+constexpr int kFwdTiles = 4;  // 16-row tiles a wavefront carries at once (independent MFMA chains)
+
+// Persistent wavefronts, each holding the whole network in registers; tiles
+// are dealt by wavefront index (grid stride), kFwdTiles at a time.
+__global__ __launch_bounds__(256) void k_mlp_forward(MlpArgs M) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, nl = lane & 15;
+    RegNet R;
+    load_regnet(M, lane, R);
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6), n_waves = gridDim.x * 4;
+    const uint32_t n_tiles = (M.n + kTileRows - 1) / kTileRows;
+    for (uint32_t t0 = wave * kFwdTiles; t0 < n_tiles; t0 += n_waves * kFwdTiles) {
+        uint32_t row[kFwdTiles];
+        uint16_t lab[kFwdTiles];
+        f32x4 z4[kFwdTiles];
+#pragma unroll
+        for (int tt = 0; tt < kFwdTiles; ++tt) {
+            row[tt] = (t0 + tt) * kTileRows + nl;
+            lab[tt] = row[tt] < M.n ? M.label[row[tt]] : (uint16_t)0xffff;
+        }
+#pragma unroll
+        for (int tt = 0; tt < kFwdTiles; ++tt) z4[tt] = net_forward(R, input_frag(M, row[tt], lab[tt], g));
+#pragma unroll
+        for (int tt = 0; tt < kFwdTiles; ++tt) {
+            if (row[tt] >= M.n || g > 1) continue;
+            float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (lab[tt] < M.n_labels) {
+                if (g == 0) {
+                    float a, b, d;
+                    radial(z4[tt][0], z4[tt][1], o.x, o.y, a, b, d);
+                    radial(z4[tt][2], z4[tt][3], o.z, o.w, a, b, d);
+                } else {
+                    o.x = 1.f / (1.f + expf(-z4[tt][0]));  // S from output 4
+                }
+            }
+            ((float4 *)(M.out + 8 * (size_t)row[tt]))[g] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward
+// One kernel: per 16-row tile, the forward recompute (keeping GELU'(z) of
+// every hidden unit and the bf16 activations), the output Jacobian, the
+// gradient chain dH = W^T dZ, dZ = dH GELU'(z) on the matrix cores
+// (transposed formulation, K order as in the forward), and the weight
+// gradients dW = dZ^T H over the tile's 16 rows (v_mfma_f32_16x16x16_bf16,
+// K = 16 rows). For the last, dZ and H of a layer are written to LDS
+// transposed ([feature][row]), so that each operand lane holds one feature
+// and 4 rows; the accumulators stay in registers for the wavefront's whole
+// life. Bias gradients are per-lane sums of the bf16-rounded dZ, embedding
+// gradients an LDS table per wavefront updated row by row. Every wavefront
+// writes its partials once; a fixed-order reduction over wavefronts gives
+// the gradients. The grid is fixed (kBwdWaves), so the result does not
+// depend on the device.
+constexpr uint32_t kBwdWaves = 1024;
+constexpr int kMaxLabels = 64;
+// Weight fragments in LDS, fragment-major (fragment f, lane l at f * 64 + l,
+// 16 B each): forward W1 (4), W2 (4 x 2), W3 (4 x 2), W4 (2); then for the
+// chain W4^T (4; K = the 16 outputs, lane group g holds outputs 4 g .. 4 g + 3
+// and zeros), W3^T (4 x 2), W2^T (4 x 2), W1^T rows 0..15 (2).
+constexpr int kFF1 = 0, kFF2 = 4, kFF3 = 12, kFF4 = 20, kFB4 = 22, kFB3 = 26, kFB2 = 34, kFB1 = 42, kFrags = 44;
+constexpr int kTrRow = 24;  // bf16 per LDS row of a transposed operand (16 rows + pad: 48 B)
+constexpr int kPartW = kWAll + kBAll;  // per-wavefront partial: weights then biases, then the embedding table
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+#define MFMA16K16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x16bf16_1k((a), (b), (c), 0, 0, 0)
+
+struct BwdShared {
+    bf16x8 frag[kFrags * 64];
+    float bias[kBAll];
+    uint16_t dzt[4][kHid * kTrRow];   // per wavefront: dZ^T of the current layer
+    uint16_t ht[4][kHid * kTrRow];    // per wavefront: its input activations H^T
+    float emb[4][kMaxLabels * kEmb];  // per wavefront: embedding-gradient table
+};
+
+__device__ __forceinline__ bf16x8 gather_frag(const uint16_t *W, int f, int lane) {
+    // element j of lane's fragment f is W[base + row * ld + col]
+    const int i = lane & 15, g = lane >> 4;
+    u32x4 p;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = 2 * q + h;
+            int row, col, base;
+            bool zero = false;
+            if (f < kFF2) { base = 0; row = 16 * (f - kFF1) + i; col = 8 * g + j; }
+            else if (f < kFF3) { base = kW1; const int t = (f - kFF2) >> 1, ks = (f - kFF2) & 1; row = 16 * t + i; col = perm_k(ks, g, j); }
+            else if (f < kFF4) { base = kW1 + kW2; const int t = (f - kFF3) >> 1, ks = (f - kFF3) & 1; row = 16 * t + i; col = perm_k(ks, g, j); }
+            else if (f < kFB4) { base = kW1 + kW2 + kW3; row = i; col = perm_k(f - kFF4, g, j); }
+            else if (f < kFB3) { base = kW1 + kW2 + kW3; row = 4 * g + (j & 3); col = 16 * (f - kFB4) + i; zero = j >= 4; }
+            else if (f < kFB2) { base = kW1 + kW2; const int t = (f - kFB3) >> 1, ks = (f - kFB3) & 1; row = perm_k(ks, g, j); col = 16 * t + i; }
+            else if (f < kFB1) { base = kW1; const int t = (f - kFB2) >> 1, ks = (f - kFB2) & 1; row = perm_k(ks, g, j); col = 16 * t + i; }
+            else { base = 0; row = perm_k(f - kFB1, g, j); col = i; }
+            const int ldw = base == 0 ? kIn : kHid;
+            v[h] = zero ? 0u : (uint32_t)W[base + row * ldw + col];
+        }
+        p[q] = v[0] | (v[1] << 16);
+    }
+    return bf8_of(p);
+}
+
+__device__ __forceinline__ void unpack8(bf16x8 v, float (&o)[8]) {
+    const u32x4 p = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        o[2 * q] = __uint_as_float(p[q] << 16);
+        o[2 * q + 1] = __uint_as_float(p[q] & 0xffff0000u);
+    }
+}
+
+__device__ __forceinline__ uint16_t elem(bf16x8 v, int j) {
+    const uint32_t p = __builtin_bit_cast(u32x4, v)[j >> 1];
+    return (uint16_t)((j & 1) ? (p >> 16) : (p & 0xffffu));
+}
+
+// A layer's 16 values of one row (the two packed fragments, K order perm_k)
+// into a transposed LDS operand [feature][row].
+__device__ __forceinline__ void put_t(uint16_t *T, const bf16x8 (&h)[2], int lane) {
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) T[perm_k(ks, g, j) * kTrRow + n] = elem(h[ks], j);
+}
+
+// K = 16 operand of a transposed LDS tile: lane (i, g) gets feature
+// 16 ft + i, rows 4 g .. 4 g + 3.
+__device__ __forceinline__ s16x4 get_t(const uint16_t *T, int ft, int lane) {
+    return *(const s16x4 *)(T + (16 * ft + (lane & 15)) * kTrRow + 4 * (lane >> 4));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_backward(MlpArgs M) {
+    __shared__ BwdShared S;
+    for (int e = threadIdx.x; e < kFrags * 64; e += 256) S.frag[e] = gather_frag(M.w, e / 64, e % 64);
+    for (int e = threadIdx.x; e < kBAll; e += 256) S.bias[e] = M.b[e];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    for (int e = lane; e < kMaxLabels * kEmb; e += 64) S.emb[wave][e] = 0.f;
+    __syncthreads();
+    const bf16x8 *F = S.frag + lane;
+    auto bias4 = [&](int off, int t) { return *(const f32x4 *)(S.bias + off + 16 * t + 4 * g); };
+    uint16_t *DZ = S.dzt[wave], *HT = S.ht[wave];
+    float *ET = S.emb[wave];
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    // weight-gradient accumulators (C layout of dW tiles: out tile a, in tile b)
+    f32x4 gw1[4][2], gw2[4][4], gw3[4][4], gw4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gw4[a] = zero;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { gw2[a][b] = zero; gw3[a][b] = zero; }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) gw1[a][b] = zero;
+    }
+    float gb1[16] = {}, gb2[16] = {}, gb3[16] = {}, gb4[4] = {};  // this lane's bias-gradient sums
+    // GELU and GELU' of a layer's outputs (C layout, bias included)
+    auto layer = [&](const f32x4 (&acc)[4], bf16x8 (&h)[2], float (&gp)[16]) {
+        float v[16];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float z = acc[t][r];
+                float e;
+                const float tail = norm_tail(z, e);
+                v[4 * t + r] = fmaf(-fabsf(z), tail, fmaxf(z, 0.f));
+                gp[4 * t + r] = fmaf(z * 0.39894228040143268f, e, z >= 0.f ? 1.0f - tail : tail);
+            }
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            h[ks] = bf8_of(u32x4{pack_bf2(v[8 * ks + 0], v[8 * ks + 1]), pack_bf2(v[8 * ks + 2], v[8 * ks + 3]),
+                                 pack_bf2(v[8 * ks + 4], v[8 * ks + 5]), pack_bf2(v[8 * ks + 6], v[8 * ks + 7])});
+    };
+    // dZ = (W^T dZ_next) GELU'(z), rounded to bf16 (K order perm_k), and its bias-gradient sums
+    auto chain = [&](int fb, const bf16x8 *src, int nks, const float (&gp)[16], bf16x8 (&out)[2], float (&gb)[16]) {
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = zero;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                if (ks < nks) acc[t] = MFMA16(F[64 * (fb + nks * t + ks)], src[ks], acc[t]);
+        }
+        float v[16];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[4 * t + r] = acc[t][r] * gp[4 * t + r];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            out[ks] = bf8_of(u32x4{pack_bf2(v[8 * ks + 0], v[8 * ks + 1]), pack_bf2(v[8 * ks + 2], v[8 * ks + 3]),
+                                   pack_bf2(v[8 * ks + 4], v[8 * ks + 5]), pack_bf2(v[8 * ks + 6], v[8 * ks + 7])});
+            float dr[8];
+            unpack8(out[ks], dr);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gb[8 * ks + j] += dr[j];  // element j of fragment ks is value 8 ks + j
+        }
+    };
+    // dW (out tiles x in tiles) += dZ^T H over the tile's rows, from the transposed LDS copies
+    auto wgrad = [&](f32x4 (*gw)[4], int n_out, int n_in) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            if (a >= n_out) continue;
+            const s16x4 av = get_t(DZ, a, lane);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < n_in) gw[a][b] = MFMA16K16(av, get_t(HT, b, lane), gw[a][b]);
+        }
+    };
+    const uint32_t wid = blockIdx.x * 4 + wave;
+    const uint32_t n_tiles = (M.n + kTileRows - 1) / kTileRows;
+    for (uint32_t tile = wid; tile < n_tiles; tile += kBwdWaves) {
+        const uint32_t row = tile * kTileRows + n;
+        const uint16_t lab = row < M.n ? M.label[row] : (uint16_t)0xffff;
+        const bool live = row < M.n && lab < M.n_labels;
+        const bf16x8 x = input_frag(M, row, lab, g);
+        bf16x8 h1[2], h2[2], h3[2];
+        float gp1[16], gp2[16], gp3[16];
+        f32x4 acc[4];
+        // forward recompute
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = MFMA16(F[64 * (kFF1 + t)], x, bias4(0, t));
+        layer(acc, h1, gp1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = MFMA16(F[64 * (kFF2 + 2 * t + 1)], h1[1], MFMA16(F[64 * (kFF2 + 2 * t)], h1[0], bias4(kHid, t)));
+        layer(acc, h2, gp2);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = MFMA16(F[64 * (kFF3 + 2 * t + 1)], h2[1], MFMA16(F[64 * (kFF3 + 2 * t)], h2[0], bias4(2 * kHid, t)));
+        layer(acc, h3, gp3);
+        const f32x4 z4 = MFMA16(F[64 * (kFF4 + 1)], h3[1],
+                                MFMA16(F[64 * kFF4], h3[0], *(const f32x4 *)(S.bias + 3 * kHid + 4 * g)));
+        // output Jacobian: lanes g = 0 (outputs 0..3) and g = 1 (output 4) of live rows
+        float dz[4] = {0.f, 0.f, 0.f, 0.f};
+        if (live && g < 2) {
+            const float *go = M.gout + 8 * (size_t)row;
+            if (g == 0) {
+                float re, im, a, b, d;
+                radial(z4[0], z4[1], re, im, a, b, d);
+                dz[0] = go[0] * a + go[1] * b;
+                dz[1] = go[0] * b + go[1] * d;
+                radial(z4[2], z4[3], re, im, a, b, d);
+                dz[2] = go[2] * a + go[3] * b;
+                dz[3] = go[2] * b + go[3] * d;
+            } else {
+                const float s4 = 1.f / (1.f + expf(-z4[0]));
+                dz[0] = go[4] * s4 * (1.f - s4);
+            }
+        }
+        const bf16x8 d4 = bf8_of(u32x4{pack_bf2(dz[0], dz[1]), pack_bf2(dz[2], dz[3]), 0u, 0u});
+        {
+            float dr[8];
+            unpack8(d4, dr);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gb4[r] += dr[r];
+        }
+        // layer 4: dZ4^T (rows 4 g + r) and H3^T, then dW4
+#pragma unroll
+        for (int r = 0; r < 4; ++r) DZ[(4 * g + r) * kTrRow + n] = elem(d4, r);
+        put_t(HT, h3, lane);
+        wave_sync();
+        wgrad(&gw4, 1, 4);  // gw4 as one out tile x four in tiles
+        wave_sync();
+        // layer 3
+        bf16x8 dz3[2], dz2[2], dz1[2];
+        chain(kFB4, &d4, 1, gp3, dz3, gb3);
+        put_t(DZ, dz3, lane);
+        put_t(HT, h2, lane);
+        wave_sync();
+        wgrad(gw3, 4, 4);
+        wave_sync();
+        // layer 2
+        chain(kFB3, dz3, 2, gp2, dz2, gb2);
+        put_t(DZ, dz2, lane);
+        put_t(HT, h1, lane);
+        wave_sync();
+        wgrad(gw2, 4, 4);
+        wave_sync();
+        // layer 1 (H = the input: 32 features in natural order, element j of lane group g is feature 8 g + j)
+        chain(kFB2, dz2, 2, gp1, dz1, gb1);
+        put_t(DZ, dz1, lane);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) HT[(8 * g + j) * kTrRow + n] = elem(x, j);
+        const f32x4 dx = MFMA16(F[64 * (kFB1 + 1)], dz1[1], MFMA16(F[64 * kFB1], dz1[0], zero));
+        wave_sync();
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const s16x4 av = get_t(DZ, a, lane);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) gw1[a][b] = MFMA16K16(av, get_t(HT, b, lane), gw1[a][b]);
+        }
+        // embedding gradient: row by row in order, the four lanes of a row add dims 4 g .. 4 g + 3
+        for (int s = 0; s < 16; ++s) {
+            if (n == s && live) {
+                float *e = ET + lab * kEmb + 4 * g;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) e[r] += dx[r];
+            }
+            wave_sync();
+        }
+    }
+    // partials: the weight gradients from the accumulators (C layout: lane
+    // holds in-feature 16 b + n, out-features 16 a + 4 g + r), the bias sums
+    // reduced over the 16 row lanes in a fixed butterfly, the embedding table
+    float *P = M.part + (size_t)wid * M.part_stride;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 16 * a + 4 * g + r;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) P[o * kIn + 16 * b + n] = gw1[a][b][r];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                P[kW1 + o * kHid + 16 * b + n] = gw2[a][b][r];
+                P[kW1 + kW2 + o * kHid + 16 * b + n] = gw3[a][b][r];
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) P[kW1 + kW2 + kW3 + (4 * g + r) * kHid + 16 * b + n] = gw4[b][r];
+    auto lane_sum16 = [&](float v) {  // over the 16 lanes of a lane group, fixed order
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        return v;
+    };
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // element 4 t + r of the sums is feature 16 t + 4 g + r
+            const float s1 = lane_sum16(gb1[4 * t + r]), s2 = lane_sum16(gb2[4 * t + r]),
+                        s3 = lane_sum16(gb3[4 * t + r]);
+            if (n == 0) {
+                P[kWAll + 16 * t + 4 * g + r] = s1;
+                P[kWAll + kHid + 16 * t + 4 * g + r] = s2;
+                P[kWAll + 2 * kHid + 16 * t + 4 * g + r] = s3;
+            }
+        }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        int row = 4 * (lane >> 4) + r, col = lane & 15;
-        Z4[row][col] = acc[r] + W.b[3 * kHid + col];
+        const float s4 = lane_sum16(gb4[r]);
+        if (n == 0) P[kWAll + 3 * kHid + 4 * g + r] = s4;
     }
-}
-
-struct WaveTile {
-    uint16_t H[kTileRows][kHPad];
-    float Z4[kTileRows][kOut];
-};
-
-__global__ __launch_bounds__(256) void k_mlp_forward(MlpArgs M) {
-    __shared__ WLds W;
-    __shared__ WaveTile wt[4];
-    load_weights(M, W);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    WaveTile &T = wt[wave];
-    const uint32_t n_tiles = (M.n + kTileRows - 1) / kTileRows;
-    for (uint32_t t = blockIdx.x * 4 + wave; t < n_tiles; t += gridDim.x * 4) {
-        const uint32_t r0 = t * kTileRows;
-        uint16_t xb[8];
-        input_bits(M, r0 + (lane & 15), lane >> 4, xb);
-        bf16x8 a_in = bits_frag(xb);
-        f32x4 acc[4];
-        layer_mfma<1>(nullptr, &a_in, W.w1, lane, acc);
-        wave_sync();  // previous tile's reads of H are done
-        store_act(acc, W.b, T.H, nullptr, lane);
-        wave_sync();
-        layer_mfma<2>(&T.H[lane & 15][0], nullptr, W.w2, lane, acc);
-        wave_sync();
-        store_act(acc, W.b + kHid, T.H, nullptr, lane);
-        wave_sync();
-        layer_mfma<2>(&T.H[lane & 15][0], nullptr, W.w3, lane, acc);
-        wave_sync();
-        store_act(acc, W.b + 2 * kHid, T.H, nullptr, lane);
-        wave_sync();
-        out_layer(W, T.H, T.Z4, lane);
-        wave_sync();
-        if (lane < kTileRows) {
-            const uint32_t row = r0 + lane;
-            if (row < M.n) {
-                uint16_t lab = M.label[row];
-                float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0;
-                if (lab != 0xffff && lab < M.n_labels) {
-                    const float *z = T.Z4[lane];
-                    float a, b, d;
-                    radial(z[0], z[1], o0.x, o0.y, a, b, d);
-                    radial(z[2], z[3], o0.z, o0.w, a, b, d);
-                    o1.x = 1.f / (1.f + expf(-z[4]));
-                }
-                float4 *o = (float4 *)(M.out + 8 * (size_t)row);
-                o[0] = o0;
-                o[1] = o1;
-            }
-        }
-    }
-}
-
-// Backward chain per 16-row tile: forward recompute (saving inputs and
-// activations for the weight GEMM), output-activation Jacobian, then
-// dz_l = (dz_{l+1} W_{l+1}) * GELU'(z_l), all bf16-operand MFMAs.
-struct BwdTile {
-    uint16_t H[kTileRows][kHPad];      // activation / gradient tile (A operand)
-    float Z[3][kTileRows][kHid];       // pre-activations of the hidden layers
-    float Z4[kTileRows][kOut];
-};
-
-__device__ __forceinline__ void save_tile(uint16_t *dst, uint32_t r0, uint32_t n, int width, uint16_t (*H)[kHPad],
-                                          int lane) {
-    for (int i = lane; i < kTileRows * width; i += 64) {
-        int row = i / width, col = i % width;
-        if (r0 + row < n) dst[(size_t)(r0 + row) * width + col] = H[row][col];
-    }
-}
-
-// dH = dZ (tile in LDS, K = KSTEPS*32) x W^T-rows (B from the transposed copy),
-// N = 64 outputs in 4 tiles.
-template <int KSTEPS, int LDW>
-__device__ __forceinline__ void back_mfma(uint16_t (*G)[kHPad], const uint16_t (*Wt)[LDW], int lane, f32x4 *acc) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-        bf16x8 a = frag16(&G[lane & 15][ks * 32 + 8 * (lane >> 4)]);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            bf16x8 bv = frag16(&Wt[nt * 16 + (lane & 15)][ks * 32 + 8 * (lane >> 4)]);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[nt], 0, 0, 0);
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void k_mlp_backward_chain(MlpArgs M) {
-    __shared__ WLds W;
-    __shared__ WtLds WT;
-    __shared__ BwdTile bt[4];
-    load_weights(M, W);
-    __syncthreads();
-    load_weights_t(W, WT);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    BwdTile &T = bt[wave];
-    const uint32_t n_tiles = (M.n + kTileRows - 1) / kTileRows;
-    for (uint32_t t = blockIdx.x * 4 + wave; t < n_tiles; t += gridDim.x * 4) {
-        const uint32_t r0 = t * kTileRows;
-        uint16_t xb[8];
-        input_bits(M, r0 + (lane & 15), lane >> 4, xb);
-        bf16x8 a_in = bits_frag(xb);
-        // save x0 (bf16) for the first layer's weight gradient
-        {
-            const uint32_t row = r0 + (lane & 15);
-            if (row < M.n) {
-                for (int j = 0; j < 8; ++j) M.x0[(size_t)row * kIn + 8 * (lane >> 4) + j] = xb[j];
-            }
-        }
-        f32x4 acc[4];
-        layer_mfma<1>(nullptr, &a_in, W.w1, lane, acc);
-        wave_sync();  // previous tile's reads of H are done
-        store_act(acc, W.b, T.H, T.Z[0], lane);
-        wave_sync();
-        save_tile(M.h1, r0, M.n, kHid, T.H, lane);
-        layer_mfma<2>(&T.H[lane & 15][0], nullptr, W.w2, lane, acc);
-        wave_sync();
-        store_act(acc, W.b + kHid, T.H, T.Z[1], lane);
-        wave_sync();
-        save_tile(M.h2, r0, M.n, kHid, T.H, lane);
-        layer_mfma<2>(&T.H[lane & 15][0], nullptr, W.w3, lane, acc);
-        wave_sync();
-        store_act(acc, W.b + 2 * kHid, T.H, T.Z[2], lane);
-        wave_sync();
-        save_tile(M.h3, r0, M.n, kHid, T.H, lane);
-        out_layer(W, T.H, T.Z4, lane);
-        wave_sync();
-        // output-activation Jacobian: dz4 (16 wide, 5 used), bf16, into the H tile
-        if (lane < kTileRows) {
-            const uint32_t row = r0 + lane;
-            float dz[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            if (row < M.n) {
-                uint16_t lab = M.label[row];
-                if (lab != 0xffff && lab < M.n_labels) {
-                    const float *z = T.Z4[lane];
-                    const float *g = M.gout + 8 * (size_t)row;
-                    float re, im, a, b, d;
-                    radial(z[0], z[1], re, im, a, b, d);
-                    dz[0] = g[0] * a + g[1] * b;
-                    dz[1] = g[0] * b + g[1] * d;
-                    radial(z[2], z[3], re, im, a, b, d);
-                    dz[2] = g[2] * a + g[3] * b;
-                    dz[3] = g[2] * b + g[3] * d;
-                    float S = 1.f / (1.f + expf(-z[4]));
-                    dz[4] = g[4] * S * (1.f - S);
-                }
-            }
-            for (int c = 0; c < 32; ++c) T.H[lane][c] = c < 5 ? to_bf(dz[c]) : (uint16_t)0;
-            if (row < M.n)
-                for (int c = 0; c < kOut; ++c) M.dz4[(size_t)row * kOut + c] = c < 5 ? to_bf(dz[c]) : (uint16_t)0;
-        }
-        wave_sync();
-        // dh3 = dz4 W4 (K = 16 padded to 32); dz3 = dh3 * GELU'(z3)
-        back_mfma<1, kOut + 16>(T.H, WT.w4t, lane, acc);
-        wave_sync();
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-                T.H[row][col] = to_bf(acc[nt][r] * gelu_grad(T.Z[2][row][col]));
-            }
-        wave_sync();
-        save_tile(M.dz3, r0, M.n, kHid, T.H, lane);
-        back_mfma<2, kHid>(T.H, WT.w3t, lane, acc);
-        wave_sync();
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-                T.H[row][col] = to_bf(acc[nt][r] * gelu_grad(T.Z[1][row][col]));
-            }
-        wave_sync();
-        save_tile(M.dz2, r0, M.n, kHid, T.H, lane);
-        back_mfma<2, kHid>(T.H, WT.w2t, lane, acc);
-        wave_sync();
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = 4 * (lane >> 4) + r, col = nt * 16 + (lane & 15);
-                T.H[row][col] = to_bf(acc[nt][r] * gelu_grad(T.Z[0][row][col]));
-            }
-        wave_sync();
-        save_tile(M.dz1, r0, M.n, kHid, T.H, lane);
-        // dx0 = dz1 W1: only the embedding columns (N tile 0)
-        {
-            f32x4 a0 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x8 a = frag16(&T.H[lane & 15][ks * 32 + 8 * (lane >> 4)]);
-                bf16x8 bv = frag16(&WT.w1t[lane & 15][ks * 32 + 8 * (lane >> 4)]);
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, a0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                uint32_t row = r0 + 4 * (lane >> 4) + r;
-                if (row < M.n) M.dx0[(size_t)row * kEmb + (lane & 15)] = a0[r];
-            }
-        }
-    }
-}
-
-// Weight gradient of one layer over a fixed block of rows:
-// dW[o][i] = sum_rows dZ[row][o] H[row][i] (A = dZ^T, B = H, K = 32 rows per
-// MFMA), and the bias gradient sum_rows dZ[row][o]. Partials per block.
-template <int OUT, int IN>
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const uint16_t *dz, const uint16_t *h, uint32_t n, float *part) {
-    __shared__ uint16_t sdz[32][OUT + 2];
-    __shared__ uint16_t sh[32][IN + 2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int TO = OUT / 16, TI = IN / 16, NT = TO * TI, PER = (NT + 3) / 4;
-    f32x4 acc[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
-    const uint32_t b0 = blockIdx.x * kGradRows, b1 = min(b0 + kGradRows, n);
-    for (uint32_t r0 = b0; r0 < b1; r0 += 32) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 32 * OUT; i += 256) {
-            int rr = i / OUT, c = i % OUT;
-            sdz[rr][c] = r0 + rr < b1 ? dz[(size_t)(r0 + rr) * OUT + c] : (uint16_t)0;
-        }
-        for (int i = threadIdx.x; i < 32 * IN; i += 256) {
-            int rr = i / IN, c = i % IN;
-            sh[rr][c] = r0 + rr < b1 ? h[(size_t)(r0 + rr) * IN + c] : (uint16_t)0;
-        }
-        __syncthreads();
-        if (threadIdx.x < OUT)
-            for (int rr = 0; rr < 32; ++rr) bsum += bf(sdz[rr][threadIdx.x]);
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int tile = wave * PER + q;
-            if (tile >= NT) continue;
-            const int o0 = (tile / TI) * 16, i0 = (tile % TI) * 16;
-            bf16x8 a, bv;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                a[j] = as_b(sdz[8 * (lane >> 4) + j][o0 + (lane & 15)]);
-                bv[j] = as_b(sh[8 * (lane >> 4) + j][i0 + (lane & 15)]);
-            }
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[q], 0, 0, 0);
-        }
-    }
-    float *P = part + (size_t)blockIdx.x * (OUT * IN + OUT);
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int tile = wave * PER + q;
-        if (tile >= NT) continue;
-        const int o0 = (tile / TI) * 16, i0 = (tile % TI) * 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) P[(o0 + 4 * (lane >> 4) + r) * IN + i0 + (lane & 15)] = acc[q][r];
-    }
-    if (threadIdx.x < OUT) P[OUT * IN + threadIdx.x] = bsum;
-}
-
-// Embedding gradient partial of one block of rows. Thread (g, d) -- row group
-// g = 0..15, embedding dimension d -- adds dx0[row][d] of rows b0 + g,
-// b0 + g + 16, ... in order into its group's LDS table acc[g][label][d]; the
-// 16 group tables are then added in group order. Fixed order, no atomics.
-constexpr int kEmbGroups = 16;
-constexpr int kMaxLabels = 64;
-__global__ __launch_bounds__(256) void k_mlp_embgrad(const uint16_t *label, const float *dx0, uint32_t n,
-                                                     uint32_t n_labels, float *part) {
-    __shared__ float acc[kEmbGroups][kMaxLabels * kEmb];
-    for (uint32_t e = threadIdx.x; e < kEmbGroups * kMaxLabels * kEmb; e += blockDim.x) (&acc[0][0])[e] = 0.f;
-    __syncthreads();
-    const uint32_t g = threadIdx.x / kEmb, d = threadIdx.x % kEmb;
-    const uint32_t b0 = blockIdx.x * kGradRows, b1 = min(b0 + kGradRows, n);
-    for (uint32_t r = b0 + g; r < b1; r += kEmbGroups) {
-        const uint32_t lab = label[r];
-        if (lab < n_labels) acc[g][lab * kEmb + d] += dx0[(size_t)r * kEmb + d];
-    }
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < n_labels * kEmb; e += blockDim.x) {
-        float s = 0.f;
-        for (int k = 0; k < kEmbGroups; ++k) s += acc[k][e];
-        part[(size_t)blockIdx.x * n_labels * kEmb + e] = s;
-    }
+    wave_sync();
+    for (uint32_t e = lane; e < M.n_labels * kEmb; e += 64) P[kPartW + e] = ET[e];
 }
 
 // Fixed-order sum of per-block partials, first stage: block (x, y) adds, for
@@ -527,25 +628,17 @@ using namespace pcrt;
 
 namespace {
 struct MlpLayout {
-    size_t x0, h1, h2, h3, dz1, dz2, dz3, dz4, dx0, part, part2, total;
-    uint32_t n_blocks;
+    size_t part, part2, total;
+    uint32_t stride;
 };
-MlpLayout mlp_layout(uint32_t n, uint32_t n_labels) {
+// Per-wavefront partials of the backward kernel (weights, biases, embedding
+// table), then the first-stage sums of the fixed-order reduction.
+MlpLayout mlp_layout(uint32_t n_labels) {
     Bump b;
     MlpLayout L;
-    L.n_blocks = std::max<uint32_t>((n + kGradRows - 1) / kGradRows, 1);
-    L.x0 = b.take(2ull * n * kIn);
-    L.h1 = b.take(2ull * n * kHid);
-    L.h2 = b.take(2ull * n * kHid);
-    L.h3 = b.take(2ull * n * kHid);
-    L.dz1 = b.take(2ull * n * kHid);
-    L.dz2 = b.take(2ull * n * kHid);
-    L.dz3 = b.take(2ull * n * kHid);
-    L.dz4 = b.take(2ull * n * kOut);
-    L.dx0 = b.take(4ull * n * kEmb);
-    size_t per = std::max<size_t>(kHid * kHid + kHid, (size_t)n_labels * kEmb);
-    L.part = b.take(4ull * L.n_blocks * per);
-    L.part2 = b.take(4ull * kSumSplits * per);
+    L.stride = kPartW + n_labels * kEmb;
+    L.part = b.take(4ull * kBwdWaves * L.stride);
+    L.part2 = b.take(4ull * kSumSplits * L.stride);
     L.total = b.off;
     return L;
 }
@@ -555,7 +648,8 @@ extern "C" {
 
 pcrt_status pcrt_mlp_workspace_size(uint32_t n, uint32_t n_labels, size_t *bytes) {
     if (!bytes) return PCRT_EINVAL;
-    *bytes = mlp_layout(n, n_labels).total;
+    (void)n;  // the partials are per wavefront of a fixed grid, not per row
+    *bytes = mlp_layout(std::max<uint32_t>(n_labels, 1)).total;
     return PCRT_OK;
 }
 
@@ -575,7 +669,8 @@ pcrt_status pcrt_mlp_forward(const pcrt_mlp *net, uint32_t n, const uint16_t *la
     M.logf = log_f;
     M.out = out;
     const uint32_t tiles = (n + kTileRows - 1) / kTileRows;
-    const uint32_t grid = std::min<uint32_t>((tiles + 3) / 4, 2048);
+    static const uint32_t cap = resident_blocks((const void *)k_mlp_forward, 256);
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((tiles + 4 * kFwdTiles - 1) / (4 * kFwdTiles), cap));
     hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(256), 0, (hipStream_t)stream, M);
     return hipGetLastError() == hipSuccess ? PCRT_OK : PCRT_EDEVICE;
 }
@@ -587,7 +682,7 @@ pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *l
         return PCRT_EINVAL;
     if (n == 0) return PCRT_EINVAL;
     if (net->n_labels == 0 || net->n_labels > 64) return PCRT_EUNSUPPORTED;
-    MlpLayout L = mlp_layout(n, net->n_labels);
+    MlpLayout L = mlp_layout(net->n_labels);
     if (ws_bytes < L.total) return PCRT_ENOMEM;
     char *w = (char *)ws;
     hipStream_t s = (hipStream_t)stream;
@@ -602,42 +697,13 @@ pcrt_status pcrt_mlp_backward(const pcrt_mlp *net, uint32_t n, const uint16_t *l
     M.cosv = cosv;
     M.logf = log_f;
     M.gout = g_out;
-    M.x0 = (uint16_t *)(w + L.x0);
-    M.h1 = (uint16_t *)(w + L.h1);
-    M.h2 = (uint16_t *)(w + L.h2);
-    M.h3 = (uint16_t *)(w + L.h3);
-    M.dz1 = (uint16_t *)(w + L.dz1);
-    M.dz2 = (uint16_t *)(w + L.dz2);
-    M.dz3 = (uint16_t *)(w + L.dz3);
-    M.dz4 = (uint16_t *)(w + L.dz4);
-    M.dx0 = (float *)(w + L.dx0);
-    float *part = (float *)(w + L.part), *part2 = (float *)(w + L.part2);
-    const uint32_t tiles = (n + kTileRows - 1) / kTileRows;
-    hipLaunchKernelGGL(k_mlp_backward_chain, dim3(std::min<uint32_t>((tiles + 3) / 4, 2048)), dim3(256), 0, s, M);
-    const uint32_t nb = L.n_blocks;
-    // layer 4 .. 1: (dz, input activation) -> grad_w slice, grad_b slice
-    struct Job {
-        int out, in;
-        const uint16_t *dz, *h;
-        size_t w_off, b_off;
-    } jobs[4] = {{kOut, kHid, M.dz4, M.h3, (size_t)(kW1 + kW2 + kW3), 3 * kHid},
-                 {kHid, kHid, M.dz3, M.h2, (size_t)(kW1 + kW2), 2 * kHid},
-                 {kHid, kHid, M.dz2, M.h1, (size_t)kW1, kHid},
-                 {kHid, kIn, M.dz1, M.x0, 0, 0}};
-    for (const Job &j : jobs) {
-        if (j.out == kOut)
-            hipLaunchKernelGGL((k_mlp_wgrad<kOut, kHid>), dim3(nb), dim3(256), 0, s, j.dz, j.h, n, part);
-        else if (j.in == kHid)
-            hipLaunchKernelGGL((k_mlp_wgrad<kHid, kHid>), dim3(nb), dim3(256), 0, s, j.dz, j.h, n, part);
-        else
-            hipLaunchKernelGGL((k_mlp_wgrad<kHid, kIn>), dim3(nb), dim3(256), 0, s, j.dz, j.h, n, part);
-        const uint32_t wsz = j.out * j.in, stride = wsz + j.out;
-        sum_parts(part, nb, wsz, stride, part2, grad_w + j.w_off, s);
-        sum_parts(part + wsz, nb, (uint32_t)j.out, stride, part2, grad_b + j.b_off, s);
-    }
-    hipLaunchKernelGGL(k_mlp_embgrad, dim3(nb), dim3(256), 0, s, label, M.dx0, n, net->n_labels, part);
-    const uint32_t ew = net->n_labels * kEmb;
-    sum_parts(part, nb, ew, ew, part2, grad_emb, s);
+    M.part = (float *)(w + L.part);
+    M.part_stride = L.stride;
+    float *part2 = (float *)(w + L.part2);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(kBwdWaves / 4), dim3(256), 0, s, M);
+    sum_parts(M.part, kBwdWaves, kWAll, L.stride, part2, grad_w, s);
+    sum_parts(M.part + kWAll, kBwdWaves, kBAll, L.stride, part2, grad_b, s);
+    sum_parts(M.part + kPartW, kBwdWaves, net->n_labels * kEmb, L.stride, part2, grad_emb, s);
     return hipGetLastError() == hipSuccess ? PCRT_OK : PCRT_EDEVICE;
 }
 
