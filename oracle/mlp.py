@@ -112,8 +112,13 @@ def forward(params, labels, cosv, freq, precision="fp64", keep=False):
     return out
 
 
-def backward(params, labels, cosv, freq, g_out, precision="fp64"):
-    """Gradients of sum(g_out * out) with respect to every parameter."""
+def backward(params, labels, cosv, freq, g_out, precision="fp64", magnitudes=False):
+    """Gradients of sum(g_out * out) with respect to every parameter.
+
+    magnitudes=True also returns, per gradient element, the sum of the
+    absolute values of the terms it adds up (|dz|^T |h| for a weight, sum
+    |dz| for a bias, the rows' sum |dz| |W| for an embedding entry): the
+    scale against which rounding differences of those terms are judged."""
     kern = precision == "kernel"
     rq = (lambda a: bf16(a).astype(np.float64)) if kern else (lambda a: a)
     acc = (lambda a, b: (a.astype(np.float32) @ b.astype(np.float32)).astype(np.float64)) if kern else np.matmul
@@ -127,14 +132,21 @@ def backward(params, labels, cosv, freq, g_out, precision="fp64"):
     dz4[:, 2] = g[:, 2] * a + g[:, 3] * cc
     dz4[:, 3] = g[:, 2] * bb + g[:, 3] * d
     dz4[:, 4] = g[:, 4] * c["S"] * (1.0 - c["S"])
-    grads = {}
+    grads, mags = {}, {}
     dz = rq(dz4)
     W, hs, zs = c["W"], c["hs"], c["zs"]
     for i in (3, 2, 1, 0):
         grads["W%d" % (i + 1)] = acc(dz.T, hs[i])
         grads["b%d" % (i + 1)] = dz.sum(0)
+        if magnitudes:
+            mags["W%d" % (i + 1)] = np.abs(dz).T @ np.abs(hs[i])
+            mags["b%d" % (i + 1)] = np.abs(dz).sum(0)
         dh = acc(dz, W[i])
         if i == 0:
+            if magnitudes:
+                memb = np.zeros_like(params["emb"])
+                np.add.at(memb, c["labels"], (np.abs(dz) @ np.abs(W[0]))[:, :N_EMB])
+                mags["emb"] = memb
             break
         dz = rq(dh * gelu_grad(zs[i - 1]))
     demb = np.zeros_like(params["emb"])
@@ -143,4 +155,4 @@ def backward(params, labels, cosv, freq, g_out, precision="fp64"):
     grads["W1"][:, N_EMB + 2:] = 0.0
     grads["W4"][5:] = 0.0
     grads["b4"][5:] = 0.0
-    return grads
+    return (grads, mags) if magnitudes else grads

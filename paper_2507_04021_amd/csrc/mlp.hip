@@ -28,8 +28,12 @@
 // share of every weight gradient in registers, written once as a partial
 // that a fixed-order reduction adds up.
 //
-// GELU uses erf by Abramowitz & Stegun 7.1.26 (absolute error below 1.5e-7
-// in erf): far below the BF16 rounding of the activations (2^-8 relative).
+// GELU: erf by Abramowitz & Stegun 7.1.26 (absolute error below 1.5e-7 in
+// erf; GELU within 3.3e-7) in the backward pass; the forward pass
+// interpolates linearly in a table of that GELU at 8193 nodes over [-8, 8]
+// (spacing 2^-9, built in LDS by every block; beyond the ends the end
+// intervals extend linearly), within 1e-6. Both are far below the BF16
+// rounding of the activations (2^-8 relative).
 #include <cstring>
 
 #include "common.h"
@@ -70,10 +74,13 @@ __device__ __forceinline__ float norm_tail(float z, float &e) {
     e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);  // 2^(-z^2 log2(e) / 2)
     return poly * e;
 }
+// max(z, 0) on the bit pattern: a non-negative float is a non-negative int32,
+// a negative one a negative int32 (one integer max, no NaN canonicalisation)
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
 __device__ __forceinline__ float gelu(float z) {
     float e;
     const float h = norm_tail(z, e);
-    return fmaf(-fabsf(z), h, fmaxf(z, 0.f));
+    return fmaf(-fabsf(z), h, relu(z));
 }
 // GELU'(z) = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi).
 __device__ __forceinline__ float gelu_grad(float z) {
@@ -194,17 +201,38 @@ __device__ __forceinline__ bf16x8 input_frag(const MlpArgs &M, uint32_t row, uin
 }
 
 // GELU of one layer's outputs (C layout, bias included) into the next layer's two B
-// fragments (K order perm_k); z, if given, receives the pre-activations.
-__device__ __forceinline__ void act_frags(const f32x4 (&acc)[4], bf16x8 (&h)[2], f32x4 (*z)[4] = nullptr) {
+// fragments (K order perm_k).
+constexpr int kGeluN = 8192;  // table intervals over [-8, 8): node i at -8 + i / 512
+// GELU from the table (value, slope to the next node) of the node below z;
+// z outside [-8, 8) uses the end interval's line (GELU(z) = z and 0 there to
+// FP32 precision).
+__device__ __forceinline__ float gelu_tab(const float2 *tab, float z) {
+    const float x = fmaf(z, 512.f, 4096.f);
+    const float c = __builtin_amdgcn_fmed3f(floorf(x), 0.f, (float)(kGeluN - 1));
+    const float2 e = tab[(int)c];
+    return fmaf(x - c, e.y, e.x);
+}
+__device__ void build_gelu_table(float2 *tab) {  // tab[kGeluN + 1], every thread of the block
+    for (int i = threadIdx.x; i <= kGeluN; i += blockDim.x) tab[i].x = gelu(-8.f + (float)i * (1.f / 512.f));
+    __syncthreads();
+    constexpr int kPer = kGeluN / 256;
+    float slope[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        slope[k] = tab[i + 1].x - tab[i].x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) tab[threadIdx.x + 256 * k].y = slope[k];
+    __syncthreads();
+}
+__device__ __forceinline__ void act_frags(const f32x4 (&acc)[4], bf16x8 (&h)[2], const float2 *tab) {
     float v[16];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float pre = acc[t][r];  // the accumulation started from the bias
-            if (z) (*z)[t][r] = pre;
-            v[4 * t + r] = gelu(pre);
-        }
+        for (int r = 0; r < 4; ++r) v[4 * t + r] = gelu_tab(tab, acc[t][r]);  // the accumulation started from the bias
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
         h[ks] = bf8_of(u32x4{pack_bf2(v[8 * ks + 0], v[8 * ks + 1]), pack_bf2(v[8 * ks + 2], v[8 * ks + 3]),
@@ -215,30 +243,45 @@ __device__ __forceinline__ void act_frags(const f32x4 (&acc)[4], bf16x8 (&h)[2],
 
 // The three hidden layers and the output layer of one 16-row tile; x: the
 // input fragment. Returns z4 (C layout: lane (n, g) holds outputs 4 g + r).
-__device__ __forceinline__ f32x4 net_forward(const RegNet &R, bf16x8 x, bf16x8 (*hs)[2] = nullptr,
-                                             f32x4 (*zs)[4] = nullptr) {
+__device__ __forceinline__ f32x4 net_forward(const RegNet &R, bf16x8 x, const float2 *tab) {
     f32x4 acc[4];
     bf16x8 h[2];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w1[t], x, R.b1[t]);
-    act_frags(acc, h, zs ? &zs[0] : nullptr);
-    if (hs) { hs[0][0] = h[0]; hs[0][1] = h[1]; }
+    act_frags(acc, h, tab);
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w2[t][1], h[1], MFMA16(R.w2[t][0], h[0], R.b2[t]));
-    act_frags(acc, h, zs ? &zs[1] : nullptr);
-    if (hs) { hs[1][0] = h[0]; hs[1][1] = h[1]; }
+    act_frags(acc, h, tab);
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = MFMA16(R.w3[t][1], h[1], MFMA16(R.w3[t][0], h[0], R.b3[t]));
-    act_frags(acc, h, zs ? &zs[2] : nullptr);
-    if (hs) { hs[2][0] = h[0]; hs[2][1] = h[1]; }
+    act_frags(acc, h, tab);
     return MFMA16(R.w4[1], h[1], MFMA16(R.w4[0], h[0], R.b4));
 }
 
-constexpr int kFwdTiles = 4;  // 16-row tiles a wavefront carries at once (independent MFMA chains)
+constexpr int kFwdTiles = 8;  // 16-row tiles a wavefront carries at once (independent MFMA chains)
 
 // Persistent wavefronts, each holding the whole network in registers; tiles
 // are dealt by wavefront index (grid stride), kFwdTiles at a time.
+// Output map of the forward pass: (u + j v) tanh(r) / r with tanh r =
+// 1 - 2 / (e^{2r} + 1) (relative error near 1e-6 down to r = 0.1), and the
+// series 1 - r^2 / 3 + 2 r^4 / 15 below (truncation 6e-8 relative).
+__device__ __forceinline__ void radial_fwd(float u, float v, float &re, float &im) {
+    const float r2 = u * u + v * v;
+    float g;
+    if (r2 < 0.01f) {
+        g = fmaf(fmaf(0.133333333f, r2, -0.333333333f), r2, 1.0f);
+    } else {
+        const float rinv = __builtin_amdgcn_rsqf(r2), r = r2 * rinv;
+        const float ex = __builtin_amdgcn_exp2f(2.8853900817779268f * r);  // e^{2r}
+        g = (1.0f - 2.0f * __builtin_amdgcn_rcpf(ex + 1.0f)) * rinv;
+    }
+    re = u * g;
+    im = v * g;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_forward(MlpArgs M) {
+    __shared__ float2 tab[kGeluN + 1];
+    build_gelu_table(tab);
     const int lane = threadIdx.x & 63, g = lane >> 4, nl = lane & 15;
     RegNet R;
     load_regnet(M, lane, R);
@@ -254,16 +297,15 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpArgs M) {
             lab[tt] = row[tt] < M.n ? M.label[row[tt]] : (uint16_t)0xffff;
         }
 #pragma unroll
-        for (int tt = 0; tt < kFwdTiles; ++tt) z4[tt] = net_forward(R, input_frag(M, row[tt], lab[tt], g));
+        for (int tt = 0; tt < kFwdTiles; ++tt) z4[tt] = net_forward(R, input_frag(M, row[tt], lab[tt], g), tab);
 #pragma unroll
         for (int tt = 0; tt < kFwdTiles; ++tt) {
             if (row[tt] >= M.n || g > 1) continue;
             float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
             if (lab[tt] < M.n_labels) {
                 if (g == 0) {
-                    float a, b, d;
-                    radial(z4[tt][0], z4[tt][1], o.x, o.y, a, b, d);
-                    radial(z4[tt][2], z4[tt][3], o.z, o.w, a, b, d);
+                    radial_fwd(z4[tt][0], z4[tt][1], o.x, o.y);
+                    radial_fwd(z4[tt][2], z4[tt][3], o.z, o.w);
                 } else {
                     o.x = 1.f / (1.f + expf(-z4[tt][0]));  // S from output 4
                 }
@@ -399,7 +441,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(MlpArgs M) {
                 const float z = acc[t][r];
                 float e;
                 const float tail = norm_tail(z, e);
-                v[4 * t + r] = fmaf(-fabsf(z), tail, fmaxf(z, 0.f));
+                v[4 * t + r] = fmaf(-fabsf(z), tail, relu(z));
                 gp[4 * t + r] = fmaf(z * 0.39894228040143268f, e, z >= 0.f ? 1.0f - tail : tail);
             }
 #pragma unroll

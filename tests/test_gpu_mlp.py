@@ -3,8 +3,12 @@ CPU reference at the kernels' rounding points, and training through the
 tracer on simulator-generated channel sets.
 
 Bars: forward outputs within 2 bf16 ulps of the activations' effect
-(max |diff| <= 2e-2, mean <= 2e-3); parameter gradients within 3 % in norm
-per tensor (bf16 operands on both sides, FP32 vs FP64 accumulation order).
+(max |diff| <= 2e-2, mean <= 2e-3). Parameter gradients element by element:
+each gradient is a sum of n products of bf16-rounded factors, and the two
+sides may differ by one bf16 rounding decision in a factor (at most 2^-8 of
+that term) and by the FP32 accumulation order (at most n 2^-24 of the sum of
+the terms' magnitudes), so |g_gpu - g_ref| <= (2^-8 + n 2^-24) M per
+element, M being that element's sum of |terms| (from the reference).
 """
 import math
 
@@ -80,11 +84,13 @@ def test_mlp_backward_matches_reference(env, n):
     print("[gpu-test] mlp backward n=%d" % n, flush=True)
     grads = net.backward_rows(lab, cs, 3.5e9, torch.tensor(g_out, device="cuda"))
     live = labels != 0xFFFF
-    ref = R.backward(params, labels[live], cosv[live].astype(np.float64), 3.5e9, g_out[live, :5], precision="kernel")
+    ref, mag = R.backward(params, labels[live], cosv[live].astype(np.float64), 3.5e9, g_out[live, :5],
+                          precision="kernel", magnitudes=True)
+    bound = 2.0 ** -8 + n * 2.0 ** -24
     for k, v in ref.items():
         got = grads[k].cpu().numpy().astype(np.float64)
-        err = np.linalg.norm(got - v) / max(np.linalg.norm(v), 1e-30)
-        assert err < 3e-2, (k, err)
+        assert np.all(np.abs(got - v) <= bound * mag[k]), (k, np.max(np.abs(got - v) / np.maximum(mag[k], 1e-300)))
+        assert np.linalg.norm(got - v) <= 1e-3 * np.linalg.norm(v), k
     # padding stays structurally zero
     assert np.all(grads["W1"].cpu().numpy()[:, R.N_EMB + 2:] == 0)
     assert np.all(grads["W4"].cpu().numpy()[5:] == 0)
