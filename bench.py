@@ -27,10 +27,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays·interactions/s and ms per scene solve (1M pts, 5 bounces); grad-step ms"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed dual issue)
+# the same chip without packed FP32 (disabled in this build): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_NONPACKED_PEAK_TFLOPS = 78.6
 
-# Algorithmic FP32 operations per unit of traversal work (add, mul, min, max,
-# compare = 1, a fused multiply-add = 2, as in the FLOP convention):
+# Headline FLOP model (coarse, fixed before any kernel was written): 15 FP32
+# operations per child-box slab test, 25 per ray-disk test. The roofline
+# fraction of the bench line is this model's FLOPs per launch over the launch
+# time, against the published FP32 vector peak.
+COARSE_OPS_BOX, COARSE_OPS_DISK = 15, 25
+
+
+def coarse_flops(cnt, stage, width):
+    return cnt[stage + "_nodes"] * width * COARSE_OPS_BOX + cnt[stage + "_disks"] * COARSE_OPS_DISK
+
+
+# Per-operation FP32 count of the kernels as written (add, mul, min, max,
+# compare = 1, a fused multiply-add = 2, as in the FLOP convention), reported
+# beside it against the non-packed peak:
 #   node visit, width W: W slab tests (per box 6 x (subtract, multiply),
 #     6 min/max per axis pair, 6 min/max to combine, 1 compare = 25) and the
 #     compares that order the entered children (1 for W = 2; sorting
@@ -46,14 +60,30 @@ OPS_DISK, OPS_DIFFUSE_PATH = 32, 60
 def ops_node(width):
     return 25 * width + ORDER_OPS[width]
 
-# HBM traffic of one k_diffuse launch, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE on this workload, scaled by the copy-kernel calibration (read x
-# 2.00, write x 1.00), together with the hash of the sources the measured
-# kernel was built from; reported only while the sources still match.
-TRAFFIC = {"kernel": "k_diffuse", "bytes": 1286390586,
-           "src_sha256": "0cc6208c7ccc0a9c0ae7360ace73cedfb90351c7a7e2dd23e1cb4acbeaaf006e"}
-TRAFFIC_SOURCES = ("paper_2507_04021_amd/csrc/common.h", "paper_2507_04021_amd/csrc/internal.h",
-                   "paper_2507_04021_amd/csrc/field.hip", "paper_2507_04021_amd/csrc/bvh.hip")
+# HBM traffic of one launch of each traversal kernel on this workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel
+# calibration (read x 2.00, write x 1.00), and its L2 hit rate (TCC_HIT /
+# (TCC_HIT + TCC_MISS)), with the hash of the sources the measured kernel was
+# built from; a figure is reported only while its sources still match.
+_CSRC = "paper_2507_04021_amd/csrc/"
+TRAFFIC = {
+    "k_diffuse": {"bytes": 1279440575, "l2_hit_rate": 0.982,
+                  "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "field.hip", "bvh.hip")),
+                  "src_sha256": "9492c4c02364d92c0717a6a4b75cc75e74a780ba3b93e31f1a6f734cb3c5ade4"},
+    "k_trace": {"bytes": 10653588321, "l2_hit_rate": 0.489,
+                "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "trace.hip", "bvh.hip")),
+                "src_sha256": "48d1c24a416061c4d8ed63fad9ad81d46478317aa0b920c8a984adab80be9a41"},
+    "k_refine": {"bytes": 10329979088, "l2_hit_rate": 0.493,
+                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "specular.hip", "bvh.hip")),
+                 "src_sha256": "5aae8cf40e1ec18ad8c4f9318c6a9057af8a2fa30f836bdc05ad5685c1644a02"},
+}
+
+
+def measured_traffic(kname):
+    t = TRAFFIC.get(kname)
+    if t and t["src_sha256"] == source_sha256(t["sources"]):
+        return t["bytes"], t["l2_hit_rate"]
+    return None, None
 
 
 def log(*a):
@@ -343,7 +373,9 @@ def mlp_workload(iters):
     materials (seed 7). 448 sets train the network through their recorded
     tapes (Adam, 8 sets per iteration), 64 are held out. Reports the held-out
     mean |dG| in dB for the nominal per-label Fresnel model (the method
-    without the learned part) and for the trained network, the training
+    without the learned part), for the per-label Fresnel model fitted
+    through the same tapes by the gradient kernels (300 Adam iterations of 8
+    sets), and for the trained network, the training
     iteration time, and the BF16 MFMA forward / backward kernels' throughput
     on 2^20 interaction rows."""
     import torch
@@ -377,23 +409,40 @@ def mlp_workload(iters):
         P.tape_fresnel(r, nominal)
         e_nom.append(M.db_error(P.tape_forward(r)[0], t))
     e_nom = float(torch.cat(e_nom).mean())
-    # kernel throughput on 2^20 rows (forward and backward MFMA GEMM chains)
-    n = 1 << 20
+    # the per-label Fresnel model fitted through the same tapes (the gradient kernels), judged the same way
+    t0 = time.perf_counter()
+    fitted, fit_hist = diff.fit_per_label(train_sets, nominal, iters=iters, batch=8, lr=0.05)
+    fit_s = time.perf_counter() - t0
+    e_fit = []
+    for r, f, t in held:
+        P.tape_fresnel(r, fitted)
+        e_fit.append(M.db_error(P.tape_forward(r)[0], t))
+    e_fit = float(torch.cat(e_fit).mean())
+    out = dict(workload="box room, 8 surface labels, 512 channel sets (256 at 3.5 GHz, 256 at 28 GHz), 1 TX + 8 RX "
+                        "each, %d rays, K=2, LOS+specular+diffuse; 448 train / 64 held out" % rays,
+               record_s=rec_s, train_iters=iters, train_iter_ms=iter_ms, loss_first=hist[0], loss_last=hist[-1],
+               heldout_db_error_nominal=e_nom, heldout_db_error_mlp=e_mlp, heldout_db_error_fitted_per_label=e_fit,
+               fitted_per_label_s=fit_s, fitted_loss_last=fit_hist[-1],
+               fitted_materials_max_rel_err=float(np.max(np.abs(fitted[:, :2] - truth[:, :2]) / truth[:, :2])))
+    out.update(mlp_kernels(net, 1 << 20, reps=5))
+    return out
+
+
+def mlp_kernels(net, n, reps):
+    """Throughput of the BF16 MFMA forward and backward kernels on n seeded
+    interaction rows (8 labels, 28 GHz)."""
+    import torch
     g = torch.Generator(device="cuda").manual_seed(3)
     lab = torch.randint(0, 8, (n,), device="cuda", generator=g).to(torch.int16)
     cs = torch.rand(n, device="cuda", generator=g)
     out = torch.empty(n, 8, device="cuda")
     g_out = torch.randn(n, 8, device="cuda", generator=g)
-    f_ms = timed(lambda: net.forward_rows(lab, cs, 28e9, out), 5)
-    b_ms = timed(lambda: net.backward_rows(lab, cs, 28e9, g_out), 5)
+    f_ms = timed(lambda: net.forward_rows(lab, cs, 28e9, out), reps)
+    b_ms = timed(lambda: net.backward_rows(lab, cs, 28e9, g_out), reps)
     # per row: forward 2 x (32x64 + 64x64 + 64x64 + 64x16) flops; backward =
     # forward recompute + input-gradient chain + weight gradients (3 x forward)
     fw = 2 * (32 * 64 + 64 * 64 + 64 * 64 + 64 * 16)
-    return dict(workload="box room, 8 surface labels, 512 channel sets (256 at 3.5 GHz, 256 at 28 GHz), 1 TX + 8 RX "
-                         "each, %d rays, K=2, LOS+specular+diffuse; 448 train / 64 held out" % rays,
-                record_s=rec_s, train_iters=iters, train_iter_ms=iter_ms, loss_first=hist[0], loss_last=hist[-1],
-                heldout_db_error_nominal=e_nom, heldout_db_error_mlp=e_mlp,
-                mlp_forward_ms_1M_rows=f_ms, mlp_backward_ms_1M_rows=b_ms,
+    return dict(mlp_forward_ms_1M_rows=f_ms, mlp_backward_ms_1M_rows=b_ms,
                 mlp_forward_tflops=fw * n / (f_ms / 1e3) / 1e12, mlp_backward_tflops=3 * fw * n / (b_ms / 1e3) / 1e12,
                 mfma_bf16_peak_tflops=2500.0)
 
@@ -410,7 +459,11 @@ def cpu_baseline(sc, rx, tx, mats, n_budget, K, n_sample):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=inter / dt, unit="rays·interactions/s", cores=cores, kind="oracle",
                 sample="%d stratified rays of 2^20 (all 64 RX, LOS+specular+diffuse, K=%d): %d interactions "
-                       "in %.1f s" % (n_sample, K, inter, dt), wall_s=dt)
+                       "in %.1f s" % (n_sample, K, inter, dt), wall_s=dt,
+                # the whole 2^20-ray solve at the sample's time per ray (approximate: the bounce loop and the
+                # diffuse connections scale with the rays; the specular refinement grows more slowly, since
+                # rays share keys)
+                extrapolated_full_solve_s=dt * n_budget / n_sample)
 
 
 def main():
@@ -427,6 +480,8 @@ def main():
     ap.add_argument("--cir-iters", type=int, default=5000, help="Adam iterations of the impulse-response learning (the paper runs 5000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and gradient workloads")
+    ap.add_argument("--mlp-kernels-only", action="store_true",
+                    help="only time the MLP forward / backward kernels on 2^20 rows (profiling)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates the profiler's byte counters)")
     args = ap.parse_args()
@@ -438,6 +493,11 @@ def main():
     import torch
     import paper_2507_04021_amd as P
 
+    if args.mlp_kernels_only:
+        from paper_2507_04021_amd import mlp as M
+        print(json.dumps(mlp_kernels(M.MaterialMLP(M.init_params(8, seed=0)), 1 << 20, reps=max(3, args.steps))),
+              flush=True)
+        return
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -491,11 +551,17 @@ def main():
     dom = max(("trace", "refine", "diffuse"), key=lambda k: stage_ms[k])
     kname = {"trace": "k_trace", "refine": "k_refine", "diffuse": "k_diffuse"}[dom]
     nbytes = algorithmic_bytes(ccnt, K, len(rx), dom, args.width)
-    flops = algorithmic_flops(ccnt, dom, args.width)
-    achieved = flops / (stage_ms[dom] / 1e3) / 1e12
-    traffic = None
-    if TRAFFIC and TRAFFIC["kernel"] == kname and TRAFFIC["src_sha256"] == source_sha256(TRAFFIC_SOURCES):
-        traffic = TRAFFIC["bytes"]
+    launch_s = stage_ms[dom] / 1e3
+    flops = coarse_flops(ccnt, dom, args.width)
+    achieved = flops / launch_s / 1e12
+    op_flops = algorithmic_flops(ccnt, dom, args.width)
+    traffic, l2_hit = measured_traffic(kname)
+    stage_traffic = {}
+    for st, kn in (("trace", "k_trace"), ("refine", "k_refine"), ("diffuse", "k_diffuse")):
+        b, h = measured_traffic(kn)
+        stage_traffic[st] = None if b is None else {
+            "bytes": b, "GBs": b / (stage_ms[st] / 1e3) / 1e9,
+            "hbm_frac": b / (stage_ms[st] / 1e3) / 1e9 / HBM_PEAK_GBS, "l2_hit_rate": h}
     log("visit counters:", {k: ccnt[k] for k in ccnt if "nodes" in k or "disks" in k})
 
     line = {
@@ -526,12 +592,25 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
+            "flop_model": "%d per child-box slab test, %d per ray-disk test (instrumented visit counts)"
+                          % (COARSE_OPS_BOX, COARSE_OPS_DISK),
             "algorithmic_flops_per_launch": flops,
-            "gathered_bytes_per_launch": nbytes,
-            "gather_GBs": nbytes / (stage_ms[dom] / 1e3) / 1e9,
             "launch_ms": stage_ms[dom],
+            # the kernels' own per-operation count against the non-packed FP32 rate
+            "op_count_flops_per_launch": op_flops,
+            "op_count_tflops": op_flops / launch_s / 1e12,
+            "op_count_frac_nonpacked": op_flops / launch_s / 1e12 / FP32_NONPACKED_PEAK_TFLOPS,
+            # HBM: measured bytes per launch (profiler counters) over the live launch time
+            "hbm_GBs": traffic / launch_s / 1e9 if traffic else None,
+            "hbm_frac": traffic / launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "l2_hit_rate": l2_hit,
+            # the bytes the walks gather (nodes, disks, records), served almost entirely by the caches
+            "gathered_bytes_per_launch": nbytes,
+            "gather_GBs_cache_served": nbytes / launch_s / 1e9,
         },
         "stage_ms": stage_ms,
+        # measured L2-to-memory traffic of each traversal kernel over its live launch time
+        "stage_traffic": stage_traffic,
         "bvh_build_ms": scene.info["build_ms"],
         "counts": {k: cnt[k] for k in ("rays", "interactions", "segments", "keys", "candidates", "specular",
                                        "diffuse", "tie_spill", "status")},

@@ -21,7 +21,7 @@ LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE, DPS_LAUNCH = 1, 2, 4, 8, 16, 32
 STAGES = ("init", "trace", "keys", "refine", "diffuse_order", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
            tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
-           diffuse_disks=14)
+           diffuse_disks=14, diffuse_occluded_nodes=15)
 KAPPA_NONE = 0xFFFFFFFF
 
 

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
     const float eps = A.thr.eps_self;
     const uint32_t n_groups = kRayChunk * K / kWave;  // groups of 64 records per chunk
     uint32_t n_seg = 0, n_vis = 0;
+    uint64_t n_occ_visits = 0;  // instrumented builds: node visits of occluded segments
     // Workgroups are dealt to the XCDs round robin, and each XCD has its own
     // L2: the wavefronts of XCD x take chunks from the x-th eighth of the
     // (Morton-ordered) chunk range first, so one XCD's L2 serves one region
@@ -189,7 +190,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
                     const int id = __float_as_int(p1.w);
                     const f3 x = xyz(p0), n = xyz(p1);
                     ++n_seg;
+                    const uint32_t nv0 = stk.nv;
                     const bool vis = !occluded<W>(A.S, rx, x, id, eps, stk);
+                    if (kCountVisits && !vis) n_occ_visits += stk.nv - nv0;
                     if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
                     if (vis) {
                         ++n_vis;
@@ -212,9 +215,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
     flush_visits(stk, A.counters, 13);
     n_seg = warp_sum_u(n_seg);
     n_vis = warp_sum_u(n_vis);
+    if (kCountVisits)
+        for (int o = 32; o > 0; o >>= 1) n_occ_visits += __shfl_xor(n_occ_visits, o, kWave);
     if (lane == 0) {
         atomicAdd((unsigned long long *)&A.counters[2], (unsigned long long)n_seg);
         atomicAdd((unsigned long long *)&A.counters[5], (unsigned long long)n_vis);
+        if (kCountVisits) atomicAdd((unsigned long long *)&A.counters[15], (unsigned long long)n_occ_visits);
     }
 }
 
