@@ -11,7 +11,7 @@ namespace pcrt {
 
 constexpr int kMaxK = 8;          // max interactions per path
 constexpr int kWave = 64;         // wavefront width
-constexpr int kStackLds = 24;     // traversal stack entries kept in LDS per lane (6 KiB per wavefront)
+constexpr int kStackLds = 23;     // traversal stack entries kept in LDS per lane (5.75 KiB per wavefront)
 constexpr int kStackMax = 96;     // max stack entries (LDS + global spill)
 constexpr int kRayChunk = 256;    // rays per diffuse reduction chunk (item ray ranges are padded to this);
                                    // office connections: 128 -> 30.3 ms, 256 -> 29.8, 512 -> 30.7

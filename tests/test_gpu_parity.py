@@ -389,10 +389,15 @@ def test_office_full_solve_specular_paths_at_scale(P, orc, office):
     g_sel = {k for k in gp if k[1] in sel}
     o_sel = {k for k in op if k[1] in sel}
     assert len(g_sel) >= 20
-    assert len(g_sel ^ o_sel) <= max(1, len(g_sel) // 100)
+    union = g_sel | o_sel
+    step("specular paths: %d gpu, %d oracle, %d in one set only" % (len(g_sel), len(o_sel), len(g_sel ^ o_sel)))
+    assert len(g_sel ^ o_sel) <= 0.001 * len(union)
+    k0 = 2 * math.pi * 28e9 / C0
     for k in g_sel & o_sel:
         assert abs(gp[k][0] - op[k][0]) <= 2e-6 * op[k][0]
-        assert abs(abs(gp[k][1]) - abs(op[k][1])) <= 1e-4 * abs(op[k][1])
+        # complex amplitude: 1e-4 plus the phase of a 4 um FP32 path-length error
+        for j in (1, 2):
+            assert abs(gp[k][j] - op[k][j]) <= (1e-4 + k0 * 4e-6) * abs(op[k][j])
 
 
 def test_office_full_size_properties(P, orc, office):
