@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcrt_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-LOS, SPECULAR, DIFFUSE, TRACE, AVERAGE, DPS_LAUNCH = 1, 2, 4, 8, 16, 32
+LOS, SPECULAR, DIFFUSE, TRACE, AVERAGE, DPS_LAUNCH, POLARIZED = 1, 2, 4, 8, 16, 32, 64
 DEFAULT_THR = dict(eps_tie=1e-4, eps_self=1e-3, t_a_deg=1.0, t_d=0.01, kappa=10)
 C0 = 299792458.0
 
@@ -180,7 +180,7 @@ class Solution:
 
 def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SPECULAR,
           thr=None, want_dvis=False, want_jac=False, cfr=None, average=None, dps_launch=None,
-          want_dpow=False) -> Solution:
+          want_dpow=False, pol=None) -> Solution:
     """Full FP64 solve for one transmitter. mats: float64[n_labels, 3] (eps_r, sigma, S).
 
     average = (rho, lambda_d): every interaction is the weighted average over
@@ -196,7 +196,12 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
 
     cfr = (bandwidth_hz, n_freq): also the channel frequency response, every
     path's centre-frequency amplitudes times exp(-j 2 pi (f_n - freq) L / c0)
-    at n_freq equally spaced frequencies f_n spanning bandwidth_hz around freq."""
+    at n_freq equally spaced frequencies f_n spanning bandwidth_hz around freq.
+
+    pol = (pol_tx, pol_rx): the polarised (Jones-vector) field of line-of-sight
+    and specular paths for these transmit and receive polarisation vectors;
+    every path's one complex amplitude is reported in both channels (no
+    diffuse paths, Jacobian or frequency response in this mode)."""
     th = dict(DEFAULT_THR)
     if thr:
         th.update(thr)
@@ -208,7 +213,11 @@ def solve(scene, mats, tx, rx, freq, n_budget, ray_ids=None, K=2, flags=LOS | SP
             raise ValueError("one voxel edge for averaging and launch")
         rho = float(np.float32(dps_launch))
         flags |= DPS_LAUNCH
-    thr_arr = np.array([th["eps_tie"], th["eps_self"], th["t_a_deg"], th["t_d"], th["kappa"], rho, lam], np.float64)
+    ptx, prx = (np.asarray(pol[0], np.float64), np.asarray(pol[1], np.float64)) if pol else (np.zeros(3), np.zeros(3))
+    if pol:
+        flags |= POLARIZED
+    thr_arr = np.array([th["eps_tie"], th["eps_self"], th["t_a_deg"], th["t_d"], th["kappa"], rho, lam,
+                        *ptx, *prx], np.float64)
     mats = np.ascontiguousarray(mats, np.float64).reshape(-1, 3)
     n_labels = mats.shape[0]
     eps_r = np.ascontiguousarray(mats[:, 0])

@@ -27,6 +27,8 @@
  *   - Field: Fresnel reflection from complex permittivity, scattering
  *     coefficient, free-space spreading (the paper delegates this to its EM
  *     back end; the readings used here are spelled out next to each function).
+ *     Two field models: the scalar TE and TM chains, or (ORC_POLARIZED) the
+ *     field vector carried through every reflection (Jones vectors).
  *
  * Everything is brute force: every query tests every disk. All arithmetic is
  * double precision; FP32 input arrays are promoted on entry. Parallelism is
@@ -55,7 +57,8 @@
 
 enum { ORC_LOS = 1, ORC_SPECULAR = 2, ORC_DIFFUSE = 4, ORC_TRACE = 8 /* trace even without paths */,
        ORC_AVERAGE = 16 /* weighted-average intersection over point sets */,
-       ORC_DPS_LAUNCH = 32 /* rays towards the reception points, visibility-gated specular candidates */ };
+       ORC_DPS_LAUNCH = 32 /* rays towards the reception points, visibility-gated specular candidates */,
+       ORC_POLARIZED = 64 /* Jones-vector field of line-of-sight and specular paths */ };
 
 typedef struct {
     int64_t n;
@@ -87,6 +90,12 @@ static double norm3(const double *a) { return sqrt(dot3(a, a)); }
 static void scale3(double *a, double s) { a[0] *= s; a[1] *= s; a[2] *= s; }
 static void copy3(double *d, const double *s) { d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; }
 static void from_f32(double *d, const float *s) { d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; }
+static void cross3(double *r, const double *a, const double *b)
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
 
 static int scene_init(scene_t *s, int64_t n, const float *pos, const float *nrm, const uint16_t *mat,
                       const uint32_t *surf, double r)
@@ -405,6 +414,69 @@ static void cfr_add(cfr_t *c, int r, double complex a_te, double complex a_tm, d
     }
 }
 
+/* Polarised field (Jones vectors; the paper takes its field from its EM back
+ * end, which carries the field vector). The transmitter radiates pol_tx
+ * projected on the plane normal to the departure direction (a short dipole);
+ * at each specular interaction, with incoming direction d_in, outgoing d_out
+ * and plane normal n, the field splits into its component along
+ * s = (d_in x n)/|d_in x n| (perpendicular to the plane of incidence: TE) and
+ * along p_in = s x d_in (in that plane: TM); the reflected field is
+ *   R (Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out),  p_out = s x d_out,
+ * which is the plane-wave relation E = Z H x k applied to the TM case, whose
+ * coefficient (fresnel() above) is that of the magnetic field along s. At
+ * normal incidence s is any unit vector normal to d_in (the result does not
+ * depend on it there, since Gamma_TM = -Gamma_TE). The receiver takes the
+ * projection of the arriving field on pol_rx projected on the plane normal
+ * to the arrival direction. x: k + 2 points (TX, interactions, RX), n: the k
+ * planes' normals. Returns the path's complex amplitude. */
+static void unit_normal_to(const double *d, double *s)
+{
+    const double ax[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    int best = 0;
+    for (int c = 1; c < 3; ++c)
+        if (fabs(d[c]) < fabs(d[best])) best = c;
+    cross3(s, d, ax[best]);
+    scale3(s, 1.0 / norm3(s));
+}
+
+static double complex path_polarized(const em_t *em, int k, const double x[][3], const double n[][3],
+                                     const int *label, double amp0, double len, const double *ptx,
+                                     const double *prx)
+{
+    double din[3], dout[3];
+    sub3(din, x[1], x[0]);
+    scale3(din, 1.0 / norm3(din));
+    double complex E[3];
+    const double pd = dot3(ptx, din);
+    for (int c = 0; c < 3; ++c) E[c] = ptx[c] - pd * din[c];
+    for (int m = 1; m <= k; ++m) {
+        sub3(dout, x[m + 1], x[m]);
+        scale3(dout, 1.0 / norm3(dout));
+        const double *nn = n[m - 1];
+        double complex gte, gtm;
+        fresnel(em, label[m - 1], fabs(dot3(din, nn)) / norm3(nn), &gte, &gtm, NULL, NULL);
+        const double S = em->scat[label[m - 1]], R = sqrt(fmax(0.0, 1.0 - S * S));
+        double s[3], pin[3], pout[3];
+        cross3(s, din, nn);
+        const double ns = norm3(s);
+        if (ns < 1e-12 * norm3(nn)) unit_normal_to(din, s);
+        else scale3(s, 1.0 / ns);
+        cross3(pin, s, din);
+        cross3(pout, s, dout);
+        double complex es = 0.0, ep = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            es += E[c] * s[c];
+            ep += E[c] * pin[c];
+        }
+        for (int c = 0; c < 3; ++c) E[c] = R * (gte * es * s[c] + gtm * ep * pout[c]);
+        copy3(din, dout);
+    }
+    const double pr = dot3(prx, din);
+    double complex a = 0.0;
+    for (int c = 0; c < 3; ++c) a += E[c] * (prx[c] - pr * din[c]);
+    return amp0 * a * cexp(-I * em->k0 * len);
+}
+
 /* ------------------------------------------------------ bounce loop (a4-a5) */
 typedef struct {
     int n;                 /* interactions recorded */
@@ -468,6 +540,7 @@ typedef struct {
     double x[ORC_KMAX + 2][3];
     double len;
     double cs[ORC_KMAX];
+    double n[ORC_KMAX][3]; /* the planes' normals the path was refined on */
 } spec_t;
 
 static int refine_on_planes(int k, const double *tx, const double *rx, double pp[][3], double pn[][3],
@@ -563,6 +636,7 @@ static void specular_one(const scene_t *s, const double *tx, const double *rx, i
             sub3(u, out->x[m], out->x[m - 1]);
             scale3(u, 1.0 / norm3(u));
             out->cs[m - 1] = fabs(dot3(u, pn[m - 1]));
+            copy3(out->n[m - 1], pn[m - 1]);
         }
         out->valid = 1;
         return;
@@ -720,9 +794,14 @@ static int key_cmp(const void *pa, const void *pb)
  * n_budget Fibonacci directions (the diffuse ray-tube weight always uses the
  * full budget).
  *
- * thr[7] = {eps_tie, eps_self, t_a (degrees), t_d, kappa, rho, lambda_d}; rho
- * (voxel edge of the point sets) and lambda_d (depth attenuation) are read
- * with ORC_AVERAGE only.
+ * thr[13] = {eps_tie, eps_self, t_a (degrees), t_d, kappa, rho, lambda_d,
+ * pol_tx (3), pol_rx (3)}; rho (voxel edge of the point sets) and lambda_d
+ * (depth attenuation) are read with ORC_AVERAGE / ORC_DPS_LAUNCH only, the
+ * polarisations with ORC_POLARIZED only. With ORC_POLARIZED every line-of-
+ * sight and specular path has one complex amplitude a (path_polarized),
+ * reported in both channels (a_TE = a_TM = a, so its power
+ * 1/2(|a_TE|^2 + |a_TM|^2) is |a|^2); diffuse paths, the Jacobian and the
+ * frequency response are refused (-1).
  *
  * Outputs (NULL = not wanted):
  *   seq      int64[n_trace*K]   hit disk per (ray, k), -1 after the ray ends
@@ -756,6 +835,9 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
     for (int64_t i = 0; i < n_pts; ++i)
         if (mat[i] >= (uint32_t)n_labels) { scene_free(&s); return -1; }
     thr_t th = {thr[0], thr[1], cos(thr[2] * ORC_PI / 180.0), thr[3], (int)thr[4]};
+    const int polarized = (flags & ORC_POLARIZED) != 0;
+    if (polarized && ((flags & ORC_DIFFUSE) || jac || out_cfr)) { scene_free(&s); return -1; }
+    const double *ptx = thr + 7, *prx = thr + 10;
     dps_t dps, *sets = NULL, *g = NULL; /* g: the sets when interactions are averaged */
     if (flags & (ORC_AVERAGE | ORC_DPS_LAUNCH)) {
         if (!(thr[5] > 0.0) || ((flags & ORC_AVERAGE) && !(thr[6] > 0.0))) { scene_free(&s); return -1; }
@@ -790,6 +872,12 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
             sub3(w, rx + 3 * r, tx);
             double d = norm3(w);
             double complex a = a_iso / d * cexp(-I * em.k0 * d);
+            if (polarized) {
+                double x2[2][3];
+                copy3(x2[0], tx);
+                copy3(x2[1], rx + 3 * r);
+                a = path_polarized(&em, 0, (const double(*)[3])x2, NULL, NULL, a_iso / d, d, ptx, prx);
+            }
             G_los[r] += 0.5 * (creal(a * conj(a)) * 2.0);
             h_te[r] += a;
             h_tm[r] += a;
@@ -1022,8 +1110,15 @@ int orc_solve(int64_t n_pts, const float *pos, const float *nrm, const uint16_t 
                             kind[m] = 0;
                         }
                         double g = 0.0;
-                        path_field(&em, uk[ki].len, label, p->cs, kind, a_iso / p->len, p->len, &ate, &atm, &g,
-                                   jac ? jac + (int64_t)r * n_labels * 3 : NULL);
+                        if (polarized) {
+                            ate = atm = path_polarized(&em, uk[ki].len, (const double(*)[3])p->x,
+                                                       (const double(*)[3])p->n, label, a_iso / p->len, p->len,
+                                                       ptx, prx);
+                            g = creal(ate * conj(ate));
+                        } else {
+                            path_field(&em, uk[ki].len, label, p->cs, kind, a_iso / p->len, p->len, &ate, &atm, &g,
+                                       jac ? jac + (int64_t)r * n_labels * 3 : NULL);
+                        }
                         G_spec[r] += g;
                         h_te[r] += ate;
                         h_tm[r] += atm;

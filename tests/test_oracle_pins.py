@@ -957,3 +957,206 @@ def test_diffraction_assembly_continuous_with_the_oracle_paths(orc, mat, phip_de
         go_jump = _side_limit(-d[::-1], go[:m]) - _side_limit(d, go[m:])
         assert abs(go_jump) > 1e-4
         assert abs(jump) <= 5e-3 * abs(go_jump), (abs(jump), abs(go_jump))
+
+
+# ------------------ polarised field (Jones vectors) of line-of-sight and specular paths
+POL_FLOOR = dict(x0=-3.0, x1=6.0, y0=-3.0, y1=3.0, spacing=0.05, radius=0.036)
+PEC = (1.0, 1e12, 0.0)  # conductivity high enough that 1/sqrt|eta| ~ 4e-7
+
+
+def _floor():
+    f = POL_FLOOR
+    return scenes.plane_patch(f["x0"], f["x1"], f["y0"], f["y1"], f["spacing"], f["radius"])
+
+
+def _unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v)
+
+
+def _transverse(p, d):
+    p = np.asarray(p, float)
+    return p - (p @ d) * d
+
+
+def _floor_path(orc, mat, tx, rx, pol, f=3.5e9, N=2000):
+    sol = orc.solve(_floor(), np.array([mat]), tx, [rx], f, N, K=1, flags=LOS | SPEC, pol=pol)
+    paths = sol.paths(0)
+    assert list(paths) == [(0,)]
+    L, ate, atm = paths[(0,)]
+    assert ate == atm  # one amplitude, reported in both channels
+    tx, rx = np.asarray(tx, float), np.asarray(rx, float)
+    img = tx * np.array([1, 1, -1])
+    assert abs(L - np.linalg.norm(rx - img)) < 1e-9
+    lam = C0 / f
+    # the amplitude over the scalar free-space factor of the unfolded path
+    return ate / (lam / (4 * math.pi) / L * np.exp(-2j * math.pi / lam * L)), sol
+
+
+@pytest.mark.parametrize("mat", [PEC, (5.0, 0.1, 0.0), (5.0, 0.1, 0.3)])
+@pytest.mark.parametrize("p", [(1, 0, 0), (0, 1, 0), (1, 1, 0), (1, 0, 1), (0.3, -0.8, 0.5)])
+def test_polarized_normal_incidence_scales_the_field_by_the_normal_coefficient(orc, mat, p):
+    """TX straight above RX over a flat floor: the specular path meets the floor
+    at normal incidence, where TE and TM are the same wave. The received field
+    is the transmitted one (transverse part of the dipole) times
+    (1 - sqrt eta) / (1 + sqrt eta) and R = sqrt(1 - S^2), whatever the
+    polarisation; for a conductor that is -1: the field reverses."""
+    tx, rx = [0.0, 0.0, 1.0], [0.0, 0.0, 2.0]
+    pol = (_unit(p), _unit(p))
+    ratio, sol = _floor_path(orc, mat, tx, rx, pol)
+    eta = mat[0] - 1j * mat[1] / (2 * math.pi * 3.5e9 * EPS0)
+    gamma = (1 - np.sqrt(eta)) / (1 + np.sqrt(eta))
+    d = np.array([0.0, 0.0, -1.0])
+    proj = _transverse(pol[0], d) @ _transverse(pol[1], d)
+    expect = math.sqrt(1 - mat[2] ** 2) * gamma * proj
+    assert abs(ratio - expect) < 1e-9 * max(1.0, abs(expect))
+    if mat is PEC and proj > 0.5:
+        assert abs(ratio / proj + 1.0) < 1e-5
+    # line of sight: the dipole pattern on both ends, free space in between
+    lam = C0 / 3.5e9
+    a_los = lam / (4 * math.pi) * np.exp(-2j * math.pi / lam) * proj
+    assert abs(sol.G_los[0] - abs(a_los) ** 2) < 1e-12 * abs(a_los) ** 2 + 1e-30
+
+
+@pytest.mark.parametrize("mat", [(5.0, 0.1, 0.0), (2.5, 0.02, 0.3), (6.3, 0.3, 0.0)])
+@pytest.mark.parametrize("rx_x", [2.0, 3.5, 0.75])
+def test_polarized_oblique_te_and_tm_from_boundary_conditions(orc, mat, rx_x):
+    """One oblique bounce in the x-z plane. TE: dipoles along y (normal to the
+    plane of incidence) receive Gamma_TE of the tangential-field boundary
+    conditions. TM: vertical dipoles; the incident magnetic field points along
+    d_in x E_0 and is scaled by the magnetic-field coefficient of the same
+    boundary conditions, and the reflected electric field is H x d_out
+    (plane wave, E = Z H x k)."""
+    tx, rx = np.array([0.0, 0.0, 1.0]), np.array([rx_x, 0.0, 1.0])
+    xr = np.array([rx_x / 2, 0.0, 0.0])  # reflection point (equal heights)
+    din, dout = _unit(xr - tx), _unit(rx - xr)
+    c = abs(din[2])
+    te_bc, tm_bc = fresnel_bc(mat[0], mat[1], 3.5e9, c)
+    R = math.sqrt(1 - mat[2] ** 2)
+    y = np.array([0.0, 1.0, 0.0])
+    ratio_te, _ = _floor_path(orc, mat, tx, rx, (y, y))
+    assert abs(ratio_te - R * te_bc) < 1e-9
+    z = np.array([0.0, 0.0, 1.0])
+    ratio_tm, _ = _floor_path(orc, mat, tx, rx, (z, z))
+    e0 = _transverse(z, din)
+    e_ref = R * tm_bc * np.cross(np.cross(din, e0), dout)
+    expect = e_ref @ _transverse(z, dout)
+    assert abs(ratio_tm - expect) < 1e-9 * max(1.0, abs(expect))
+
+
+def test_polarized_brewster_angle_reflects_no_tm(orc):
+    """Lossless floor (eps_r = 4) at the Brewster angle atan 2: the vertical
+    dipoles' TM wave is not reflected, the TE wave is."""
+    tx, rx = [0.0, 0.0, 1.0], [4.0, 0.0, 1.0]
+    mat = (4.0, 0.0, 0.0)
+    z, y = np.array([0.0, 0.0, 1.0]), np.array([0.0, 1.0, 0.0])
+    r_tm, _ = _floor_path(orc, mat, tx, rx, (z, z))
+    r_te, _ = _floor_path(orc, mat, tx, rx, (y, y))
+    assert abs(r_tm) < 1e-12 and abs(r_te) > 0.3
+
+
+@pytest.mark.parametrize("rx", [(2.0, 0.0, 1.0), (3.0, 1.0, 0.5), (0.4, -0.3, 2.5)])
+def test_polarized_conductor_cancels_the_tangential_field(orc, rx):
+    """On a conductor the tangential electric field vanishes: for any incident
+    polarisation, the incident field plus the reflected one (read back as its
+    x, y, z components through three receive polarisations) has no component
+    in the floor's plane, and the reflected field is transverse to d_out."""
+    tx = np.array([0.0, 0.0, 1.0])
+    rx = np.asarray(rx, np.float32).astype(float)
+    ex = np.eye(3)
+    for p in ([1, 0, 0], [0, 1, 0], [0, 0, 1], [0.5, -0.2, 0.8]):
+        e_k = np.array([_floor_path(orc, PEC, tx, rx, (_unit(p), ex[c]))[0] for c in range(3)])
+        t = rx[2] / (tx[2] + rx[2])
+        xr = rx + t * (tx * np.array([1, 1, -1]) - rx)  # where the unfolded line meets z = 0
+        din, dout = _unit(xr - tx), _unit(rx - xr)
+        e0 = _transverse(_unit(p), din)
+        tot = e0 + e_k
+        assert np.abs(tot[:2]).max() < 1e-5 * np.linalg.norm(e0)
+        assert abs(e_k @ dout) < 1e-9
+
+
+def test_polarized_conducting_room_paths_are_mirror_images(orc, room_holefree):
+    """All-conducting hole-free room, paths up to two reflections: a conductor
+    maps a field E to 2 (E.n) n - E (tangential part reversed, normal part
+    kept), so every path's field is the product of those mirror maps over its
+    walls, applied to the transmit dipole's transverse field; the received
+    amplitude is its projection on the receive dipole. Paths come from the
+    image method on the exact planes."""
+    f = 3.5e9
+    lam = C0 / f
+    mats = np.tile(PEC, (4, 1))
+    p_tx, p_rx = _unit([0.3, 0.5, 0.8]), _unit([-0.6, 0.2, 0.7])
+    sol = orc.solve(room_holefree, mats, scenes.BOX_TX, [scenes.BOX_RX], f, 20000, K=2, flags=SPEC,
+                    pol=(p_tx, p_rx))
+    got = sol.paths(0)
+    face_of = {0: 0, 1: 1, 2: 2, 3: 3, 4: 4, 5: 5, 6: scenes.BOX_WINDOW["face"], 7: scenes.BOX_DOOR["face"]}
+    tx = np.asarray(scenes.BOX_TX, np.float32).astype(float)
+    rx = np.asarray(scenes.BOX_RX, np.float32).astype(float)
+    checked = 0
+    for key, (L, ate, atm) in got.items():
+        faces = [face_of[s] for s in key]
+        imgs = [tx]
+        for fc in faces:
+            ax, val = FACE_PLANE[fc]
+            q = imgs[-1].copy()
+            q[ax] = 2 * val - q[ax]
+            imgs.append(q)
+        pts = [None] * (len(faces) + 2)
+        pts[0], pts[-1] = tx, rx
+        cur = rx
+        for m in range(len(faces), 0, -1):
+            ax, val = FACE_PLANE[faces[m - 1]]
+            seg = imgs[m] - cur
+            cur = cur + (val - cur[ax]) / seg[ax] * seg
+            pts[m] = cur
+        assert abs(L - np.linalg.norm(rx - imgs[-1])) < 1e-9
+        e = _transverse(p_tx, _unit(pts[1] - pts[0]))
+        for fc in faces:
+            n = np.zeros(3)
+            n[FACE_PLANE[fc][0]] = 1.0
+            e = 2 * (e @ n) * n - e
+        a_exp = lam / (4 * math.pi) / L * np.exp(-2j * math.pi / lam * L) * (
+            e @ _transverse(p_rx, _unit(pts[-1] - pts[-2])))
+        assert ate == atm
+        assert abs(ate - a_exp) < 1e-5 * np.linalg.norm(e) * lam / (4 * math.pi) / L
+        checked += 1
+    assert checked >= 20
+
+
+def test_polarized_two_lossy_bounces_keep_te_and_tm_apart(orc):
+    """Floor (z = 0) then ceiling (z = 2), lossy and different, with TX and RX
+    in the plane y = 0: both planes of incidence are that plane, so a wave
+    normal to it stays TE (Gamma_TE of each bounce, from the boundary
+    conditions, multiplies) and vertical dipoles stay TM, the magnetic-field
+    relation of the single bounce applied at each reflection with complex
+    fields in between."""
+    f = 3.5e9
+    lam = C0 / f
+    floor = scenes.plane_patch(-1.0, 5.0, -2.0, 2.0, 0.05, 0.036, z=0.0, material=0, surface=0)
+    ceil = scenes.plane_patch(-1.0, 5.0, -2.0, 2.0, 0.05, 0.036, z=2.0, material=1, surface=1)
+    sc = scenes.concat([floor, ceil])
+    mats = np.array([[5.0, 0.1, 0.2], [3.0, 0.5, 0.0]])
+    tx, rx = np.array([0.0, 0.0, 0.5]), np.array([3.0, 0.0, 1.5])
+    i1 = tx * np.array([1, 1, -1])           # image in the floor
+    i2 = np.array([i1[0], i1[1], 4.0 - i1[2]])  # then in the ceiling
+    p2 = rx + (2.0 - rx[2]) / (i2[2] - rx[2]) * (i2 - rx)
+    p1 = p2 + (0.0 - p2[2]) / (i1[2] - p2[2]) * (i1 - p2)
+    d0, d1, d2 = _unit(p1 - tx), _unit(p2 - p1), _unit(rx - p2)
+    L = np.linalg.norm(rx - i2)
+    base = lam / (4 * math.pi) / L * np.exp(-2j * math.pi / lam * L)
+    R1 = math.sqrt(1 - 0.2 ** 2)
+    te1, tm1 = fresnel_bc(5.0, 0.1, f, abs(d0[2]))
+    te2, tm2 = fresnel_bc(3.0, 0.5, f, abs(d1[2]))
+    y, z = np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    for pol, expect in (((y, y), R1 * te1 * te2),):
+        sol = orc.solve(sc, mats, tx, [rx], f, 4000, K=2, flags=SPEC, pol=pol)
+        L_got, a, _ = sol.paths(0)[(0, 1)]
+        assert abs(L_got - L) < 1e-9
+        assert abs(a / base - expect) < 1e-9
+    e0 = _transverse(z, d0)
+    e1 = R1 * tm1 * np.cross(np.cross(d0, e0), d1)
+    e2 = tm2 * np.cross(np.cross(d1, e1), d2)
+    sol = orc.solve(sc, mats, tx, [rx], f, 4000, K=2, flags=SPEC, pol=(z, z))
+    _, a, _ = sol.paths(0)[(0, 1)]
+    expect = e2 @ _transverse(z, d2)
+    assert abs(a / base - expect) < 1e-9 * max(1.0, abs(expect))
