@@ -74,7 +74,7 @@ TRAFFIC = {
                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "trace.hip", "bvh.hip")),
                 "src_sha256": "48d1c24a416061c4d8ed63fad9ad81d46478317aa0b920c8a984adab80be9a41"},
     "k_refine": {"bytes": 10329979088, "l2_hit_rate": 0.493,
-                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "specular.hip", "bvh.hip")),
+                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "refine.h", "specular.hip", "bvh.hip")),
                  "src_sha256": "5aae8cf40e1ec18ad8c4f9318c6a9057af8a2fa30f836bdc05ad5685c1644a02"},
 }
 

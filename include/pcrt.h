@@ -187,7 +187,24 @@ enum {
      * With PCRT_DIFFUSE, diffuse paths are deduplicated per voxel, each an
      * area rho^2 (Sec. II-B.4); PCRT_DIFFUSE together with PCRT_RECORD is
      * refused (EUNSUPPORTED: no tape of those paths), as are batches. */
-    PCRT_DPS_LAUNCH = 64
+    PCRT_DPS_LAUNCH = 64,
+    /* Polarised field (Jones vectors) of line-of-sight and specular paths, for
+     * the field the paper takes from its EM back end: the transmitter radiates
+     * pol_tx projected on the plane normal to the departure direction (a short
+     * dipole); at every reflection the field splits into its components
+     * normal to the plane of incidence (s = d_in x n / |d_in x n|, TE) and in
+     * it (p_in = s x d_in, TM) and leaves as
+     *   R (Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out),  p_out = s x d_out
+     * (R = sqrt(1 - S^2)); the receiver takes the arriving field's projection
+     * on pol_rx projected on the plane normal to the arrival direction. Each
+     * path then has one complex amplitude a, reported in both channels
+     * (a_TE = a_TM = a, as line of sight is in the scalar model): G = sum |a|^2
+     * and h_te = h_tm = sum a; a PCRT_RECORD solve's path list
+     * (pcrt_paths_copy) carries a in both amplitude pairs. PCRT_DIFFUSE is
+     * refused with it, and so are the tape calls on such a solve
+     * (EUNSUPPORTED: the tape holds the scalar model); pol_tx and pol_rx must
+     * be finite (EINVAL). */
+    PCRT_POLARIZED = 128
 };
 
 /* One transmitter. rx: device float[n_rx][3]. n_rays: ray budget N (Fibonacci
@@ -211,6 +228,8 @@ typedef struct {
     uint32_t wave_rays; /* rays a wavefront takes per work fetch, multiple of 64 up to 1024 (0 = 64) */
     float lambda_d;     /* depth attenuation of PCRT_AVERAGE, 1/m (0 = 100) */
     const uint8_t *dps_vis; /* PCRT_DPS_LAUNCH: device uint8[n_rx][n_point_sets] from pcrt_visibility for rx */
+    float pol_tx[3];        /* PCRT_POLARIZED: transmit and receive polarisation vectors (any length; */
+    float pol_rx[3];        /* the amplitude scales with both) */
 } pcrt_solve_params;
 
 /* Outputs (device pointers; NULL = not wanted unless marked required).

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcrt.so")
 LIB_COUNT_PATH = os.path.join(_HERE, "libpcrt_count.so")  # measurement build with visit counters
 
-LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE, DPS_LAUNCH = 1, 2, 4, 8, 16, 32, 64
+LOS, SPECULAR, DIFFUSE, RECORD, TIMING, AVERAGE, DPS_LAUNCH, POLARIZED = 1, 2, 4, 8, 16, 32, 64, 128
 STAGES = ("init", "trace", "keys", "refine", "diffuse_order", "diffuse", "los_combine")
 CNT = dict(interactions=0, rays=1, segments=2, keys=3, specular=4, diffuse=5, status=6, candidates=7,
            tie_spill=8, trace_nodes=9, trace_disks=10, refine_nodes=11, refine_disks=12, diffuse_nodes=13,
@@ -62,7 +62,8 @@ class SolveParams(ctypes.Structure):
                 ("freq_hz", ctypes.c_double), ("n_rays", ctypes.c_uint32), ("max_interactions", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("ray_subset", ctypes.c_void_p), ("n_subset", ctypes.c_uint32),
                 ("thr", Thresholds), ("key_capacity", ctypes.c_uint32), ("wave_rays", ctypes.c_uint32),
-                ("lambda_d", ctypes.c_float), ("dps_vis", ctypes.c_void_p)]
+                ("lambda_d", ctypes.c_float), ("dps_vis", ctypes.c_void_p), ("pol_tx", ctypes.c_float * 3),
+                ("pol_rx", ctypes.c_float * 3)]
 
 
 class Edge(ctypes.Structure):
@@ -387,12 +388,14 @@ def make_params(tx, rx_t, freq, n_rays, K, flags, subset_t=None, thr=None, key_c
 
 def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, ray_subset=None, thr=None,
           want_seq=False, stream=None, ws=None, out=None, key_capacity=0, wave_rays=0,
-          lambda_d=0.0, dps_vis=None) -> SolveResult:
+          lambda_d=0.0, dps_vis=None, pol=None) -> SolveResult:
     """One transmitter against all receivers. mats: (n_labels, 3) or a device tensor from materials_tensor.
     flags with AVERAGE: point-set averaged interactions (scene built with dps_voxel > 0), depth
     attenuation lambda_d (0 = 100 per metre). flags with DPS_LAUNCH: one ray per point set towards its
     reception point (n_rays = the scene's n_point_sets) and specular candidates gated by dps_vis
-    (the uint8[n_rx, n_point_sets] tensor from visibility() for the same receivers)."""
+    (the uint8[n_rx, n_point_sets] tensor from visibility() for the same receivers).
+    pol = (pol_tx, pol_rx): the polarised (Jones-vector) field of line-of-sight and specular paths for
+    these transmit and receive polarisation vectors (sets POLARIZED)."""
     torch = _torch()
     L = lib(scene._variant)
     dev = scene.device
@@ -405,7 +408,12 @@ def solve(scene: Scene, mats, tx, rx, freq, n_rays, K=2, flags=LOS | SPECULAR, r
                      else ray_subset, torch.int32, dev)
     if dps_vis is not None:
         dps_vis = dps_vis.contiguous()
+    if pol is not None:
+        flags |= POLARIZED
     p = make_params(tx, rx_t, freq, n_rays, K, flags, sub_t, thr, key_capacity, wave_rays, lambda_d, dps_vis)
+    if pol is not None:
+        p.pol_tx[:] = [float(v) for v in np.asarray(pol[0], np.float32).reshape(3)]
+        p.pol_rx[:] = [float(v) for v in np.asarray(pol[1], np.float32).reshape(3)]
     nbytes = ctypes.c_size_t(0)
     _check(L.pcrt_solve_workspace_size(scene.handle, ctypes.byref(p), ctypes.byref(nbytes)), L)
     if ws is None or ws.numel() < nbytes.value:

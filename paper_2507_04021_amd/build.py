@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libpcrt.so")
 # same sources with node-visit / disk-test counters compiled in (measurement only)
 LIB_COUNT = os.path.join(HERE, "libpcrt_count.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["api.cpp", "bvh.hip", "trace.hip", "specular.hip", "field.hip", "tape.hip", "mlp.hip", "sort.hip", "dps.hip", "visibility.hip", "diffraction.hip"]
+SOURCES = ["api.cpp", "bvh.hip", "trace.hip", "specular.hip", "specular_pol.hip", "field.hip", "tape.hip", "mlp.hip", "sort.hip", "dps.hip", "visibility.hip", "diffraction.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -133,6 +133,13 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     uint64_t nt = p->ray_subset ? p->n_subset : p->n_rays;
     if (nt * p->max_interactions > 0x7fffffffull) return fail(PCRT_EUNSUPPORTED, "too many rays x interactions");
     if ((uint64_t)p->n_rx > kMaxPairs) return fail(PCRT_EUNSUPPORTED, "too many receivers");
+    if (p->flags & PCRT_POLARIZED) {
+        if (p->flags & PCRT_DIFFUSE)
+            return fail(PCRT_EUNSUPPORTED, "PCRT_POLARIZED covers line-of-sight and specular paths");
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(p->pol_tx[c]) || !std::isfinite(p->pol_rx[c]))
+                return fail(PCRT_EINVAL, "pol_tx and pol_rx must be finite");
+    }
     if ((p->flags & PCRT_AVERAGE) && !sc->dev.dps_pt)
         return fail(PCRT_EINVAL, "PCRT_AVERAGE needs a scene built with dps_voxel > 0");
     if (!(p->lambda_d >= 0.f) || !std::isfinite(p->lambda_d)) return fail(PCRT_EINVAL, "lambda_d must be >= 0");
@@ -267,6 +274,10 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.n_labels = n_labels;
     A.n_surf1 = sc->info.n_surfaces + 1;
     A.flags = p->flags;
+    if (p->flags & PCRT_POLARIZED) {
+        A.pol_tx = {p->pol_tx[0], p->pol_tx[1], p->pol_tx[2]};
+        A.pol_rx = {p->pol_rx[0], p->pol_rx[1], p->pol_rx[2]};
+    }
     A.dps_vis = (p->flags & PCRT_DPS_LAUNCH) ? p->dps_vis : nullptr;
     if ((p->flags & PCRT_DPS_LAUNCH) && (p->flags & PCRT_DIFFUSE)) {
         A.rb.dslot = (uint32_t *)at(L.rec_dslot);
@@ -978,6 +989,8 @@ static pcrt_status tape_args(const pcrt_scene *scene, const pcrt_solve_params *p
     pcrt_status st = check_params(scene, p);
     if (st) return st;
     if (!(p->flags & PCRT_RECORD)) return fail(PCRT_EINVAL, "the tape needs a solve with PCRT_RECORD");
+    if (p->flags & PCRT_POLARIZED)
+        return fail(PCRT_EUNSUPPORTED, "the tape evaluates the scalar TE/TM field, not PCRT_POLARIZED");
     if (!ws) return fail(PCRT_EINVAL, "ws is required");
     *P = make_plan(scene, p);
     st = plan_check(*P);

@@ -647,6 +647,49 @@ __device__ __forceinline__ c32 propagate(float L, float inv_lam_hi, float inv_la
     return {c, -s};
 }
 
+// Polarised field (Jones vectors): a complex 3-vector carried along a path.
+// The transmitter radiates its polarisation vector projected on the plane
+// normal to the departure direction; a reflection (incoming di, outgoing
+// dout, plane normal n) splits the field along s = di x n / |di x n| (TE) and
+// p_in = s x di (TM) and sends R (Gamma_TE (E.s) s + Gamma_TM (E.p_in) p_out),
+// p_out = s x dout; the receiver projects on its polarisation vector
+// projected on the plane normal to the arrival direction. At normal
+// incidence s is any unit vector normal to di: Gamma_TM = -Gamma_TE there, so
+// the result does not depend on the choice.
+struct cv3 {
+    c32 x, y, z;
+};
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 transverse(f3 p, f3 d) { return p - dot(p, d) * d; }
+__device__ __forceinline__ cv3 pol_launch(f3 p, f3 d) {
+    const f3 t = transverse(p, d);
+    return {{t.x, 0.f}, {t.y, 0.f}, {t.z, 0.f}};
+}
+__device__ __forceinline__ c32 cdot(const cv3 &e, f3 v) {
+    return {e.x.re * v.x + e.y.re * v.y + e.z.re * v.z, e.x.im * v.x + e.y.im * v.y + e.z.im * v.z};
+}
+__device__ __forceinline__ void pol_reflect(cv3 &e, f3 di, f3 dout, f3 n, c32 gte, c32 gtm, float R) {
+    f3 s = cross(di, n);
+    const float ns = len(s);
+    if (ns > 1e-6f) {
+        s = (1.0f / ns) * s;
+    } else {  // normal incidence: the axis least aligned with di, crossed with it
+        const f3 ax = fabsf(di.x) <= fabsf(di.y) && fabsf(di.x) <= fabsf(di.z) ? mk(1.f, 0.f, 0.f)
+                      : fabsf(di.y) <= fabsf(di.z)                         ? mk(0.f, 1.f, 0.f)
+                                                                           : mk(0.f, 0.f, 1.f);
+        s = normalize(cross(di, ax));
+    }
+    const f3 pin = cross(s, di), pout = cross(s, dout);
+    const c32 a = cmul({R * gte.re, R * gte.im}, cdot(e, s));
+    const c32 b = cmul({R * gtm.re, R * gtm.im}, cdot(e, pin));
+    e.x = {a.re * s.x + b.re * pout.x, a.im * s.x + b.im * pout.x};
+    e.y = {a.re * s.y + b.re * pout.y, a.im * s.y + b.im * pout.y};
+    e.z = {a.re * s.z + b.re * pout.z, a.im * s.z + b.im * pout.z};
+}
+__device__ __forceinline__ c32 pol_receive(const cv3 &e, f3 p, f3 d) { return cdot(e, transverse(p, d)); }
+
 struct FieldConst {
     float amp_iso;      // lambda / (4 pi)
     float inv_lam_hi;   // 1/lambda, high part

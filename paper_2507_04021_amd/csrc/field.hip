@@ -350,7 +350,11 @@ __global__ __launch_bounds__(kWave) void k_los(LaunchArgs A) {
     }
     const float d = len(rx - tx);
     const c32 ph = propagate(d, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
-    const float a0 = A.fc.amp_iso / d;
+    float a0 = A.fc.amp_iso / d;
+    if (A.flags & PCRT_POLARIZED) {  // the two dipoles' transverse parts
+        const f3 u = (1.0f / d) * (rx - tx);
+        a0 *= dot(transverse(A.pol_tx, u), transverse(A.pol_rx, u));
+    }
     const double ar = a0 * ph.re, ai = a0 * ph.im;
     o[0] = ar * ar + ai * ai;
     o[1] = ar;

@@ -162,6 +162,7 @@ struct LaunchArgs {
     HashBufs hb;
     SpecBufs sb;
     uint32_t wave_rays; // rays a wavefront takes per work fetch (multiple of 64)
+    f3 pol_tx, pol_rx;  // polarised field: transmit and receive polarisation vectors
     const uint8_t *dps_vis;  // launch at the reception points: [n_rx][n_sets] receiver sees reception point
     HashBufs dhb;            // ... and its voxel diffuse keys (labels before the last interaction, last set)
     uint32_t *dkeylist, *dkey_off, *dchunk_off;
@@ -198,6 +199,7 @@ __device__ __forceinline__ f3 record_normal(const LaunchArgs &A, uint32_t ri) {
 void launch_trace(const LaunchArgs &A, hipStream_t s);
 void launch_keys(const LaunchArgs &A, hipStream_t s);
 void launch_refine(const LaunchArgs &A, hipStream_t s);
+void launch_refine_pol(const LaunchArgs &A, dim3 grid, hipStream_t s);  // PCRT_POLARIZED instances
 // Morton order of the interaction records: sorts them, fills A.dsort.pack and
 // returns the sorted record indices
 const uint32_t *launch_diffuse_order(const LaunchArgs &A, hipStream_t s);
