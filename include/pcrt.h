@@ -185,8 +185,9 @@ enum {
      * the receiver sees the reception point of the set the key's
      * representative ray ends in. Needs point sets and dps_vis (EINVAL).
      * With PCRT_DIFFUSE, diffuse paths are deduplicated per voxel, each an
-     * area rho^2 (Sec. II-B.4); PCRT_DIFFUSE together with PCRT_RECORD is
-     * refused (EUNSUPPORTED: no tape of those paths), as are batches. */
+     * area rho^2 (Sec. II-B.4); with PCRT_RECORD the tape covers them (gains
+     * and material gradients; pcrt_diffuse_vis_copy and the frequency-response
+     * calls refuse such a solve: EUNSUPPORTED). Batches are refused. */
     PCRT_DPS_LAUNCH = 64,
     /* Polarised field (Jones vectors) of line-of-sight and specular paths, for
      * the field the paper takes from its EM back end: the transmitter radiates

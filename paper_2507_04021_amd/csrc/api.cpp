@@ -145,8 +145,6 @@ pcrt_status check_params(const pcrt_scene *sc, const pcrt_solve_params *p) {
     if (!(p->lambda_d >= 0.f) || !std::isfinite(p->lambda_d)) return fail(PCRT_EINVAL, "lambda_d must be >= 0");
     if (p->flags & PCRT_DPS_LAUNCH) {
         if (!sc->dev.dps_pt) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs a scene built with dps_voxel > 0");
-        if ((p->flags & PCRT_DIFFUSE) && (p->flags & PCRT_RECORD))
-            return fail(PCRT_EUNSUPPORTED, "PCRT_DPS_LAUNCH keeps no tape of its diffuse paths");
         if (p->n_rays != sc->info.n_point_sets) return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH: n_rays must be n_point_sets");
         if ((p->flags & (PCRT_SPECULAR | PCRT_DIFFUSE)) && !p->dps_vis)
             return fail(PCRT_EINVAL, "PCRT_DPS_LAUNCH needs dps_vis");
@@ -321,7 +319,10 @@ LaunchArgs make_args(const pcrt_scene *sc, const pcrt_material *mats, uint32_t n
     A.spec_ovr = ((p->flags & PCRT_SPECULAR) && (p->flags & PCRT_AVERAGE)) ? (float4 *)at(L.spec_ovr) : nullptr;
     A.diff_part = (double *)at(L.diff_part);
     A.los_part = (double *)at(L.los_part);
-    A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE)) ? (uint8_t *)at(L.dvis) : nullptr;
+    A.dvis = ((p->flags & PCRT_RECORD) && (p->flags & PCRT_DIFFUSE) && !(p->flags & PCRT_DPS_LAUNCH))
+                 ? (uint8_t *)at(L.dvis)
+                 : nullptr;
+    A.dps_area = sc->info.dps_voxel * sc->info.dps_voxel;
     if (p->flags & PCRT_DIFFUSE) {
         A.dsort.key0 = (uint64_t *)at(L.dkey0);
         A.dsort.key1 = (uint64_t *)at(L.dkey1);
@@ -370,7 +371,7 @@ SolveLayout solve_layout(const SolveDims &D, uint32_t flags) {
         L.rec_coef = b.take(sizeof(float4) * nrec);
         L.dpack = b.take(2 * sizeof(float4) * nrec);
         L.diff_part = b.take(sizeof(double) * 5 * (size_t)D.n_ray_chunks * D.n_rx);
-        if (rec) L.dvis = b.take(nrec * D.n_rx);
+        if (rec && !(flags & PCRT_DPS_LAUNCH)) L.dvis = b.take(nrec * D.n_rx);  // ray-tube connections only
         if (flags & PCRT_DPS_LAUNCH) {  // voxel diffuse keys of the reception-point launch
             const size_t cap = dps_key_cap(D);
             L.rec_dslot = b.take(sizeof(uint32_t) * nrec);
@@ -974,6 +975,8 @@ pcrt_status pcrt_diffuse_vis_copy(const pcrt_scene *scene, const pcrt_solve_para
     if (st) return st;
     if (!(p->flags & PCRT_RECORD) || !(p->flags & PCRT_DIFFUSE))
         return fail(PCRT_EINVAL, "visibility needs a solve with RECORD and DIFFUSE");
+    if (p->flags & PCRT_DPS_LAUNCH)
+        return fail(PCRT_EUNSUPPORTED, "the reception-point launch gates its diffuse paths by the visibility matrix");
     if (!ws || !vis) return fail(PCRT_EINVAL, "ws and vis are required");
     Plan P = make_plan(scene, p);
     st = plan_check(P);
@@ -1058,6 +1061,8 @@ pcrt_status pcrt_tape_cfr(const pcrt_scene *scene, const pcrt_solve_params *p, v
     Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
+    if ((p->flags & PCRT_DPS_LAUNCH) && (p->flags & PCRT_DIFFUSE))
+        return fail(PCRT_EUNSUPPORTED, "frequency responses of the voxel diffuse paths are not kept");
     if (!cfr) return fail(PCRT_EINVAL, "cfr is required");
     if (n_freq == 0 || n_freq > 65535) return fail(PCRT_EINVAL, "n_freq must be in 1..65535");
     if (!(bandwidth_hz >= 0.0) || !std::isfinite(bandwidth_hz)) return fail(PCRT_EINVAL, "bandwidth_hz must be >= 0");
@@ -1072,6 +1077,8 @@ pcrt_status pcrt_tape_cfr_backward(const pcrt_scene *scene, const pcrt_solve_par
     Plan P{};  // every field zero until set
     pcrt_status st = tape_args(scene, p, ws, &A, &P);
     if (st) return st;
+    if ((p->flags & PCRT_DPS_LAUNCH) && (p->flags & PCRT_DIFFUSE))
+        return fail(PCRT_EUNSUPPORTED, "frequency responses of the voxel diffuse paths are not kept");
     if (!dL_dcfr) return fail(PCRT_EINVAL, "dL_dcfr is required");
     if (n_freq == 0 || n_freq > 65535) return fail(PCRT_EINVAL, "n_freq must be in 1..65535");
     if (!(bandwidth_hz >= 0.0) || !std::isfinite(bandwidth_hz)) return fail(PCRT_EINVAL, "bandwidth_hz must be >= 0");

@@ -163,6 +163,7 @@ struct LaunchArgs {
     SpecBufs sb;
     uint32_t wave_rays; // rays a wavefront takes per work fetch (multiple of 64)
     f3 pol_tx, pol_rx;  // polarised field: transmit and receive polarisation vectors
+    float dps_area;     // point sets: the area rho^2 a voxel diffuse path stands for
     const uint8_t *dps_vis;  // launch at the reception points: [n_rx][n_sets] receiver sees reception point
     HashBufs dhb;            // ... and its voxel diffuse keys (labels before the last interaction, last set)
     uint32_t *dkeylist, *dkey_off, *dchunk_off;

@@ -153,6 +153,61 @@ __global__ __launch_bounds__(256) void k_tape_diffuse(LaunchArgs A) {
     }
 }
 
+// Geometry of a voxel diffuse path of the reception-point launch
+// (representative record ri, receiver r): gated by the visibility matrix and
+// the lit side, amplitude factor lambda/(4 pi) sqrt(rho^2 cos_i cos_s / pi)
+// / (L r_s) (the solve's k_dps_diffuse) and the phase length.
+__device__ __forceinline__ bool voxel_geom(const LaunchArgs &A, uint32_t ri, uint32_t r, f3 rx, float &a0,
+                                           float &plen) {
+    const int id = A.rb.id[ri];
+    if (!A.dps_vis[(size_t)r * A.S.n_sets + A.S.dps_of[id]]) return false;
+    const float4 xl = A.rb.xl[ri];
+    const f3 v = rx - xyz(xl);
+    const float vn = dot(v, record_normal(A, ri));
+    if (!(vn > 0.f)) return false;
+    const float rs = len(v);
+    a0 = A.fc.amp_iso * sqrtf(A.dps_area * fabsf(A.rb.cs[ri]) * (vn / rs) * (float)(1.0 / kPi)) / (xl.w * rs);
+    plen = xl.w + rs;
+    return true;
+}
+
+// Tape forward, voxel diffuse paths of the reception-point launch: one block
+// per key chunk and 64 receivers, as the solve's k_dps_diffuse, the chain's
+// coefficients taken from the tape's slots.
+__global__ __launch_bounds__(kWave) void k_tape_dps_diffuse(LaunchArgs A) {
+    const uint32_t n_rx = A.D.n_rx, K = A.D.K, CH = kRayChunk * K;
+    const uint32_t n_keys = A.dkey_off[A.D.n_items];
+    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + threadIdx.x;
+    if (r >= n_rx) return;
+    double acc[5] = {0, 0, 0, 0, 0};
+    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
+    const uint32_t k1 = min(n_keys, (c + 1) * CH);
+    for (uint32_t q = c * CH; q < k1; ++q) {
+        const uint32_t ri = A.dkeylist[q];
+        float a0, plen;
+        if (!voxel_geom(A, ri, r, rx, a0, plen)) continue;
+        const uint32_t g = ri / K, k = ri % K;
+        c32 pte = {1.f, 0.f}, ptm = {1.f, 0.f};
+        for (uint32_t m = 0; m <= k; ++m) {
+            SlotCoef cf = load_coef(A.slot_coef, (size_t)g * K + m);
+            float f = m < k ? sqrtf(fmaxf(0.f, 1.f - cf.S * cf.S)) : cf.S;
+            pte = cmul(pte, {f * cf.te.re, f * cf.te.im});
+            ptm = cmul(ptm, {f * cf.tm.re, f * cf.tm.im});
+        }
+        const c32 ph = propagate(plen, A.fc.inv_lam_hi, A.fc.inv_lam_lo);
+        const c32 te = cmul({a0 * pte.re, a0 * pte.im}, ph);
+        const c32 tm = cmul({a0 * ptm.re, a0 * ptm.im}, ph);
+        const double tr = te.re, ti = te.im, mr = tm.re, mi = tm.im;
+        acc[0] += 0.5 * (tr * tr + ti * ti + mr * mr + mi * mi);
+        acc[1] += tr;
+        acc[2] += ti;
+        acc[3] += mr;
+        acc[4] += mi;
+    }
+    double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
+    for (int a = 0; a < 5; ++a) o[a] = acc[a];
+}
+
 // Tape forward, specular part: per key chunk, receivers across lanes.
 __global__ __launch_bounds__(256) void k_tape_specular(LaunchArgs A) {
     __shared__ double red[256][5];
@@ -216,7 +271,10 @@ __global__ __launch_bounds__(256) void k_tape_specular(LaunchArgs A) {
 
 void launch_tape_forward(const LaunchArgs &A, double *gain, double *h_te, double *h_tm, double *parts,
                          hipStream_t s) {
-    if (A.flags & 4)
+    if ((A.flags & 4) && A.dps_vis)
+        hipLaunchKernelGGL(k_tape_dps_diffuse, dim3(std::max<uint32_t>(A.D.n_ray_chunks, 1), (A.D.n_rx + kWave - 1) / kWave),
+                           dim3(kWave), 0, s, A);
+    else if (A.flags & 4)
         hipLaunchKernelGGL(k_tape_diffuse, dim3(std::min<uint32_t>(std::max<uint32_t>(A.D.n_ray_chunks, 1), 2048)),
                            dim3(256), 0, s, A);
     if (A.flags & 2)
@@ -272,7 +330,35 @@ __global__ __launch_bounds__(256) void k_tape_adjoint_trace(LaunchArgs A, const 
 #pragma unroll
         for (int m = 0; m < KM; ++m)
             for (int a = 0; a < 5; ++a) adj[m][a] = 0.0;
-        if (A.flags & 4) {
+        if ((A.flags & 4) && A.dps_vis) {
+            // voxel diffuse paths whose representative is one of this ray's
+            // records (the key list is in record order; one transmitter)
+            SlotCoef cf[KM];
+            bool de[KM];
+#pragma unroll
+            for (int m = 0; m < KM; ++m)
+                if (m < (int)K) cf[m] = load_coef(A.slot_coef, (size_t)g * K + m);
+            const uint32_t n_keys = A.dkey_off[A.D.n_items];
+            uint32_t lo = 0, hi = n_keys;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (A.dkeylist[mid] < g * K) lo = mid + 1;
+                else hi = mid;
+            }
+            for (uint32_t q = lo; q < n_keys && A.dkeylist[q] < (g + 1) * K; ++q) {
+                const uint32_t ri = A.dkeylist[q], k = ri % K;
+                double W = 0.0;
+                for (uint32_t r = 0; r < n_rx; ++r) {
+                    float a0, plen;
+                    if (voxel_geom(A, ri, r, mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]), a0, plen))
+                        W += dldg[r] * (double)a0 * a0;
+                }
+                if (W == 0.0) continue;
+#pragma unroll
+                for (int m = 0; m < KM; ++m) de[m] = (m == (int)k);
+                chain_adjoint<KM>((int)k + 1, cf, de, W, adj);
+            }
+        } else if (A.flags & 4) {
             const int it = find_item(A.items, A.D.n_items, g);
             const float budget = (float)A.items[it].budget;
             SlotCoef cf[KM];

@@ -270,11 +270,16 @@ def test_dps_launch_errors(P, calm):
     mats = scenes.box_room_materials()
     for kw, code in ((dict(n_rays=ns, flags=LOS | SPEC | P.DPS_LAUNCH), -1),
                      (dict(n_rays=ns, flags=LOS | DIFF | P.DPS_LAUNCH), -1),
-                     (dict(n_rays=ns + 1, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis), -1),
-                     (dict(n_rays=ns, flags=LOS | DIFF | REC | P.DPS_LAUNCH, dps_vis=vis), -4)):
+                     (dict(n_rays=ns + 1, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis), -1)):
         with pytest.raises(P.PcrtError) as e:
             P.solve(sg, mats, [1.1, 0.7, 1.3], rx, 3.5e9, K=2, **kw)
         assert e.value.code == code
+    # a tape of the voxel diffuse paths has no ray-tube visibility and no frequency response
+    rec = P.solve(sg, mats, [1.1, 0.7, 1.3], rx, 3.5e9, ns, K=2, flags=LOS | DIFF | REC | P.DPS_LAUNCH, dps_vis=vis)
+    for call in (lambda: P.diffuse_vis(rec), lambda: P.tape_cfr(rec, 1.5e9, 33)):
+        with pytest.raises(P.PcrtError) as e:
+            call()
+        assert e.value.code == -4
     plain = P.Scene.from_scene(calm)
     with pytest.raises(P.PcrtError) as e:
         P.solve(plain, mats, [1.1, 0.7, 1.3], rx, 3.5e9, ns, K=2, flags=LOS | SPEC | P.DPS_LAUNCH, dps_vis=vis)
@@ -400,3 +405,51 @@ def test_dps_launch_office_full_size_sampled(P, orc, office15):
     same = np.all(seq[ids] == sol.seq, 1)
     step("identical: %d of 1024" % same.sum())
     assert same.mean() >= 0.99
+
+
+@pytest.mark.parametrize("avg", [False, True])
+@pytest.mark.parametrize("spec", [False, True])
+def test_dps_launch_voxel_diffuse_tape_and_gradient(P, orc, calm, avg, spec):
+    """The reception-point launch on a tape, voxel diffuse paths included: the
+    tape's forward reproduces the solve's gains; the gradient of a dB loss
+    through the adjoint matches the oracle's analytic Jacobian (which carries
+    the voxel diffuse paths) and central differences of the tape's own loss.
+    Bars as in the averaged gradient test (one set in a thousand may change
+    its key's representative between FP32 and FP64)."""
+    import torch
+    from paper_2507_04021_amd import diff
+    mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
+    rx = np.array([[2.2, 1.4, 1.0], [0.6, 1.5, 1.6], [2.5, 0.4, 0.8]], np.float32)
+    tx = [1.1, 0.7, 1.3]
+    step("dps launch tape avg=%s spec=%s" % (avg, spec))
+    sg = P.Scene.from_scene(calm, dps_voxel=RHO)
+    ns = sg.info["n_point_sets"]
+    vis = P.visibility(sg, rx)
+    fl = LOS | DIFF | P.DPS_LAUNCH | (SPEC if spec else 0) | (AVG if avg else 0)
+    rec = diff.record(sg, mats, tx, rx, 3.5e9, ns, K=3, flags=fl, lambda_d=LAM, dps_vis=vis)
+    g0 = rec.gain.clone()
+    P.tape_fresnel(rec, mats)
+    assert torch.allclose(P.tape_forward(rec)[0], g0, rtol=2e-6, atol=0)
+    ref = orc.solve(calm, mats, tx, rx, 3.5e9, ns, K=3, flags=LOS | DIFF | (SPEC if spec else 0), want_jac=True,
+                    dps_launch=RHO, average=(RHO, LAM) if avg else None)
+    assert np.allclose(g0.cpu().numpy(), ref.G, rtol=1e-3)
+    target = torch.tensor(10 * np.log10(ref.G) + np.array([0.5, -0.3, 0.2]), device="cuda")
+    m = torch.tensor(mats, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = diff.db_mse_loss(diff.gains(m, rec), target)
+    loss.backward()
+    g_gpu = m.grad.cpu().numpy()
+    dl_dg = 2 * (10 * np.log10(ref.G) - target.cpu().numpy()) * 10 / (ref.G * np.log(10)) / len(ref.G)
+    g_orc = np.einsum("r,rlp->lp", dl_dg, ref.jac)
+    scale = np.abs(g_orc).max()
+    assert np.all(np.abs(g_gpu - g_orc) <= 5e-3 * np.abs(g_orc) + 1e-3 * scale), (g_gpu, g_orc)
+    # central differences of the tape's loss in eps_r and S of the first two labels
+    for lab, par in ((0, 0), (0, 2), (1, 0), (1, 2)):
+        h = 1e-3 * mats[lab, par]
+        vals = []
+        for sgn in (1, -1):
+            mm = mats.copy()
+            mm[lab, par] += sgn * h
+            with torch.no_grad():
+                vals.append(float(diff.db_mse_loss(diff.gains(torch.tensor(mm, device="cuda"), rec), target)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g_gpu[lab, par]) <= 2e-2 * abs(g_gpu[lab, par]) + 1e-3 * scale, (lab, par, fd, g_gpu[lab, par])

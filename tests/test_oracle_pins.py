@@ -412,6 +412,33 @@ def test_gradient_matches_finite_differences(orc, room_holefree):
             assert np.all(np.abs(fd - an) <= 2e-5 * scale), (lab, p, fd, an)
 
 
+def test_gradient_of_the_reception_point_launch_matches_finite_differences(orc):
+    """The analytic Jacobian with the paper's launch (rays towards the point
+    sets' reception points, candidates gated by the visibility matrix, voxel
+    diffuse paths of area rho^2) against central differences of G."""
+    s = scenes.box_room(spacing=0.1, radius=0.0708, labels="surface")
+    mats = scenes.box_room_materials("surface", scatter=0.3)
+    rx = np.array([scenes.BOX_RX, [2.0, 3.0, 2.0]], np.float32)
+    rho = 0.25
+    n_sets = int(np.unique(np.floor(s.pos.astype(np.float64) / np.float64(np.float32(rho))), axis=0).shape[0])
+    kw = dict(K=2, flags=LOS | SPEC | DIFF, dps_launch=rho)
+    base = orc.solve(s, mats, scenes.BOX_TX, rx, 3.5e9, n_sets, want_jac=True, **kw)
+    assert base.G_diff.min() > 0 and base.G_spec.min() > 0
+    for lab in range(8):
+        for p, rel in ((0, 1e-5), (1, 1e-4), (2, 1e-4)):
+            h = rel * mats[lab, p]
+            mp, mn = mats.copy(), mats.copy()
+            mp[lab, p] += h
+            mn[lab, p] -= h
+            gp = orc.solve(s, mp, scenes.BOX_TX, rx, 3.5e9, n_sets, **kw).G
+            gn = orc.solve(s, mn, scenes.BOX_TX, rx, 3.5e9, n_sets, **kw).G
+            fd = (gp - gn) / (2 * h)
+            an = base.jac[:, lab, p]
+            # the differences' rounding: a few ulp of G over 2h
+            floor = 8 * np.finfo(float).eps * np.abs(base.G).max() / (2 * h)
+            assert np.all(np.abs(fd - an) <= 2e-5 * np.abs(an) + floor), (lab, p, fd, an)
+
+
 def _lambert_integral_vertical(tx, rx, x0, zc, R, weight):
     """Integral over the vertical disk x = x0 (centre (x0, 0, zc), radius R) of
     cos_i cos_s / (pi r_i^2 r_s^2) * weight(point)."""
