@@ -123,6 +123,11 @@ struct Stack {
     }
 };
 
+// Rank of this lane among the lanes set in a ballot mask (lanes below it).
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ f3 safe_inv(f3 d) {
     const float tiny = 1e-30f;
     float x = fabsf(d.x) < tiny ? copysignf(tiny, d.x) : d.x;
@@ -331,13 +336,22 @@ __device__ __forceinline__ void wide_hits(const float4 *node, int ref, const Oct
         cr[4 * k + 2] = __float_as_int(v.z);
         cr[4 * k + 3] = __float_as_int(v.w);
     }
+    // Entry and exit distances as integer max / min of the float bit patterns.
+    // The bounds are positive (t_lo = eps_self, t_hi > t_lo), so the entry
+    // distance is positive and, among non-negative floats, the integer order is
+    // the float order; a negative exit distance stays negative (only its value
+    // differs), so the test t0 <= t1 and the entry distance are those of the
+    // float forms. The slab distances are never NaN (inv is finite, box
+    // planes finite or 1e30). Unlike fmaxf / fminf, the integer forms need no
+    // canonicalisation of their loop-invariant bound.
+    const int lo_i = __float_as_int(t_lo), hi_i = __float_as_int(t_hi);
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        const float t0 = fmaxf(fmaxf(fmaf(nx[j], inv.x, -oi.x), fmaf(ny[j], inv.y, -oi.y)),
-                               fmaxf(fmaf(nz[j], inv.z, -oi.z), t_lo));
-        const float t1 = fminf(fminf(fmaf(fx[j], inv.x, -oi.x), fmaf(fy[j], inv.y, -oi.y)),
-                               fminf(fmaf(fz[j], inv.z, -oi.z), t_hi));
-        tn[j] = t0 <= t1 ? t0 : INFINITY;
+        const int t0 = max(max(__float_as_int(fmaf(nx[j], inv.x, -oi.x)), __float_as_int(fmaf(ny[j], inv.y, -oi.y))),
+                           max(__float_as_int(fmaf(nz[j], inv.z, -oi.z)), lo_i));
+        const int t1 = min(min(__float_as_int(fmaf(fx[j], inv.x, -oi.x)), __float_as_int(fmaf(fy[j], inv.y, -oi.y))),
+                           min(__float_as_int(fmaf(fz[j], inv.z, -oi.z)), hi_i));
+        tn[j] = __int_as_float(t0) <= __int_as_float(t1) ? __int_as_float(t0) : INFINITY;
     }
 }
 
@@ -529,7 +543,8 @@ __device__ __forceinline__ bool step_any(const DevScene &S, int &ref, int &sp, c
 constexpr int kNoRef = -0x7fffffff - 1;
 
 // True iff a disk != excl is hit with eps_self < t < |b - a| - eps_self on the
-// segment from a towards b.
+// segment from a towards b. eps_self > 0 (every entry point maps other values
+// to its default), which the integer clamps of wide_hits rely on.
 //
 // Leaves are parked: a lane that reaches a leaf keeps it (one at a time) and
 // walks on through nodes; the wavefront tests the parked leaves together once
