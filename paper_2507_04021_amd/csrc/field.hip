@@ -20,18 +20,20 @@ namespace pcrt {
 // Mapping. The records are first put in Morton order of their hit points,
 // with the transmitter index as the high key bits: a transmitter's records
 // keep their range of chunks and only their order inside it changes, so the
-// per-chunk partial sums still add up per transmitter. A wavefront takes 64
-// spatially adjacent interaction points and one receiver at a time, and each
-// lane walks its segment FROM THE RECEIVER towards its interaction point (the
-// test is symmetric in the two end points). All 64 walks then start at the
-// same point with nearly the same direction, make the same near-child
-// choices through the upper tree and only part near their own end points,
-// which keeps the lanes of a wavefront on the same nodes for most of the walk.
+// per-chunk partial sums still add up per transmitter. A wavefront takes a
+// chunk of spatially adjacent interaction points and one receiver at a time,
+// and each lane walks its segment FROM THE RECEIVER towards its interaction
+// point (the test is symmetric in the two end points). Walks started together
+// then leave the same point with nearly the same direction, make the same
+// near-child choices through the upper tree and only part near their own end
+// points, which keeps the lanes of a wavefront on the same nodes for most of
+// the walk.
 //
-// Sums: each lane adds its own records' contributions to a receiver over the
-// chunk's record groups in order; one fixed xor-butterfly over the lanes then
-// gives the chunk's partial sum for that receiver. The result does not
-// depend on timing or on the hierarchy.
+// Sums: lane l adds the contributions of the chunk's visible records l,
+// l + 64, ... to a receiver in record order; one fixed xor-butterfly over the
+// lanes then gives the chunk's partial sum for that receiver. The result does
+// not depend on timing, on which lane walked which segment, or on the
+// hierarchy.
 __global__ void k_diffuse_keys(LaunchArgs A) {
     const uint32_t n_rec = A.D.T * A.D.K;
     const float *B = A.S.bounds;
@@ -109,29 +111,45 @@ __global__ void k_diffuse_pack(LaunchArgs A, const uint32_t *order) {
 // 47.8 / 45.7 / 44.4 / 43.5 ms), and the units of one chunk (consecutive
 // counter values) then run at the same time on one XCD and share its L2.
 //
-// Lit compaction. The wavefront reads the chunk's records 64 at a time and
-// queues the indices of those on the receiver's lit side in LDS, in record
-// order; every full 64 (and the rest at the end) go through the walks
-// together. A wave then never carries a lane whose record is dark or empty
-// for the receiver (a fifth of them on the office), so the chunk takes
-// fewer wave-wide walks. Two queues: connections that leave their surface
-// at a grazing angle (exit cosine below 1/2) run long through the surface's
-// own leaves, so they walk in batches of their own and the other lanes of a
-// batch wait less for its longest walk (diffuse 29.1 -> 28.6 ms on the
-// office). Which lane takes which record depends only on the geometry, so
-// the sums stay fixed-order.
+// Lit compaction. The wavefront classifies the chunk's records 64 at a time
+// and queues the offsets of those on the receiver's lit side in LDS, in
+// record order, so no lane ever walks a record that is dark or empty for the
+// receiver (a fifth of them on the office).
+//
+// Resumable walks with ballot-compacted refill. Each lane keeps one
+// connection's any-hit walk (the walk of occluded(): node, stack, parked
+// leaf) across rounds. The wavefront steps its walking lanes until at most a
+// quarter of its busy lanes still walk, then hands the lanes whose walks
+// ended the next queued records, in lane order (classifying further groups as
+// the queue runs low). A lane no longer waits for the longest walk of a
+// batch of 64, and the lanes refilled together start from the receiver
+// together, on the same upper nodes. Measured on the office (4-wide tree):
+// batches of 64 walks 28.7 ms (with grazing and steep connections queued
+// apart; 29.1 in one queue); refill when at most half / a quarter / an eighth
+// of the busy lanes walk 29.1 / 27.05 / 27.05 ms (at half, the lanes part
+// too early to share nodes); grazing and steep queues under refill 0.45 ms
+// slower. Parked leaves are tested once half of the walking lanes hold one
+// (a third or two thirds: 27.2 and 27.4 ms).
+//
+// Sums. The walks only decide visibility, kept as one bit per record of the
+// chunk in LDS; once the chunk's walks have ended, lane l adds the visible
+// records l, l + 64, ... in record order and one fixed butterfly adds the
+// lanes. The sums do not depend on which lane walked which connection, nor on
+// the hierarchy.
 //
 // Occupancy: six wavefronts per SIMD for the 2- and 4-wide walks (the
 // register budget that allows, with 6.25 KiB of LDS per wavefront, beat
-// five by 2-3 % on the office; seven and eight spilled and lost).
-constexpr uint32_t kLitQueue = 2 * kWave;  // < 64 carried over + 64 added
-constexpr float kGrazeCos = 0.5f;          // exit cosine below which a connection counts as grazing
+// five by 2-3 % on the office; seven and eight spilled and lost). A second
+// queue of 256 B took the LDS to 6.5 KiB and the kernel lost 0.6 ms.
+constexpr uint32_t kLitQueue = 2 * kWave;  // < 64 queued before a classification + 64 added
+constexpr int kRefillShift = 2;            // refill once at most busy / 2^kRefillShift lanes still walk
 
 template <int W>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 4 : 6, 8))) void k_diffuse(
     LaunchArgs A) {
     __shared__ int lds_stack[kStackLds * kWave];
-    __shared__ uint16_t lit_q[2][kLitQueue];  // chunk-relative record offsets: steep, grazing
+    __shared__ uint16_t lit_q[kLitQueue];                 // chunk-relative offsets of lit records
+    __shared__ uint32_t vis_bits[kRayChunk * kMaxK / 32];  // visible connections of the chunk
     const int lane = threadIdx.x;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
@@ -148,6 +166,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
     // of the scene, then help the other ranges in turn. Within a range, units
     // are receiver-minor, so consecutive units reuse a chunk's records.
     const uint32_t xcd = blockIdx.x % kXcds;
+    enum { kIdle = 0, kWalk = 1, kDone = 2 };
     for (;;) {
         uint32_t u = 0xffffffffu;
         if (lane == 0) {
@@ -166,61 +185,117 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
         if (u == 0xffffffffu) break;
         const uint32_t c = u / n_rx, r = u % n_rx;
         const uint32_t g0 = c * kRayChunk;
-        const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
-        const float budget = (float)I.budget;
         const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-        double acc[5] = {};  // this lane's records, in the order it takes them
-        uint32_t head[2] = {0, 0}, tail[2] = {0, 0};  // queue positions (wave-uniform, increasing)
-        // one batch of walks: lanes take n0 queued records of queue 0, then n1 of queue 1
-        auto walk_batch = [&](uint32_t n0, uint32_t n1) {
-            if ((uint32_t)lane < n0 + n1) {
-                const uint32_t b = (uint32_t)lane < n0 ? 0u : 1u;
-                const uint32_t pos = (uint32_t)lane < n0 ? head[0] + lane : head[1] + lane - n0;
-                const uint32_t j = g0 * K + lit_q[b][pos % kLitQueue];
-                const uint32_t ri = A.dsort.order[j];
+        for (uint32_t i = lane; i < 2 * n_groups; i += kWave) vis_bits[i] = 0u;
+        uint32_t q = 0, head = 0, tail = 0;  // next group to classify; queue positions (wave-uniform)
+        int phase = kIdle;
+        uint32_t mo = 0;  // this lane's record, chunk-relative
+        int excl = -1, ref = kNoRef, sp = 0, park = kNoRef;
+        bool hit = false;
+        f3 d = mk(0.f, 0.f, 1.f), inv = mk(1.f, 1.f, 1.f), oi = mk(0.f, 0.f, 0.f);
+        float t_hi = 0.f;
+        Octant oq = octant<W>(inv);
+        uint32_t nv0 = 0;
+        for (;;) {
+            const uint64_t idle = __ballot(phase == kIdle);
+            const uint32_t n_idle = (uint32_t)__popcll(idle);
+            while (tail - head < n_idle && q < n_groups) {
+                const uint32_t o = q * kWave + lane;
+                const uint32_t j = g0 * K + o;
                 const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
-                const int id = __float_as_int(p1.w);
-                const f3 x = xyz(p0), n = xyz(p1);
-                ++n_seg;
-                const uint32_t nv0 = stk.nv;
-                const bool vis = !occluded<W>(A.S, rx, x, id, eps, stk);
-                if (kCountVisits && !vis) n_occ_visits += stk.nv - nv0;
-                if (rec) A.dvis[(size_t)ri * n_rx + r] = vis;
-                if (vis) {
-                    ++n_vis;
-                    double v5[5];
-                    diffuse_amplitude(A, ri, x, n, p0.w, rx, budget, v5);
-                    for (int a = 0; a < 5; ++a) acc[a] += v5[a];
-                }
-            }
-            head[0] += n0;
-            head[1] += n1;
-            __syncthreads();  // the taken slots may be refilled next
-        };
-        for (uint32_t q = 0; q < n_groups; ++q) {
-            const uint32_t o = q * kWave + lane;
-            const uint32_t j = g0 * K + o;
-            const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
-            const f3 v = rx - xyz(p0);
-            const float vn = dot(v, xyz(p1));
-            const bool lit = __float_as_int(p1.w) >= 0 && vn > 0.f;
-            if (rec && !lit) A.dvis[(size_t)A.dsort.order[j] * n_rx + r] = 0;
-            const bool graze = vn < kGrazeCos * len(v);
-            for (uint32_t b = 0; b < 2; ++b) {
-                const uint64_t m = __ballot(lit && graze == (b == 1));
-                if (lit && graze == (b == 1)) lit_q[b][(tail[b] + mbcnt(m)) % kLitQueue] = (uint16_t)o;
-                tail[b] += (uint32_t)__popcll(m);
+                const float vn = dot(rx - xyz(p0), xyz(p1));
+                const bool lit = __float_as_int(p1.w) >= 0 && vn > 0.f;
+                if (rec && !lit) A.dvis[(size_t)A.dsort.order[j] * n_rx + r] = 0;
+                const uint64_t m = __ballot(lit);
+                if (lit) lit_q[(tail + mbcnt(m)) % kLitQueue] = (uint16_t)o;
+                tail += (uint32_t)__popcll(m);
+                ++q;
             }
             __syncthreads();
-            for (uint32_t b = 0; b < 2; ++b)
-                if (tail[b] - head[b] >= (uint32_t)kWave) walk_batch(b == 0 ? kWave : 0, b == 1 ? kWave : 0);
+            const uint32_t avail = min(tail - head, n_idle);
+            if (phase == kIdle && mbcnt(idle) < avail) {
+                mo = lit_q[(head + mbcnt(idle)) % kLitQueue];
+                const uint32_t j = g0 * K + mo;
+                const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
+                excl = __float_as_int(p1.w);
+                // the set-up of occluded(rx, x): walked from the receiver
+                const f3 dv = xyz(p0) - rx;
+                const float L = len(dv);
+                d = (1.0f / L) * dv;
+                inv = safe_inv(d);
+                oi = times(rx, inv);
+                oq = octant<W>(inv);
+                t_hi = L - eps;
+                ref = t_hi > eps ? A.S.root : kNoRef;
+                sp = 0;
+                park = kNoRef;
+                hit = false;
+                phase = kWalk;
+                ++n_seg;
+                nv0 = stk.nv;
+            }
+            head += avail;
+            __syncthreads();  // the taken queue slots may be refilled next round
+            const uint32_t n_busy = (uint32_t)__popcll(__ballot(phase != kIdle));
+            if (n_busy == 0) break;  // the chunk's lit records are all walked
+            for (;;) {
+                for (;;) {
+                    if (phase == kWalk && ref < 0 && ref != kNoRef && park == kNoRef) {
+                        park = ref;
+                        ref = sp > 0 ? stk.get(--sp) : kNoRef;
+                    }
+                    const uint32_t n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
+                    const uint32_t n_park = (uint32_t)__popcll(__ballot(phase == kWalk && park != kNoRef));
+                    if (!__ballot(phase == kWalk && ref >= 0) || 2 * n_park >= n_walk) break;
+                    if (phase == kWalk && ref >= 0) {
+                        stk.visit();
+                        if (!step_any<W>(A.S, ref, sp, oq, inv, oi, eps, t_hi, stk))
+                            ref = sp > 0 ? stk.get(--sp) : kNoRef;
+                    }
+                }
+                if (phase == kWalk && park != kNoRef) {
+                    const int v = -1 - park;
+                    const int first = v >> 3, cnt = (v & 7) + 1;
+                    stk.test(cnt);
+                    for (int i = 0; i < cnt; ++i) {
+                        const float4 dp = ld4(A.S.disk, (uint32_t)(first + i) * 32u);
+                        const float4 dn = ld4(A.S.disk, (uint32_t)(first + i) * 32u + 16u);
+                        float t, d2;
+                        const bool h = disk_hit(rx, d, xyz(dp), xyz(dn), A.S.r2, t, d2);
+                        if (h & (__float_as_int(dp.w) != excl) & (t > eps) & (t < t_hi)) {
+                            hit = true;
+                            break;
+                        }
+                    }
+                    park = kNoRef;
+                    if (hit) ref = kNoRef;
+                }
+                if (phase == kWalk && ref == kNoRef && park == kNoRef) phase = kDone;
+                const uint32_t n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
+                if (n_walk == 0 || (n_walk << kRefillShift) <= n_busy) break;
+            }
+            if (phase == kDone) {
+                if (kCountVisits && hit) n_occ_visits += stk.nv - nv0;
+                if (rec) A.dvis[(size_t)A.dsort.order[g0 * K + mo] * n_rx + r] = !hit;
+                if (!hit) {
+                    atomicOr(&vis_bits[mo >> 5], 1u << (mo & 31));
+                    ++n_vis;
+                }
+                phase = kIdle;
+            }
         }
-        {  // the rest of both queues, merged
-            const uint32_t r0 = tail[0] - head[0], r1 = tail[1] - head[1];
-            if (r0 + r1 > 0) {
-                const uint32_t t1 = min(r1, (uint32_t)kWave - r0);
-                walk_batch(r0, t1);
-                if (r1 > t1) walk_batch(0, r1 - t1);
+        __syncthreads();
+        const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
+        const float budget = (float)I.budget;
+        double acc[5] = {};
+        for (uint32_t g = 0; g < n_groups; ++g) {
+            const uint32_t o = g * kWave + lane;
+            if ((vis_bits[o >> 5] >> (o & 31)) & 1u) {
+                const uint32_t j = g0 * K + o;
+                const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
+                double v5[5];
+                diffuse_amplitude(A, A.dsort.order[j], xyz(p0), xyz(p1), p0.w, rx, budget, v5);
+                for (int a = 0; a < 5; ++a) acc[a] += v5[a];
             }
         }
         double sv[5];
@@ -229,6 +304,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
             double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
             for (int a = 0; a < 5; ++a) o[a] = sv[a];
         }
+        __syncthreads();  // the visibility bits are cleared for the next unit
     }
     flush_visits(stk, A.counters, 13);
     n_seg = warp_sum_u(n_seg);
