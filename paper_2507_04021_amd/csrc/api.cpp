@@ -512,6 +512,10 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     const uint32_t n = pts->n_points;
     sc->dev.node = (const float4 *)(sc->ws + (width > 2 ? L.wnode : L.node));
     sc->dev.width = (int)width;
+    if (width > 2) {
+        sc->dev.qnode = (const float4 *)(sc->ws + L.qnode);
+        sc->dev.qref = (const int *)(sc->ws + L.qref);
+    }
     sc->dev.disk = (const float4 *)(sc->ws + L.disk);
     sc->dev.pos = (const float4 *)(sc->ws + L.pos_id);
     sc->dev.nrm = (const float4 *)(sc->ws + L.nrm_id);

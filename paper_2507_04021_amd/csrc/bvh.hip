@@ -642,6 +642,66 @@ __global__ void k_wide_emit(const float4 *__restrict__ bnode, const uint8_t *__r
     }
 }
 
+// Compact copy of the wide nodes for the any-hit walks (layout and error
+// bound at wide_hits): per axis, the grid step is the power of two 2^e with
+// 2^e >= the node's extent / 2040 and >= 2^-19 times its largest coordinate
+// (so the origin's rounding stays below 1/16 step); the origin is the largest
+// float at or below lo - 2^e; lower planes round down, upper planes up (in
+// FP64, where these differences and quotients are exact). Coordinates then
+// lie in 1..2042. Empty slots get lo = 2047, hi = 0 on every axis, a box no
+// segment enters.
+template <int W>
+__global__ void k_wide_quant(const float *__restrict__ wnode, uint32_t n_nodes, float4 *__restrict__ qnode,
+                             int *__restrict__ qref) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    const float *o = wnode + (size_t)i * 8 * W;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = 0; j < W; ++j) {
+        if (!(o[j] < 1e30f)) continue;  // empty slot
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], o[a * W + j]);
+            hi[a] = fmaxf(hi[a], o[(3 + a) * W + j]);
+        }
+    }
+    float org[3];
+    double step[3];
+    uint32_t eb = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(lo[a] <= hi[a])) lo[a] = hi[a] = 0.f;  // no child (never for a built node)
+        const double ext = (double)hi[a] - (double)lo[a];
+        const double m = fmax(fmax(fabs((double)lo[a]), fabs((double)hi[a])), 1.0);
+        const double need = fmax(ext / 2040.0, m * 0x1p-19);
+        int e;
+        frexp(need, &e);  // need < 2^e
+        e = max(e, -100);
+        step[a] = ldexp(1.0, e);
+        const double od = (double)lo[a] - step[a];
+        float of = (float)od;
+        if ((double)of > od) of = nextafterf(of, -INFINITY);
+        org[a] = of;
+        eb |= ((uint32_t)e & 0xffu) << (8 * a);
+    }
+    char *q = (char *)qnode + (size_t)i * (16 + 12 * W);
+    *(float4 *)q = make_float4(org[0], org[1], org[2], __uint_as_float(eb));
+    _Float16 *rows = (_Float16 *)(q + 16);
+    for (int j = 0; j < W; ++j) {
+        const bool empty = !(o[j] < 1e30f);
+        for (int a = 0; a < 3; ++a) {
+            double gl = 2047.0, gh = 0.0;
+            if (!empty) {
+                gl = floor(((double)o[a * W + j] - (double)org[a]) / step[a]);
+                gh = ceil(((double)o[(3 + a) * W + j] - (double)org[a]) / step[a]);
+                gl = fmin(fmax(gl, 0.0), 2047.0);
+                gh = fmin(fmax(gh, 0.0), 2047.0);
+            }
+            rows[a * W + j] = (_Float16)gl;
+            rows[(3 + a) * W + j] = (_Float16)gh;
+        }
+        qref[(size_t)i * W + j] = __float_as_int(o[6 * W + j]);
+    }
+}
+
 SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps) {
     Bump b;
     SceneLayout L;
@@ -688,6 +748,8 @@ SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps)
     }
     if (width > 2) {  // every wide node stands for a distinct binary internal node
         L.wnode = b.take(sizeof(float) * 8 * width * (size_t)ni);
+        L.qnode = b.take((16 + 12 * (size_t)width) * ni);
+        L.qref = b.take(sizeof(int) * width * (size_t)ni);
         L.front0 = b.take(sizeof(int) * ni);
         L.front1 = b.take(sizeof(int) * ni);
         L.wcnt = b.take(sizeof(uint32_t) * ni);
@@ -804,6 +866,8 @@ hipError_t build_wide_w(const SceneLayout &L, char *ws, hipStream_t s, int broot
     }
     *levels = lv;
     *nodes = base;
+    hipLaunchKernelGGL(k_wide_quant<W>, dim3(cdiv(base, 256)), dim3(256), 0, s, wnode, base, (float4 *)(ws + L.qnode),
+                       (int *)(ws + L.qref));
     return hipGetLastError();
 }
 

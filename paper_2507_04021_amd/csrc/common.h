@@ -60,6 +60,8 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t off) {
 
 struct DevScene {
     const float4 *node;  // binary nodes (4 float4: child boxes + refs) or wide nodes (2W float4)
+    const float4 *qnode; // wide nodes only: compact copies for the any-hit walks (16 + 12 W bytes each)
+    const int *qref;     // wide nodes only: the child references, W per node
     const float4 *disk;  // 2 float4 per leaf-ordered disk: (p.xyz, id bits), (n.xyz, point set bits or 0)
     const float4 *pos;   // by id: (p.xyz, surface bits)
     const float4 *nrm;   // by id: (n.xyz, material bits)
@@ -257,30 +259,6 @@ __device__ __forceinline__ void visit_disk(const DevScene &S, int i, f3 o, f3 d,
 // Children of a wide node (8W floats: lo x[W], lo y[W], lo z[W], hi x[W],
 // hi y[W], hi z[W], refs[W], pad): entry distance per child (INFINITY for a
 // child the segment misses) and its reference.
-//
-// Octant form of the slab test: the sign of each inverse direction
-// component fixes which of lo / hi is the near plane on that axis for every
-// box, so a lane loads its near and far coordinate rows directly (per-lane
-// float4 offsets into the same node) and needs no per-box min/max. The
-// slab values are the same FMAs as in box_hit, and rounding is monotonic,
-// so each near / far value is exactly the one min / max would pick.
-struct Octant {
-    uint32_t nx, ny, nz, fx, fy, fz;  // byte offsets of the near and far plane rows in a node
-};
-
-template <int W>
-__device__ __forceinline__ Octant octant(f3 inv) {
-    constexpr uint32_t row = 4 * W;  // bytes per row of W floats
-    Octant q;
-    q.nx = inv.x >= 0.f ? 0 : 3 * row;
-    q.ny = inv.y >= 0.f ? row : 4 * row;
-    q.nz = inv.z >= 0.f ? 2 * row : 5 * row;
-    q.fx = 3 * row - q.nx;
-    q.fy = 5 * row - q.ny;
-    q.fz = 7 * row - q.nz;
-    return q;
-}
-
 // Same children test without the octant registers (the closest-hit walks are
 // register-bound: per-box min / max instead of per-lane row offsets).
 template <int W>
@@ -306,51 +284,106 @@ __device__ __forceinline__ void wide_hits_minmax(const float4 *node, int ref, f3
     }
 }
 
+// Compact wide nodes for the any-hit walks (16 + 12 W bytes: 64 for W = 4).
+// A header holds the origin of a grid (xyz) and its per-axis steps 2^e (the
+// three e as signed bytes in the fourth word); six rows of W FP16 values
+// follow (lo x, lo y, lo z, hi x, hi y, hi z), each a grid coordinate (an
+// integer 0..2047, exact in FP16) rounded outward with at least one step of
+// margin, so every compact child box contains its float child box. The child
+// references are a separate array of W ints per node.
+//
+// Slab distance of a plane at grid coordinate g: g * (2^e inv) + (origin -
+// o) * inv. 2^e inv is exact (ldexp); (origin - o) inv is one FMA per axis
+// and node (origin * inv - o * inv, o * inv precomputed); each plane is then
+// one mixed-precision FMA whose FP16 operand is widened exactly. The
+// roundings, a few units of 2^-24 of the coordinates and distances, stay far
+// below the float boxes' padding (1e-5 + 2e-6 (|c| + r)), so no box that the
+// exact slab test of the float box would enter is skipped.
 template <int W>
-__device__ __forceinline__ void wide_hits(const float4 *node, int ref, const Octant &q, f3 inv, f3 oi, float t_lo,
+constexpr uint32_t qnode_bytes() {
+    return 16u + 12u * W;
+}
+
+// Octant form of the slab test: the sign of each inverse direction
+// component fixes which of lo / hi is the near plane on that axis for every
+// box, so a lane selects its near and far coordinate rows once per node
+// (two-dword selects) and needs no per-box min/max. Rounding is monotonic, so
+// each near / far value is exactly the one min / max would pick.
+struct Octant {
+    bool px, py, pz;  // inverse direction component >= 0: lo is the near plane
+};
+
+template <int W>
+__device__ __forceinline__ Octant octant(f3 inv) {
+    return {inv.x >= 0.f, inv.y >= 0.f, inv.z >= 0.f};
+}
+
+// The whole compact node is loaded (four 16-byte loads for W = 4, then one
+// for the references): the any-hit walks are bound by the number of vector
+// load instructions (the texture address and data units stay busy about 17
+// and 21 cycles per wavefront load, whatever its width). On the office's
+// diffuse connections: float nodes (six 16-byte row loads chosen by octant +
+// references) 27.0 ms; compact rows as six 8-byte loads chosen by octant
+// 28.1 ms; whole compact node 21.75 ms, with the same visibility.
+template <int W>
+__device__ __forceinline__ void wide_hits(const DevScene &S, int ref, const Octant &q, f3 inv, f3 oi, float t_lo,
                                           float t_hi, float (&tn)[W], int (&cr)[W]) {
-    constexpr int R = W / 4;  // float4 per row of W floats
-    const uint32_t nb = (uint32_t)ref * (32u * W);
-    float nx[W], ny[W], nz[W], fx[W], fy[W], fz[W];
-    auto row = [&](uint32_t r, float (&out)[W]) {
+    constexpr int NQ = (int)qnode_bytes<W>() / 16;  // 16-byte loads per node
+    constexpr int RW = W / 2;                       // dwords per row of W FP16 values
+    const uint32_t nb = (uint32_t)ref * qnode_bytes<W>();
+    uint32_t w[4 * NQ];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const float4 v = ld4(node, nb + r + 16u * k);
-            out[4 * k] = v.x;
-            out[4 * k + 1] = v.y;
-            out[4 * k + 2] = v.z;
-            out[4 * k + 3] = v.w;
-        }
-    };
-    row(q.nx, nx);
-    row(q.ny, ny);
-    row(q.nz, nz);
-    row(q.fx, fx);
-    row(q.fy, fy);
-    row(q.fz, fz);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const float4 v = ld4(node, nb + 6u * 4 * W + 16u * k);
-        cr[4 * k] = __float_as_int(v.x);
-        cr[4 * k + 1] = __float_as_int(v.y);
-        cr[4 * k + 2] = __float_as_int(v.z);
-        cr[4 * k + 3] = __float_as_int(v.w);
+    for (int k = 0; k < NQ; ++k) {
+        const uint4 v = *(const uint4 *)((const char *)S.qnode + nb + 16u * k);
+        w[4 * k] = v.x;
+        w[4 * k + 1] = v.y;
+        w[4 * k + 2] = v.z;
+        w[4 * k + 3] = v.w;
     }
+#pragma unroll
+    for (int k = 0; k < W / 4; ++k) {
+        const int4 v = *(const int4 *)((const char *)S.qref + (uint32_t)ref * (4u * W) + 16u * k);
+        cr[4 * k] = v.x;
+        cr[4 * k + 1] = v.y;
+        cr[4 * k + 2] = v.z;
+        cr[4 * k + 3] = v.w;
+    }
+    uint32_t rn[3][RW], rf[3][RW];  // near / far rows per axis
+    const bool pos[3] = {q.px, q.py, q.pz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const uint32_t lo = w[4 + ax * RW + k], hi = w[4 + (3 + ax) * RW + k];
+            rn[ax][k] = pos[ax] ? lo : hi;
+            rf[ax][k] = pos[ax] ? hi : lo;
+        }
+    _Float16 nx[W], ny[W], nz[W], fx[W], fy[W], fz[W];
+    __builtin_memcpy(nx, rn[0], sizeof nx);
+    __builtin_memcpy(ny, rn[1], sizeof ny);
+    __builtin_memcpy(nz, rn[2], sizeof nz);
+    __builtin_memcpy(fx, rf[0], sizeof fx);
+    __builtin_memcpy(fy, rf[1], sizeof fy);
+    __builtin_memcpy(fz, rf[2], sizeof fz);
+    const int eb = (int)w[3];
+    const f3 a = {ldexpf(inv.x, (eb << 24) >> 24), ldexpf(inv.y, (eb << 16) >> 24), ldexpf(inv.z, (eb << 8) >> 24)};
+    const f3 b = {fmaf(__uint_as_float(w[0]), inv.x, -oi.x), fmaf(__uint_as_float(w[1]), inv.y, -oi.y),
+                  fmaf(__uint_as_float(w[2]), inv.z, -oi.z)};
     // Entry and exit distances as integer max / min of the float bit patterns.
     // The bounds are positive (t_lo = eps_self, t_hi > t_lo), so the entry
     // distance is positive and, among non-negative floats, the integer order is
     // the float order; a negative exit distance stays negative (only its value
     // differs), so the test t0 <= t1 and the entry distance are those of the
-    // float forms. The slab distances are never NaN (inv is finite, box
-    // planes finite or 1e30). Unlike fmaxf / fminf, the integer forms need no
+    // float forms. The slab distances are never NaN (inv, the grid steps and
+    // coordinates are finite). Unlike fmaxf / fminf, the integer forms need no
     // canonicalisation of their loop-invariant bound.
     const int lo_i = __float_as_int(t_lo), hi_i = __float_as_int(t_hi);
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        const int t0 = max(max(__float_as_int(fmaf(nx[j], inv.x, -oi.x)), __float_as_int(fmaf(ny[j], inv.y, -oi.y))),
-                           max(__float_as_int(fmaf(nz[j], inv.z, -oi.z)), lo_i));
-        const int t1 = min(min(__float_as_int(fmaf(fx[j], inv.x, -oi.x)), __float_as_int(fmaf(fy[j], inv.y, -oi.y))),
-                           min(__float_as_int(fmaf(fz[j], inv.z, -oi.z)), hi_i));
+        const int t0 = max(max(__float_as_int(fmaf((float)nx[j], a.x, b.x)), __float_as_int(fmaf((float)ny[j], a.y, b.y))),
+                           max(__float_as_int(fmaf((float)nz[j], a.z, b.z)), lo_i));
+        const int t1 = min(min(__float_as_int(fmaf((float)fx[j], a.x, b.x)), __float_as_int(fmaf((float)fy[j], a.y, b.y))),
+                           min(__float_as_int(fmaf((float)fz[j], a.z, b.z)), hi_i));
         tn[j] = __int_as_float(t0) <= __int_as_float(t1) ? __int_as_float(t0) : INFINITY;
     }
 }
@@ -410,7 +443,7 @@ __device__ __forceinline__ bool wide_step_any(const DevScene &S, int &ref, int &
                                               float t_lo, float t_hi, Stack &stk) {
     float tn[W];
     int cr[W];
-    wide_hits<W>(S.node, ref, q, inv, oi, t_lo, t_hi, tn, cr);
+    wide_hits<W>(S, ref, q, inv, oi, t_lo, t_hi, tn, cr);
     float tb = tn[0];
     int jb = 0;
 #pragma unroll

@@ -49,6 +49,7 @@ struct SceneLayout {
     size_t cbox[2] = {0, 0}, cid[2] = {0, 0}, csz[2] = {0, 0};  // clustering build (builder == kBuildPloc)
     size_t nn = 0, mflag = 0, kflag = 0, pblk = 0, nsize = 0, noff = 0, leaf_pos = 0, perm2 = 0, pleaf2 = 0;
     size_t wnode = 0, front0 = 0, front1 = 0, wcnt = 0, wblk = 0;  // wide collapse (width > 2)
+    size_t qnode = 0, qref = 0;                                     // its compact any-hit copy
     size_t sah_pending = 0, sah_cost = 0, sah_choice = 0;           // its surface-area choices
     size_t dps_pt = 0, dps_off = 0, dps_of = 0, dps_flag = 0, dps_blk = 0, dps_stat = 0, dps_recv = 0;  // point sets
     size_t total;
