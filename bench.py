@@ -67,15 +67,15 @@ def ops_node(width):
 # built from; a figure is reported only while its sources still match.
 _CSRC = "paper_2507_04021_amd/csrc/"
 TRAFFIC = {
-    "k_diffuse": {"bytes": 1333109206, "l2_hit_rate": 0.981,
+    "k_diffuse": {"bytes": 1960859008, "l2_hit_rate": 0.980,
                   "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "field.hip", "bvh.hip")),
-                  "src_sha256": "8ee082c55f45709192e71e04bbff70a209c4fce0cb79405ffcdcceb265eaadea"},
-    "k_trace": {"bytes": 10377208412, "l2_hit_rate": 0.495,
+                  "src_sha256": "38c677a2a0b631812422f9c32b41e95c8fa898e4620284043a773f2d5de520a1"},
+    "k_trace": {"bytes": 10368346842, "l2_hit_rate": 0.497,
                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "trace.hip", "bvh.hip")),
-                "src_sha256": "f24eda2897d779d9c7050dd87c80ab2adc73f3a6d4c0336e37b6859968e5415d"},
-    "k_refine": {"bytes": 10298522914, "l2_hit_rate": 0.482,
+                "src_sha256": "69e262373f3318aebcee0c5cf1ca5f70e2d168aae83378bf40ef8e43cba25cbd"},
+    "k_refine": {"bytes": 10553446253, "l2_hit_rate": 0.485,
                  "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "refine.h", "specular.hip", "bvh.hip")),
-                 "src_sha256": "73662d52068db16dfa0ac2407bb5facc3f6f5b56de553111b413836fb31a23b4"},
+                 "src_sha256": "e20bfd01ac2f1855a14af76aca49866014ffc8fb863992df9431e8b9e4ac1d13"},
 }
 
 
@@ -99,18 +99,22 @@ def office_inputs():
 def algorithmic_bytes(cnt, K, n_rx, stage, width=2):
     """Bytes the method gathers in one launch of a stage's kernel.
 
-    Traversal: 32 W bytes per node of width W visited + 32 B per disk tested
-    (counted by the instrumented build). Streams: the trace kernel writes a
-    48 B record per interaction; the diffuse kernel reads every record slot's
-    packed copy (32 B) and its index (4 B) once per receiver and writes 40 B
-    of FP64 partial sums per (ray chunk of 256, receiver).
+    Traversal: per node visited, 32 W bytes of width W for the closest-hit
+    walks (7 W floats + pad) and, for the any-hit walks of the diffuse
+    connections, 16 + 16 W bytes (the compact node, 16 + 12 W, and its W
+    child references; binary nodes: 64 B); 32 B per disk tested (counted by
+    the instrumented build). Streams: the trace kernel writes a 48 B record
+    per interaction; the diffuse kernel reads every record slot's packed copy
+    (32 B) and its index (4 B) once per receiver and writes 40 B of FP64
+    partial sums per (ray chunk of 256, receiver).
     """
     nb = 32 * width
     if stage == "trace":
         return cnt["trace_nodes"] * nb + cnt["trace_disks"] * 32 + cnt["interactions"] * 48
     if stage == "diffuse":
+        nq = 16 + 16 * width if width > 2 else 64
         chunks = (cnt["rays"] + 255) // 256
-        return (cnt["diffuse_nodes"] * nb + cnt["diffuse_disks"] * 32 + chunks * 256 * K * n_rx * 36
+        return (cnt["diffuse_nodes"] * nq + cnt["diffuse_disks"] * 32 + chunks * 256 * K * n_rx * 36
                 + chunks * n_rx * 40)
     if stage == "refine":
         return cnt["refine_nodes"] * nb + cnt["refine_disks"] * 32
