@@ -238,22 +238,25 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
             __syncthreads();  // the taken queue slots may be refilled next round
             const uint32_t n_busy = (uint32_t)__popcll(__ballot(phase != kIdle));
             if (n_busy == 0) break;  // the chunk's lit records are all walked
+            // A lane that is not walking holds ref = park = kNoRef, so the node
+            // and leaf conditions below need no phase test; the count of walking
+            // lanes only changes when walks end, between the rounds of node steps.
+            uint32_t n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
             for (;;) {
                 for (;;) {
-                    if (phase == kWalk && ref < 0 && ref != kNoRef && park == kNoRef) {
+                    if (ref < 0 && ref != kNoRef && park == kNoRef) {
                         park = ref;
                         ref = sp > 0 ? stk.get(--sp) : kNoRef;
                     }
-                    const uint32_t n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
-                    const uint32_t n_park = (uint32_t)__popcll(__ballot(phase == kWalk && park != kNoRef));
-                    if (!__ballot(phase == kWalk && ref >= 0) || 2 * n_park >= n_walk) break;
-                    if (phase == kWalk && ref >= 0) {
+                    const uint32_t n_park = (uint32_t)__popcll(__ballot(park != kNoRef));
+                    if (!__ballot(ref >= 0) || 2 * n_park >= n_walk) break;
+                    if (ref >= 0) {
                         stk.visit();
                         if (!step_any<W>(A.S, ref, sp, oq, inv, oi, eps, t_hi, stk))
                             ref = sp > 0 ? stk.get(--sp) : kNoRef;
                     }
                 }
-                if (phase == kWalk && park != kNoRef) {
+                if (park != kNoRef) {
                     const int v = -1 - park;
                     const int first = v >> 3, cnt = (v & 7) + 1;
                     stk.test(cnt);
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
                     if (hit) ref = kNoRef;
                 }
                 if (phase == kWalk && ref == kNoRef && park == kNoRef) phase = kDone;
-                const uint32_t n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
+                n_walk = (uint32_t)__popcll(__ballot(phase == kWalk));
                 if (n_walk == 0 || (n_walk << kRefillShift) <= n_busy) break;
             }
             if (phase == kDone) {
