@@ -29,9 +29,10 @@ namespace pcrt {
 // points, which keeps the lanes of a wavefront on the same nodes for most of
 // the walk.
 //
-// Sums: lane l adds the contributions of the chunk's visible records l,
-// l + 64, ... to a receiver in record order; one fixed xor-butterfly over the
-// lanes then gives the chunk's partial sum for that receiver. The result does
+// Sums: the chunk's visible records for a receiver are listed in record
+// order and lane l adds the contributions of list entries l, l + 64, ...; one
+// fixed xor-butterfly over the lanes then gives the chunk's partial sum for
+// that receiver. The result does
 // not depend on timing, on which lane walked which segment, or on the
 // hierarchy.
 __global__ void k_diffuse_keys(LaunchArgs A) {
@@ -132,10 +133,11 @@ __global__ void k_diffuse_pack(LaunchArgs A, const uint32_t *order) {
 // (a third or two thirds: 27.2 and 27.4 ms).
 //
 // Sums. The walks only decide visibility, kept as one bit per record of the
-// chunk in LDS; once the chunk's walks have ended, lane l adds the visible
-// records l, l + 64, ... in record order and one fixed butterfly adds the
-// lanes. The sums do not depend on which lane walked which connection, nor on
-// the hierarchy.
+// chunk in LDS; once the chunk's walks have ended, the visible records are
+// listed in record order, lane l adds list entries l, l + 64, ... and one
+// fixed butterfly adds the lanes. The sums do not depend on which lane walked
+// which connection, nor on the hierarchy. (Groups of 64 records with one lane
+// per record, half of them idle, took 0.3 ms more on the office.)
 //
 // Occupancy: six wavefronts per SIMD for the 2- and 4-wide walks (the
 // register budget that allows, with 6.25 KiB of LDS per wavefront, beat
@@ -150,6 +152,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
     __shared__ int lds_stack[kStackLds * kWave];
     __shared__ uint16_t lit_q[kLitQueue];                 // chunk-relative offsets of lit records
     __shared__ uint32_t vis_bits[kRayChunk * kMaxK / 32];  // visible connections of the chunk
+    static_assert(kRayChunk * kMaxK * sizeof(uint16_t) <= sizeof(lds_stack), "the visible list fits the stacks");
     const int lane = threadIdx.x;
     const uint32_t glane = blockIdx.x * kWave + lane;
     Stack stk{lds_stack + lane, A.S.spill + glane, A.S.spill_lanes};
@@ -288,18 +291,27 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
             }
         }
         __syncthreads();
+        // The visible records in record order, listed in the LDS of the walks'
+        // stacks (every walk has ended: at most 2 KiB of offsets); lane l then
+        // adds list entries l, l + 64, ..., so every lane computes amplitudes
+        // (not only those whose own record of a group is visible).
+        uint16_t *vlist = (uint16_t *)lds_stack;
+        uint32_t n_list = 0;
+        for (uint32_t g = 0; g < n_groups; ++g) {
+            const uint64_t m = (uint64_t)vis_bits[2 * g] | ((uint64_t)vis_bits[2 * g + 1] << 32);
+            if ((m >> lane) & 1u) vlist[n_list + mbcnt(m)] = (uint16_t)(g * kWave + lane);
+            n_list += (uint32_t)__popcll(m);
+        }
+        __syncthreads();
         const Item I = A.items[find_item(A.items, A.D.n_items, g0)];
         const float budget = (float)I.budget;
         double acc[5] = {};
-        for (uint32_t g = 0; g < n_groups; ++g) {
-            const uint32_t o = g * kWave + lane;
-            if ((vis_bits[o >> 5] >> (o & 31)) & 1u) {
-                const uint32_t j = g0 * K + o;
-                const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
-                double v5[5];
-                diffuse_amplitude(A, A.dsort.order[j], xyz(p0), xyz(p1), p0.w, rx, budget, v5);
-                for (int a = 0; a < 5; ++a) acc[a] += v5[a];
-            }
+        for (uint32_t i = (uint32_t)lane; i < n_list; i += kWave) {
+            const uint32_t j = g0 * K + vlist[i];
+            const float4 p0 = A.dsort.pack[2 * (size_t)j], p1 = A.dsort.pack[2 * (size_t)j + 1];
+            double v5[5];
+            diffuse_amplitude(A, A.dsort.order[j], xyz(p0), xyz(p1), p0.w, rx, budget, v5);
+            for (int a = 0; a < 5; ++a) acc[a] += v5[a];
         }
         double sv[5];
         for (int a = 0; a < 5; ++a) sv[a] = wave_sum_d(acc[a]);
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
             double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
             for (int a = 0; a < 5; ++a) o[a] = sv[a];
         }
-        __syncthreads();  // the visibility bits are cleared for the next unit
+        __syncthreads();  // the visibility bits are cleared and the stacks reused by the next unit
     }
     flush_visits(stk, A.counters, 13);
     n_seg = warp_sum_u(n_seg);
