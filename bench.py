@@ -69,7 +69,7 @@ _CSRC = "paper_2507_04021_amd/csrc/"
 TRAFFIC = {
     "k_diffuse": {"bytes": 1885809370, "l2_hit_rate": 0.980,
                   "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "field.hip", "bvh.hip")),
-                  "src_sha256": "499e177f628fa6a85edd2cb7fdb2bddf4a3c87932aa5716bf99e80bb4ac6edff"},
+                  "src_sha256": "eb4a2123f4d65851a98012815a494ac7c2e13b8911f8fd4f4b2579c47a15984d"},
     "k_trace": {"bytes": 10380300973, "l2_hit_rate": 0.497,
                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "trace.hip", "bvh.hip")),
                 "src_sha256": "69e262373f3318aebcee0c5cf1ca5f70e2d168aae83378bf40ef8e43cba25cbd"},

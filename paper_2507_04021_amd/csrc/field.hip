@@ -139,10 +139,11 @@ __global__ void k_diffuse_pack(LaunchArgs A, const uint32_t *order) {
 // which connection, nor on the hierarchy. (Groups of 64 records with one lane
 // per record, half of them idle, took 0.3 ms more on the office.)
 //
-// Occupancy: six wavefronts per SIMD for the 2- and 4-wide walks (the
-// register budget that allows, with 6.25 KiB of LDS per wavefront, beat
-// five by 2-3 % on the office; seven and eight spilled and lost). A second
-// queue of 256 B took the LDS to 6.5 KiB and the kernel lost 0.6 ms.
+// Occupancy: the 6.25 KiB of LDS per wavefront let 25 wavefronts share a
+// compute unit's 160 KiB; the 2- and 4-wide walks stay within the register
+// budget of six per SIMD (at 80 registers, six beat five by 2-3 % on the
+// office; seven and eight spilled and lost). A second queue of 256 B took the
+// LDS to 6.5 KiB and the kernel lost 0.6 ms.
 constexpr uint32_t kLitQueue = 2 * kWave;  // < 64 queued before a classification + 64 added
 constexpr int kRefillShift = 2;            // refill once at most busy / 2^kRefillShift lanes still walk
 
