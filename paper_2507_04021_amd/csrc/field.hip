@@ -376,19 +376,23 @@ void launch_diffuse(const LaunchArgs &A, hipStream_t s) {
 // scattered by an area rho^2 there, a Lambertian patch lit from the (image)
 // transmitter at the unfolded length L:
 //   a0 = sqrt(rho^2 cos_i cos_s / pi) / (L r_s)   (times lambda/4pi S and the chain, in coef)
-// Block: one chunk of keys x 64 receivers; each thread adds its receiver's
-// paths over the chunk in key order (keys are in record order), FP64.
-__global__ __launch_bounds__(kWave) void k_dps_diffuse(LaunchArgs A, float area) {
-    const uint32_t n_rx = A.D.n_rx, CH = kRayChunk * A.D.K;
+// Block: a share of the keys x 64 receivers (dps_key_range); each thread adds
+// its receiver's paths over its part in key order (keys are in record order),
+// FP64.
+__global__ __launch_bounds__(kDpsWaves * kWave) void k_dps_diffuse(LaunchArgs A, float area) {
+    __shared__ double red[kDpsWaves][kWave][5];
+    const uint32_t n_rx = A.D.n_rx;
     const uint32_t n_keys = A.dkey_off[A.D.n_items];
-    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + threadIdx.x;
+    const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + lane;
     const float inv_pi = (float)(1.0 / kPi);
     double acc[5] = {0, 0, 0, 0, 0};
     uint32_t n_vis = 0;
     if (r < n_rx) {
         const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-        const uint32_t k1 = min(n_keys, (c + 1) * CH);
-        for (uint32_t q = c * CH; q < k1; ++q) {
+        uint32_t q0, k1;
+        dps_key_range(n_keys, c, A.D.n_ray_chunks, w, q0, k1);
+        for (uint32_t q = q0; q < k1; ++q) {
             const uint32_t ri = A.dkeylist[q];
             const int id = A.rb.id[ri];
             if (!A.dps_vis[(size_t)r * A.S.n_sets + A.S.dps_of[id]]) continue;
@@ -410,11 +414,10 @@ __global__ __launch_bounds__(kWave) void k_dps_diffuse(LaunchArgs A, float area)
             acc[4] += mi;
             ++n_vis;
         }
-        double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
-        for (int a = 0; a < 5; ++a) o[a] = acc[a];
     }
+    dps_block_sum(red, w, lane, acc, r < n_rx ? A.diff_part + ((size_t)c * n_rx + r) * 5 : nullptr);
     n_vis = warp_sum_u(n_vis);
-    if (threadIdx.x == 0 && n_vis) atomicAdd((unsigned long long *)&A.counters[5], (unsigned long long)n_vis);
+    if (lane == 0 && n_vis) atomicAdd((unsigned long long *)&A.counters[5], (unsigned long long)n_vis);
 }
 
 uint32_t dps_key_cap(const SolveDims &D) {  // twice the records, a power of two
@@ -437,7 +440,7 @@ void launch_dps_diffuse(const LaunchArgs &A, float area, hipStream_t s) {
     fill_u32(B.chunk_off, 0, A.D.n_items + 1, s);
     launch_keys(B, s);
     const dim3 g(A.D.n_ray_chunks, (A.D.n_rx + kWave - 1) / kWave);
-    hipLaunchKernelGGL(k_dps_diffuse, g, dim3(kWave), 0, s, A, area);
+    hipLaunchKernelGGL(k_dps_diffuse, g, dim3(kDpsWaves * kWave), 0, s, A, area);
 }
 
 template <int W>

@@ -195,6 +195,37 @@ struct LaunchArgs {
     SortBufs dsort;
 };
 
+// Voxel diffuse keys of the reception-point launch: block c of n_blocks (the
+// ray chunks) takes an equal share of the n_keys keys, in key order, and each
+// of its kDpsWaves wavefronts an equal share of that (receivers across the
+// lanes); the wavefronts' sums are added in wavefront order, the blocks' in
+// block order. Every wavefront has work and enough of them run to hide the
+// chain of dependent loads per key. (With the ray chunks' 1 280 key positions
+// per single-wavefront block, the office's 53 k keys sat in 42 blocks.)
+constexpr uint32_t kDpsWaves = 8;
+__device__ __forceinline__ void dps_key_range(uint32_t n_keys, uint32_t c, uint32_t n_blocks, uint32_t w,
+                                              uint32_t &q0, uint32_t &q1) {
+    const uint32_t per = (n_keys + n_blocks - 1) / n_blocks;
+    const uint32_t b0 = min(n_keys, c * per), b1 = min(n_keys, b0 + per);
+    const uint32_t sub = (b1 - b0 + kDpsWaves - 1) / kDpsWaves;
+    q0 = min(b1, b0 + w * sub);
+    q1 = min(b1, q0 + sub);
+}
+
+// Wavefront w of a voxel diffuse block hands its lane's five sums over in
+// LDS; wavefront 0 adds them in wavefront order into out (if out is set).
+__device__ __forceinline__ void dps_block_sum(double (*red)[kWave][5], uint32_t w, uint32_t lane, const double *acc,
+                                              double *out) {
+    for (int a = 0; a < 5; ++a) red[w][lane][a] = acc[a];
+    __syncthreads();
+    if (w == 0 && out) {
+        double t[5] = {0, 0, 0, 0, 0};
+        for (uint32_t v = 0; v < kDpsWaves; ++v)
+            for (int a = 0; a < 5; ++a) t[a] += red[v][lane][a];
+        for (int a = 0; a < 5; ++a) out[a] = t[a];
+    }
+}
+
 // Normal of interaction record ri, turned to face the ray that arrived there:
 // the point-set average's normal when it ran, else the hit disk's normal.
 __device__ __forceinline__ f3 record_normal(const LaunchArgs &A, uint32_t ri) {

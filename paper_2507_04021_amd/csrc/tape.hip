@@ -171,18 +171,21 @@ __device__ __forceinline__ bool voxel_geom(const LaunchArgs &A, uint32_t ri, uin
     return true;
 }
 
-// Tape forward, voxel diffuse paths of the reception-point launch: one block
-// per key chunk and 64 receivers, as the solve's k_dps_diffuse, the chain's
+// Tape forward, voxel diffuse paths of the reception-point launch: the same
+// blocks, key shares and sum order as the solve's k_dps_diffuse, the chain's
 // coefficients taken from the tape's slots.
-__global__ __launch_bounds__(kWave) void k_tape_dps_diffuse(LaunchArgs A) {
-    const uint32_t n_rx = A.D.n_rx, K = A.D.K, CH = kRayChunk * K;
+__global__ __launch_bounds__(kDpsWaves * kWave) void k_tape_dps_diffuse(LaunchArgs A) {
+    __shared__ double red[kDpsWaves][kWave][5];
+    const uint32_t n_rx = A.D.n_rx, K = A.D.K;
     const uint32_t n_keys = A.dkey_off[A.D.n_items];
-    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + threadIdx.x;
-    if (r >= n_rx) return;
+    const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint32_t c = blockIdx.x, r = blockIdx.y * kWave + lane;
     double acc[5] = {0, 0, 0, 0, 0};
-    const f3 rx = mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]);
-    const uint32_t k1 = min(n_keys, (c + 1) * CH);
-    for (uint32_t q = c * CH; q < k1; ++q) {
+    const f3 rx = r < n_rx ? mk(A.rx[3 * r], A.rx[3 * r + 1], A.rx[3 * r + 2]) : mk(0.f, 0.f, 0.f);
+    uint32_t q0, k1;
+    dps_key_range(n_keys, c, A.D.n_ray_chunks, w, q0, k1);
+    if (r >= n_rx) k1 = q0;
+    for (uint32_t q = q0; q < k1; ++q) {
         const uint32_t ri = A.dkeylist[q];
         float a0, plen;
         if (!voxel_geom(A, ri, r, rx, a0, plen)) continue;
@@ -204,8 +207,7 @@ __global__ __launch_bounds__(kWave) void k_tape_dps_diffuse(LaunchArgs A) {
         acc[3] += mr;
         acc[4] += mi;
     }
-    double *o = A.diff_part + ((size_t)c * n_rx + r) * 5;
-    for (int a = 0; a < 5; ++a) o[a] = acc[a];
+    dps_block_sum(red, w, lane, acc, r < n_rx ? A.diff_part + ((size_t)c * n_rx + r) * 5 : nullptr);
 }
 
 // Tape forward, specular part: per key chunk, receivers across lanes.
@@ -273,7 +275,7 @@ void launch_tape_forward(const LaunchArgs &A, double *gain, double *h_te, double
                          hipStream_t s) {
     if ((A.flags & 4) && A.dps_vis)
         hipLaunchKernelGGL(k_tape_dps_diffuse, dim3(std::max<uint32_t>(A.D.n_ray_chunks, 1), (A.D.n_rx + kWave - 1) / kWave),
-                           dim3(kWave), 0, s, A);
+                           dim3(kDpsWaves * kWave), 0, s, A);
     else if (A.flags & 4)
         hipLaunchKernelGGL(k_tape_diffuse, dim3(std::min<uint32_t>(std::max<uint32_t>(A.D.n_ray_chunks, 1), 2048)),
                            dim3(256), 0, s, A);
