@@ -69,13 +69,13 @@ _CSRC = "paper_2507_04021_amd/csrc/"
 TRAFFIC = {
     "k_diffuse": {"bytes": 1885809370, "l2_hit_rate": 0.980,
                   "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "field.hip", "bvh.hip")),
-                  "src_sha256": "eb4a2123f4d65851a98012815a494ac7c2e13b8911f8fd4f4b2579c47a15984d"},
+                  "src_sha256": "701f6a05ca428189f0331b01a4947d63dafa2c29d60f027c7ede39babaab5bb1"},
     "k_trace": {"bytes": 10380300973, "l2_hit_rate": 0.497,
                 "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "trace.hip", "bvh.hip")),
-                "src_sha256": "69e262373f3318aebcee0c5cf1ca5f70e2d168aae83378bf40ef8e43cba25cbd"},
+                "src_sha256": "e669d677a8b4e87922636de5f52add6d718c6a0e009921a1008be58b8afda3ee"},
     "k_refine": {"bytes": 10567116838, "l2_hit_rate": 0.484,
                  "sources": tuple(_CSRC + f for f in ("common.h", "internal.h", "refine.h", "specular.hip", "bvh.hip")),
-                 "src_sha256": "e20bfd01ac2f1855a14af76aca49866014ffc8fb863992df9431e8b9e4ac1d13"},
+                 "src_sha256": "a0e9790cb9b071496f72f9e43432bcd2f0773a3be0c812e7f6f7be0d407cedda"},
 }
 
 
