@@ -515,6 +515,7 @@ pcrt_status pcrt_scene_create(const pcrt_points *pts, const pcrt_bvh_opts *opts,
     if (width > 2) {
         sc->dev.qnode = (const float4 *)(sc->ws + L.qnode);
         sc->dev.qref = (const int *)(sc->ws + L.qref);
+        sc->dev.qstride = (uint32_t)((16 + 12 * width) * wide_nodes);
     }
     sc->dev.disk = (const float4 *)(sc->ws + L.disk);
     sc->dev.pos = (const float4 *)(sc->ws + L.pos_id);

@@ -649,7 +649,10 @@ __global__ void k_wide_emit(const float4 *__restrict__ bnode, const uint8_t *__r
 // float at or below lo - 2^e; lower planes round down, upper planes up (in
 // FP64, where these differences and quotients are exact). Coordinates then
 // lie in 1..2042. Empty slots get lo = 2047, hi = 0 on every axis, a box no
-// segment enters.
+// segment enters. The node is written in eight copies, one per direction
+// octant (copy o: bit a set for a negative direction component on axis a),
+// the near plane rows first: lo rows on positive axes, hi rows on negative
+// ones.
 template <int W>
 __global__ void k_wide_quant(const float *__restrict__ wnode, uint32_t n_nodes, float4 *__restrict__ qnode,
                              int *__restrict__ qref) {
@@ -682,23 +685,26 @@ __global__ void k_wide_quant(const float *__restrict__ wnode, uint32_t n_nodes, 
         org[a] = of;
         eb |= ((uint32_t)e & 0xffu) << (8 * a);
     }
-    char *q = (char *)qnode + (size_t)i * (16 + 12 * W);
-    *(float4 *)q = make_float4(org[0], org[1], org[2], __uint_as_float(eb));
-    _Float16 *rows = (_Float16 *)(q + 16);
-    for (int j = 0; j < W; ++j) {
-        const bool empty = !(o[j] < 1e30f);
-        for (int a = 0; a < 3; ++a) {
-            double gl = 2047.0, gh = 0.0;
-            if (!empty) {
-                gl = floor(((double)o[a * W + j] - (double)org[a]) / step[a]);
-                gh = ceil(((double)o[(3 + a) * W + j] - (double)org[a]) / step[a]);
-                gl = fmin(fmax(gl, 0.0), 2047.0);
-                gh = fmin(fmax(gh, 0.0), 2047.0);
+    for (uint32_t oc = 0; oc < 8u; ++oc) {
+        char *q = (char *)qnode + ((size_t)oc * n_nodes + i) * (16 + 12 * W);
+        *(float4 *)q = make_float4(org[0], org[1], org[2], __uint_as_float(eb));
+        _Float16 *rows = (_Float16 *)(q + 16);
+        for (int j = 0; j < W; ++j) {
+            const bool empty = !(o[j] < 1e30f);
+            for (int a = 0; a < 3; ++a) {
+                double gl = 2047.0, gh = 0.0;
+                if (!empty) {
+                    gl = floor(((double)o[a * W + j] - (double)org[a]) / step[a]);
+                    gh = ceil(((double)o[(3 + a) * W + j] - (double)org[a]) / step[a]);
+                    gl = fmin(fmax(gl, 0.0), 2047.0);
+                    gh = fmin(fmax(gh, 0.0), 2047.0);
+                }
+                const bool neg = (oc >> a) & 1u;  // copy for a negative direction component
+                rows[a * W + j] = (_Float16)(neg ? gh : gl);      // near plane first
+                rows[(3 + a) * W + j] = (_Float16)(neg ? gl : gh);
             }
-            rows[a * W + j] = (_Float16)gl;
-            rows[(3 + a) * W + j] = (_Float16)gh;
+            qref[(size_t)i * W + j] = __float_as_int(o[6 * W + j]);
         }
-        qref[(size_t)i * W + j] = __float_as_int(o[6 * W + j]);
     }
 }
 
@@ -748,7 +754,7 @@ SceneLayout scene_layout(uint32_t n, uint32_t width, uint32_t builder, bool dps)
     }
     if (width > 2) {  // every wide node stands for a distinct binary internal node
         L.wnode = b.take(sizeof(float) * 8 * width * (size_t)ni);
-        L.qnode = b.take((16 + 12 * (size_t)width) * ni);
+        L.qnode = b.take((16 + 12 * (size_t)width) * ni * 8);  // one copy per octant
         L.qref = b.take(sizeof(int) * width * (size_t)ni);
         L.front0 = b.take(sizeof(int) * ni);
         L.front1 = b.take(sizeof(int) * ni);
