@@ -198,6 +198,8 @@ def test_visibility_matrix_parity(P, orc, room):
     for leaf, width, builder in ((2, 4, 2), (4, 2, 1), (1, 8, 2), (8, 4, 1)):
         step("visibility leaf=%d width=%d builder=%d" % (leaf, width, builder))
         sg = P.Scene.from_scene(room, leaf_size=leaf, width=width, builder=builder, dps_voxel=RHO)
+        ns = sg.info["n_point_sets"]
+        assert ns > 2 * 1024 and ns % 1024 != 0  # several 1024-point units of the kernel, a ragged last one
         v = P.visibility(sg, rx).cpu().numpy()
         assert v.shape == ref.shape
         assert (v == ref).mean() >= 0.999
