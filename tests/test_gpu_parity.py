@@ -441,6 +441,34 @@ def test_office_node_width_bitwise(P, office):
         del g, r
 
 
+def test_compact_nodes_far_from_origin_bitwise(P):
+    """The any-hit walks of 4- and 8-wide trees read compact nodes (grid
+    coordinates in FP16, rounded outward); the binary tree reads its float
+    boxes. Far from the origin, where FP32 rounding is coarse, every output of
+    a solve with LOS, specular and diffuse paths is still bit for bit that of
+    the binary tree: the compact boxes cull nothing the float boxes enter."""
+    import dataclasses
+    off = np.array([2000.0, -1500.0, 300.0], np.float32)
+    base = scenes.noisy(scenes.box_room(spacing=0.05, radius=0.03, size=(6.0, 4.0, 3.0)), seed=4)
+    sc = dataclasses.replace(base, pos=(base.pos + off).astype(np.float32))
+    mats = scenes.box_room_materials("four", scatter=0.3)
+    tx = np.array([1.5, 1.2, 1.6], np.float32) + off
+    rx = np.array([[4.5, 2.8, 1.1], [2.2, 3.1, 2.0], [5.1, 0.9, 0.7]], np.float32) + off
+    want = None
+    for w, b in ((2, 2), (4, 2), (8, 1), (4, 1)):
+        step("far-from-origin box room, width %d, builder %d" % (w, b))
+        g = P.Scene.from_scene(sc, leaf_size=2, width=w, builder=b)
+        r = gpu_solve(P, g, mats, tx, rx, 3.5e9, 1 << 16, 3, LOS | SPEC | DIFF)
+        got = [x.cpu().numpy() for x in (r.seq, r.gain, r.h_te, r.h_tm, r.parts)]
+        assert r.counter("diffuse") > 0 and r.counter("specular") > 0
+        if want is None:
+            want = got
+        else:
+            for a, c in zip(got, want):
+                assert np.array_equal(a, c)
+        del g, r
+
+
 # ------------------- validation thresholds and kappa retries (Table I)
 @pytest.mark.parametrize("kind,v,at_x,thr", [("offset", 0.005, 1.3, {}), ("offset", 0.015, 1.3, {}),
                                              ("offset", 0.015, 1.3, dict(kappa=0)),
