@@ -445,8 +445,9 @@ def test_compact_nodes_far_from_origin_bitwise(P):
     """The any-hit walks of 4- and 8-wide trees read compact nodes (grid
     coordinates in FP16, rounded outward); the binary tree reads its float
     boxes. Far from the origin, where FP32 rounding is coarse, every output of
-    a solve with LOS, specular and diffuse paths is still bit for bit that of
-    the binary tree: the compact boxes cull nothing the float boxes enter."""
+    a solve with LOS, specular and diffuse paths, and the visibility matrix to
+    the reception points, are still bit for bit those of the binary tree: the
+    compact boxes cull nothing the float boxes enter."""
     import dataclasses
     off = np.array([2000.0, -1500.0, 300.0], np.float32)
     base = scenes.noisy(scenes.box_room(spacing=0.05, radius=0.03, size=(6.0, 4.0, 3.0)), seed=4)
@@ -457,10 +458,11 @@ def test_compact_nodes_far_from_origin_bitwise(P):
     want = None
     for w, b in ((2, 2), (4, 2), (8, 1), (4, 1)):
         step("far-from-origin box room, width %d, builder %d" % (w, b))
-        g = P.Scene.from_scene(sc, leaf_size=2, width=w, builder=b)
+        g = P.Scene.from_scene(sc, leaf_size=2, width=w, builder=b, dps_voxel=0.125)
         r = gpu_solve(P, g, mats, tx, rx, 3.5e9, 1 << 16, 3, LOS | SPEC | DIFF)
         got = [x.cpu().numpy() for x in (r.seq, r.gain, r.h_te, r.h_tm, r.parts)]
-        assert r.counter("diffuse") > 0 and r.counter("specular") > 0
+        got.append(P.visibility(g, rx).cpu().numpy())  # set-excluding any-hit walks
+        assert r.counter("diffuse") > 0 and r.counter("specular") > 0 and 0.1 < got[-1].mean() < 0.99
         if want is None:
             want = got
         else:
