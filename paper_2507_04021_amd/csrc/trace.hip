@@ -38,7 +38,7 @@ struct Walk {
     f3 inv, oi;
     int ref, sp, park;
     float tmin;
-    Cand c[4];
+    Cand c[kTieList];
     bool spill, pass2;  // candidate list overflowed; second (exact) pass running
     float t_win, bd2, bt;
     int bid;
@@ -52,7 +52,7 @@ __device__ __forceinline__ void walk_start(Walk &w, int root, f3 o, f3 d) {
     w.park = kNoRef;
     w.tmin = INFINITY;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w.c[q] = {INFINITY, INFINITY, -1};
+    for (int q = 0; q < kTieList; ++q) w.c[q] = {INFINITY, INFINITY, -1};
     w.spill = w.pass2 = false;
     w.t_win = 0.f;
     w.bd2 = w.bt = INFINITY;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
                 t = w.bt;
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < kTieList; ++q)
                     if (w.c[q].id >= 0 && (w.c[q].d2 < w.bd2 || (w.c[q].d2 == w.bd2 && w.c[q].id < w.bid))) {
                         w.bd2 = w.c[q].d2;
                         w.bid = w.c[q].id;

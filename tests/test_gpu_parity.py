@@ -471,6 +471,46 @@ def test_compact_nodes_far_from_origin_bitwise(P):
         del g, r
 
 
+def test_stacked_coplanar_disks_take_the_exact_second_pass(P, orc):
+    """A floor and a ceiling tiled with overlapping coplanar disks (spacing
+    0.02 m, radius 0.05 m: about twenty disks share every hit point at the
+    same t). Each bounce overflows the short tie-window list, so every
+    nearest hit is decided by the exact second pass over the final window
+    -- in the resumable walks of the bounce loop and in the refinement's
+    walks. Sequences, path records and per-receiver sums match the oracle
+    (same bars as the random scenes) for binary, 4- and 8-wide trees."""
+    floor = scenes.plane_patch(-1.0, 1.0, -1.0, 1.0, 0.02, 0.05)
+    ceil = scenes.plane_patch(-1.0, 1.0, -1.0, 1.0, 0.02, 0.05, z=1.5, material=1, surface=1)
+    ceil.normal[:] = [0.0, 0.0, -1.0]
+    sc = scenes.concat([floor, ceil])
+    mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2]])
+    tx = np.array([0.013, -0.007, 0.75], np.float32)
+    rx = np.array([[0.31, 0.22, 0.4], [-0.25, 0.4, 1.1]], np.float32)
+    N, K = 2000, 3
+    ref = orc.solve(sc, mats, tx, rx, 28e9, N, K=K, flags=LOS | SPEC | DIFF)
+    op = oracle_paths_by_key(ref, len(rx))
+    assert len(op) >= 4 and ref.G_diff.min() > 0
+    k0 = 2 * math.pi * 28e9 / C0
+    for w, b in ((2, 1), (4, 2), (8, 1)):
+        step("stacked coplanar disks, width %d, builder %d" % (w, b))
+        sg = P.Scene.from_scene(sc, leaf_size=2, width=w, builder=b)
+        r = gpu_solve(P, sg, mats, tx, rx, 28e9, N, K, LOS | SPEC | DIFF | REC)
+        n_int = r.counter("interactions")
+        assert n_int > 1000 and r.counter("tie_spill") >= 0.9 * n_int
+        assert np.mean(np.all(r.seq.cpu().numpy() == ref.seq, 1)) >= 0.999
+        gp, _ = gpu_paths_by_key(P, r, sc)
+        assert set(gp) == set(op)
+        for k, (L, te, tm) in op.items():
+            gl, gte, gtm = gp[k]
+            assert abs(gl - L) <= 2e-6 * L
+            assert abs(gte - te) <= (1e-4 + k0 * 4e-6) * abs(te)
+            assert abs(gtm - tm) <= (1e-4 + k0 * 4e-6) * abs(tm)
+        parts = r.parts.cpu().numpy()
+        for c, ref_part in enumerate((ref.G_los, ref.G_spec, ref.G_diff)):
+            assert np.allclose(parts[:, c], ref_part, rtol=1e-4, atol=1e-30)
+        del sg, r
+
+
 # ------------------- validation thresholds and kappa retries (Table I)
 @pytest.mark.parametrize("kind,v,at_x,thr", [("offset", 0.005, 1.3, {}), ("offset", 0.015, 1.3, {}),
                                              ("offset", 0.015, 1.3, dict(kappa=0)),
