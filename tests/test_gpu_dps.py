@@ -70,6 +70,42 @@ def test_average_needs_point_sets(P, room):
     assert e.value.code == -1  # PCRT_EINVAL
 
 
+def test_average_on_stacked_coplanar_disks(P, orc):
+    """Averaged interactions where about twenty coplanar disks share every
+    hit point (a floor and a ceiling tiled at 0.02 m with 0.05 m disks): each
+    nearest hit overflows the short tie-window list and is decided by the exact
+    second pass, then averaged over the hit disk's point set. Sequences, sums
+    and specular paths match the oracle at the averaged-solve bars."""
+    floor = scenes.plane_patch(-1.0, 1.0, -1.0, 1.0, 0.02, 0.05)
+    ceil = scenes.plane_patch(-1.0, 1.0, -1.0, 1.0, 0.02, 0.05, z=1.5, material=1, surface=1)
+    ceil.normal[:] = [0.0, 0.0, -1.0]
+    sc = scenes.concat([floor, ceil])
+    mats = np.array([[3.0, 0.1, 0.3], [5.0, 0.5, 0.2]])
+    tx = [0.013, -0.007, 0.75]
+    rx = np.array([[0.31, 0.22, 0.4], [-0.25, 0.4, 1.1]], np.float32)
+    N, K = 2000, 3
+    ref = orc.solve(sc, mats, tx, rx, 3.5e9, N, K=K, flags=LOS | SPEC | DIFF, average=(RHO, LAM))
+    for w in (2, 4):
+        step("averaged stacked coplanar disks, width %d" % w)
+        sg = P.Scene.from_scene(sc, leaf_size=2, width=w, dps_voxel=RHO)
+        r = P.solve(sg, mats, tx, rx, 3.5e9, N, K=K, flags=LOS | SPEC | DIFF | REC | AVG, want_seq=True,
+                    lambda_d=LAM)
+        n_int = r.counter("interactions")
+        assert n_int > 1000 and r.counter("tie_spill") >= 0.9 * n_int
+        assert np.mean(np.all(r.seq.cpu().numpy() == ref.seq, 1)) >= 0.999
+        parts = r.parts.cpu().numpy()
+        for c, ref_part in enumerate((ref.G_los, ref.G_spec, ref.G_diff)):
+            assert np.allclose(parts[:, c], ref_part, rtol=2e-3, atol=1e-30)
+        pth = P.paths(r)
+        gp = set()
+        for q in range(pth["n_keys"]):
+            key = tuple(int(sc.surface[i]) for i in pth["key_seq"][q, :int(pth["key_len"][q])])
+            gp |= {(j, key) for j in range(len(rx)) if pth["valid"][q, j]}
+        op = {(j, k) for j in range(len(rx)) for k in ref.paths(j)}
+        assert len(op) >= 4 and gp == op
+        del sg, r
+
+
 @pytest.mark.parametrize("leaf,width,builder", [(2, 4, 2), (4, 2, 1), (1, 8, 2)])
 def test_average_solve_parity(P, orc, room, leaf, width, builder):
     mats = np.array([[5.0, 0.1, 0.3], [6.0, 0.01, 0.2], [3.0, 0.05, 0.4], [2.0, 1e4, 0.1]])
