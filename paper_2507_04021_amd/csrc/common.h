@@ -40,6 +40,8 @@ __device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; 
 __device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+// s * a + b with one rounding per component (fused multiply-add)
+__device__ __forceinline__ f3 fma3(float s, f3 a, f3 b) { return {fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
 __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 __device__ __forceinline__ float len(f3 a) { return sqrtf(dot(a, a)); }
 __device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / len(a)) * a; }
@@ -164,7 +166,7 @@ __device__ __forceinline__ f3 times(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, 
 __device__ __forceinline__ bool disk_hit(f3 o, f3 d, f3 p, f3 n, float r2, float &t, float &d2) {
     const float a = dot(d, n);
     t = dot(p - o, n) / a;
-    const f3 q = o + t * d;
+    const f3 q = fma3(t, d, o);
     const f3 e = q - p;
     d2 = dot(e, e);
     return (fabsf(a) >= kParallelEps) & (d2 <= r2);

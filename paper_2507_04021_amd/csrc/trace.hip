@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
         const float dn = dot(d, n);
         const float sgn = dn > 0.f ? -1.f : 1.f;
         const float cosi = fabsf(dn);
-        const f3 q = o + t * d;
+        const f3 q = fma3(t, d, o);
         L += t;
         A.rb.id[rb + k] = h;
         if (want_geom) {
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(W == 8 ? 
             enc = enc * (uint64_t)A.n_surf1 + (uint64_t)(su + 1);
             if (want_spec) A.rb.slot[rb + k] = key_insert(A.hb, (uint32_t)it * A.hb.cap, enc, j, A.counters + 6);
         }
-        d = normalize(d - (2.f * dn) * n);
+        d = normalize(fma3(-2.f * dn, n, d));
         o = q;
         excl = h;
         k += 1;
